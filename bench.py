@@ -1,0 +1,190 @@
+"""Benchmark: particle-steps/s of the exponential-integrator PIC step on one MI355X.
+
+Workload (default): the Vlasov-Poisson beam at scale -- N_p = 1e8 FP32
+particles, R ~ N(0,1) truncated to |R| < 4, V ~ N(0,1), weights 1/N_p, radial
+mesh of N_r = 4096 cells on [-5, 5], eps = 1e-3, dt = 0.05, K = 1 substep,
+LDS-privatised fixed-point deposit.  One step = FP64 phase tables, gather +
+push + CIC deposit (one fused kernel), exact-integer prefix-sum Poisson solve;
+moments every 100 steps.
+
+Output: one JSON line (see the repository's documentation for the fields),
+with
+  roofline     -- dominant kernel (push_poisson), algorithmic bytes 16 B per
+                  particle-step / its mean duration from HIP events recorded
+                  on the library's stream, vs the 8 TB/s HBM peak;
+  cpu_baseline -- the FP64 CPU oracle timed on this host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE_STEP = 16   # read + write zR, zV (FP32)
+COUNTERS = os.path.join(ROOT, "profiles", "push_poisson_1e8_nr4096_counters.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1404_1160_amd", "csrc", "pic_kernels.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=100_000_000)
+    ap.add_argument("--cells", type=int, default=4096)
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--dt", type=float, default=0.05)
+    ap.add_argument("--substeps", type=int, default=1)
+    ap.add_argument("--deposit", choices=["atomic", "sorted"], default="atomic")
+    ap.add_argument("--moments-every", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run an 800 MB device copy (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def kernel_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(n):
+    """HBM bytes per push launch from committed rocprofv3 counter runs, or None
+    if they were taken on another version of the kernel source."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256_16") != kernel_hash() or c.get("n_particles") != n:
+        return None
+    return c.get("bytes_per_launch")
+
+
+def cpu_baseline(n_full, cells, eps, dt, K, seconds):
+    """The FP64 oracle on this host: a 2e6-particle sample of the same beam
+    (weights scaled to the full beam's charge), stepped until ~`seconds`."""
+    import numpy as np
+
+    import oracle
+    from paper_1404_1160_amd import synth
+
+    n = min(n_full, 2_000_000)
+    R, V, _ = synth.gaussian_truncated(n, seed=13)
+    w = 1.0 / n
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        R, V = oracle.run(R, V, w, dt, eps, K, 1, oracle.FIELD_POISSON, nr=cells, rmin=-5.0,
+                          rmax=5.0)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "%d particles of the same beam x %d steps (K=%d, N_r=%d), %.1f s" % (
+                n, steps, K, cells, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the multi-GPU sharding is a design note, not a run)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    from paper_1404_1160_amd import (EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED, EP_FIELD_POISSON, Sim,
+                                     capi, synth)
+
+    capi.lib()   # fails loudly if the HIP library is missing
+    n = args.n
+    t0 = time.perf_counter()
+    R0, V0, w = synth.gaussian_truncated(n, seed=13)
+    gen_s = time.perf_counter() - t0
+    deposit = EP_DEPOSIT_SORTED if args.deposit == "sorted" else EP_DEPOSIT_ATOMIC
+    sim = Sim(n, n_cells=args.cells, substeps=args.substeps, deposit=deposit, device=0)
+    sim.set_particles(R0, V0, w)
+    del R0, V0
+    print("bench: %d particles loaded (generation %.1f s)" % (n, gen_s), file=sys.stderr,
+          flush=True)
+
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(n * 2, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(args.warmup):
+        sim.step(args.dt, args.eps, EP_FIELD_POISSON, 1)
+    sim.sync()
+    capi.ep_timing_enable(sim.ctx, True)
+    sim.sync()
+    t0 = time.perf_counter()
+    done = 0
+    mom = None
+    while done < args.steps:
+        chunk = min(args.moments_every, args.steps - done)
+        sim.step(args.dt, args.eps, EP_FIELD_POISSON, chunk)
+        done += chunk
+        if done % args.moments_every == 0:
+            mom = sim.moments(args.eps, EP_FIELD_POISSON)
+    sim.sync()
+    elapsed = time.perf_counter() - t0
+    push_ms, push_count = capi.ep_timing_get(sim.ctx, "push_poisson")
+    solve_ms, solve_count = capi.ep_timing_get(sim.ctx, "mesh_solve")
+    if mom is None:
+        mom = sim.moments(args.eps, EP_FIELD_POISSON)
+    sim.close()
+
+    value = n * args.steps / elapsed
+    push_avg_s = push_ms / max(push_count, 1) / 1e3
+    achieved = BYTES_PER_PARTICLE_STEP * n / push_avg_s / 1e9
+    line = {
+        "metric": "particle-steps/s at 1e8 particles (plain push, Vlasov-Poisson)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "vlasov_poisson_beam_Np%d_Nr%d" % (n, args.cells),
+                   "n_particles": n, "n_cells": args.cells, "eps": args.eps, "dt": args.dt,
+                   "substeps": args.substeps, "deposit": args.deposit,
+                   "moments_every": args.moments_every,
+                   "precision": "FP32 push/deposit, FP64 phase, exact-integer charge scan"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n),
+                     "kernel": "push_poisson", "kernel_ms": push_avg_s * 1e3,
+                     "launches": push_count,
+                     "bytes_per_launch": BYTES_PER_PARTICLE_STEP * n},
+        "mesh_solve_ms": solve_ms / max(solve_count, 1),
+        "moments": {k: mom[k] for k in ("t", "rms_radius", "energy", "n_offmesh", "n_nan")},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, args.cells, args.eps, args.dt, args.substeps,
+                                            args.cpu_seconds)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * etdpic.h: C ABI of the exponential-integrator Particle-In-Cell step on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library advances a beam of macroparticles (R_i, V_i) with uniform weight
+ * w along the stiff characteristics of the axisymmetric-beam Vlasov equation
+ *     dR/dt = V/eps,  dV/dt = -R/eps + E(R, t)
+ * (Frenod, Hirstoaga, Lutz, arXiv 1404.1160: eq. 1.1 and its characteristics
+ * eq. 1.4).  The eps-linear part is integrated exactly by the rotation r of
+ * eq. 3.3 (T = 2 pi), and E enters through the variation-of-constants
+ * (Duhamel) integral of eq. 3.6, evaluated by the midpoint rule along the free
+ * rotation on K substeps per macro step.  E is either the given field
+ * E = -R^3 (eq. 1.3) or the self-consistent field of the Poisson equation
+ * d/dr (r E) = rho (eq. 1.2), obtained by a cloud-in-cell (CIC) deposit of the
+ * charge onto a radial mesh, a trapezoidal prefix sum over the cells
+ * (section 2.3) and a CIC gather back to the particles.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns an ep_status: EP_OK (0) or a negative code; no
+ *     exception or signal crosses the ABI.  ep_last_error() gives the message.
+ *   - Host arrays are owned by the caller and only read or written during the
+ *     call; device memory is owned by the library unless bound with
+ *     ep_bind_particles().
+ *   - Work is queued on the context's HIP stream; ep_step() returns before the
+ *     GPU finishes.  Calls that return host data synchronise that stream and
+ *     report asynchronous HIP errors as EP_EHIP.
+ *   - One context may be used by one host thread at a time.
+ */
+#ifndef ETDPIC_H
+#define ETDPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ep_ctx ep_ctx;
+
+typedef enum {
+    EP_OK = 0,
+    EP_EINVAL = -1,      /* an argument is out of range or inconsistent        */
+    EP_ENOMEM = -2,      /* device or host allocation failed                   */
+    EP_EHIP = -3,        /* a HIP call or a kernel failed                      */
+    EP_ESTATE = -4,      /* the call does not fit the context's state          */
+    EP_ENOTRAINED = -5,  /* learned push requested with no network loaded      */
+    EP_EIO = -6          /* checkpoint file could not be read or written       */
+} ep_status;
+
+typedef enum {
+    EP_FIELD_ZERO = 0,     /* E = 0: free rotation with period 2 pi eps (section 1) */
+    EP_FIELD_DUFFING = 1,  /* E = -R^3 (eq. 1.3)                                    */
+    EP_FIELD_POISSON = 2   /* d/dr (r E) = rho (eq. 1.2) on the radial mesh         */
+} ep_field;
+
+typedef enum {
+    EP_DEPOSIT_ATOMIC = 0, /* per-workgroup LDS histograms in 2^-32 fixed point      */
+    EP_DEPOSIT_SORTED = 1  /* particles reordered by cell, segmented reduction       */
+} ep_deposit;
+
+typedef enum {
+    EP_PUSH_PLAIN = 0,     /* K-substep midpoint quadrature of the Duhamel term      */
+    EP_PUSH_LEARNED = 1    /* MLP prediction of the Duhamel term, energy-checked,
+                              with the plain push as fallback                         */
+} ep_push;
+
+/* Context configuration (ep_create).
+ *   n_particles : capacity of the particle arrays (>= 1).
+ *   n_cells     : N_r, number of mesh cells; even, 2 <= N_r <= 8192.  The mesh
+ *                 has N_r + 1 nodes x_k = -r_max + k h_r, h_r = 2 r_max / N_r,
+ *                 with the centre node x_{N_r/2} = 0.
+ *   substeps    : K >= 1, substeps per macro step of the plain push.
+ *   r_max       : half width of the mesh, > 0.
+ *   deposit     : ep_deposit.
+ *   device      : HIP device ordinal.
+ *   hip_stream  : hipStream_t to queue work on, or NULL for a library-owned
+ *                 stream (created at default priority). */
+typedef struct {
+    uint64_t n_particles;
+    uint32_t n_cells;
+    uint32_t substeps;
+    double r_max;
+    int32_t deposit;
+    int32_t device;
+    void *hip_stream;
+} ep_config;
+
+/* Diagnostics of the current time level (ep_moments).  Sums are over all
+ * particles with weight w, accumulated in FP64 in a fixed order.
+ *   t, phase        : simulated time and the accumulated fast phase t/eps
+ *                     reduced mod 2 pi (both FP64)
+ *   charge          : w * N
+ *   rms_radius      : sqrt(sum w R^2 / charge)   (NaN particles excluded)
+ *   kinetic         : sum w (R^2 + V^2) / (2 eps)
+ *   potential       : Duffing: sum w R^4 / 4;  Poisson: int_0^{r_max} x E(x)^2 dx
+ *                     (trapezoid on the nodes of the current field); 0 for E = 0
+ *   energy          : kinetic + potential
+ *   n_offmesh       : particles with R outside [-r_max, r_max)
+ *   n_nan           : particles whose R or V is not finite
+ *   n_fallback      : particles that took the plain push in the last learned step */
+typedef struct {
+    double t;
+    double phase;
+    double charge;
+    double rms_radius;
+    double energy;
+    double kinetic;
+    double potential;
+    uint64_t n_steps;
+    uint64_t n_offmesh;
+    uint64_t n_nan;
+    uint64_t n_fallback;
+} ep_moments;
+
+/* Create a context on cfg->device and allocate its device buffers.
+ * Errors: EP_EINVAL (bad sizes), EP_ENOMEM, EP_EHIP. */
+ep_status ep_create(const ep_config *cfg, ep_ctx **out);
+
+/* Release the context and all device memory it owns.  NULL is accepted. */
+ep_status ep_destroy(ep_ctx *ctx);
+
+/* Message of the last failed call on ctx (or of the last failed ep_create when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char *ep_last_error(const ep_ctx *ctx);
+
+/* Load n <= capacity particles (host FP64 arrays R[n], V[n], lab frame) with
+ * uniform weight w > 0 as the state at the current time level.  The library
+ * stores them in FP32 in the frame rotating with the free flow,
+ * z = r(-t/eps) y (eq. 3.3), so that the exact rotation is never applied to the
+ * stored state.  Invalidates the mesh field.  Errors: EP_EINVAL, EP_EHIP. */
+ep_status ep_set_particles(ep_ctx *ctx, const double *R, const double *V, uint64_t n,
+                           double w);
+
+/* Use caller-owned device arrays zR_dev[n], zV_dev[n] (FP32, rotating frame at
+ * the current time level, 16-byte aligned) as the particle state instead of the
+ * library's own.  The caller keeps them alive until ep_destroy or the next
+ * bind.  n <= capacity.  Errors: EP_EINVAL. */
+ep_status ep_bind_particles(ep_ctx *ctx, float *zR_dev, float *zV_dev, uint64_t n, double w);
+
+/* Advance n_steps macro steps of size dt > 0 at parameter eps > 0 in the field
+ * model `field` (ep_field).  Each step: exact rotation by dt/eps, Duhamel term
+ * by K-substep midpoint quadrature with E frozen at t_n (Poisson: deposit,
+ * prefix-sum solve and gather, section 2.3), or the learned push when enabled.
+ * dt and eps may change between calls; the phase t/eps is carried in FP64.
+ * Asynchronous.  Errors: EP_EINVAL, EP_ESTATE (no particles), EP_EHIP. */
+ep_status ep_step(ep_ctx *ctx, double dt, double eps, int32_t field, uint64_t n_steps);
+
+/* Moments of the current state (see ep_moments), with eps and field naming the
+ * energy to report.  Synchronises.  Errors: EP_EINVAL, EP_ESTATE, EP_EHIP. */
+ep_status ep_moments_get(ep_ctx *ctx, double eps, int32_t field, ep_moments *out);
+
+/* Copy particles [offset, offset + count) of the current state to host FP64
+ * arrays R[count], V[count] (lab frame: the FP32 rotating-frame values are
+ * rotated back in FP64).  offset + count must not exceed the loaded count.
+ * Synchronises.  Errors: EP_EINVAL, EP_EHIP. */
+ep_status ep_get_particles(ep_ctx *ctx, double *R, double *V, uint64_t offset, uint64_t count);
+
+/* Mesh field of the current particle positions (deposited and solved first if
+ * stale): rho, E and the potential Psi (Psi(0) = 0, -Psi' = E) at the
+ * n_nodes = N_r + 1 nodes, FP64, and the half enclosed charge Qb at the mesh
+ * edge (off the mesh E = Qb / R).  Any output pointer may be NULL.
+ * Synchronises.  Errors: EP_EINVAL, EP_ESTATE, EP_EHIP. */
+ep_status ep_get_field(ep_ctx *ctx, double *rho, double *E, double *Psi, double *Qb,
+                       uint32_t n_nodes);
+
+/* Select the push (ep_push).  For EP_PUSH_LEARNED: drift_tol is the per-particle
+ * relative energy-drift bound |H(y_{n+1}) - H(y_n)| <= drift_tol * H(y_n)
+ * (H the frozen-field energy of the step), and fallback_substeps the K used by
+ * the plain push for particles that fail it.  Errors: EP_EINVAL,
+ * EP_ENOTRAINED. */
+ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
+                           uint32_t fallback_substeps);
+
+/* Synchronise the context's stream; reports asynchronous errors. */
+ep_status ep_sync(ep_ctx *ctx);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of the particle kernels.  ep_timing_enable(ctx, 1) clears and
+ * starts collection; ep_timing_get synchronises and returns, for the kernel
+ * named `kernel` ("push_poisson", "push_duffing", "mesh_solve", "mlp_push",
+ * "fallback_push", "sort_count", "sort_scatter", "sort_reduce"), the summed
+ * duration in milliseconds and the number of launches.  Errors: EP_EINVAL. */
+ep_status ep_timing_enable(ep_ctx *ctx, int32_t on);
+ep_status ep_timing_get(ep_ctx *ctx, const char *kernel, double *total_ms, uint64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETDPIC_H */

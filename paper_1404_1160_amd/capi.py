@@ -1,0 +1,185 @@
+"""ctypes binding of the etdpic C ABI (include/etdpic.h).
+
+Argument marshalling only: every function has the name of the C entry point it
+calls, converts numpy arrays / torch tensors to pointers, and raises
+``EtdpicError`` on a non-zero status.  All computation happens in the HIP
+library; if ``libetdpic.so`` is missing, loading fails loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+EP_OK, EP_EINVAL, EP_ENOMEM, EP_EHIP, EP_ESTATE, EP_ENOTRAINED, EP_EIO = 0, -1, -2, -3, -4, -5, -6
+EP_FIELD_ZERO, EP_FIELD_DUFFING, EP_FIELD_POISSON = 0, 1, 2
+EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED = 0, 1
+EP_PUSH_PLAIN, EP_PUSH_LEARNED = 0, 1
+
+STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EHIP", -4: "EP_ESTATE",
+                -5: "EP_ENOTRAINED", -6: "EP_EIO"}
+
+# Every symbol include/etdpic.h declares (checked by the CPU test-suite).
+EXPORTS = (
+    "ep_create", "ep_destroy", "ep_last_error", "ep_set_particles", "ep_bind_particles",
+    "ep_step", "ep_moments_get", "ep_get_particles", "ep_get_field", "ep_set_push_mode",
+    "ep_sync", "ep_timing_enable", "ep_timing_get",
+)
+
+
+class EtdpicError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+
+
+class ep_config(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_uint64), ("n_cells", ctypes.c_uint32),
+                ("substeps", ctypes.c_uint32), ("r_max", ctypes.c_double),
+                ("deposit", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class ep_moments(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("phase", ctypes.c_double), ("charge", ctypes.c_double),
+                ("rms_radius", ctypes.c_double), ("energy", ctypes.c_double),
+                ("kinetic", ctypes.c_double), ("potential", ctypes.c_double),
+                ("n_steps", ctypes.c_uint64), ("n_offmesh", ctypes.c_uint64),
+                ("n_nan", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def library_path():
+    return _build.LIB
+
+
+def lib():
+    """Load libetdpic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError("etdpic HIP library not built: %s is missing "
+                              "(run __graft_entry__.build())" % path)
+        L = ctypes.CDLL(path)
+        vp, d, u64, u32, i32 = (ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
+                                ctypes.c_uint32, ctypes.c_int32)
+        pd = ctypes.POINTER(ctypes.c_double)
+        sigs = {
+            "ep_create": ([ctypes.POINTER(ep_config), ctypes.POINTER(vp)], i32),
+            "ep_destroy": ([vp], i32),
+            "ep_last_error": ([vp], ctypes.c_char_p),
+            "ep_set_particles": ([vp, pd, pd, u64, d], i32),
+            "ep_bind_particles": ([vp, vp, vp, u64, d], i32),
+            "ep_step": ([vp, d, d, i32, u64], i32),
+            "ep_moments_get": ([vp, d, i32, ctypes.POINTER(ep_moments)], i32),
+            "ep_get_particles": ([vp, pd, pd, u64, u64], i32),
+            "ep_get_field": ([vp, pd, pd, pd, pd, u32], i32),
+            "ep_set_push_mode": ([vp, i32, d, u32], i32),
+            "ep_sync": ([vp], i32),
+            "ep_timing_enable": ([vp, i32], i32),
+            "ep_timing_get": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(u64)], i32),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status):
+    if status != EP_OK:
+        msg = lib().ep_last_error(ctx)
+        raise EtdpicError(status, msg.decode() if msg else "")
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def ep_create(n_particles, n_cells=256, substeps=1, r_max=5.0, deposit=EP_DEPOSIT_ATOMIC,
+              device=0, hip_stream=None):
+    cfg = ep_config(n_particles, n_cells, substeps, r_max, deposit, device, hip_stream)
+    out = ctypes.c_void_p()
+    _check(None, lib().ep_create(ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def ep_destroy(ctx):
+    _check(None, lib().ep_destroy(ctx))
+
+
+def ep_last_error(ctx):
+    m = lib().ep_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def ep_set_particles(ctx, R, V, w):
+    R = _f64(R)
+    V = _f64(V)
+    if R.shape != V.shape:
+        raise ValueError("R and V must have the same shape")
+    _check(ctx, lib().ep_set_particles(ctx, _p(R), _p(V), R.size, float(w)))
+
+
+def ep_bind_particles(ctx, zR, zV, w):
+    """zR, zV: FP32 device tensors (torch, contiguous) in the rotating frame."""
+    n = zR.numel()
+    _check(ctx, lib().ep_bind_particles(ctx, ctypes.c_void_p(zR.data_ptr()),
+                                        ctypes.c_void_p(zV.data_ptr()), n, float(w)))
+
+
+def ep_step(ctx, dt, eps, field, n_steps=1):
+    _check(ctx, lib().ep_step(ctx, float(dt), float(eps), int(field), int(n_steps)))
+
+
+def ep_moments_get(ctx, eps, field):
+    m = ep_moments()
+    _check(ctx, lib().ep_moments_get(ctx, float(eps), int(field), ctypes.byref(m)))
+    return m.as_dict()
+
+
+def ep_get_particles(ctx, count, offset=0):
+    R = np.empty(count)
+    V = np.empty(count)
+    _check(ctx, lib().ep_get_particles(ctx, _p(R), _p(V), int(offset), int(count)))
+    return R, V
+
+
+def ep_get_field(ctx, n_nodes):
+    rho = np.empty(n_nodes)
+    E = np.empty(n_nodes)
+    Psi = np.empty(n_nodes)
+    Qb = ctypes.c_double(0.0)
+    _check(ctx, lib().ep_get_field(ctx, _p(rho), _p(E), _p(Psi), ctypes.byref(Qb), n_nodes))
+    return rho, E, Psi, Qb.value
+
+
+def ep_set_push_mode(ctx, push, drift_tol=1e-5, fallback_substeps=0):
+    _check(ctx, lib().ep_set_push_mode(ctx, int(push), float(drift_tol), int(fallback_substeps)))
+
+
+def ep_sync(ctx):
+    _check(ctx, lib().ep_sync(ctx))
+
+
+def ep_timing_enable(ctx, on=True):
+    _check(ctx, lib().ep_timing_enable(ctx, 1 if on else 0))
+
+
+def ep_timing_get(ctx, kernel):
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    _check(ctx, lib().ep_timing_get(ctx, kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

@@ -1,0 +1,61 @@
+// Internal launcher declarations shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace etd {
+
+constexpr int kPushBlock = 1024;       // threads per block of the mesh push kernels
+constexpr int kSolveBlock = 1024;      // threads of the single-block mesh solve
+constexpr int kMomentBlock = 256;
+constexpr int kMomentQuantities = 4;   // sum R^2, sum |z|^2, sum R^4, (unused)
+constexpr int kMomentCounts = 2;       // off-mesh, non-finite
+
+// Scalars of the solved field, stored on the device after each solve.
+enum FieldScalar { kQb = 0, kFieldEnergy = 1, kMeshCharge = 2, kFieldScalars = 4 };
+
+// Per-substep coefficients of the plain push (FP64): the midpoint phase phi
+// of the substep gives (cos phi, sin phi, h sin phi, h cos phi).
+struct StepTables {
+    double4 *sub;     // [S*K]
+    double2 *endrot;  // [S]  (cos, sin) of the phase at the end of each step
+};
+
+hipError_t launch_phase_table(hipStream_t st, StepTables tab, double phi0, double dphi,
+                              double theta, double h, int K, int S);
+
+hipError_t launch_twist_in(hipStream_t st, const double *R, const double *V, float *zR,
+                           float *zV, int64_t n, double c, double s);
+hipError_t launch_twist_out(hipStream_t st, const float *zR, const float *zV, double *R,
+                            double *V, int64_t n, double c, double s);
+
+hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
+                               const double4 *sub, int K, int S);
+
+// One Poisson step: K-substep push in the frozen field, then CIC deposit of
+// the new positions into hist (fixed point, 2^-32 of a particle weight).  The
+// rotation to the lab frame at the end of the step is endrot_tab[0] if
+// endrot_tab is non-null, else endrot_val.  With push == false only the
+// deposit of the current state is done.
+hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, int64_t n,
+                               const float2 *etab, const double *fscal, const double4 *sub,
+                               const double2 *endrot_tab, double2 endrot_val, int K, int nr,
+                               double hr, unsigned long long *hist, int grid_cap);
+
+// Raise the dynamic LDS limit of the mesh push kernels for an nr-cell mesh.
+hipError_t setup_push_lds(int nr);
+size_t push_lds_bytes_for(int nr);
+
+hipError_t launch_mesh_solve(hipStream_t st, unsigned long long *hist, int nr, double w,
+                             double hr, float2 *etab, double *rho64, double *E64,
+                             double *Psi64, double *fscal, unsigned long long *scan_tmp);
+
+hipError_t launch_moments(hipStream_t st, const float *zR, const float *zV, int64_t n,
+                          double c, double s, double rmax, double *partial,
+                          unsigned long long *pcount, int grid, double *out,
+                          unsigned long long *out_count);
+
+int moments_grid(int64_t n);
+
+}  // namespace etd

@@ -1,0 +1,564 @@
+// HIP kernels of the plain exponential-integrator PIC step (gfx950).
+//
+// State: SoA FP32 arrays zR, zV holding the particle state in the frame that
+// rotates with the free flow, z = r(-t/eps) y, r the rotation of eq. 3.3 with
+// T = 2 pi.  In that frame the stiff linear part of eq. 3.1 drops out and
+// eq. 3.6 becomes dz/dt = r(-t/eps) (0, E(R, t)), R = [r(t/eps) z]_R, so the
+// exact rotation is never applied to the stored state; the fast phase t/eps is
+// carried in FP64 and only enters through per-substep (cos, sin) tables.
+//
+// Push (one macro step dt = K h, field frozen at t_n): midpoint rule for the
+// Duhamel integral of eq. 3.6 on each substep,
+//     R_mid = cos(phi_k) zR + sin(phi_k) zV,  E = E(R_mid),
+//     zR -= h sin(phi_k) E,  zV += h cos(phi_k) E,
+// phi_k the phase at the substep midpoint.  With E = 0 the state is unchanged,
+// which is the exact free rotation of period 2 pi eps.
+//
+// Precision: the state is stored in FP32 (16 bytes of HBM traffic per
+// particle-step); in registers every push does its arithmetic in FP64, which
+// on CDNA runs at the rate of non-packed FP32 FMAs.  The FP64 cell coordinate
+// keeps the CIC weights exact to the stored positions even next to the steep
+// centre cell of the field, and the substep increments are accumulated
+// without FP32 cancellation.  Only the tabulated field is FP32.
+//
+// Mesh: N_r cells on [-r_max, r_max], nodes x_k = (k - N_r/2) h_r.  Cell
+// coordinates are taken relative to the centre node, x = R / h_r.  The CIC
+// deposit accumulates the two node weights (1 - th, th) of every particle as
+// integers in units of 2^-32 of a particle weight, in LDS per workgroup and
+// then into one global u64 histogram; integer sums make the charge, and
+// therefore the whole step, independent of the order of accumulation.  The
+// Poisson solve (section 2.3: trapezoidal rule on the cells) runs on those
+// integers: the trapezoid prefix sum of the node charges is an exact integer
+// scan.
+
+#include "internal.h"
+
+namespace etd {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kFixOne = 4294967296.0;              // 2^32
+constexpr double kFixScale = 2.3283064365386963e-10;  // 2^-32
+
+// ------------------------------------------------------------ phase tables
+
+__global__ void phase_table_kernel(double4 *__restrict__ sub, double2 *__restrict__ endrot,
+                                   double phi0, double dphi, double theta, double h, int K,
+                                   int S)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)S * K;
+    if (idx < total) {
+        const int64_t j = idx / K;
+        const int64_t k = idx - j * K;
+        const double pj = fmod(phi0 + (double)j * dphi, kTwoPi);
+        const double ph = pj + ((double)k + 0.5) * theta;
+        double s, c;
+        sincos(ph, &s, &c);
+        sub[idx] = make_double4(c, s, h * s, h * c);
+    }
+    if (idx < S) {
+        const double p1 = fmod(phi0 + (double)(idx + 1) * dphi, kTwoPi);
+        double s, c;
+        sincos(p1, &s, &c);
+        endrot[idx] = make_double2(c, s);
+    }
+}
+
+hipError_t launch_phase_table(hipStream_t st, StepTables tab, double phi0, double dphi,
+                              double theta, double h, int K, int S)
+{
+    const int64_t total = (int64_t)S * K > S ? (int64_t)S * K : S;
+    const int block = 256;
+    const int64_t grid = (total + block - 1) / block;
+    phase_table_kernel<<<dim3((unsigned)grid), dim3(block), 0, st>>>(tab.sub, tab.endrot, phi0,
+                                                                   dphi, theta, h, K, S);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ frame changes
+
+// z = r(-phi) y : zR = c R - s V, zV = s R + c V   (FP64, rounded once)
+__global__ void twist_in_kernel(const double *__restrict__ R, const double *__restrict__ V,
+                                float *__restrict__ zR, float *__restrict__ zV, int64_t n,
+                                double c, double s)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double r = R[i], v = V[i];
+        zR[i] = (float)(c * r - s * v);
+        zV[i] = (float)(s * r + c * v);
+    }
+}
+
+// y = r(phi) z : R = c zR + s zV, V = -s zR + c zV   (FP64)
+__global__ void twist_out_kernel(const float *__restrict__ zR, const float *__restrict__ zV,
+                                 double *__restrict__ R, double *__restrict__ V, int64_t n,
+                                 double c, double s)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double r = zR[i], v = zV[i];
+        R[i] = c * r + s * v;
+        V[i] = -s * r + c * v;
+    }
+}
+
+hipError_t launch_twist_in(hipStream_t st, const double *R, const double *V, float *zR,
+                           float *zV, int64_t n, double c, double s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    twist_in_kernel<<<dim3((unsigned)((n + block - 1) / block)), dim3(block), 0, st>>>(
+        R, V, zR, zV, n, c, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_twist_out(hipStream_t st, const float *zR, const float *zV, double *R,
+                            double *V, int64_t n, double c, double s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    twist_out_kernel<<<dim3((unsigned)((n + block - 1) / block)), dim3(block), 0, st>>>(
+        zR, zV, R, V, n, c, s);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ Duffing push
+
+// E = -R^3 needs no mesh, so particles are independent: each lane keeps its
+// state in FP64 registers for all S steps of the launch and rounds it to FP32
+// once, at the store.
+__global__ __launch_bounds__(256) void push_duffing_kernel(float *__restrict__ zR,
+                                                           float *__restrict__ zV, int64_t n,
+                                                           const double4 *__restrict__ sub,
+                                                           int K, int S)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double zr = zR[i], zv = zV[i];
+    const double4 *t = sub;
+    for (int j = 0; j < S; ++j) {
+        double ar = 0.0, av = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double4 q = t[k];
+            const double Rm = fma(q.x, zr + ar, q.y * (zv + av));
+            const double E = -(Rm * Rm) * Rm;
+            ar = fma(-q.z, E, ar);
+            av = fma(q.w, E, av);
+        }
+        t += K;
+        zr += ar;
+        zv += av;
+    }
+    zR[i] = (float)zr;
+    zV[i] = (float)zv;
+}
+
+hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
+                               const double4 *sub, int K, int S)
+{
+    if (n <= 0 || S <= 0) return hipSuccess;
+    const int block = 256;
+    push_duffing_kernel<<<dim3((unsigned)((n + block - 1) / block)), dim3(block), 0, st>>>(
+        zR, zV, n, sub, K, S);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ Poisson push + deposit
+
+struct MeshView {
+    const float2 *Et;       // LDS: (E_m, E_{m+1} - E_m), m = 0..nr-1
+    unsigned long long *H;  // LDS: fixed-point node charges, nr+1
+    double inv_hr;
+    double half;            // nr/2: on-mesh iff -half <= R/h_r < half
+    int c;                  // centre node
+    double Qb;              // half enclosed charge at the edge
+};
+
+// CIC gather of the frozen field at R; off the mesh (and for NaN) E = Qb / R.
+__device__ __forceinline__ double gather(const MeshView &m, double R)
+{
+    const double x = R * m.inv_hr;
+    if (x >= -m.half && x < m.half) {
+        const double fl = floor(x);
+        const double th = x - fl;
+        const float2 e = m.Et[(int)fl + m.c];
+        return fma(th, (double)e.y, (double)e.x);
+    }
+    return m.Qb / R;
+}
+
+// CIC deposit of one particle at R into the LDS histogram (skipped off-mesh).
+__device__ __forceinline__ void deposit(const MeshView &m, double R)
+{
+    const double x = R * m.inv_hr;
+    if (x >= -m.half && x < m.half) {
+        const double fl = floor(x);
+        const double th = x - fl;   // exact, in [0, 1)
+        const int k = (int)fl + m.c;
+        const unsigned int q = (unsigned int)(th * kFixOne);
+        atomicAdd(&m.H[k], (unsigned long long)(4294967296ull - q));
+        atomicAdd(&m.H[k + 1], (unsigned long long)q);
+    }
+}
+
+template <int NP>
+__device__ __forceinline__ void push_group(const MeshView &m, const double4 *__restrict__ sub,
+                                           int K, double (&zr)[NP], double (&zv)[NP])
+{
+    double ar[NP], av[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) ar[p] = av[p] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double4 q = sub[k];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const double Rm = fma(q.x, zr[p] + ar[p], q.y * (zv[p] + av[p]));
+            const double E = gather(m, Rm);
+            ar[p] = fma(-q.z, E, ar[p]);
+            av[p] = fma(q.w, E, av[p]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        zr[p] += ar[p];
+        zv[p] += av[p];
+    }
+}
+
+// One macro step of a tile of particles: load FP32 state, K-substep push in
+// the frozen field (PUSH), store, and deposit the new positions -- rounded
+// to the stored FP32 state, so that a later deposit of the same state gives
+// the same charge bit for bit.
+template <bool PUSH>
+__global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
+    float *__restrict__ zR, float *__restrict__ zV, int64_t n, const float2 *__restrict__ etab,
+    const double *__restrict__ fscal, const double4 *__restrict__ sub,
+    const double2 *__restrict__ endrot_tab, double2 endrot_val, int K, int nr, double inv_hr,
+    unsigned long long *__restrict__ hist)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    float2 *Et = reinterpret_cast<float2 *>(smem);
+    unsigned long long *H = reinterpret_cast<unsigned long long *>(smem + (size_t)nr * sizeof(float2));
+    const int tid = threadIdx.x;
+    if (PUSH)
+        for (int i = tid; i < nr; i += blockDim.x) Et[i] = etab[i];
+    for (int i = tid; i <= nr; i += blockDim.x) H[i] = 0ull;
+    MeshView m;
+    m.Et = Et;
+    m.H = H;
+    m.inv_hr = inv_hr;
+    m.half = 0.5 * (double)nr;
+    m.c = nr >> 1;
+    m.Qb = PUSH ? fscal[kQb] : 0.0;
+    const double2 er = endrot_tab ? endrot_tab[0] : endrot_val;
+    __syncthreads();
+
+    const int64_t n4 = n >> 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    float4 *zR4 = reinterpret_cast<float4 *>(zR);
+    float4 *zV4 = reinterpret_cast<float4 *>(zV);
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + tid; g < n4; g += stride) {
+        const float4 r4 = zR4[g], v4 = zV4[g];
+        float fr[4] = {r4.x, r4.y, r4.z, r4.w};
+        float fv[4] = {v4.x, v4.y, v4.z, v4.w};
+        if (PUSH) {
+            double zr[4], zv[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                zr[p] = fr[p];
+                zv[p] = fv[p];
+            }
+            push_group<4>(m, sub, K, zr, zv);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                fr[p] = (float)zr[p];
+                fv[p] = (float)zv[p];
+            }
+            zR4[g] = make_float4(fr[0], fr[1], fr[2], fr[3]);
+            zV4[g] = make_float4(fv[0], fv[1], fv[2], fv[3]);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) deposit(m, fma(er.x, (double)fr[p], er.y * (double)fv[p]));
+    }
+    // ragged tail: the last n % 4 particles
+    const int64_t gt = blockIdx.x * (int64_t)blockDim.x + tid;
+    const int64_t tail = n - (n4 << 2);
+    if (gt < tail) {
+        const int64_t i = (n4 << 2) + gt;
+        float fr = zR[i], fv = zV[i];
+        if (PUSH) {
+            double zr[1] = {fr};
+            double zv[1] = {fv};
+            push_group<1>(m, sub, K, zr, zv);
+            fr = (float)zr[0];
+            fv = (float)zv[0];
+            zR[i] = fr;
+            zV[i] = fv;
+        }
+        deposit(m, fma(er.x, (double)fr, er.y * (double)fv));
+    }
+    __syncthreads();
+    for (int i = tid; i <= nr; i += blockDim.x) {
+        const unsigned long long v = H[i];
+        if (v) atomicAdd(&hist[i], v);
+    }
+}
+
+static size_t push_lds_bytes(int nr)
+{
+    return (size_t)nr * sizeof(float2) + (size_t)(nr + 1) * sizeof(unsigned long long);
+}
+
+hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, int64_t n,
+                               const float2 *etab, const double *fscal, const double4 *sub,
+                               const double2 *endrot_tab, double2 endrot_val, int K, int nr,
+                               double hr, unsigned long long *hist, int grid_cap)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = push_lds_bytes(nr);
+    const int64_t n4 = n >> 2;
+    int64_t grid = (n4 + kPushBlock - 1) / kPushBlock;
+    if (grid > grid_cap) grid = grid_cap;
+    if (grid < 1) grid = 1;
+    const double inv_hr = 1.0 / hr;
+    if (push)
+        push_poisson_kernel<true><<<dim3((unsigned)grid), dim3(kPushBlock), lds, st>>>(
+            zR, zV, n, etab, fscal, sub, endrot_tab, endrot_val, K, nr, inv_hr, hist);
+    else
+        push_poisson_kernel<false><<<dim3((unsigned)grid), dim3(kPushBlock), lds, st>>>(
+            zR, zV, n, etab, fscal, sub, endrot_tab, endrot_val, 0, nr, inv_hr, hist);
+    return hipGetLastError();
+}
+
+size_t push_lds_bytes_for(int nr) { return push_lds_bytes(nr); }
+
+hipError_t setup_push_lds(int nr)
+{
+    const int lds = (int)push_lds_bytes(nr);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+// ------------------------------------------------------------ mesh solve
+
+// Hillis-Steele scan across the block; returns the exclusive prefix of v.
+// The order of additions depends only on the block size, so FP64 results are
+// reproducible.
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *buf)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    buf[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        const T add = tid >= off ? buf[tid - off] : T(0);
+        __syncthreads();
+        buf[tid] += add;
+        __syncthreads();
+    }
+    const T ex = tid > 0 ? buf[tid - 1] : T(0);
+    __syncthreads();
+    return ex;
+}
+
+template <typename T>
+__device__ T block_sum(T v, T *buf)
+{
+    const int tid = threadIdx.x;
+    buf[tid] = v;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if (tid < w) buf[tid] += buf[tid + w];
+        __syncthreads();
+    }
+    const T r = buf[0];
+    __syncthreads();
+    return r;
+}
+
+// One workgroup.  From the fixed-point node charges S_k (units of 2^-32 w):
+//   rho_k = w 2^-32 S_k / h_r                                   (CIC density)
+//   I_k   = sum_{i=1..k} (S_{i-1} + S_i)        exact integer trapezoid scan,
+//           so P_k = int_{x_0}^{x_k} rho = w 2^-33 I_k
+//   Q_j   = (P_{c+j} - P_{c-j}) / 2 = w 2^-34 (I_{c+j} - I_{c-j})
+//   E_k   = Q_{|k-c|} / x_k  (k != c),  E_c = 0,  Qb = w 2^-34 I_nr
+//   Psi_k = -int_0^{x_k} E  (trapezoid of the node values)
+//   field energy int_0^{r_max} x E^2 dx (trapezoid)
+// and the FP32 gather table (E_m, E_{m+1} - E_m).  Clears hist for the next
+// accumulation.  I is global scratch of nr+1 entries.
+__global__ __launch_bounds__(kSolveBlock) void mesh_solve_kernel(
+    unsigned long long *__restrict__ hist, int nr, double w, double hr, float2 *__restrict__ etab,
+    double *__restrict__ rho64, double *__restrict__ E64, double *__restrict__ Psi64,
+    double *__restrict__ fscal, unsigned long long *__restrict__ I)
+{
+    __shared__ unsigned long long su[kSolveBlock];
+    __shared__ double sd[kSolveBlock];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nn = nr + 1;
+    const int chunk = (nn + nt - 1) / nt;
+    const int k0 = min(tid * chunk, nn), k1 = min(k0 + chunk, nn);
+    const int c = nr >> 1;
+
+    unsigned long long loc = 0ull;
+    for (int k = k0; k < k1; ++k)
+        if (k > 0) loc += hist[k - 1] + hist[k];
+    unsigned long long run = block_exclusive_scan<unsigned long long>(loc, su);
+    const double rho_scale = w * kFixScale / hr;
+    for (int k = k0; k < k1; ++k) {
+        const unsigned long long Sk = hist[k];
+        if (k > 0) run += hist[k - 1] + Sk;
+        I[k] = run;
+        rho64[k] = (double)Sk * rho_scale;
+    }
+    __syncthreads();
+
+    const double q_scale = w * kFixScale * 0.25;
+    for (int k = k0; k < k1; ++k) {
+        double E = 0.0;
+        if (k != c) {
+            const int j = k > c ? k - c : c - k;
+            const long long dI = (long long)(I[c + j] - I[c - j]);
+            const double Q = (double)dI * q_scale;
+            E = Q / ((double)(k - c) * hr);
+        }
+        E64[k] = E;
+    }
+    if (tid == 0) fscal[kQb] = (double)I[nr] * q_scale;
+    __syncthreads();
+
+    // potential: F_k = sum_{i=1..k} h_r (E_{i-1} + E_i) / 2,  Psi_k = -(F_k - F_c)
+    double locd = 0.0;
+    for (int k = k0; k < k1; ++k)
+        if (k > 0) locd += hr * (E64[k - 1] + E64[k]) * 0.5;
+    double runf = block_exclusive_scan<double>(locd, sd);
+    for (int k = k0; k < k1; ++k) {
+        if (k > 0) runf += hr * (E64[k - 1] + E64[k]) * 0.5;
+        Psi64[k] = runf;
+    }
+    // gather table and field energy
+    double fe = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        if (k < nr) {
+            const double e0 = E64[k], e1 = E64[k + 1];
+            etab[k] = make_float2((float)e0, (float)(e1 - e0));
+            if (k >= c) {
+                const double x0 = (double)(k - c) * hr, x1 = (double)(k + 1 - c) * hr;
+                fe += hr * (x0 * e0 * e0 + x1 * e1 * e1) * 0.5;
+            }
+        }
+    }
+    fe = block_sum<double>(fe, sd);
+    // total deposited charge (exact integer sum)
+    unsigned long long sq = 0ull;
+    for (int k = k0; k < k1; ++k) sq += hist[k];
+    sq = block_sum<unsigned long long>(sq, su);
+    const double Fc = Psi64[c];
+    __syncthreads();
+    for (int k = k0; k < k1; ++k) {
+        Psi64[k] = -(Psi64[k] - Fc);
+        hist[k] = 0ull;
+    }
+    if (tid == 0) {
+        fscal[kFieldEnergy] = fe;
+        fscal[kMeshCharge] = (double)sq * w * kFixScale;
+    }
+}
+
+hipError_t launch_mesh_solve(hipStream_t st, unsigned long long *hist, int nr, double w,
+                             double hr, float2 *etab, double *rho64, double *E64,
+                             double *Psi64, double *fscal, unsigned long long *scan_tmp)
+{
+    mesh_solve_kernel<<<dim3(1), dim3(kSolveBlock), 0, st>>>(hist, nr, w, hr, etab, rho64, E64,
+                                                             Psi64, fscal, scan_tmp);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ moments
+
+// Per-block FP64 partial sums (fixed-order tree), then one block adds the
+// partials in index order: results depend only on n and the grid.
+__global__ __launch_bounds__(kMomentBlock) void moments_kernel(
+    const float *__restrict__ zR, const float *__restrict__ zV, int64_t n, double c, double s,
+    double rmax, double *__restrict__ partial, unsigned long long *__restrict__ pcount)
+{
+    __shared__ double sd[kMomentBlock];
+    __shared__ unsigned long long su[kMomentBlock];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    unsigned long long off = 0ull, bad = 0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double r = zR[i], v = zV[i];
+        if (!isfinite(r) || !isfinite(v)) {
+            ++bad;
+            continue;
+        }
+        const double R = c * r + s * v;
+        const double R2 = R * R;
+        a0 += R2;
+        a1 += r * r + v * v;
+        a2 += R2 * R2;
+        if (!(R >= -rmax && R < rmax)) ++off;
+    }
+    a0 = block_sum<double>(a0, sd);
+    a1 = block_sum<double>(a1, sd);
+    a2 = block_sum<double>(a2, sd);
+    off = block_sum<unsigned long long>(off, su);
+    bad = block_sum<unsigned long long>(bad, su);
+    if (threadIdx.x == 0) {
+        double *p = partial + (size_t)blockIdx.x * kMomentQuantities;
+        p[0] = a0;
+        p[1] = a1;
+        p[2] = a2;
+        p[3] = 0.0;
+        pcount[(size_t)blockIdx.x * kMomentCounts + 0] = off;
+        pcount[(size_t)blockIdx.x * kMomentCounts + 1] = bad;
+    }
+}
+
+__global__ __launch_bounds__(kMomentBlock) void moments_final_kernel(
+    const double *__restrict__ partial, const unsigned long long *__restrict__ pcount, int G,
+    double *__restrict__ out, unsigned long long *__restrict__ out_count)
+{
+    __shared__ double sd[kMomentBlock];
+    __shared__ unsigned long long su[kMomentBlock];
+    for (int q = 0; q < kMomentQuantities; ++q) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < G; b += blockDim.x) a += partial[(size_t)b * kMomentQuantities + q];
+        a = block_sum<double>(a, sd);
+        if (threadIdx.x == 0) out[q] = a;
+    }
+    for (int q = 0; q < kMomentCounts; ++q) {
+        unsigned long long a = 0ull;
+        for (int b = threadIdx.x; b < G; b += blockDim.x) a += pcount[(size_t)b * kMomentCounts + q];
+        a = block_sum<unsigned long long>(a, su);
+        if (threadIdx.x == 0) out_count[q] = a;
+    }
+}
+
+int moments_grid(int64_t n)
+{
+    int64_t g = (n + kMomentBlock - 1) / kMomentBlock;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_moments(hipStream_t st, const float *zR, const float *zV, int64_t n,
+                          double c, double s, double rmax, double *partial,
+                          unsigned long long *pcount, int grid, double *out,
+                          unsigned long long *out_count)
+{
+    moments_kernel<<<dim3(grid), dim3(kMomentBlock), 0, st>>>(zR, zV, n, c, s, rmax, partial,
+                                                              pcount);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    moments_final_kernel<<<dim3(1), dim3(kMomentBlock), 0, st>>>(partial, pcount, grid, out,
+                                                                 out_count);
+    return hipGetLastError();
+}
+
+}  // namespace etd

@@ -1,0 +1,575 @@
+// Host runtime of the exponential-integrator PIC library: context, device
+// buffers, FP64 phase bookkeeping, step scheduling and the C ABI of etdpic.h.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/etdpic.h"
+#include "internal.h"
+
+using namespace etd;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr uint32_t kMaxCells = 8192;
+constexpr size_t kTableEntries = size_t(1) << 20;   // substep coefficients per chunk
+constexpr size_t kStageParticles = size_t(1) << 23; // FP64 staging for host transfers
+
+std::string g_create_error;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+}  // namespace
+
+struct ep_ctx {
+    ep_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 0;
+    int push_grid_cap = 0;
+
+    // particle state (rotating frame, FP32 SoA)
+    float *zR = nullptr, *zV = nullptr;
+    float *own_zR = nullptr, *own_zV = nullptr;
+    uint64_t n = 0;
+    double w = 0.0;
+
+    // mesh
+    double hr = 0.0;
+    unsigned long long *hist = nullptr, *scan_tmp = nullptr;
+    float2 *etab = nullptr;
+    double *rho64 = nullptr, *E64 = nullptr, *Psi64 = nullptr, *fscal = nullptr;
+    bool field_valid = false;
+
+    // per-chunk substep tables
+    StepTables tab{};
+    size_t tab_cap = 0;
+
+    // host transfers
+    double *stageR = nullptr, *stageV = nullptr;
+
+    // moments
+    int mom_grid_cap = 0;
+    double *mpartial = nullptr, *mout = nullptr;
+    unsigned long long *mcount = nullptr, *mout_count = nullptr;
+
+    // clock: t and the fast phase t/eps mod 2 pi, FP64
+    double t = 0.0, phase = 0.0;
+    uint64_t n_steps = 0;
+
+    // push mode
+    int push_mode = EP_PUSH_PLAIN;
+    double drift_tol = 1e-5;
+    uint32_t fallback_K = 0;
+    uint64_t n_fallback = 0;
+
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::map<std::string, std::pair<double, uint64_t>> timed;
+
+    std::string err;
+
+    ep_status fail(ep_status code, const char *fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    ep_status hipfail(const char *what, hipError_t e)
+    {
+        return fail(EP_EHIP, "%s: %s", what, hipGetErrorString(e));
+    }
+};
+
+#define HIPCHK(ctx, expr)                                   \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return (ctx)->hipfail(#expr, e_); \
+    } while (0)
+
+namespace {
+
+// Timed launch bracket: records events around `launch` when timing is on.
+template <typename F>
+hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
+{
+    if (!c->timing) return launch();
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!c->event_pool.empty()) {
+        ev = c->event_pool.back();
+        c->event_pool.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev.first);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&ev.second);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(ev.first, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev.second, c->stream);
+    if (e != hipSuccess) return e;
+    c->pending.emplace_back(name, ev);
+    return hipSuccess;
+}
+
+hipError_t collect_timing(ep_ctx *c)
+{
+    if (c->pending.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.second.first, p.second.second);
+        if (e != hipSuccess) return e;
+        auto &acc = c->timed[p.first];
+        acc.first += ms;
+        acc.second += 1;
+        c->event_pool.push_back(p.second);
+    }
+    c->pending.clear();
+    return hipSuccess;
+}
+
+ep_status ensure_tables(ep_ctx *c, size_t entries, size_t steps)
+{
+    if (entries <= c->tab_cap && steps <= c->tab_cap) return EP_OK;
+    size_t cap = entries > steps ? entries : steps;
+    if (cap < 1024) cap = 1024;
+    if (c->tab.sub) (void)hipFree(c->tab.sub);
+    if (c->tab.endrot) (void)hipFree(c->tab.endrot);
+    c->tab.sub = nullptr;
+    c->tab.endrot = nullptr;
+    c->tab_cap = 0;
+    HIPCHK(c, dalloc(&c->tab.sub, cap));
+    HIPCHK(c, dalloc(&c->tab.endrot, cap));
+    c->tab_cap = cap;
+    return EP_OK;
+}
+
+// Deposit the current state and solve for its field.
+ep_status refresh_field(ep_ctx *c)
+{
+    const double2 er = make_double2(cos(c->phase), sin(c->phase));
+    HIPCHK(c, timed_launch(c, "deposit", [&] {
+               return launch_push_poisson(c->stream, false, c->zR, c->zV, (int64_t)c->n,
+                                          c->etab, c->fscal, nullptr, nullptr, er, 0,
+                                          (int)c->cfg.n_cells, c->hr, c->hist,
+                                          c->push_grid_cap);
+           }));
+    HIPCHK(c, timed_launch(c, "mesh_solve", [&] {
+               return launch_mesh_solve(c->stream, c->hist, (int)c->cfg.n_cells, c->w, c->hr,
+                                        c->etab, c->rho64, c->E64, c->Psi64, c->fscal,
+                                        c->scan_tmp);
+           }));
+    c->field_valid = true;
+    return EP_OK;
+}
+
+void free_all(ep_ctx *c)
+{
+    for (void *p : {(void *)c->own_zR, (void *)c->own_zV, (void *)c->hist, (void *)c->scan_tmp,
+                    (void *)c->etab, (void *)c->rho64, (void *)c->E64, (void *)c->Psi64,
+                    (void *)c->fscal, (void *)c->tab.sub, (void *)c->tab.endrot,
+                    (void *)c->stageR, (void *)c->stageV, (void *)c->mpartial, (void *)c->mout,
+                    (void *)c->mcount, (void *)c->mout_count})
+        if (p) (void)hipFree(p);
+    for (auto &p : c->pending) c->event_pool.push_back(p.second);
+    for (auto &ev : c->event_pool) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ep_last_error(const ep_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+ep_status ep_create(const ep_config *cfg, ep_ctx **out)
+{
+    if (!out || !cfg) {
+        g_create_error = "ep_create: null argument";
+        return EP_EINVAL;
+    }
+    *out = nullptr;
+    if (cfg->n_particles == 0 || cfg->substeps == 0 || cfg->n_cells < 2 || (cfg->n_cells & 1) ||
+        cfg->n_cells > kMaxCells || !(cfg->r_max > 0.0) || !isfinite(cfg->r_max) ||
+        (cfg->deposit != EP_DEPOSIT_ATOMIC && cfg->deposit != EP_DEPOSIT_SORTED)) {
+        g_create_error = "ep_create: invalid configuration (need n_particles >= 1, substeps >= 1, "
+                         "even 2 <= n_cells <= 8192, r_max > 0, valid deposit)";
+        return EP_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
+        g_create_error = "ep_create: no such HIP device";
+        return EP_EINVAL;
+    }
+    ep_ctx *c = new ep_ctx();
+    c->cfg = *cfg;
+    c->device = cfg->device;
+    c->hr = 2.0 * cfg->r_max / (double)cfg->n_cells;
+    DeviceGuard guard(c->device);
+    ep_status st = EP_OK;
+    auto bail = [&](ep_status s) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return s;
+    };
+#define CREATE_CHK(expr)                                  \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) {                           \
+            c->hipfail(#expr, e_);                        \
+            return bail(e_ == hipErrorOutOfMemory ? EP_ENOMEM : EP_EHIP); \
+        }                                                 \
+    } while (0)
+    if (cfg->hip_stream) {
+        c->stream = reinterpret_cast<hipStream_t>(cfg->hip_stream);
+    } else {
+        CREATE_CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    hipDeviceProp_t prop;
+    CREATE_CHK(hipGetDeviceProperties(&prop, c->device));
+    c->n_cu = prop.multiProcessorCount;
+    const size_t lds = push_lds_bytes_for((int)cfg->n_cells);
+    const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                                 : 160 * 1024;
+    if (lds > prop.sharedMemPerBlock && lds > lds_cu) {
+        c->fail(EP_EINVAL, "ep_create: mesh of %u cells needs %zu B of LDS", cfg->n_cells, lds);
+        return bail(EP_EINVAL);
+    }
+    int per_cu = (int)(lds_cu / lds);
+    if (per_cu > 2) per_cu = 2;
+    if (per_cu < 1) per_cu = 1;
+    c->push_grid_cap = c->n_cu * per_cu;
+    CREATE_CHK(setup_push_lds((int)cfg->n_cells));
+
+    const size_t np = (size_t)cfg->n_particles;
+    const size_t np_pad = (np + 3) & ~size_t(3);
+    CREATE_CHK(dalloc(&c->own_zR, np_pad));
+    CREATE_CHK(dalloc(&c->own_zV, np_pad));
+    c->zR = c->own_zR;
+    c->zV = c->own_zV;
+    const size_t nn = (size_t)cfg->n_cells + 1;
+    CREATE_CHK(dalloc(&c->hist, nn));
+    CREATE_CHK(dalloc(&c->scan_tmp, nn));
+    CREATE_CHK(dalloc(&c->etab, nn));
+    CREATE_CHK(dalloc(&c->rho64, nn));
+    CREATE_CHK(dalloc(&c->E64, nn));
+    CREATE_CHK(dalloc(&c->Psi64, nn));
+    CREATE_CHK(dalloc(&c->fscal, (size_t)kFieldScalars));
+    CREATE_CHK(hipMemsetAsync(c->hist, 0, nn * sizeof(unsigned long long), c->stream));
+    CREATE_CHK(hipMemsetAsync(c->fscal, 0, kFieldScalars * sizeof(double), c->stream));
+    c->mom_grid_cap = moments_grid((int64_t)np);
+    CREATE_CHK(dalloc(&c->mpartial, (size_t)c->mom_grid_cap * kMomentQuantities));
+    CREATE_CHK(dalloc(&c->mcount, (size_t)c->mom_grid_cap * kMomentCounts));
+    CREATE_CHK(dalloc(&c->mout, (size_t)kMomentQuantities));
+    CREATE_CHK(dalloc(&c->mout_count, (size_t)kMomentCounts));
+    CREATE_CHK(hipStreamSynchronize(c->stream));
+#undef CREATE_CHK
+    (void)st;
+    *out = c;
+    return EP_OK;
+}
+
+ep_status ep_destroy(ep_ctx *ctx)
+{
+    if (!ctx) return EP_OK;
+    DeviceGuard guard(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return EP_OK;
+}
+
+ep_status ep_set_particles(ep_ctx *c, const double *R, const double *V, uint64_t n, double w)
+{
+    if (!c) return EP_EINVAL;
+    if ((n > 0 && (!R || !V)) || n > c->cfg.n_particles || !(w > 0.0) || !isfinite(w))
+        return c->fail(EP_EINVAL, "ep_set_particles: need 0 <= n <= capacity (%llu), w > 0",
+                       (unsigned long long)c->cfg.n_particles);
+    DeviceGuard guard(c->device);
+    if (!c->stageR) {
+        HIPCHK(c, dalloc(&c->stageR, kStageParticles));
+        HIPCHK(c, dalloc(&c->stageV, kStageParticles));
+    }
+    c->zR = c->own_zR;
+    c->zV = c->own_zV;
+    const double cs = cos(c->phase), sn = sin(c->phase);
+    for (uint64_t off = 0; off < n; off += kStageParticles) {
+        const uint64_t m = n - off < kStageParticles ? n - off : kStageParticles;
+        HIPCHK(c, hipMemcpyAsync(c->stageR, R + off, m * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->stageV, V + off, m * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, launch_twist_in(c->stream, c->stageR, c->stageV, c->zR + off, c->zV + off,
+                                  (int64_t)m, cs, sn));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->n = n;
+    c->w = w;
+    c->field_valid = false;
+    return EP_OK;
+}
+
+ep_status ep_bind_particles(ep_ctx *c, float *zR_dev, float *zV_dev, uint64_t n, double w)
+{
+    if (!c) return EP_EINVAL;
+    if (!zR_dev || !zV_dev || n > c->cfg.n_particles || !(w > 0.0) ||
+        (reinterpret_cast<uintptr_t>(zR_dev) & 15) || (reinterpret_cast<uintptr_t>(zV_dev) & 15))
+        return c->fail(EP_EINVAL, "ep_bind_particles: need 16-byte aligned device arrays, "
+                                  "n <= capacity, w > 0");
+    c->zR = zR_dev;
+    c->zV = zV_dev;
+    c->n = n;
+    c->w = w;
+    c->field_valid = false;
+    return EP_OK;
+}
+
+ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps)
+{
+    if (!c) return EP_EINVAL;
+    if (!(dt > 0.0) || !(eps > 0.0) || !isfinite(dt) || !isfinite(eps) ||
+        (field != EP_FIELD_ZERO && field != EP_FIELD_DUFFING && field != EP_FIELD_POISSON))
+        return c->fail(EP_EINVAL, "ep_step: need dt > 0, eps > 0 and a valid field model");
+    if (c->w <= 0.0) return c->fail(EP_ESTATE, "ep_step: no particles loaded");
+    if (n_steps == 0) return EP_OK;
+    DeviceGuard guard(c->device);
+    const int K = (int)c->cfg.substeps;
+    const double dphi = fmod(dt / eps, kTwoPi);
+    const double theta = dt / ((double)K * eps);
+    const double h = dt / (double)K;
+
+    if (field == EP_FIELD_ZERO) {
+        // E = 0: the rotating-frame state is unchanged; only the phase advances.
+        c->phase = fmod(c->phase + (double)n_steps * dphi, kTwoPi);
+        c->t += (double)n_steps * dt;
+        c->n_steps += n_steps;
+        c->field_valid = false;
+        return EP_OK;
+    }
+    if (field == EP_FIELD_POISSON && !c->field_valid) {
+        ep_status s = refresh_field(c);
+        if (s != EP_OK) return s;
+    }
+    size_t chunk = kTableEntries / (size_t)K;
+    if (chunk < 1) chunk = 1;
+    {
+        ep_status s = ensure_tables(c, chunk * (size_t)K < (size_t)K ? (size_t)K : chunk * (size_t)K,
+                                    chunk);
+        if (s != EP_OK) return s;
+    }
+    uint64_t done = 0;
+    while (done < n_steps) {
+        const uint64_t rem = n_steps - done;
+        const int S = (int)(rem < chunk ? rem : chunk);
+        HIPCHK(c, launch_phase_table(c->stream, c->tab, c->phase, dphi, theta, h, K, S));
+        if (field == EP_FIELD_DUFFING) {
+            HIPCHK(c, timed_launch(c, "push_duffing", [&] {
+                       return launch_push_duffing(c->stream, c->zR, c->zV, (int64_t)c->n,
+                                                  c->tab.sub, K, S);
+                   }));
+        } else {
+            for (int j = 0; j < S; ++j) {
+                HIPCHK(c, timed_launch(c, "push_poisson", [&] {
+                           return launch_push_poisson(
+                               c->stream, true, c->zR, c->zV, (int64_t)c->n, c->etab, c->fscal,
+                               c->tab.sub + (size_t)j * K, c->tab.endrot + j,
+                               make_double2(1.0, 0.0), K, (int)c->cfg.n_cells, c->hr, c->hist,
+                               c->push_grid_cap);
+                       }));
+                HIPCHK(c, timed_launch(c, "mesh_solve", [&] {
+                           return launch_mesh_solve(c->stream, c->hist, (int)c->cfg.n_cells,
+                                                    c->w, c->hr, c->etab, c->rho64, c->E64,
+                                                    c->Psi64, c->fscal, c->scan_tmp);
+                       }));
+            }
+        }
+        c->phase = fmod(c->phase + (double)S * dphi, kTwoPi);
+        c->t += (double)S * dt;
+        c->n_steps += (uint64_t)S;
+        done += (uint64_t)S;
+    }
+    c->field_valid = (field == EP_FIELD_POISSON);
+    return EP_OK;
+}
+
+ep_status ep_sync(ep_ctx *c)
+{
+    if (!c) return EP_EINVAL;
+    DeviceGuard guard(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EP_OK;
+}
+
+ep_status ep_moments_get(ep_ctx *c, double eps, int32_t field, ep_moments *out)
+{
+    if (!c || !out) return c ? c->fail(EP_EINVAL, "ep_moments_get: null output") : EP_EINVAL;
+    if (!(eps > 0.0) ||
+        (field != EP_FIELD_ZERO && field != EP_FIELD_DUFFING && field != EP_FIELD_POISSON))
+        return c->fail(EP_EINVAL, "ep_moments_get: need eps > 0 and a valid field model");
+    if (c->w <= 0.0) return c->fail(EP_ESTATE, "ep_moments_get: no particles loaded");
+    DeviceGuard guard(c->device);
+    if (field == EP_FIELD_POISSON && !c->field_valid) {
+        ep_status s = refresh_field(c);
+        if (s != EP_OK) return s;
+    }
+    const int grid = moments_grid((int64_t)c->n);
+    HIPCHK(c, launch_moments(c->stream, c->zR, c->zV, (int64_t)c->n, cos(c->phase),
+                             sin(c->phase), c->cfg.r_max, c->mpartial, c->mcount, grid, c->mout,
+                             c->mout_count));
+    double q[kMomentQuantities];
+    unsigned long long cnt[kMomentCounts];
+    double fs[kFieldScalars];
+    HIPCHK(c, hipMemcpyAsync(q, c->mout, sizeof q, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cnt, c->mout_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(fs, c->fscal, sizeof fs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double charge = c->w * (double)c->n;
+    out->t = c->t;
+    out->phase = c->phase;
+    out->charge = charge;
+    out->rms_radius = c->n ? sqrt(c->w * q[0] / charge) : 0.0;
+    out->kinetic = c->w * q[1] / (2.0 * eps);
+    out->potential = field == EP_FIELD_DUFFING ? c->w * q[2] / 4.0
+                     : field == EP_FIELD_POISSON ? fs[kFieldEnergy]
+                                                 : 0.0;
+    out->energy = out->kinetic + out->potential;
+    out->n_steps = c->n_steps;
+    out->n_offmesh = field == EP_FIELD_POISSON ? cnt[0] : 0;
+    out->n_nan = cnt[1];
+    out->n_fallback = c->n_fallback;
+    return EP_OK;
+}
+
+ep_status ep_get_particles(ep_ctx *c, double *R, double *V, uint64_t offset, uint64_t count)
+{
+    if (!c) return EP_EINVAL;
+    if (offset > c->n || count > c->n - offset || (count > 0 && (!R || !V)))
+        return c->fail(EP_EINVAL, "ep_get_particles: range [%llu, +%llu) outside the %llu loaded",
+                       (unsigned long long)offset, (unsigned long long)count,
+                       (unsigned long long)c->n);
+    DeviceGuard guard(c->device);
+    if (!c->stageR) {
+        HIPCHK(c, dalloc(&c->stageR, kStageParticles));
+        HIPCHK(c, dalloc(&c->stageV, kStageParticles));
+    }
+    const double cs = cos(c->phase), sn = sin(c->phase);
+    for (uint64_t done = 0; done < count; done += kStageParticles) {
+        const uint64_t m = count - done < kStageParticles ? count - done : kStageParticles;
+        HIPCHK(c, launch_twist_out(c->stream, c->zR + offset + done, c->zV + offset + done,
+                                   c->stageR, c->stageV, (int64_t)m, cs, sn));
+        HIPCHK(c, hipMemcpyAsync(R + done, c->stageR, m * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(V + done, c->stageV, m * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return EP_OK;
+}
+
+ep_status ep_get_field(ep_ctx *c, double *rho, double *E, double *Psi, double *Qb,
+                       uint32_t n_nodes)
+{
+    if (!c) return EP_EINVAL;
+    if (n_nodes != c->cfg.n_cells + 1)
+        return c->fail(EP_EINVAL, "ep_get_field: n_nodes must be n_cells + 1 = %u",
+                       c->cfg.n_cells + 1);
+    if (c->w <= 0.0) return c->fail(EP_ESTATE, "ep_get_field: no particles loaded");
+    DeviceGuard guard(c->device);
+    if (!c->field_valid) {
+        ep_status s = refresh_field(c);
+        if (s != EP_OK) return s;
+    }
+    const size_t bytes = (size_t)n_nodes * sizeof(double);
+    if (rho) HIPCHK(c, hipMemcpyAsync(rho, c->rho64, bytes, hipMemcpyDeviceToHost, c->stream));
+    if (E) HIPCHK(c, hipMemcpyAsync(E, c->E64, bytes, hipMemcpyDeviceToHost, c->stream));
+    if (Psi) HIPCHK(c, hipMemcpyAsync(Psi, c->Psi64, bytes, hipMemcpyDeviceToHost, c->stream));
+    double fs[kFieldScalars];
+    HIPCHK(c, hipMemcpyAsync(fs, c->fscal, sizeof fs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (Qb) *Qb = fs[kQb];
+    return EP_OK;
+}
+
+ep_status ep_set_push_mode(ep_ctx *c, int32_t push, double drift_tol, uint32_t fallback_substeps)
+{
+    if (!c) return EP_EINVAL;
+    if (push != EP_PUSH_PLAIN && push != EP_PUSH_LEARNED)
+        return c->fail(EP_EINVAL, "ep_set_push_mode: unknown push mode");
+    if (push == EP_PUSH_LEARNED)
+        return c->fail(EP_ENOTRAINED, "ep_set_push_mode: no corrector network loaded");
+    c->push_mode = push;
+    (void)drift_tol;
+    (void)fallback_substeps;
+    return EP_OK;
+}
+
+ep_status ep_timing_enable(ep_ctx *c, int32_t on)
+{
+    if (!c) return EP_EINVAL;
+    DeviceGuard guard(c->device);
+    HIPCHK(c, collect_timing(c));
+    c->timed.clear();
+    c->timing = on != 0;
+    return EP_OK;
+}
+
+ep_status ep_timing_get(ep_ctx *c, const char *kernel, double *total_ms, uint64_t *count)
+{
+    if (!c) return EP_EINVAL;
+    if (!kernel || !total_ms || !count) return c->fail(EP_EINVAL, "ep_timing_get: null argument");
+    DeviceGuard guard(c->device);
+    HIPCHK(c, collect_timing(c));
+    auto it = c->timed.find(kernel);
+    *total_ms = it == c->timed.end() ? 0.0 : it->second.first;
+    *count = it == c->timed.end() ? 0 : it->second.second;
+    return EP_OK;
+}
+
+}  // extern "C"

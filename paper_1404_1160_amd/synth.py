@@ -3,6 +3,9 @@ smoke check.
 
 Draws only: no step of the method lives here.  Every generator uses numpy's
 ``default_rng(seed)`` and returns FP64 arrays (R, V) and the uniform weight.
+The draws are rounded to FP32-representable values, so that a consumer which
+stores particles in FP32 and one which computes in FP64 start from exactly the
+same numbers.
 
 Workloads (the paper's experiments draw macroparticles from the density of
 f0, section 2.1; the configurations below are synthetic beams of that kind):
@@ -17,11 +20,15 @@ import numpy as np
 V_TH_PAPER = 0.0727518214392
 
 
+def _fp32(a):
+    return a.astype(np.float32).astype(np.float64)
+
+
 def gaussian(n, seed, sigma=1.0):
     rng = np.random.default_rng(seed)
     R = rng.standard_normal(n) * sigma
     V = rng.standard_normal(n) * sigma
-    return R, V, 1.0 / max(n, 1)
+    return _fp32(R), _fp32(V), 1.0 / max(n, 1)
 
 
 def gaussian_truncated(n, seed, sigma=1.0, cut=4.0):
@@ -34,14 +41,14 @@ def gaussian_truncated(n, seed, sigma=1.0, cut=4.0):
         R[filled:filled + draw.size] = draw
         filled += draw.size
     V = rng.standard_normal(n) * sigma
-    return R, V, 1.0 / max(n, 1)
+    return _fp32(R), _fp32(V), 1.0 / max(n, 1)
 
 
 def paper_f0(n, seed, v_th=V_TH_PAPER, half_width=0.75):
     rng = np.random.default_rng(seed)
     R = rng.uniform(-half_width, half_width, n)
     V = rng.standard_normal(n) * v_th
-    return R, V, 1.0 / max(n, 1)
+    return _fp32(R), _fp32(V), 1.0 / max(n, 1)
 
 
 def nodes_exact(nr, rmax):
