@@ -3,9 +3,9 @@
 Workload (default): the Vlasov-Poisson beam at scale -- N_p = 1e8 FP32
 particles, R ~ N(0,1) truncated to |R| < 4, V ~ N(0,1), weights 1/N_p, radial
 mesh of N_r = 4096 cells on [-5, 5], eps = 1e-3, dt = 0.05, K = 1 substep,
-LDS-privatised fixed-point deposit.  One step = FP64 phase tables, gather +
-push + CIC deposit (one fused kernel), exact-integer prefix-sum Poisson solve;
-moments every 100 steps.
+LDS-privatised fixed-point deposit.  One step = gather + push + CIC deposit (one
+fused kernel) and the exact-integer prefix-sum Poisson solve for the next step
+(one workgroup); FP64 phase tables per chunk of steps; moments every 100 steps.
 
 Output: one JSON line (see the repository's documentation for the fields),
 with

@@ -33,23 +33,31 @@ hipError_t launch_twist_out(hipStream_t st, const float *zR, const float *zV, do
 hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
                                const double4 *sub, int K, int S);
 
+// Device arrays and scalars of the mesh.
+struct MeshArgs {
+    int nr;                   // cells
+    double w;                 // particle weight
+    double hr;                // cell width
+    unsigned long long *hist; // [nr+1] fixed-point node charges being accumulated
+    float2 *etab;             // [nr]   FP32 gather table (E_m, E_{m+1} - E_m)
+    double *rho64, *E64, *Psi64;  // [nr+1] FP64 node values
+    double *fscal;            // [kFieldScalars]
+};
+
 // One Poisson step: K-substep push in the frozen field, then CIC deposit of
 // the new positions into hist (fixed point, 2^-32 of a particle weight).  The
 // rotation to the lab frame at the end of the step is endrot_tab[0] if
 // endrot_tab is non-null, else endrot_val.  With push == false only the
 // deposit of the current state is done.
 hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, int64_t n,
-                               const float2 *etab, const double *fscal, const double4 *sub,
-                               const double2 *endrot_tab, double2 endrot_val, int K, int nr,
-                               double hr, unsigned long long *hist, int grid_cap);
+                               const double4 *sub, const double2 *endrot_tab, double2 endrot_val,
+                               int K, const MeshArgs &ma, int grid_cap);
 
-// Raise the dynamic LDS limit of the mesh push kernels for an nr-cell mesh.
-hipError_t setup_push_lds(int nr);
+// Raise the dynamic LDS limit of the mesh kernels for an nr-cell mesh.
+hipError_t setup_mesh_lds(int nr);
 size_t push_lds_bytes_for(int nr);
 
-hipError_t launch_mesh_solve(hipStream_t st, unsigned long long *hist, int nr, double w,
-                             double hr, float2 *etab, double *rho64, double *E64,
-                             double *Psi64, double *fscal, unsigned long long *scan_tmp);
+hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &ma);
 
 hipError_t launch_moments(hipStream_t st, const float *zR, const float *zV, int64_t n,
                           double c, double s, double rmax, double *partial,

@@ -164,6 +164,184 @@ hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ mesh solve
+
+// Wave (64-lane) and block scans and sums with a fixed combination order, so
+// FP64 results are reproducible run to run.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Exclusive prefix of v over the block (wtot: LDS scratch of >= 16 entries).
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *wtot)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const T incl = wave_inclusive_scan(v);
+    T excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = T(0);
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        const T t = lane < nw ? wtot[lane] : T(0);
+        const T ti = wave_inclusive_scan(t);
+        T te = __shfl_up(ti, 1, 64);
+        if (lane == 0) te = T(0);
+        if (lane < nw) wtot[lane] = te;
+    }
+    __syncthreads();
+    const T r = wtot[w] + excl;
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ T block_sum(T v, T *wtot)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) wtot[w] = v;
+    __syncthreads();
+    T r = T(0);
+    for (int i = 0; i < nw; ++i) r += wtot[i];
+    __syncthreads();
+    return r;
+}
+
+// One workgroup.  From the fixed-point node charges S_k (units of 2^-32 w):
+//   rho_k = w 2^-32 S_k / h_r                                   (CIC density)
+//   I_k   = sum_{i=1..k} (S_{i-1} + S_i)        exact integer trapezoid scan,
+//           so P_k = int_{x_0}^{x_k} rho = w 2^-33 I_k
+//   Q_j   = (P_{c+j} - P_{c-j}) / 2 = w 2^-34 (I_{c+j} - I_{c-j})
+//   E_k   = Q_{|k-c|} / x_k  (k != c),  E_c = 0,  Qb = w 2^-34 I_nr
+//   Psi_k = -int_0^{x_k} E  (trapezoid of the node values)
+//   field energy int_0^{r_max} x E^2 dx (trapezoid)
+// and the FP32 gather table (E_m, E_{m+1} - E_m).  Clears hist for the next
+// accumulation.  Node arrays live in the caller's LDS (2 (nr+1) u64): S and
+// I as u64, then E as FP64 in the storage of S and the potential's prefix in
+// the storage of I.  Elementwise passes run node-contiguous across threads;
+// the two scans run over contiguous per-thread chunks.
+__device__ void mesh_solve_block(unsigned char *smem, unsigned long long *__restrict__ hist,
+                                 int nr, double w, double hr, float2 *__restrict__ etab,
+                                 double *__restrict__ rho64, double *__restrict__ E64,
+                                 double *__restrict__ Psi64, double *__restrict__ fscal)
+{
+    const int nn = nr + 1;
+    unsigned long long *S = reinterpret_cast<unsigned long long *>(smem);
+    double *Ed = reinterpret_cast<double *>(smem);
+    unsigned long long *I = S + nn;
+    double *Fd = reinterpret_cast<double *>(I);
+    __shared__ unsigned long long wu[kSolveBlock / 64];
+    __shared__ double wd[kSolveBlock / 64];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int c = nr >> 1;
+    const double rho_scale = w * kFixScale / hr;
+
+#pragma unroll 1
+    for (int k = tid; k < nn; k += nt) {
+        const unsigned long long v = hist[k];
+        S[k] = v;
+        rho64[k] = (double)v * rho_scale;
+        hist[k] = 0ull;
+    }
+    __syncthreads();
+
+    const int chunk = (nn + nt - 1) / nt;
+    const int k0 = min(tid * chunk, nn), k1 = min(k0 + chunk, nn);
+    unsigned long long loc = 0ull, charge = 0ull;
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+        charge += S[k];
+        if (k > 0) loc += S[k - 1] + S[k];
+    }
+    unsigned long long run = block_exclusive_scan<unsigned long long>(loc, wu);
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+        if (k > 0) run += S[k - 1] + S[k];
+        I[k] = run;
+    }
+    charge = block_sum<unsigned long long>(charge, wu);   // syncs: I is complete
+
+    const double q_scale = w * kFixScale * 0.25;
+#pragma unroll 1
+    for (int k = tid; k < nn; k += nt) {
+        double E = 0.0;
+        if (k != c) {
+            const int j = k > c ? k - c : c - k;
+            const double Q = (double)(I[c + j] - I[c - j]) * q_scale;
+            E = Q / ((double)(k - c) * hr);
+        }
+        Ed[k] = E;
+        E64[k] = E;
+    }
+    if (tid == 0) {
+        fscal[kQb] = (double)I[nr] * q_scale;
+        fscal[kMeshCharge] = (double)charge * w * kFixScale;
+    }
+    __syncthreads();
+
+    double fe = 0.0;
+#pragma unroll 1
+    for (int k = tid; k < nr; k += nt) {
+        const double e0 = Ed[k], e1 = Ed[k + 1];
+        etab[k] = make_float2((float)e0, (float)(e1 - e0));
+        if (k >= c) {
+            const double x0 = (double)(k - c) * hr, x1 = (double)(k + 1 - c) * hr;
+            fe += hr * (x0 * e0 * e0 + x1 * e1 * e1) * 0.5;
+        }
+    }
+    // potential: F_k = sum_{i=1..k} h_r (E_{i-1} + E_i) / 2,  Psi_k = -(F_k - F_c)
+    double locd = 0.0;
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k)
+        if (k > 0) locd += hr * (Ed[k - 1] + Ed[k]) * 0.5;
+    double runf = block_exclusive_scan<double>(locd, wd);
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+        if (k > 0) runf += hr * (Ed[k - 1] + Ed[k]) * 0.5;
+        Fd[k] = runf;
+    }
+    fe = block_sum<double>(fe, wd);   // syncs: Fd is complete
+    const double Fc = Fd[c];
+#pragma unroll 1
+    for (int k = tid; k < nn; k += nt) Psi64[k] = -(Fd[k] - Fc);
+    if (tid == 0) fscal[kFieldEnergy] = fe;
+}
+
+__global__ __launch_bounds__(kSolveBlock) void mesh_solve_kernel(
+    unsigned long long *__restrict__ hist, int nr, double w, double hr, float2 *__restrict__ etab,
+    double *__restrict__ rho64, double *__restrict__ E64, double *__restrict__ Psi64,
+    double *__restrict__ fscal)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    mesh_solve_block(smem, hist, nr, w, hr, etab, rho64, E64, Psi64, fscal);
+}
+
+static size_t mesh_lds_bytes(int nr) { return (size_t)2 * (nr + 1) * sizeof(unsigned long long); }
+
+hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &a)
+{
+    mesh_solve_kernel<<<dim3(1), dim3(kSolveBlock), mesh_lds_bytes(a.nr), st>>>(
+        a.hist, a.nr, a.w, a.hr, a.etab, a.rho64, a.E64, a.Psi64, a.fscal);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ Poisson push + deposit
 
 struct MeshView {
@@ -232,11 +410,12 @@ __device__ __forceinline__ void push_group(const MeshView &m, const double4 *__r
 // the same charge bit for bit.
 template <bool PUSH>
 __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
-    float *__restrict__ zR, float *__restrict__ zV, int64_t n, const float2 *__restrict__ etab,
-    const double *__restrict__ fscal, const double4 *__restrict__ sub,
-    const double2 *__restrict__ endrot_tab, double2 endrot_val, int K, int nr, double inv_hr,
-    unsigned long long *__restrict__ hist)
+    float *__restrict__ zR, float *__restrict__ zV, int64_t n, const double4 *__restrict__ sub,
+    const double2 *__restrict__ endrot_tab, double2 endrot_val, int K, double inv_hr, MeshArgs ma)
 {
+    const int nr = ma.nr;
+    const float2 *__restrict__ etab = ma.etab;
+    unsigned long long *__restrict__ hist = ma.hist;
     extern __shared__ __align__(16) unsigned char smem[];
     float2 *Et = reinterpret_cast<float2 *>(smem);
     unsigned long long *H = reinterpret_cast<unsigned long long *>(smem + (size_t)nr * sizeof(float2));
@@ -250,7 +429,7 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
     m.inv_hr = inv_hr;
     m.half = 0.5 * (double)nr;
     m.c = nr >> 1;
-    m.Qb = PUSH ? fscal[kQb] : 0.0;
+    m.Qb = PUSH ? ma.fscal[kQb] : 0.0;
     const double2 er = endrot_tab ? endrot_tab[0] : endrot_val;
     __syncthreads();
 
@@ -299,182 +478,63 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
         deposit(m, fma(er.x, (double)fr, er.y * (double)fv));
     }
     __syncthreads();
-    for (int i = tid; i <= nr; i += blockDim.x) {
+    // flush: each workgroup starts at its own node offset so that concurrent
+    // workgroups add to different addresses
+    const int nn = nr + 1;
+    const int start = (int)(((unsigned)blockIdx.x * 131u) % (unsigned)nn);
+    for (int i0 = tid; i0 < nn; i0 += blockDim.x) {
+        int i = i0 + start;
+        if (i >= nn) i -= nn;
         const unsigned long long v = H[i];
         if (v) atomicAdd(&hist[i], v);
     }
 }
 
+// field table + histogram
 static size_t push_lds_bytes(int nr)
 {
     return (size_t)nr * sizeof(float2) + (size_t)(nr + 1) * sizeof(unsigned long long);
 }
 
 hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, int64_t n,
-                               const float2 *etab, const double *fscal, const double4 *sub,
-                               const double2 *endrot_tab, double2 endrot_val, int K, int nr,
-                               double hr, unsigned long long *hist, int grid_cap)
+                               const double4 *sub, const double2 *endrot_tab, double2 endrot_val,
+                               int K, const MeshArgs &ma, int grid_cap)
 {
     if (n <= 0) return hipSuccess;
-    const size_t lds = push_lds_bytes(nr);
+    const size_t lds = push_lds_bytes(ma.nr);
     const int64_t n4 = n >> 2;
     int64_t grid = (n4 + kPushBlock - 1) / kPushBlock;
     if (grid > grid_cap) grid = grid_cap;
     if (grid < 1) grid = 1;
-    const double inv_hr = 1.0 / hr;
+    const double inv_hr = 1.0 / ma.hr;
+    const dim3 g((unsigned)grid), b(kPushBlock);
     if (push)
-        push_poisson_kernel<true><<<dim3((unsigned)grid), dim3(kPushBlock), lds, st>>>(
-            zR, zV, n, etab, fscal, sub, endrot_tab, endrot_val, K, nr, inv_hr, hist);
+        push_poisson_kernel<true><<<g, b, lds, st>>>(zR, zV, n, sub, endrot_tab, endrot_val, K,
+                                                     inv_hr, ma);
     else
-        push_poisson_kernel<false><<<dim3((unsigned)grid), dim3(kPushBlock), lds, st>>>(
-            zR, zV, n, etab, fscal, sub, endrot_tab, endrot_val, 0, nr, inv_hr, hist);
+        push_poisson_kernel<false><<<g, b, lds, st>>>(zR, zV, n, sub, endrot_tab, endrot_val, 0,
+                                                      inv_hr, ma);
     return hipGetLastError();
 }
 
 size_t push_lds_bytes_for(int nr) { return push_lds_bytes(nr); }
 
-hipError_t setup_push_lds(int nr)
+template <bool P>
+static hipError_t raise_lds(int lds)
 {
-    const int lds = (int)push_lds_bytes(nr);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<false>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<P>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-// ------------------------------------------------------------ mesh solve
-
-// Hillis-Steele scan across the block; returns the exclusive prefix of v.
-// The order of additions depends only on the block size, so FP64 results are
-// reproducible.
-template <typename T>
-__device__ T block_exclusive_scan(T v, T *buf)
+hipError_t setup_mesh_lds(int nr)
 {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    buf[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < nt; off <<= 1) {
-        const T add = tid >= off ? buf[tid - off] : T(0);
-        __syncthreads();
-        buf[tid] += add;
-        __syncthreads();
-    }
-    const T ex = tid > 0 ? buf[tid - 1] : T(0);
-    __syncthreads();
-    return ex;
-}
-
-template <typename T>
-__device__ T block_sum(T v, T *buf)
-{
-    const int tid = threadIdx.x;
-    buf[tid] = v;
-    __syncthreads();
-    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-        if (tid < w) buf[tid] += buf[tid + w];
-        __syncthreads();
-    }
-    const T r = buf[0];
-    __syncthreads();
-    return r;
-}
-
-// One workgroup.  From the fixed-point node charges S_k (units of 2^-32 w):
-//   rho_k = w 2^-32 S_k / h_r                                   (CIC density)
-//   I_k   = sum_{i=1..k} (S_{i-1} + S_i)        exact integer trapezoid scan,
-//           so P_k = int_{x_0}^{x_k} rho = w 2^-33 I_k
-//   Q_j   = (P_{c+j} - P_{c-j}) / 2 = w 2^-34 (I_{c+j} - I_{c-j})
-//   E_k   = Q_{|k-c|} / x_k  (k != c),  E_c = 0,  Qb = w 2^-34 I_nr
-//   Psi_k = -int_0^{x_k} E  (trapezoid of the node values)
-//   field energy int_0^{r_max} x E^2 dx (trapezoid)
-// and the FP32 gather table (E_m, E_{m+1} - E_m).  Clears hist for the next
-// accumulation.  I is global scratch of nr+1 entries.
-__global__ __launch_bounds__(kSolveBlock) void mesh_solve_kernel(
-    unsigned long long *__restrict__ hist, int nr, double w, double hr, float2 *__restrict__ etab,
-    double *__restrict__ rho64, double *__restrict__ E64, double *__restrict__ Psi64,
-    double *__restrict__ fscal, unsigned long long *__restrict__ I)
-{
-    __shared__ unsigned long long su[kSolveBlock];
-    __shared__ double sd[kSolveBlock];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int nn = nr + 1;
-    const int chunk = (nn + nt - 1) / nt;
-    const int k0 = min(tid * chunk, nn), k1 = min(k0 + chunk, nn);
-    const int c = nr >> 1;
-
-    unsigned long long loc = 0ull;
-    for (int k = k0; k < k1; ++k)
-        if (k > 0) loc += hist[k - 1] + hist[k];
-    unsigned long long run = block_exclusive_scan<unsigned long long>(loc, su);
-    const double rho_scale = w * kFixScale / hr;
-    for (int k = k0; k < k1; ++k) {
-        const unsigned long long Sk = hist[k];
-        if (k > 0) run += hist[k - 1] + Sk;
-        I[k] = run;
-        rho64[k] = (double)Sk * rho_scale;
-    }
-    __syncthreads();
-
-    const double q_scale = w * kFixScale * 0.25;
-    for (int k = k0; k < k1; ++k) {
-        double E = 0.0;
-        if (k != c) {
-            const int j = k > c ? k - c : c - k;
-            const long long dI = (long long)(I[c + j] - I[c - j]);
-            const double Q = (double)dI * q_scale;
-            E = Q / ((double)(k - c) * hr);
-        }
-        E64[k] = E;
-    }
-    if (tid == 0) fscal[kQb] = (double)I[nr] * q_scale;
-    __syncthreads();
-
-    // potential: F_k = sum_{i=1..k} h_r (E_{i-1} + E_i) / 2,  Psi_k = -(F_k - F_c)
-    double locd = 0.0;
-    for (int k = k0; k < k1; ++k)
-        if (k > 0) locd += hr * (E64[k - 1] + E64[k]) * 0.5;
-    double runf = block_exclusive_scan<double>(locd, sd);
-    for (int k = k0; k < k1; ++k) {
-        if (k > 0) runf += hr * (E64[k - 1] + E64[k]) * 0.5;
-        Psi64[k] = runf;
-    }
-    // gather table and field energy
-    double fe = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        if (k < nr) {
-            const double e0 = E64[k], e1 = E64[k + 1];
-            etab[k] = make_float2((float)e0, (float)(e1 - e0));
-            if (k >= c) {
-                const double x0 = (double)(k - c) * hr, x1 = (double)(k + 1 - c) * hr;
-                fe += hr * (x0 * e0 * e0 + x1 * e1 * e1) * 0.5;
-            }
-        }
-    }
-    fe = block_sum<double>(fe, sd);
-    // total deposited charge (exact integer sum)
-    unsigned long long sq = 0ull;
-    for (int k = k0; k < k1; ++k) sq += hist[k];
-    sq = block_sum<unsigned long long>(sq, su);
-    const double Fc = Psi64[c];
-    __syncthreads();
-    for (int k = k0; k < k1; ++k) {
-        Psi64[k] = -(Psi64[k] - Fc);
-        hist[k] = 0ull;
-    }
-    if (tid == 0) {
-        fscal[kFieldEnergy] = fe;
-        fscal[kMeshCharge] = (double)sq * w * kFixScale;
-    }
-}
-
-hipError_t launch_mesh_solve(hipStream_t st, unsigned long long *hist, int nr, double w,
-                             double hr, float2 *etab, double *rho64, double *E64,
-                             double *Psi64, double *fscal, unsigned long long *scan_tmp)
-{
-    mesh_solve_kernel<<<dim3(1), dim3(kSolveBlock), 0, st>>>(hist, nr, w, hr, etab, rho64, E64,
-                                                             Psi64, fscal, scan_tmp);
-    return hipGetLastError();
+    const int lds = (int)push_lds_bytes(nr);
+    hipError_t e;
+    if ((e = raise_lds<true>(lds)) != hipSuccess) return e;
+    if ((e = raise_lds<false>(lds)) != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&mesh_solve_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)mesh_lds_bytes(nr));
 }
 
 // ------------------------------------------------------------ moments

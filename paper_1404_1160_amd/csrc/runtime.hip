@@ -65,10 +65,25 @@ struct ep_ctx {
 
     // mesh
     double hr = 0.0;
-    unsigned long long *hist = nullptr, *scan_tmp = nullptr;
+    unsigned long long *hist = nullptr;
     float2 *etab = nullptr;
     double *rho64 = nullptr, *E64 = nullptr, *Psi64 = nullptr, *fscal = nullptr;
     bool field_valid = false;
+
+    MeshArgs mesh() const
+    {
+        MeshArgs m;
+        m.nr = (int)cfg.n_cells;
+        m.w = w;
+        m.hr = hr;
+        m.hist = hist;
+        m.etab = etab;
+        m.rho64 = rho64;
+        m.E64 = E64;
+        m.Psi64 = Psi64;
+        m.fscal = fscal;
+        return m;
+    }
 
     // per-chunk substep tables
     StepTables tab{};
@@ -187,24 +202,19 @@ ep_status ensure_tables(ep_ctx *c, size_t entries, size_t steps)
 ep_status refresh_field(ep_ctx *c)
 {
     const double2 er = make_double2(cos(c->phase), sin(c->phase));
+    const MeshArgs ma = c->mesh();
     HIPCHK(c, timed_launch(c, "deposit", [&] {
                return launch_push_poisson(c->stream, false, c->zR, c->zV, (int64_t)c->n,
-                                          c->etab, c->fscal, nullptr, nullptr, er, 0,
-                                          (int)c->cfg.n_cells, c->hr, c->hist,
-                                          c->push_grid_cap);
+                                          nullptr, nullptr, er, 0, ma, c->push_grid_cap);
            }));
-    HIPCHK(c, timed_launch(c, "mesh_solve", [&] {
-               return launch_mesh_solve(c->stream, c->hist, (int)c->cfg.n_cells, c->w, c->hr,
-                                        c->etab, c->rho64, c->E64, c->Psi64, c->fscal,
-                                        c->scan_tmp);
-           }));
+    HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, ma); }));
     c->field_valid = true;
     return EP_OK;
 }
 
 void free_all(ep_ctx *c)
 {
-    for (void *p : {(void *)c->own_zR, (void *)c->own_zV, (void *)c->hist, (void *)c->scan_tmp,
+    for (void *p : {(void *)c->own_zR, (void *)c->own_zV, (void *)c->hist,
                     (void *)c->etab, (void *)c->rho64, (void *)c->E64, (void *)c->Psi64,
                     (void *)c->fscal, (void *)c->tab.sub, (void *)c->tab.endrot,
                     (void *)c->stageR, (void *)c->stageV, (void *)c->mpartial, (void *)c->mout,
@@ -286,7 +296,7 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     if (per_cu > 2) per_cu = 2;
     if (per_cu < 1) per_cu = 1;
     c->push_grid_cap = c->n_cu * per_cu;
-    CREATE_CHK(setup_push_lds((int)cfg->n_cells));
+    CREATE_CHK(setup_mesh_lds((int)cfg->n_cells));
 
     const size_t np = (size_t)cfg->n_particles;
     const size_t np_pad = (np + 3) & ~size_t(3);
@@ -296,7 +306,6 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     c->zV = c->own_zV;
     const size_t nn = (size_t)cfg->n_cells + 1;
     CREATE_CHK(dalloc(&c->hist, nn));
-    CREATE_CHK(dalloc(&c->scan_tmp, nn));
     CREATE_CHK(dalloc(&c->etab, nn));
     CREATE_CHK(dalloc(&c->rho64, nn));
     CREATE_CHK(dalloc(&c->E64, nn));
@@ -415,19 +424,16 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
                                                   c->tab.sub, K, S);
                    }));
         } else {
+            const MeshArgs ma = c->mesh();
             for (int j = 0; j < S; ++j) {
                 HIPCHK(c, timed_launch(c, "push_poisson", [&] {
-                           return launch_push_poisson(
-                               c->stream, true, c->zR, c->zV, (int64_t)c->n, c->etab, c->fscal,
-                               c->tab.sub + (size_t)j * K, c->tab.endrot + j,
-                               make_double2(1.0, 0.0), K, (int)c->cfg.n_cells, c->hr, c->hist,
-                               c->push_grid_cap);
+                           return launch_push_poisson(c->stream, true, c->zR, c->zV,
+                                                      (int64_t)c->n, c->tab.sub + (size_t)j * K,
+                                                      c->tab.endrot + j, make_double2(1.0, 0.0),
+                                                      K, ma, c->push_grid_cap);
                        }));
-                HIPCHK(c, timed_launch(c, "mesh_solve", [&] {
-                           return launch_mesh_solve(c->stream, c->hist, (int)c->cfg.n_cells,
-                                                    c->w, c->hr, c->etab, c->rho64, c->E64,
-                                                    c->Psi64, c->fscal, c->scan_tmp);
-                       }));
+                HIPCHK(c, timed_launch(c, "mesh_solve",
+                                       [&] { return launch_mesh_solve(c->stream, ma); }));
             }
         }
         c->phase = fmod(c->phase + (double)S * dphi, kTwoPi);
