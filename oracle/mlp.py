@@ -4,8 +4,10 @@ learned push).
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  Plain numpy in FP64;
 ``@`` (matmul) is the only library primitive used for the layers.
 
-Network (5 or 6 inputs -> 64 -> 64 -> 2, tanh):
-    h1 = tanh(W1 x + b1),  h2 = tanh(W2 h1 + b2),  o = W3 h2 + b3
+Network (5 or 6 inputs -> 64 -> 64 -> 2):
+    h1 = act(W1 x + b1),  h2 = act(W2 h1 + b2),  o = W3 h2 + b3
+with the inverse-square-root unit act(z) = z / sqrt(1 + z^2) (Carlile et al.,
+2017), a smooth odd saturating activation like tanh; act'(z) = (1 + z^2)^(-3/2).
 Parameters are one flat FP32/FP64 vector in the order W1[64,n_in], b1[64],
 W2[64,64], b2[64], W3[2,64], b3[2] (row-major).
 
@@ -55,29 +57,37 @@ def pack(parts):
     return np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in parts])
 
 
+def act(z):
+    return z / np.sqrt(1.0 + z * z)
+
+
+def act_grad(z):
+    return (1.0 + z * z) ** -1.5
+
+
 def forward(p, X, n_in=None):
     """X: [B, n_in].  Returns (O [B, 2], cache)."""
     X = np.asarray(X, dtype=np.float64)
     n_in = X.shape[1] if n_in is None else n_in
     W1, b1, W2, b2, W3, b3 = unpack(p, n_in)
     z1 = X @ W1.T + b1
-    h1 = np.tanh(z1)
+    h1 = act(z1)
     z2 = h1 @ W2.T + b2
-    h2 = np.tanh(z2)
+    h2 = act(z2)
     O = h2 @ W3.T + b3
-    return O, (X, h1, h2, W1, W2, W3)
+    return O, (X, z1, h1, z2, h2, W1, W2, W3)
 
 
 def backward(cache, dO):
     """Gradient of sum(dO * O) with respect to the flat parameter vector."""
-    X, h1, h2, W1, W2, W3 = cache
+    X, z1, h1, z2, h2, W1, W2, W3 = cache
     dO = np.asarray(dO, dtype=np.float64)
     dW3 = dO.T @ h2
     db3 = dO.sum(0)
-    dz2 = (dO @ W3) * (1.0 - h2 * h2)
+    dz2 = (dO @ W3) * act_grad(z2)
     dW2 = dz2.T @ h1
     db2 = dz2.sum(0)
-    dz1 = (dz2 @ W2) * (1.0 - h1 * h1)
+    dz1 = (dz2 @ W2) * act_grad(z1)
     dW1 = dz1.T @ X
     db1 = dz1.sum(0)
     return pack([dW1, db1, dW2, db2, dW3, db3])

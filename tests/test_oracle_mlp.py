@@ -1,0 +1,131 @@
+"""Pins of the learned-corrector oracle (no GPU): finite differences, the
+linear limit, Adam's closed-form first step, the exact free rotation and the
+label round trip of the polar output map, and the fallback limits."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import duffing, mlp
+from paper_1404_1160_amd import synth
+
+
+@pytest.mark.parametrize("n_in", [5, 6])
+def test_backward_matches_central_differences(n_in):
+    rng = np.random.default_rng(1)
+    p = synth.mlp_init(n_in, 64, 2, seed=3).astype(np.float64)
+    p += rng.normal(0, 0.05, p.size)          # non-zero biases too
+    X = rng.normal(0, 1, (7, n_in))
+    Y = rng.normal(0, 1, (7, 2))
+    _, g = mlp.mse_loss_grad(p, X, Y)
+    idx = rng.choice(p.size, 120, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(p.size)
+        e[i] = h
+        fd = (mlp.mse_loss_grad(p + e, X, Y)[0] - mlp.mse_loss_grad(p - e, X, Y)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1e-3, abs(fd)) + 1e-10, (i, fd, g[i])
+
+
+def test_activation_derivative_and_limits():
+    z = np.linspace(-6, 6, 1001)
+    h = 1e-6
+    assert np.max(np.abs((mlp.act(z + h) - mlp.act(z - h)) / (2 * h) - mlp.act_grad(z))) < 1e-9
+    assert np.all(np.abs(mlp.act(z)) < 1) and np.allclose(mlp.act(-z), -mlp.act(z))
+    assert abs(mlp.act(1e8) - 1.0) < 1e-12
+
+
+def test_linear_limit():
+    """With weights of scale s the activation is the identity up to O(z^3), so
+    the network differs from the product of its affine maps by O(s^3):
+    halving s divides the difference by ~8."""
+    rng = np.random.default_rng(2)
+    base = [rng.normal(0, 1, (64, 5)), rng.normal(0, 1, 64), rng.normal(0, 1, (64, 64)),
+            rng.normal(0, 1, 64)]
+    W3, b3 = rng.normal(0, 1, (2, 64)), rng.normal(0, 1, 2)
+    X = rng.normal(0, 1, (9, 5))
+    errs = []
+    for s in (4e-4, 2e-4, 1e-4):
+        W1, b1, W2, b2 = [a * s for a in base]
+        O, _ = mlp.forward(mlp.pack([W1, b1, W2, b2, W3, b3]), X)
+        lin = ((X @ W1.T + b1) @ W2.T + b2) @ W3.T + b3
+        errs.append(np.max(np.abs(O - lin)))
+    r = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all((r > 7.0) & (r < 9.5)), (errs, r)
+
+
+def test_adam_first_step_is_signed_lr():
+    """Bias correction makes the first update -lr g/(|g| + eps): a signed step."""
+    rng = np.random.default_rng(3)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50)
+    g[np.abs(g) < 1e-2] = 0.5      # keep eps/|g| below 1e-6
+    p1, m, v = mlp.adam_step(p, g, np.zeros(50), np.zeros(50), 1, lr=1e-2)
+    assert np.allclose(p1 - p, -1e-2 * np.sign(g), rtol=2e-6, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_minimises_a_quadratic():
+    target = np.linspace(-2, 3, 20)
+    p = np.zeros(20)
+    m = np.zeros(20)
+    v = np.zeros(20)
+    for t in range(1, 3001):
+        p, m, v = mlp.adam_step(p, p - target, m, v, t, lr=1e-2)
+    assert np.max(np.abs(p - target)) < 1e-3
+
+
+def test_polar_map_identity_is_free_rotation():
+    R, V, _ = synth.gaussian(100, seed=4)
+    dt, eps = 0.05, 1e-3
+    R1, V1 = mlp.apply_polar(R, V, dt, eps, 0.0, 0.0)
+    Rx, Vx = oracle.push(R, V, dt, eps, 3, field=oracle.FIELD_ZERO)
+    assert np.max(np.abs(R1 - Rx)) < 1e-12 and np.max(np.abs(V1 - Vx)) < 1e-12
+
+
+def test_polar_labels_round_trip():
+    rng = np.random.default_rng(5)
+    R, V, _ = synth.gaussian(500, seed=5, sigma=1.5)
+    dt, eps = 0.05, 1e-3
+    d = rng.uniform(-3, 3, R.size)
+    k = rng.uniform(-0.01, 0.01, R.size)
+    R1, V1 = mlp.apply_polar(R, V, dt, eps, d, k)
+    d2, k2 = mlp.polar_labels(R, V, R1, V1, dt, eps)
+    assert np.max(np.abs(d2 - d)) < 1e-12 and np.max(np.abs(k2 - k)) < 1e-12
+    # exact Duffing step: labels reproduce the exact end point
+    Rx, Vx = duffing.solution(R, V, eps, dt)
+    d3, k3 = mlp.polar_labels(R, V, Rx, Vx, dt, eps)
+    R3, V3 = mlp.apply_polar(R, V, dt, eps, d3, k3)
+    assert np.max(np.hypot(R3 - Rx, V3 - Vx)) < 1e-12
+    # the Duffing flow advances the phase (harder spring: shorter period) and
+    # changes |y| only through the orbit's shape, O(eps R^2)
+    assert np.all(d3 > -1e-12) and np.max(np.abs(k3)) < 0.02
+
+
+def _duffing_fallback(dt, eps, K):
+    return lambda R, V: oracle.push(R, V, dt, eps, K, field=oracle.FIELD_DUFFING)
+
+
+def test_learned_step_fallback_limits():
+    """tol = 0: every particle falls back and the step equals the plain push;
+    tol = inf: none does and the step equals the network's polar map."""
+    R, V, _ = synth.gaussian(300, seed=6, sigma=1.5)
+    dt, eps = 0.05, 1e-3
+    p = synth.mlp_init(5, 64, 2, seed=7).astype(np.float64)
+    norm = mlp.Norm(mu_d=0.1, sig_d=0.05, mu_k=0.0, sig_k=1e-3)
+    pot = lambda r: r ** 4 / 4
+    R0, V0, fb, _ = mlp.learned_step(p, R, V, dt, eps, norm, pot, _duffing_fallback(dt, eps, 40), 0.0)
+    Rp, Vp = oracle.push(R, V, dt, eps, 40, field=oracle.FIELD_DUFFING)
+    assert fb.all() and np.array_equal(R0, Rp) and np.array_equal(V0, Vp)
+    R1, V1, fb, _ = mlp.learned_step(p, R, V, dt, eps, norm, pot, _duffing_fallback(dt, eps, 40),
+                                     math.inf)
+    d, k = mlp.predict(p, R, V, dt, eps, norm)
+    Rq, Vq = mlp.apply_polar(R, V, dt, eps, d, k)
+    assert not fb.any() and np.array_equal(R1, Rq) and np.array_equal(V1, Vq)
+    # a NaN weight makes every prediction fail the check (NaN <= tol is false)
+    p_bad = p.copy()
+    p_bad[100] = np.nan
+    R2, V2, fb, _ = mlp.learned_step(p_bad, R, V, dt, eps, norm, pot,
+                                     _duffing_fallback(dt, eps, 40), 1.0)
+    assert fb.all() and np.array_equal(R2, Rp)
