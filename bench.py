@@ -12,7 +12,11 @@ with
   roofline     -- dominant kernel (push_poisson), algorithmic bytes 16 B per
                   particle-step / its mean duration from HIP events recorded
                   on the library's stream, vs the 8 TB/s HBM peak;
-  cpu_baseline -- the FP64 CPU oracle timed on this host on a bounded sample.
+  cpu_baseline -- the FP64 CPU oracle timed on this host on a bounded sample;
+  learned_vs_plain -- the equal-error comparison of the learned corrector
+                  (Duffing field, eps = 1e-3, dt = 0.05, trained on 1e7
+                  samples, evaluated on 1e7 particles; see
+                  paper_1404_1160_amd/compare.py).
 """
 import argparse
 import hashlib
@@ -46,6 +50,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run an 800 MB device copy (for HBM counter scaling)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the plain-vs-learned equal-error comparison")
+    ap.add_argument("--learned-train", type=int, default=10_000_000)
+    ap.add_argument("--learned-eval", type=int, default=10_000_000)
     return ap.parse_args()
 
 
@@ -178,6 +186,12 @@ def main():
         "mesh_solve_ms": solve_ms / max(solve_count, 1),
         "moments": {k: mom[k] for k in ("t", "rms_radius", "energy", "n_offmesh", "n_nan")},
     }
+    if not args.no_learned:
+        from paper_1404_1160_amd import compare
+        print("bench: learned-vs-plain comparison", file=sys.stderr, flush=True)
+        line["learned_vs_plain"] = compare.equal_error(
+            n_train=args.learned_train, n_eval=args.learned_eval,
+            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cells, args.eps, args.dt, args.substeps,
                                             args.cpu_seconds)

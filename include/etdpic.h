@@ -172,6 +172,71 @@ ep_status ep_get_field(ep_ctx *ctx, double *rho, double *E, double *Psi, double 
 ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
                            uint32_t fallback_substeps);
 
+/* ---------------------------------------------------------------- learned
+ * Learned Duhamel corrector: a 5 -> 64 -> 64 -> 2 network (6 inputs for the
+ * Poisson field) with the activation z / sqrt(1 + z^2).  Features of a
+ * particle y = (R, V) for a step dt at eps:
+ *   (R / s_in, V / s_in, cos phi, sin phi, (dt/eps) / s_t [, E^n(R) / s_E]),
+ *   phi = (dt/eps) mod 2 pi.
+ * Its outputs o give the step's Duhamel term (eq. 3.6) in polar form around
+ * the exact rotation: delta = mu_d + sig_d o_0, kappa = mu_k + sig_k o_1 and
+ *   y_{n+1} = (1 + kappa) r(dt/eps + delta) y_n.
+ * Parameters: one FP32 vector W1[64][n_in], b1[64], W2[64][64], b2[64],
+ * W3[2][64], b3[2] (row-major; 4674 values for n_in = 5, 4738 for 6).
+ * Normalisation: 8 doubles {s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, 0}. */
+typedef struct {
+    double dt, eps;            /* step the corrector is trained for (> 0)            */
+    int32_t field;             /* EP_FIELD_DUFFING                                   */
+    uint32_t fine_substeps;    /* K of the plain push that makes the labels (>= 1)  */
+    uint32_t batch;            /* samples per Adam step, a multiple of 64            */
+    uint32_t epochs;           /* passes over the samples (>= 1)                     */
+    double lr, lr_final;       /* Adam step size, cosine-decayed from lr to lr_final */
+    double s_in;               /* feature scale of R and V (> 0)                     */
+} ep_train_cfg;
+
+typedef struct {
+    uint64_t steps;            /* Adam steps taken                                   */
+    double loss_first;         /* mean loss (normalised labels) of the first epoch   */
+    double loss_last;          /* mean loss of the last epoch                        */
+    double mu_delta, sig_delta, mu_kappa, sig_kappa;  /* label normalisation         */
+    double label_ms, train_ms; /* GPU time of label generation and of training       */
+} ep_train_report;
+
+/* Load network parameters (n_params = 4674 or 4738 FP32 values, layout above)
+ * and their normalisation (8 doubles).  Errors: EP_EINVAL. */
+ep_status ep_mlp_set_weights(ep_ctx *ctx, const float *params, uint32_t n_params,
+                             const double *norm);
+
+/* Copy the current parameters and normalisation out.  n_params must match.
+ * Errors: EP_EINVAL, EP_ENOTRAINED, EP_EHIP. */
+ep_status ep_mlp_get_weights(ep_ctx *ctx, float *params, uint32_t n_params, double *norm);
+
+/* Training labels: for n samples (R, V) (host FP64, rounded to FP32 like the
+ * features), one plain step of dt at eps with K fine substeps in the Duffing
+ * field, returned in polar form delta[n], kappa[n] (FP32): the phase advance
+ * beyond the free rotation and the relative change of |y|.
+ * Errors: EP_EINVAL, EP_EHIP. */
+ep_status ep_mlp_labels(ep_ctx *ctx, double dt, double eps, uint32_t fine_substeps,
+                        const double *R, const double *V, uint64_t n, float *delta,
+                        float *kappa);
+
+/* Gradient of the loss mean((o - (y - mu)/sig)^2) over a batch (X[batch][n_in]
+ * features, Y[batch][2] raw labels (delta, kappa); mu, sig from the current
+ * normalisation) at the current parameters, as computed by the training
+ * kernels (BF16 MFMA products, FP32 accumulation).  grad has n_params entries.
+ * Errors: EP_EINVAL, EP_ENOTRAINED, EP_EHIP. */
+ep_status ep_mlp_grad(ep_ctx *ctx, const float *X, const float *Y, uint32_t batch, float *grad,
+                      double *loss);
+
+/* Train the network on the GPU: labels of the n samples (R, V) are made with
+ * the plain push (cfg->fine_substeps), the normalisation of the labels is set
+ * from their mean and standard deviation, and Adam runs cfg->epochs passes in
+ * batches of cfg->batch in sample order, starting from the parameters loaded
+ * with ep_mlp_set_weights.  Errors: EP_EINVAL, EP_ENOTRAINED, EP_ENOMEM,
+ * EP_EHIP. */
+ep_status ep_mlp_train(ep_ctx *ctx, const ep_train_cfg *cfg, const double *R, const double *V,
+                       uint64_t n, ep_train_report *report);
+
 /* Synchronise the context's stream; reports asynchronous errors. */
 ep_status ep_sync(ep_ctx *ctx);
 

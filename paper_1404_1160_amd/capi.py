@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EHIP", -4:
 EXPORTS = (
     "ep_create", "ep_destroy", "ep_last_error", "ep_set_particles", "ep_bind_particles",
     "ep_step", "ep_moments_get", "ep_get_particles", "ep_get_field", "ep_set_push_mode",
-    "ep_sync", "ep_timing_enable", "ep_timing_get",
+    "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
+    "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train",
 )
 
 
@@ -52,6 +53,24 @@ class ep_moments(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ep_train_cfg(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("eps", ctypes.c_double), ("field", ctypes.c_int32),
+                ("fine_substeps", ctypes.c_uint32), ("batch", ctypes.c_uint32),
+                ("epochs", ctypes.c_uint32), ("lr", ctypes.c_double),
+                ("lr_final", ctypes.c_double), ("s_in", ctypes.c_double)]
+
+
+class ep_train_report(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("loss_first", ctypes.c_double),
+                ("loss_last", ctypes.c_double), ("mu_delta", ctypes.c_double),
+                ("sig_delta", ctypes.c_double), ("mu_kappa", ctypes.c_double),
+                ("sig_kappa", ctypes.c_double), ("label_ms", ctypes.c_double),
+                ("train_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -71,6 +90,7 @@ def lib():
         vp, d, u64, u32, i32 = (ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
                                 ctypes.c_uint32, ctypes.c_int32)
         pd = ctypes.POINTER(ctypes.c_double)
+        pf = ctypes.POINTER(ctypes.c_float)
         sigs = {
             "ep_create": ([ctypes.POINTER(ep_config), ctypes.POINTER(vp)], i32),
             "ep_destroy": ([vp], i32),
@@ -85,6 +105,12 @@ def lib():
             "ep_sync": ([vp], i32),
             "ep_timing_enable": ([vp, i32], i32),
             "ep_timing_get": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(u64)], i32),
+            "ep_mlp_set_weights": ([vp, pf, u32, pd], i32),
+            "ep_mlp_get_weights": ([vp, pf, u32, pd], i32),
+            "ep_mlp_labels": ([vp, d, d, u32, pd, pd, u64, pf, pf], i32),
+            "ep_mlp_grad": ([vp, pf, pf, u32, pf, pd], i32),
+            "ep_mlp_train": ([vp, ctypes.POINTER(ep_train_cfg), pd, pd, u64,
+                              ctypes.POINTER(ep_train_report)], i32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -106,6 +132,14 @@ def _f64(a):
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _pf(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
 
 def ep_create(n_particles, n_cells=256, substeps=1, r_max=5.0, deposit=EP_DEPOSIT_ATOMIC,
@@ -183,3 +217,48 @@ def ep_timing_get(ctx, kernel):
     cnt = ctypes.c_uint64(0)
     _check(ctx, lib().ep_timing_get(ctx, kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def ep_mlp_set_weights(ctx, params, norm):
+    params = _f32(params)
+    norm = _f64(norm)
+    if norm.size != 8:
+        raise ValueError("norm must hold 8 values")
+    _check(ctx, lib().ep_mlp_set_weights(ctx, _pf(params), params.size, _p(norm)))
+
+
+def ep_mlp_get_weights(ctx, n_params):
+    params = np.empty(n_params, dtype=np.float32)
+    norm = np.empty(8)
+    _check(ctx, lib().ep_mlp_get_weights(ctx, _pf(params), n_params, _p(norm)))
+    return params, norm
+
+
+def ep_mlp_labels(ctx, dt, eps, fine_substeps, R, V):
+    R = _f64(R)
+    V = _f64(V)
+    delta = np.empty(R.size, dtype=np.float32)
+    kappa = np.empty(R.size, dtype=np.float32)
+    _check(ctx, lib().ep_mlp_labels(ctx, float(dt), float(eps), int(fine_substeps), _p(R), _p(V),
+                                    R.size, _pf(delta), _pf(kappa)))
+    return delta, kappa
+
+
+def ep_mlp_grad(ctx, X, Y, n_params):
+    X = _f32(X)
+    Y = _f32(Y)
+    grad = np.empty(n_params, dtype=np.float32)
+    loss = ctypes.c_double(0.0)
+    _check(ctx, lib().ep_mlp_grad(ctx, _pf(X), _pf(Y), X.shape[0], _pf(grad), ctypes.byref(loss)))
+    return grad, loss.value
+
+
+def ep_mlp_train(ctx, R, V, dt, eps, fine_substeps, batch, epochs, lr, lr_final, s_in,
+                 field=EP_FIELD_DUFFING):
+    R = _f64(R)
+    V = _f64(V)
+    cfg = ep_train_cfg(dt, eps, field, fine_substeps, batch, epochs, lr, lr_final, s_in)
+    rep = ep_train_report()
+    _check(ctx, lib().ep_mlp_train(ctx, ctypes.byref(cfg), _p(R), _p(V), R.size,
+                                   ctypes.byref(rep)))
+    return rep.as_dict()

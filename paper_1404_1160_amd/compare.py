@@ -1,0 +1,132 @@
+"""Equal-error comparison of the plain push and the learned corrector.
+
+Workload (learned corrector on the Duffing field): eps = 1e-3, dt = 0.05,
+R, V ~ N(0, 1.5); the network (5 -> 64 -> 64 -> 2) is trained on the GPU on
+samples labelled by the plain push with K_fine substeps, then both forms push
+an evaluation beam for `steps` steps.  Error = the largest relative
+rms-radius error over the run (recorded every `every` steps) against a
+reference run of the plain push with K_ref substeps; the maximum over the run
+rather than the final value, because the signed final error of a single run
+can pass through zero by chance.  Throughput = particle-steps/s of the whole run (wall clock around
+synchronised GPU work, particles resident in HBM).  The equal-error point is
+the smallest plain K whose error does not exceed the learned form's.
+
+Everything here calls the HIP library through its C ABI.
+"""
+import time
+
+import numpy as np
+
+from . import EP_FIELD_DUFFING, EP_PUSH_LEARNED, EP_PUSH_PLAIN, Sim, capi, synth
+
+DT, EPS, SIGMA = 0.05, 1e-3, 1.5
+NORM_INIT = np.array([SIGMA, 100.0, 1.0, 0.0, 1.0, 0.0, 1.0, 0.0])
+
+
+def _timed_run(sim, steps):
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(DT, EPS, EP_FIELD_DUFFING, steps)
+    sim.sync()
+    return time.perf_counter() - t0
+
+
+def _rms_history(sim, R0, V0, w, steps, every):
+    sim.set_particles(R0, V0, w)
+    out = [sim.moments(EPS, EP_FIELD_DUFFING)["rms_radius"]]
+    for _ in range(steps // every):
+        sim.step(DT, EPS, EP_FIELD_DUFFING, every)
+        out.append(sim.moments(EPS, EP_FIELD_DUFFING)["rms_radius"])
+    return np.array(out)
+
+
+def train(sim, n_train, epochs, K_fine, seed=14, init_seed=5, batch=None, lr=3e-3,
+          lr_final=1e-5):
+    """Train from Glorot-initialised weights; the batch defaults to ~n/512
+    (64-aligned, between 1024 and 16384) so that small sets still take
+    enough Adam steps."""
+    if batch is None:
+        batch = max(1024, min(16384, (n_train // 512) // 64 * 64))
+    R, V, _ = synth.gaussian(n_train, seed=seed, sigma=SIGMA)
+    capi.ep_mlp_set_weights(sim.ctx, synth.mlp_init(5, 64, 2, seed=init_seed), NORM_INIT)
+    return capi.ep_mlp_train(sim.ctx, R, V, DT, EPS, K_fine, batch, epochs, lr, lr_final, SIGMA)
+
+
+def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=10, K_fine=800,
+                plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5, K_fb=100,
+                seed_eval=15, every=10, log=None):
+    """Returns a dict with the training report, the plain sweep, the learned
+    runs and the equal-error point."""
+    def say(msg):
+        if log:
+            log(msg)
+
+    Re, Ve, we = synth.gaussian(n_eval, seed=seed_eval, sigma=SIGMA)
+    out = {"workload": {"field": "duffing", "eps": EPS, "dt": DT, "sigma": SIGMA,
+                        "n_train": n_train, "n_eval": n_eval, "steps": steps, "K_fine": K_fine,
+                        "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb}}
+    with Sim(n_eval, substeps=K_ref) as ref:
+        hist_ref = _rms_history(ref, Re, Ve, we, steps, every)
+        Rr, Vr = ref.particles()
+    rms_ref = float(hist_ref[-1])
+    out["rms_ref"] = rms_ref
+    say("reference K=%d rms %.6f" % (K_ref, rms_ref))
+
+    def run_error(sim):
+        hist = _rms_history(sim, Re, Ve, we, steps, every)
+        R, V = sim.particles()
+        return (float(np.max(np.abs(hist - hist_ref) / hist_ref)),
+                float(np.median(np.hypot(R - Rr, V - Vr))))
+
+    plain = []
+    for K in plain_Ks:
+        with Sim(n_eval, substeps=K) as s:
+            s.set_particles(Re, Ve, we)
+            el = _timed_run(s, steps)
+            err, perr = run_error(s)
+        plain.append({"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
+                      "median_particle_err": perr})
+        say("plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, plain[-1]["particle_steps_per_s"], err))
+    out["plain"] = plain
+
+    with Sim(n_eval, substeps=1) as sim:
+        rep = train(sim, n_train, epochs, K_fine)
+        out["train"] = rep
+        say("trained: loss %.4f -> %.4f in %d steps (%.0f ms)" % (
+            rep["loss_first"], rep["loss_last"], rep["steps"], rep["train_ms"]))
+        learned = []
+        for t in (tol, float("inf")):
+            sim.set_particles(Re, Ve, we)
+            capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, 1e300 if t == float("inf") else t,
+                                  K_fb)
+            f0 = sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"]
+            capi.ep_timing_enable(sim.ctx, True)
+            el = _timed_run(sim, steps)
+            mlp_ms, _ = capi.ep_timing_get(sim.ctx, "mlp_push")
+            fb_ms, _ = capi.ep_timing_get(sim.ctx, "fallback_push")
+            f1 = sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"]
+            capi.ep_timing_enable(sim.ctx, False)
+            err, perr = run_error(sim)
+            learned.append({"drift_tol": None if t == float("inf") else t,
+                            "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
+                            "median_particle_err": perr,
+                            "fallback_rate": (f1 - f0) / (n_eval * steps),
+                            "network_particle_steps_per_s": n_eval * steps / (mlp_ms / 1e3),
+                            "fallback_ms": fb_ms})
+            say("learned tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
+                t, learned[-1]["particle_steps_per_s"], err, learned[-1]["fallback_rate"]))
+        capi.ep_set_push_mode(sim.ctx, EP_PUSH_PLAIN)
+    out["learned"] = learned
+
+    main = learned[0]
+    match = [p for p in plain if p["rms_err"] <= main["rms_err"]]
+    if match:
+        p = min(match, key=lambda q: q["K"])
+        out["equal_error"] = {"plain_K": p["K"], "plain_particle_steps_per_s": p["particle_steps_per_s"],
+                              "learned_particle_steps_per_s": main["particle_steps_per_s"],
+                              "gain": main["particle_steps_per_s"] / p["particle_steps_per_s"],
+                              "rms_err_learned": main["rms_err"], "rms_err_plain": p["rms_err"]}
+    else:
+        out["equal_error"] = {"plain_K": None, "gain": None,
+                              "note": "no plain K in the sweep reached the learned error"}
+    return out

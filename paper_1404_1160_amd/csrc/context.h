@@ -1,0 +1,194 @@
+// Context of the etdpic library: device buffers, clock, push mode and the
+// learned corrector's state; shared by the host runtime translation units.
+#pragma once
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/etdpic.h"
+#include "internal.h"
+
+namespace etd {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr uint32_t kMaxCells = 8192;
+constexpr size_t kTableEntries = size_t(1) << 20;   // substep coefficients per chunk
+constexpr size_t kStageParticles = size_t(1) << 23; // FP64 staging for host transfers
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+// Learned corrector state.
+struct Learned {
+    int n_in = 0;                    // 0: no network loaded
+    std::vector<float> params;       // FP32 master copy (host)
+    double norm[8] = {0};
+    float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
+    // inference constants for (dt, eps) = cached_dt, cached_eps
+    uint4 *d_w2hi = nullptr, *d_w2lo = nullptr;
+    float4 *d_l1 = nullptr;
+    float *d_b2 = nullptr, *d_w3 = nullptr;
+    bool packed = false;
+    double cached_dt = -1.0, cached_eps = -1.0;
+    MlpInfer infer{};
+    // fallback queue
+    unsigned *d_qcount = nullptr, *d_queue = nullptr;
+    unsigned long long *d_total = nullptr;
+    uint64_t queue_cap = 0;
+};
+
+}  // namespace etd
+
+using etd::Learned;
+using etd::MeshArgs;
+using etd::StepTables;
+
+struct ep_ctx {
+    etd::Learned mlp;
+    ep_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 0;
+    int push_grid_cap = 0;
+
+    // particle state (rotating frame, FP32 SoA)
+    float *zR = nullptr, *zV = nullptr;
+    float *own_zR = nullptr, *own_zV = nullptr;
+    uint64_t n = 0;
+    double w = 0.0;
+
+    // mesh
+    double hr = 0.0;
+    unsigned long long *hist = nullptr;
+    float2 *etab = nullptr;
+    double *rho64 = nullptr, *E64 = nullptr, *Psi64 = nullptr, *fscal = nullptr;
+    bool field_valid = false;
+
+    MeshArgs mesh() const
+    {
+        MeshArgs m;
+        m.nr = (int)cfg.n_cells;
+        m.w = w;
+        m.hr = hr;
+        m.hist = hist;
+        m.etab = etab;
+        m.rho64 = rho64;
+        m.E64 = E64;
+        m.Psi64 = Psi64;
+        m.fscal = fscal;
+        return m;
+    }
+
+    // per-chunk substep tables
+    StepTables tab{};
+    size_t tab_cap = 0;
+
+    // host transfers
+    double *stageR = nullptr, *stageV = nullptr;
+
+    // moments
+    int mom_grid_cap = 0;
+    double *mpartial = nullptr, *mout = nullptr;
+    unsigned long long *mcount = nullptr, *mout_count = nullptr;
+
+    // clock: t and the fast phase t/eps mod 2 pi, FP64
+    double t = 0.0, phase = 0.0;
+    uint64_t n_steps = 0;
+
+    // push mode
+    int push_mode = EP_PUSH_PLAIN;
+    double drift_tol = 1e-5;
+    uint32_t fallback_K = 0;
+
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::map<std::string, std::pair<double, uint64_t>> timed;
+
+    std::string err;
+
+    ep_status fail(ep_status code, const char *fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    ep_status hipfail(const char *what, hipError_t e)
+    {
+        return fail(EP_EHIP, "%s: %s", what, hipGetErrorString(e));
+    }
+};
+
+#define HIPCHK(ctx, expr)                                   \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return (ctx)->hipfail(#expr, e_); \
+    } while (0)
+
+namespace etd {
+
+// Timed launch bracket: records events around `launch` when timing is on.
+template <typename F>
+inline hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
+{
+    if (!c->timing) return launch();
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!c->event_pool.empty()) {
+        ev = c->event_pool.back();
+        c->event_pool.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev.first);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&ev.second);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(ev.first, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev.second, c->stream);
+    if (e != hipSuccess) return e;
+    c->pending.emplace_back(name, ev);
+    return hipSuccess;
+}
+
+hipError_t collect_timing(ep_ctx *c);
+ep_status ensure_tables(ep_ctx *c, size_t entries, size_t steps);
+ep_status refresh_field(ep_ctx *c);
+void free_learned(ep_ctx *c);
+// Learned push of n_steps steps (Duffing field); defined with the learned API.
+ep_status learned_steps(ep_ctx *c, double dt, double eps, uint64_t n_steps);
+
+}  // namespace etd

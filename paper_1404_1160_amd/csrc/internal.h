@@ -59,6 +59,49 @@ size_t push_lds_bytes_for(int nr);
 
 hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &ma);
 
+// ------------------------------------------------------------ learned corrector
+
+constexpr int kH = 64;    // hidden width
+constexpr int kOut = 2;   // outputs (delta, kappa)
+
+__host__ __device__ constexpr int mlp_n_params(int n_in)
+{
+    return kH * n_in + kH + kH * kH + kH + kOut * kH + kOut;
+}
+
+// Inference constants of a trained network for one (dt, eps).
+struct MlpInfer {
+    const uint4 *w2hi;   // [8 fragments][64 lanes] BF16 x 8: high parts of W2
+    const uint4 *w2lo;   //                                   low parts
+    const float4 *l1;    // [64] (w_R, w_V, w_E, b1'): layer 1 with the constant
+                         //      features folded into the bias
+    const float *b2;     // [64]
+    const float *w3;     // [2][64]
+    float b3_0, b3_1, mu_d, sig_d, mu_k, sig_k;
+};
+
+hipError_t launch_gen_labels_duffing(hipStream_t st, const float *R, const float *V, int64_t n,
+                                     const double4 *sub, int K, float inv_sin, float c_phi,
+                                     float s_phi, float th_scaled, float *X, float *Y);
+hipError_t setup_train_lds(int n_in);
+// Gradient of the MSE loss over samples [first, first + batch) (X: [.][n_in],
+// Y: [.][2] raw labels, norm = {mu_d, 1/sig_d, mu_k, 1/sig_k}).
+hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const float *X,
+                           const float *Y, int64_t first, int batch, const float norm[4],
+                           float *gpart, float *lpart, float *grad, float *loss);
+hipError_t launch_mlp_adam(hipStream_t st, float *p, float *m, float *v, const float *g, int np,
+                           float lr, float b1, float b2, float bc1, float bc2, float eps);
+// Learned Duffing step: network prediction, energy check |dH| <= tol |H|,
+// passing particles updated in place, failing ones appended to queue.
+hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
+                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
+                                   double tol, unsigned *qcount, unsigned *queue, int n_cu);
+// Plain K-substep Duffing push of the *qcount queued particles; adds the count
+// to *total.
+hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,
+                                   const unsigned *qcount, const double4 *sub, int K,
+                                   unsigned long long *total, int n_cu);
+
 hipError_t launch_moments(hipStream_t st, const float *zR, const float *zV, int64_t n,
                           double c, double s, double rmax, double *partial,
                           unsigned long long *pcount, int grid, double *out,

@@ -1,0 +1,427 @@
+// Host side of the learned Duhamel corrector: parameters, label generation,
+// training loop (Adam, cosine-decayed step size), inference constants and the
+// learned step with energy check and plain fallback.
+
+#include "context.h"
+
+using namespace etd;
+
+namespace {
+
+constexpr double kAdamB1 = 0.9, kAdamB2 = 0.999, kAdamEps = 1e-8;
+constexpr double kTimeScale = 100.0;   // s_t: feature scale of dt/eps
+constexpr uint32_t kNormSamples = 65536;
+
+uint16_t host_bf16(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float host_bf16_value(uint16_t b)
+{
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+struct Offsets {
+    int W1, b1, W2, b2, W3, b3, total;
+};
+
+Offsets offsets(int n_in)
+{
+    Offsets o;
+    o.W1 = 0;
+    o.b1 = kH * n_in;
+    o.W2 = o.b1 + kH;
+    o.b2 = o.W2 + kH * kH;
+    o.W3 = o.b2 + kH;
+    o.b3 = o.W3 + kOut * kH;
+    o.total = o.b3 + kOut;
+    return o;
+}
+
+ep_status ensure_mlp_buffers(ep_ctx *c, int n_in)
+{
+    Learned &L = c->mlp;
+    if (L.d_params && L.n_in == n_in) return EP_OK;
+    free_learned(c);
+    const size_t np = (size_t)mlp_n_params(n_in);
+    HIPCHK(c, dalloc(&L.d_params, np));
+    HIPCHK(c, dalloc(&L.d_m, np));
+    HIPCHK(c, dalloc(&L.d_v, np));
+    HIPCHK(c, dalloc(&L.d_grad, np));
+    HIPCHK(c, dalloc(&L.d_w2hi, (size_t)8 * 64));
+    HIPCHK(c, dalloc(&L.d_w2lo, (size_t)8 * 64));
+    HIPCHK(c, dalloc(&L.d_l1, (size_t)kH));
+    HIPCHK(c, dalloc(&L.d_b2, (size_t)kH));
+    HIPCHK(c, dalloc(&L.d_w3, (size_t)kOut * kH));
+    HIPCHK(c, dalloc(&L.d_qcount, (size_t)1));
+    HIPCHK(c, dalloc(&L.d_total, (size_t)1));
+    HIPCHK(c, hipMemsetAsync(L.d_total, 0, sizeof(unsigned long long), c->stream));
+    L.n_in = n_in;
+    return EP_OK;
+}
+
+// Inference constants for one (dt, eps): W2 as split-BF16 MFMA A-fragments
+// (fragment f = 4 mt + kk, lane l: W2[32 mt + l%32][16 kk + 8 (l/32) + e],
+// e = 0..7), layer 1 with the constant features folded into the bias.
+ep_status prepare_inference(ep_ctx *c, double dt, double eps)
+{
+    Learned &L = c->mlp;
+    if (L.packed && L.cached_dt == dt && L.cached_eps == eps) return EP_OK;
+    const Offsets o = offsets(L.n_in);
+    const float *P = L.params.data();
+    std::vector<uint16_t> hi((size_t)8 * 64 * 8), lo((size_t)8 * 64 * 8);
+    for (int mt = 0; mt < 2; ++mt)
+        for (int kk = 0; kk < 4; ++kk)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    const int i = mt * 32 + (lane & 31), k = kk * 16 + 8 * (lane >> 5) + e;
+                    const float w = P[o.W2 + i * kH + k];
+                    const uint16_t h = host_bf16(w);
+                    const size_t at = ((size_t)(mt * 4 + kk) * 64 + lane) * 8 + e;
+                    hi[at] = h;
+                    lo[at] = host_bf16(w - host_bf16_value(h));
+                }
+    const double s_in = L.norm[0], s_t = L.norm[1], s_E = L.norm[2];
+    const double th = dt / eps;
+    const double phi = fmod(th, kTwoPi);
+    std::vector<float4> l1(kH);
+    for (int u = 0; u < kH; ++u) {
+        const float *w = P + o.W1 + u * L.n_in;
+        const double b = (double)P[o.b1 + u] + (double)w[2] * cos(phi) + (double)w[3] * sin(phi) +
+                         (double)w[4] * th / s_t;
+        l1[u] = make_float4((float)(w[0] / s_in), (float)(w[1] / s_in),
+                            L.n_in == 6 ? (float)(w[5] / s_E) : 0.f, (float)b);
+    }
+    HIPCHK(c, hipMemcpy(L.d_w2hi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_w2lo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_l1, l1.data(), l1.size() * sizeof(float4), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_b2, P + o.b2, kH * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_w3, P + o.W3, kOut * kH * sizeof(float), hipMemcpyHostToDevice));
+    MlpInfer &I = L.infer;
+    I.w2hi = L.d_w2hi;
+    I.w2lo = L.d_w2lo;
+    I.l1 = L.d_l1;
+    I.b2 = L.d_b2;
+    I.w3 = L.d_w3;
+    I.b3_0 = P[o.b3];
+    I.b3_1 = P[o.b3 + 1];
+    I.mu_d = (float)L.norm[3];
+    I.sig_d = (float)L.norm[4];
+    I.mu_k = (float)L.norm[5];
+    I.sig_k = (float)L.norm[6];
+    L.packed = true;
+    L.cached_dt = dt;
+    L.cached_eps = eps;
+    return EP_OK;
+}
+
+ep_status ensure_queue(ep_ctx *c)
+{
+    Learned &L = c->mlp;
+    if (L.queue_cap >= c->n && L.d_queue) return EP_OK;
+    if (L.d_queue) (void)hipFree(L.d_queue);
+    L.d_queue = nullptr;
+    L.queue_cap = 0;
+    HIPCHK(c, dalloc(&L.d_queue, (size_t)c->n));
+    L.queue_cap = c->n;
+    return EP_OK;
+}
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+ep_status upload_fp32(ep_ctx *c, const double *src, uint64_t n, float *dst)
+{
+    std::vector<float> tmp(n);
+    for (uint64_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+    HIPCHK(c, hipMemcpy(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    return EP_OK;
+}
+
+// Features and raw labels of n samples into device arrays X[n][5], Y[n][2].
+ep_status make_labels(ep_ctx *c, double dt, double eps, uint32_t K, double s_in, const double *R,
+                      const double *V, uint64_t n, float *dX, float *dY)
+{
+    DevBuf<float> dR, dV;
+    HIPCHK(c, dalloc(&dR.p, (size_t)n));
+    HIPCHK(c, dalloc(&dV.p, (size_t)n));
+    ep_status s = upload_fp32(c, R, n, dR.p);
+    if (s != EP_OK) return s;
+    if ((s = upload_fp32(c, V, n, dV.p)) != EP_OK) return s;
+    if ((s = ensure_tables(c, K, 1)) != EP_OK) return s;
+    const double th = dt / eps;
+    HIPCHK(c, launch_phase_table(c->stream, c->tab, 0.0, fmod(th, kTwoPi), th / K, dt / K, (int)K, 1));
+    const double phi = fmod(th, kTwoPi);
+    HIPCHK(c, launch_gen_labels_duffing(c->stream, dR.p, dV.p, (int64_t)n, c->tab.sub, (int)K,
+                                        (float)(1.0 / s_in), (float)cos(phi), (float)sin(phi),
+                                        (float)(th / kTimeScale), dX, dY));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EP_OK;
+}
+
+}  // namespace
+
+namespace etd {
+
+void free_learned(ep_ctx *c)
+{
+    Learned &L = c->mlp;
+    for (void *p : {(void *)L.d_params, (void *)L.d_m, (void *)L.d_v, (void *)L.d_grad,
+                    (void *)L.d_w2hi, (void *)L.d_w2lo, (void *)L.d_l1, (void *)L.d_b2,
+                    (void *)L.d_w3, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total})
+        if (p) (void)hipFree(p);
+    L = Learned();
+}
+
+ep_status learned_steps(ep_ctx *c, double dt, double eps, uint64_t n_steps)
+{
+    Learned &L = c->mlp;
+    if (L.n_in != 5)
+        return c->fail(EP_ENOTRAINED, "ep_step: the learned push needs a 5-input network");
+    ep_status s = prepare_inference(c, dt, eps);
+    if (s != EP_OK) return s;
+    if ((s = ensure_queue(c)) != EP_OK) return s;
+    const int K = (int)c->fallback_K;
+    const double dphi = fmod(dt / eps, kTwoPi);
+    size_t chunk = kTableEntries / (size_t)K;
+    if (chunk < 1) chunk = 1;
+    if ((s = ensure_tables(c, chunk * (size_t)K, chunk)) != EP_OK) return s;
+    uint64_t done = 0;
+    while (done < n_steps) {
+        const uint64_t rem = n_steps - done;
+        const int S = (int)(rem < chunk ? rem : chunk);
+        HIPCHK(c, launch_phase_table(c->stream, c->tab, c->phase, dphi, dt / ((double)K * eps),
+                                     dt / K, K, S));
+        for (int j = 0; j < S; ++j) {
+            const double p0 = fmod(c->phase + (double)j * dphi, kTwoPi);
+            const double p1 = fmod(c->phase + (double)(j + 1) * dphi, kTwoPi);
+            HIPCHK(c, hipMemsetAsync(L.d_qcount, 0, sizeof(unsigned), c->stream));
+            HIPCHK(c, timed_launch(c, "mlp_push", [&] {
+                       return launch_mlp_push_duffing(
+                           c->stream, c->zR, c->zV, (int64_t)c->n, L.infer,
+                           make_double2(cos(p0), sin(p0)), make_double2(cos(p1), sin(p1)), eps,
+                           c->drift_tol, L.d_qcount, L.d_queue, c->n_cu);
+                   }));
+            HIPCHK(c, timed_launch(c, "fallback_push", [&] {
+                       return launch_fallback_duffing(c->stream, c->zR, c->zV, L.d_queue,
+                                                      L.d_qcount, c->tab.sub + (size_t)j * K, K,
+                                                      L.d_total, c->n_cu);
+                   }));
+        }
+        c->phase = fmod(c->phase + (double)S * dphi, kTwoPi);
+        c->t += (double)S * dt;
+        c->n_steps += (uint64_t)S;
+        done += (uint64_t)S;
+    }
+    c->field_valid = false;
+    return EP_OK;
+}
+
+}  // namespace etd
+
+extern "C" {
+
+ep_status ep_mlp_set_weights(ep_ctx *c, const float *params, uint32_t n_params, const double *norm)
+{
+    if (!c) return EP_EINVAL;
+    int n_in = 0;
+    if (n_params == (uint32_t)mlp_n_params(5)) n_in = 5;
+    if (n_params == (uint32_t)mlp_n_params(6)) n_in = 6;
+    if (!params || !norm || n_in == 0)
+        return c->fail(EP_EINVAL, "ep_mlp_set_weights: need %d (5 inputs) or %d (6 inputs) "
+                                  "parameters and 8 normalisation values",
+                       mlp_n_params(5), mlp_n_params(6));
+    if (!(norm[0] > 0.0) || !(norm[1] > 0.0) || !(norm[2] > 0.0))
+        return c->fail(EP_EINVAL, "ep_mlp_set_weights: feature scales must be positive");
+    DeviceGuard guard(c->device);
+    ep_status s = ensure_mlp_buffers(c, n_in);
+    if (s != EP_OK) return s;
+    Learned &L = c->mlp;
+    L.params.assign(params, params + n_params);
+    for (int i = 0; i < 8; ++i) L.norm[i] = norm[i];
+    HIPCHK(c, hipMemcpy(L.d_params, params, n_params * sizeof(float), hipMemcpyHostToDevice));
+    L.packed = false;
+    return EP_OK;
+}
+
+ep_status ep_mlp_get_weights(ep_ctx *c, float *params, uint32_t n_params, double *norm)
+{
+    if (!c) return EP_EINVAL;
+    if (c->mlp.n_in == 0) return c->fail(EP_ENOTRAINED, "ep_mlp_get_weights: no network loaded");
+    if (!params || !norm || n_params != (uint32_t)c->mlp.params.size())
+        return c->fail(EP_EINVAL, "ep_mlp_get_weights: n_params must be %zu",
+                       c->mlp.params.size());
+    memcpy(params, c->mlp.params.data(), n_params * sizeof(float));
+    for (int i = 0; i < 8; ++i) norm[i] = c->mlp.norm[i];
+    return EP_OK;
+}
+
+ep_status ep_mlp_labels(ep_ctx *c, double dt, double eps, uint32_t K, const double *R,
+                        const double *V, uint64_t n, float *delta, float *kappa)
+{
+    if (!c) return EP_EINVAL;
+    if (!(dt > 0.0) || !(eps > 0.0) || K == 0 || (n > 0 && (!R || !V || !delta || !kappa)))
+        return c->fail(EP_EINVAL, "ep_mlp_labels: need dt > 0, eps > 0, K >= 1");
+    if (n == 0) return EP_OK;
+    DeviceGuard guard(c->device);
+    DevBuf<float> dX, dY;
+    HIPCHK(c, dalloc(&dX.p, (size_t)n * 5));
+    HIPCHK(c, dalloc(&dY.p, (size_t)n * 2));
+    ep_status s = make_labels(c, dt, eps, K, 1.0, R, V, n, dX.p, dY.p);
+    if (s != EP_OK) return s;
+    std::vector<float> Y((size_t)n * 2);
+    HIPCHK(c, hipMemcpy(Y.data(), dY.p, Y.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) {
+        delta[i] = Y[2 * i];
+        kappa[i] = Y[2 * i + 1];
+    }
+    return EP_OK;
+}
+
+ep_status ep_mlp_grad(ep_ctx *c, const float *X, const float *Y, uint32_t batch, float *grad,
+                      double *loss)
+{
+    if (!c) return EP_EINVAL;
+    Learned &L = c->mlp;
+    if (L.n_in == 0) return c->fail(EP_ENOTRAINED, "ep_mlp_grad: no network loaded");
+    if (!X || !Y || !grad || batch == 0)
+        return c->fail(EP_EINVAL, "ep_mlp_grad: need a batch >= 1 and output arrays");
+    DeviceGuard guard(c->device);
+    const int np = mlp_n_params(L.n_in);
+    const int tiles = (int)((batch + 63) / 64);
+    DevBuf<float> dX, dY, gpart, lpart, dloss;
+    HIPCHK(c, dalloc(&dX.p, (size_t)batch * L.n_in));
+    HIPCHK(c, dalloc(&dY.p, (size_t)batch * 2));
+    HIPCHK(c, dalloc(&gpart.p, (size_t)tiles * np));
+    HIPCHK(c, dalloc(&lpart.p, (size_t)tiles));
+    HIPCHK(c, dalloc(&dloss.p, (size_t)1));
+    HIPCHK(c, hipMemcpy(dX.p, X, (size_t)batch * L.n_in * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(dY.p, Y, (size_t)batch * 2 * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, setup_train_lds(L.n_in));
+    const float nf[4] = {(float)L.norm[3], (float)(1.0 / L.norm[4]), (float)L.norm[5],
+                         (float)(1.0 / L.norm[6])};
+    HIPCHK(c, launch_mlp_grad(c->stream, L.n_in, L.d_params, dX.p, dY.p, 0, (int)batch, nf,
+                              gpart.p, lpart.p, L.d_grad, dloss.p));
+    float lo = 0.f;
+    HIPCHK(c, hipMemcpyAsync(grad, L.d_grad, (size_t)np * sizeof(float), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(&lo, dloss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (loss) *loss = lo;
+    return EP_OK;
+}
+
+ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, const double *V,
+                       uint64_t n, ep_train_report *rep)
+{
+    if (!c) return EP_EINVAL;
+    Learned &L = c->mlp;
+    if (L.n_in == 0)
+        return c->fail(EP_ENOTRAINED, "ep_mlp_train: load initial weights first");
+    if (!cfg || !R || !V || !rep || cfg->field != EP_FIELD_DUFFING || L.n_in != 5 ||
+        !(cfg->dt > 0.0) || !(cfg->eps > 0.0) || cfg->fine_substeps == 0 || cfg->batch == 0 ||
+        cfg->batch % 64 || cfg->batch > n || cfg->epochs == 0 || !(cfg->lr > 0.0) ||
+        !(cfg->lr_final >= 0.0) || !(cfg->s_in > 0.0))
+        return c->fail(EP_EINVAL, "ep_mlp_train: invalid configuration (Duffing field, 5-input "
+                                  "network, batch a multiple of 64 and <= n, positive rates)");
+    DeviceGuard guard(c->device);
+    const int np = mlp_n_params(5);
+    DevBuf<float> dX, dY, gpart, lpart, dloss;
+    HIPCHK(c, dalloc(&dX.p, (size_t)n * 5));
+    HIPCHK(c, dalloc(&dY.p, (size_t)n * 2));
+    hipEvent_t e0, e1, e2;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventCreate(&e2));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    ep_status s = make_labels(c, cfg->dt, cfg->eps, cfg->fine_substeps, cfg->s_in, R, V, n, dX.p,
+                              dY.p);
+    if (s != EP_OK) return s;
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+
+    // normalisation of the labels from their first samples
+    const uint64_t ns = n < kNormSamples ? n : kNormSamples;
+    std::vector<float> Yh((size_t)ns * 2);
+    HIPCHK(c, hipMemcpy(Yh.data(), dY.p, Yh.size() * sizeof(float), hipMemcpyDeviceToHost));
+    double m[2] = {0, 0}, q[2] = {0, 0};
+    for (uint64_t i = 0; i < ns; ++i)
+        for (int j = 0; j < 2; ++j) m[j] += Yh[2 * i + j];
+    for (int j = 0; j < 2; ++j) m[j] /= (double)ns;
+    for (uint64_t i = 0; i < ns; ++i)
+        for (int j = 0; j < 2; ++j) q[j] += (Yh[2 * i + j] - m[j]) * (Yh[2 * i + j] - m[j]);
+    double sd[2];
+    for (int j = 0; j < 2; ++j) {
+        sd[j] = sqrt(q[j] / (double)ns);
+        if (!(sd[j] > 0.0)) sd[j] = 1.0;
+    }
+    const double norm[8] = {cfg->s_in, kTimeScale, 1.0, m[0], sd[0], m[1], sd[1], 0.0};
+    for (int i = 0; i < 8; ++i) L.norm[i] = norm[i];
+    const float nf[4] = {(float)m[0], (float)(1.0 / sd[0]), (float)m[1], (float)(1.0 / sd[1])};
+
+    const int batch = (int)cfg->batch;
+    const int tiles = batch / 64;
+    const uint64_t per_epoch = n / (uint64_t)batch;
+    const uint64_t T = per_epoch * cfg->epochs;
+    HIPCHK(c, dalloc(&gpart.p, (size_t)tiles * np));
+    HIPCHK(c, dalloc(&lpart.p, (size_t)tiles));
+    HIPCHK(c, dalloc(&dloss.p, (size_t)T));
+    HIPCHK(c, hipMemsetAsync(L.d_m, 0, np * sizeof(float), c->stream));
+    HIPCHK(c, hipMemsetAsync(L.d_v, 0, np * sizeof(float), c->stream));
+    HIPCHK(c, setup_train_lds(5));
+    for (uint64_t t = 0; t < T; ++t) {
+        const uint64_t b = t % per_epoch;
+        const double lr = cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) *
+                                              (1.0 + cos(3.141592653589793 * (double)t / (double)T));
+        HIPCHK(c, launch_mlp_grad(c->stream, 5, L.d_params, dX.p, dY.p, (int64_t)(b * batch), batch,
+                                  nf, gpart.p, lpart.p, L.d_grad, dloss.p + t));
+        const double bc1 = 1.0 / (1.0 - pow(kAdamB1, (double)(t + 1)));
+        const double bc2 = 1.0 / (1.0 - pow(kAdamB2, (double)(t + 1)));
+        HIPCHK(c, launch_mlp_adam(c->stream, L.d_params, L.d_m, L.d_v, L.d_grad, np, (float)lr,
+                                  (float)kAdamB1, (float)kAdamB2, (float)bc1, (float)bc2,
+                                  (float)kAdamEps));
+    }
+    HIPCHK(c, hipEventRecord(e2, c->stream));
+    std::vector<float> losses((size_t)T);
+    HIPCHK(c, hipMemcpyAsync(losses.data(), dloss.p, T * sizeof(float), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(L.params.data(), L.d_params, np * sizeof(float),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float ms_label = 0.f, ms_train = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms_label, e0, e1));
+    HIPCHK(c, hipEventElapsedTime(&ms_train, e1, e2));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    double lf = 0.0, ll = 0.0;
+    for (uint64_t t = 0; t < per_epoch; ++t) {
+        lf += losses[t];
+        ll += losses[T - per_epoch + t];
+    }
+    rep->steps = T;
+    rep->loss_first = lf / (double)per_epoch;
+    rep->loss_last = ll / (double)per_epoch;
+    rep->mu_delta = m[0];
+    rep->sig_delta = sd[0];
+    rep->mu_kappa = m[1];
+    rep->sig_kappa = sd[1];
+    rep->label_ms = ms_label;
+    rep->train_ms = ms_train;
+    L.packed = false;
+    return EP_OK;
+}
+
+}  // extern "C"

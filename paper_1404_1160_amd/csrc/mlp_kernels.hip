@@ -1,0 +1,534 @@
+// HIP kernels of the learned Duhamel corrector (gfx950).
+//
+// Network 5 (or 6) -> 64 -> 64 -> 2 with the inverse-square-root unit
+// act(z) = z / sqrt(1 + z^2).  Its two outputs give the per-step Duhamel term
+// of eq. 3.6 in polar form around the exact rotation: a phase advance delta
+// and a relative amplitude change kappa, y_{n+1} = (1 + kappa) r(dt/eps + delta)
+// y_n.  In the rotating frame z = r(-t/eps) y this is z_{n+1} = (1 + kappa)
+// r(delta) z_n.
+//
+//   gen_labels_duffing_kernel  training pairs: the plain push with K_fine
+//                              substeps (FP64 in registers) gives the labels
+//   mlp_train_kernel           forward + backward of a 64-sample tile; the
+//                              three 64x64x64 products run on BF16 MFMA with
+//                              FP32 accumulation (forward split into hi/lo
+//                              BF16 halves, three MFMAs, for ~16-bit operands)
+//   mlp_grad_reduce_kernel     per-tile gradients summed in tile order
+//   mlp_adam_kernel            Adam on the FP32 master weights
+//   mlp_push_duffing_kernel    inference, 32 particles per wave, W2 fragments
+//                              resident in registers, FP64 energy check,
+//                              failing particles appended to a queue
+//   fallback_duffing_kernel    plain push of the queued particles
+
+#include "internal.h"
+
+namespace etd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ------------------------------------------------------------ helpers
+
+__device__ __forceinline__ float act(float z) { return z * __frsqrt_rn(fmaf(z, z, 1.f)); }
+
+// act'(z) from h = act(z): (1 - h^2)^(3/2)
+__device__ __forceinline__ float act_grad_h(float h)
+{
+    const float t = fmaf(-h, h, 1.f);
+    return t * __fsqrt_rn(t);
+}
+
+// FP32 -> BF16 bits, round to nearest even.
+__device__ __forceinline__ unsigned short bf16_bits(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_value(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const unsigned short (&b)[8])
+{
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, b[e]);
+    return v;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 q) { return __builtin_bit_cast(bf16x8, q); }
+
+// Wave-level 32x32 tile of a 64x64x64 product from FP32 LDS operands:
+//   acc(i, j) += sum_k A(i0 + i, k) B(k, j0 + j),
+//   A(i, k) = A[i*ai + k*ak],  B(k, j) = B[k*bk + j*bj].
+// MFMA 32x32x16 operand layout: lane l holds rows/cols (l % 32) and the 8
+// consecutive k of group (l / 32) of each 16-wide k step; result element q of
+// lane l is (i = 8 (q/4) + 4 (l/32) + q%4, j = l % 32).
+template <bool SPLIT>
+__device__ void mma64_wave(const float *A, int ai, int ak, const float *B, int bk, int bj, int i0,
+                           int j0, f32x16 &acc)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 31, g = lane >> 5;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        unsigned short ah[8], al[8], bh[8], bl[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = kk * 16 + g * 8 + e;
+            const float a = A[(i0 + r) * ai + k * ak];
+            const float b = B[k * bk + (j0 + r) * bj];
+            ah[e] = bf16_bits(a);
+            bh[e] = bf16_bits(b);
+            if (SPLIT) {
+                al[e] = bf16_bits(a - bf16_value(ah[e]));
+                bl[e] = bf16_bits(b - bf16_value(bh[e]));
+            }
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah), as_bf16x8(bh), acc, 0, 0, 0);
+        if (SPLIT) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah), as_bf16x8(bl), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al), as_bf16x8(bh), acc, 0, 0, 0);
+        }
+    }
+}
+
+__device__ __forceinline__ int tile_row(int q, int g) { return 8 * (q >> 2) + 4 * g + (q & 3); }
+
+// ------------------------------------------------------------ labels
+
+// Training pairs for the Duffing field.  Each sample y = (R, V) is pushed one
+// step with the plain scheme (K_fine substeps, FP64) from phase 0; the labels
+// are the polar form of the step: delta = angle from z_n to z_fine in the
+// direction r advances, kappa = |z_fine| / |z_n| - 1.  Features x = (R/s_in,
+// V/s_in, cos phi, sin phi, (dt/eps)/s_t).
+__global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
+    const float *__restrict__ Rs, const float *__restrict__ Vs, int64_t n,
+    const double4 *__restrict__ sub, int K, float inv_sin, float c_phi, float s_phi,
+    float th_scaled, float *__restrict__ X, float *__restrict__ Y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float R = Rs[i], V = Vs[i];
+    const double zr0 = R, zv0 = V;
+    double zr = zr0, zv = zv0, ar = 0.0, av = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double4 q = sub[k];
+        const double Rm = fma(q.x, zr + ar, q.y * (zv + av));
+        const double E = -(Rm * Rm) * Rm;
+        ar = fma(-q.z, E, ar);
+        av = fma(q.w, E, av);
+    }
+    zr += ar;
+    zv += av;
+    const double n0 = sqrt(zr0 * zr0 + zv0 * zv0);
+    double delta = 0.0, kappa = 0.0;
+    if (n0 > 0.0) {
+        delta = atan2(zr * zv0 - zv * zr0, zr * zr0 + zv * zv0);
+        kappa = sqrt(zr * zr + zv * zv) / n0 - 1.0;
+    }
+    float *x = X + i * 5;
+    x[0] = R * inv_sin;
+    x[1] = V * inv_sin;
+    x[2] = c_phi;
+    x[3] = s_phi;
+    x[4] = th_scaled;
+    Y[i * 2] = (float)delta;
+    Y[i * 2 + 1] = (float)kappa;
+}
+
+hipError_t launch_gen_labels_duffing(hipStream_t st, const float *R, const float *V, int64_t n,
+                                     const double4 *sub, int K, float inv_sin, float c_phi,
+                                     float s_phi, float th_scaled, float *X, float *Y)
+{
+    if (n <= 0) return hipSuccess;
+    gen_labels_duffing_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
+        R, V, n, sub, K, inv_sin, c_phi, s_phi, th_scaled, X, Y);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ training
+
+constexpr int kTile = 64;   // samples per training workgroup
+constexpr int kLd = kH + 1; // LDS row stride of the 64x64 matrices (no bank conflicts)
+
+static size_t train_lds_floats(int n_in)
+{
+    return (size_t)mlp_n_params(n_in) + kTile * n_in + kTile * 2 + 5 * kTile * kLd + kTile * 2;
+}
+
+// Forward and backward of the MSE loss over one tile of 64 samples
+// (first + tile*64 ...), samples at or beyond `batch` masked out.  Labels are
+// normalised on load, Yn = (Y - mu) * inv_sig.  Writes this tile's gradient
+// (flat parameter order) to gpart[tile] and its sum of squared errors to
+// lpart[tile]; the loss is the mean over the batch and both outputs.
+template <int NIN>
+__global__ __launch_bounds__(256) void mlp_train_kernel(
+    const float *__restrict__ params, const float *__restrict__ X, const float *__restrict__ Y,
+    int64_t first, int batch, float mu_d, float is_d, float mu_k, float is_k,
+    float *__restrict__ gpart, float *__restrict__ lpart)
+{
+    constexpr int NP = kH * NIN + kH + kH * kH + kH + kOut * kH + kOut;
+    constexpr int oW1 = 0, ob1 = kH * NIN, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+                  ob3 = oW3 + kOut * kH;
+    extern __shared__ __align__(16) float sm[];
+    float *sP = sm;                     // parameters (flat)
+    float *sX = sP + NP;                // [64][NIN]
+    float *sY = sX + kTile * NIN;       // [64][2]
+    float *sW2 = sY + kTile * 2;        // [64][kLd] padded copy of W2[u][k]
+    float *sH1 = sW2 + kH * kLd;        // [64 samples][kLd]
+    float *sH2 = sH1 + kTile * kLd;
+    float *sG = sH2 + kTile * kLd;      // dZ2
+    float *sD = sG + kTile * kLd;       // dZ1
+    float *sdO = sD + kTile * kLd;      // [64][2]
+
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, r = lane & 31, g = lane >> 5;
+    const int s_base = blockIdx.x * kTile;
+    float *gp = gpart + (size_t)blockIdx.x * NP;
+
+    for (int i = tid; i < NP; i += nt) sP[i] = params[i];
+    for (int i = tid; i < kH * kH; i += nt) sW2[(i >> 6) * kLd + (i & 63)] = params[oW2 + i];
+    for (int i = tid; i < kTile * NIN; i += nt) {
+        const int s = i / NIN;
+        sX[i] = (s_base + s < batch) ? X[(first + s_base) * NIN + i] : 0.f;
+    }
+    for (int i = tid; i < kTile * 2; i += nt) {
+        const int s = i >> 1;
+        const float y = (s_base + s < batch) ? Y[(first + s_base) * 2 + i] : 0.f;
+        sY[i] = (i & 1) ? (y - mu_k) * is_k : (y - mu_d) * is_d;
+    }
+    __syncthreads();
+
+    // layer 1 (VALU): H1[s][u] = act(b1[u] + sum_f W1[u][f] X[s][f])
+    for (int i = tid; i < kTile * kH; i += nt) {
+        const int s = i >> 6, u = i & 63;
+        float z = sP[ob1 + u];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) z = fmaf(sP[oW1 + u * NIN + f], sX[s * NIN + f], z);
+        sH1[s * kLd + u] = act(z);
+    }
+    __syncthreads();
+
+    // layer 2 (MFMA, split BF16): Z2[s][u] = sum_k H1[s][k] W2[u][k]
+    const int i0 = (wave >> 1) * 32, j0 = (wave & 1) * 32;
+    {
+        f32x16 acc = {};
+        mma64_wave<true>(sH1, kLd, 1, sW2, 1, kLd, i0, j0, acc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int s = i0 + tile_row(q, g), u = j0 + r;
+            sH2[s * kLd + u] = act(acc[q] + sP[ob2 + u]);
+        }
+    }
+    __syncthreads();
+
+    // layer 3 (VALU), loss and dO = d loss / d O
+    if (tid < kTile * 2) {
+        const int s = tid >> 1, m = tid & 1;
+        float o = sP[ob3 + m];
+        for (int u = 0; u < kH; ++u) o = fmaf(sP[oW3 + m * kH + u], sH2[s * kLd + u], o);
+        const bool valid = s_base + s < batch;
+        const float d = valid ? o - sY[tid] : 0.f;
+        sdO[tid] = 2.f * d / (float)(batch * 2);
+        sY[tid] = d * d;   // reused: squared error
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float l = 0.f;
+        for (int i = 0; i < kTile * 2; ++i) l += sY[i];
+        lpart[blockIdx.x] = l;
+    }
+    // dW3, db3
+    if (tid < kOut * kH) {
+        const int m = tid >> 6, u = tid & 63;
+        float a = 0.f;
+        for (int s = 0; s < kTile; ++s) a = fmaf(sdO[s * 2 + m], sH2[s * kLd + u], a);
+        gp[oW3 + tid] = a;
+    }
+    if (tid < kOut) {
+        float a = 0.f;
+        for (int s = 0; s < kTile; ++s) a += sdO[s * 2 + tid];
+        gp[ob3 + tid] = a;
+    }
+    // G = dZ2 = (dO W3) * act'(Z2)
+    for (int i = tid; i < kTile * kH; i += nt) {
+        const int s = i >> 6, u = i & 63;
+        const float d = fmaf(sdO[s * 2], sP[oW3 + u], sdO[s * 2 + 1] * sP[oW3 + kH + u]);
+        sG[s * kLd + u] = d * act_grad_h(sH2[s * kLd + u]);
+    }
+    __syncthreads();
+
+    // dW2[u][k] = sum_s G[s][u] H1[s][k]   (MFMA)
+    {
+        f32x16 acc = {};
+        mma64_wave<false>(sG, 1, kLd, sH1, kLd, 1, i0, j0, acc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) gp[oW2 + (i0 + tile_row(q, g)) * kH + j0 + r] = acc[q];
+    }
+    if (tid < kH) {
+        float a = 0.f;
+        for (int s = 0; s < kTile; ++s) a += sG[s * kLd + tid];
+        gp[ob2 + tid] = a;
+    }
+    // dH1[s][k] = sum_u G[s][u] W2[u][k]   (MFMA), D = dZ1 = dH1 * act'(Z1)
+    {
+        f32x16 acc = {};
+        mma64_wave<false>(sG, kLd, 1, sW2, kLd, 1, i0, j0, acc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int s = i0 + tile_row(q, g), k = j0 + r;
+            sD[s * kLd + k] = acc[q] * act_grad_h(sH1[s * kLd + k]);
+        }
+    }
+    __syncthreads();
+    // dW1, db1
+    for (int i = tid; i < kH * NIN; i += nt) {
+        const int u = i / NIN, f = i - u * NIN;
+        float a = 0.f;
+        for (int s = 0; s < kTile; ++s) a = fmaf(sD[s * kLd + u], sX[s * NIN + f], a);
+        gp[oW1 + i] = a;
+    }
+    if (tid < kH) {
+        float a = 0.f;
+        for (int s = 0; s < kTile; ++s) a += sD[s * kLd + tid];
+        gp[ob1 + tid] = a;
+    }
+}
+
+// grad[p] = sum over tiles in tile order; loss = sum of lpart / (batch * 2).
+__global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(const float *__restrict__ gpart,
+                                                              const float *__restrict__ lpart,
+                                                              int tiles, int np, int batch,
+                                                              float *__restrict__ grad,
+                                                              float *__restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < np) {
+        float a = 0.f;
+        for (int t = 0; t < tiles; ++t) a += gpart[(size_t)t * np + p];
+        grad[p] = a;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double l = 0.0;
+        for (int t = 0; t < tiles; ++t) l += lpart[t];
+        *loss = (float)(l / (double)(batch * 2));
+    }
+}
+
+// Adam (Kingma & Ba) with bias corrections bc1 = 1/(1 - b1^t), bc2 = 1/(1 - b2^t).
+__global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ p,
+                                                       float *__restrict__ m,
+                                                       float *__restrict__ v,
+                                                       const float *__restrict__ g, int np,
+                                                       float lr, float b1, float b2, float bc1,
+                                                       float bc2, float eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * bc1) / (__fsqrt_rn(vi * bc2) + eps);
+}
+
+hipError_t setup_train_lds(int n_in)
+{
+    const int lds = (int)(train_lds_floats(n_in) * sizeof(float));
+    if (n_in == 5)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_train_kernel<5>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_train_kernel<6>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const float *X,
+                           const float *Y, int64_t first, int batch, const float norm[4],
+                           float *gpart, float *lpart, float *grad, float *loss)
+{
+    const int tiles = (batch + kTile - 1) / kTile;
+    const size_t lds = train_lds_floats(n_in) * sizeof(float);
+    if (n_in == 5)
+        mlp_train_kernel<5><<<dim3(tiles), dim3(256), lds, st>>>(
+            params, X, Y, first, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
+    else
+        mlp_train_kernel<6><<<dim3(tiles), dim3(256), lds, st>>>(
+            params, X, Y, first, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int np = mlp_n_params(n_in);
+    mlp_grad_reduce_kernel<<<dim3((np + 255) / 256), dim3(256), 0, st>>>(gpart, lpart, tiles, np,
+                                                                       batch, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(hipStream_t st, float *p, float *m, float *v, const float *g, int np,
+                           float lr, float b1, float b2, float bc1, float bc2, float eps)
+{
+    mlp_adam_kernel<<<dim3((np + 255) / 256), dim3(256), 0, st>>>(p, m, v, g, np, lr, b1, b2, bc1,
+                                                                  bc2, eps);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ inference
+
+// One learned step of the Duffing beam.  A workgroup of 4 waves takes 128
+// particles per iteration, 32 per wave; lanes l and l+32 share particle l%32
+// and split its hidden units.  Layers 1 and 3 run on VALU (FP32), layer 2 on
+// MFMA with split BF16 operands, one 16-wide k step at a time so that few
+// activations are live.  All weights stay in LDS and are read where used.
+// The update and the energy check H = |z|^2/(2 eps) + R^4/4 run in FP64;
+// particles that fail keep their state and are appended to the fallback
+// queue with one global atomic per workgroup iteration.
+__global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
+    float *__restrict__ zR, float *__restrict__ zV, int64_t n, MlpInfer net, double2 rot0,
+    double2 rot1, double inv2eps, double tol, unsigned *__restrict__ qcount,
+    unsigned *__restrict__ queue)
+{
+    __shared__ uint4 sAh[8 * 64], sAl[8 * 64];
+    __shared__ float4 sl1[kH];
+    __shared__ float sb2[kH];
+    __shared__ float sw3[kOut * kH];
+    __shared__ unsigned s_cnt[4], s_base;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 8 * 64; i += blockDim.x) {
+        sAh[i] = net.w2hi[i];
+        sAl[i] = net.w2lo[i];
+    }
+    if (tid < kH) {
+        sl1[tid] = net.l1[tid];
+        sb2[tid] = net.b2[tid];
+    }
+    if (tid < kOut * kH) sw3[tid] = net.w3[tid];
+    const int lane = tid & 63, wave = tid >> 6, r = lane & 31, g = lane >> 5;
+    __syncthreads();
+
+    const int64_t nbg = (n + 127) >> 7;
+    for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
+        // keep the LDS reads below inside the loop (no hoisting into registers)
+        asm volatile("" ::: "memory");
+        const int64_t p = bg * 128 + wave * 32 + r;
+        const bool valid = p < n;
+        const double zr = valid ? (double)zR[p] : 0.0;
+        const double zv = valid ? (double)zV[p] : 0.0;
+        const double R = fma(rot0.x, zr, rot0.y * zv);
+        const double Vl = fma(-rot0.y, zr, rot0.x * zv);
+        const float x0 = (float)R, x1 = (float)Vl;
+
+        f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            unsigned short h[8], l[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float4 w = sl1[kk * 16 + g * 8 + e];
+                const float a = act(fmaf(w.x, x0, fmaf(w.y, x1, w.w)));
+                h[e] = bf16_bits(a);
+                l[e] = bf16_bits(a - bf16_value(h[e]));
+            }
+            const bf16x8 bh = as_bf16x8(h), bl = as_bf16x8(l);
+            const bf16x8 Ah0 = as_bf16x8(sAh[kk * 64 + lane]), Al0 = as_bf16x8(sAl[kk * 64 + lane]);
+            const bf16x8 Ah1 = as_bf16x8(sAh[(4 + kk) * 64 + lane]);
+            const bf16x8 Al1 = as_bf16x8(sAl[(4 + kk) * 64 + lane]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah0, bh, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah1, bh, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah0, bl, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah1, bl, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al0, bh, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al1, bh, acc1, 0, 0, 0);
+        }
+        float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int u0 = tile_row(q, g), u1 = 32 + tile_row(q, g);
+            const float h0 = act(acc0[q] + sb2[u0]);
+            const float h1 = act(acc1[q] + sb2[u1]);
+            o0 = fmaf(sw3[u0], h0, o0);
+            o1 = fmaf(sw3[kH + u0], h0, o1);
+            o0 = fmaf(sw3[u1], h1, o0);
+            o1 = fmaf(sw3[kH + u1], h1, o1);
+        }
+        o0 += __shfl_xor(o0, 32, 64);
+        o1 += __shfl_xor(o1, 32, 64);
+        const float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);
+        const float kappa = fmaf(net.sig_k, o1 + net.b3_1, net.mu_k);
+        float sd, cd;
+        sincosf(delta, &sd, &cd);
+        const double sc = 1.0 + (double)kappa;
+        const double nr = sc * fma((double)cd, zr, (double)sd * zv);
+        const double nv = sc * fma(-(double)sd, zr, (double)cd * zv);
+        const double H0 = (zr * zr + zv * zv) * inv2eps + 0.25 * (R * R) * (R * R);
+        const double R1 = fma(rot1.x, nr, rot1.y * nv);
+        const double H1 = (nr * nr + nv * nv) * inv2eps + 0.25 * (R1 * R1) * (R1 * R1);
+        const bool ok = fabs(H1 - H0) <= tol * fabs(H0);
+        const bool mine = valid && g == 0;
+        if (mine && ok) {
+            zR[p] = (float)nr;
+            zV[p] = (float)nv;
+        }
+        // fallback queue: wave ballots, workgroup prefix, one global atomic
+        const unsigned long long fail = __ballot(mine && !ok);
+        if (lane == 0) s_cnt[wave] = (unsigned)__popcll(fail);
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+            s_base = tot ? atomicAdd(qcount, tot) : 0u;
+        }
+        __syncthreads();
+        if (mine && !ok) {
+            unsigned slot = s_base + (unsigned)__popcll(fail & ((1ull << lane) - 1ull));
+            for (int w = 0; w < wave; ++w) slot += s_cnt[w];
+            queue[slot] = (unsigned)p;
+        }
+        __syncthreads();
+    }
+}
+
+// Plain push (K substeps, FP64) of the queued particles.
+__global__ __launch_bounds__(256) void fallback_duffing_kernel(
+    float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
+    const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K,
+    unsigned long long *__restrict__ total)
+{
+    const unsigned count = *qcount;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total += count;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += gridDim.x * blockDim.x) {
+        const unsigned p = queue[i];
+        double zr = zR[p], zv = zV[p], ar = 0.0, av = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double4 q = sub[k];
+            const double Rm = fma(q.x, zr + ar, q.y * (zv + av));
+            const double E = -(Rm * Rm) * Rm;
+            ar = fma(-q.z, E, ar);
+            av = fma(q.w, E, av);
+        }
+        zR[p] = (float)(zr + ar);
+        zV[p] = (float)(zv + av);
+    }
+}
+
+hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
+                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
+                                   double tol, unsigned *qcount, unsigned *queue, int n_cu)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t grid = (n + 127) / 128;
+    if (grid > (int64_t)n_cu * 8) grid = (int64_t)n_cu * 8;
+    mlp_push_duffing_kernel<<<dim3((unsigned)grid), dim3(256), 0, st>>>(
+        zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,
+                                   const unsigned *qcount, const double4 *sub, int K,
+                                   unsigned long long *total, int n_cu)
+{
+    fallback_duffing_kernel<<<dim3((unsigned)n_cu * 8), dim3(256), 0, st>>>(zR, zV, queue, qcount,
+                                                                         sub, K, total);
+    return hipGetLastError();
+}
+
+}  // namespace etd

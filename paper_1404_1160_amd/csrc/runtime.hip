@@ -1,168 +1,34 @@
 // Host runtime of the exponential-integrator PIC library: context, device
 // buffers, FP64 phase bookkeeping, step scheduling and the C ABI of etdpic.h.
 
-#include <math.h>
-#include <stdarg.h>
-#include <stdio.h>
-#include <string.h>
-
-#include <map>
-#include <string>
-#include <utility>
-#include <vector>
-
-#include "../../include/etdpic.h"
-#include "internal.h"
+#include "context.h"
 
 using namespace etd;
 
 namespace {
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr uint32_t kMaxCells = 8192;
-constexpr size_t kTableEntries = size_t(1) << 20;   // substep coefficients per chunk
-constexpr size_t kStageParticles = size_t(1) << 23; // FP64 staging for host transfers
-
 std::string g_create_error;
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-template <typename T>
-hipError_t dalloc(T **p, size_t count)
+void free_all(ep_ctx *c)
 {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    for (void *p : {(void *)c->own_zR, (void *)c->own_zV, (void *)c->hist,
+                    (void *)c->etab, (void *)c->rho64, (void *)c->E64, (void *)c->Psi64,
+                    (void *)c->fscal, (void *)c->tab.sub, (void *)c->tab.endrot,
+                    (void *)c->stageR, (void *)c->stageV, (void *)c->mpartial, (void *)c->mout,
+                    (void *)c->mcount, (void *)c->mout_count})
+        if (p) (void)hipFree(p);
+    for (auto &p : c->pending) c->event_pool.push_back(p.second);
+    for (auto &ev : c->event_pool) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    free_learned(c);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
 }  // namespace
 
-struct ep_ctx {
-    ep_config cfg{};
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int n_cu = 0;
-    int push_grid_cap = 0;
-
-    // particle state (rotating frame, FP32 SoA)
-    float *zR = nullptr, *zV = nullptr;
-    float *own_zR = nullptr, *own_zV = nullptr;
-    uint64_t n = 0;
-    double w = 0.0;
-
-    // mesh
-    double hr = 0.0;
-    unsigned long long *hist = nullptr;
-    float2 *etab = nullptr;
-    double *rho64 = nullptr, *E64 = nullptr, *Psi64 = nullptr, *fscal = nullptr;
-    bool field_valid = false;
-
-    MeshArgs mesh() const
-    {
-        MeshArgs m;
-        m.nr = (int)cfg.n_cells;
-        m.w = w;
-        m.hr = hr;
-        m.hist = hist;
-        m.etab = etab;
-        m.rho64 = rho64;
-        m.E64 = E64;
-        m.Psi64 = Psi64;
-        m.fscal = fscal;
-        return m;
-    }
-
-    // per-chunk substep tables
-    StepTables tab{};
-    size_t tab_cap = 0;
-
-    // host transfers
-    double *stageR = nullptr, *stageV = nullptr;
-
-    // moments
-    int mom_grid_cap = 0;
-    double *mpartial = nullptr, *mout = nullptr;
-    unsigned long long *mcount = nullptr, *mout_count = nullptr;
-
-    // clock: t and the fast phase t/eps mod 2 pi, FP64
-    double t = 0.0, phase = 0.0;
-    uint64_t n_steps = 0;
-
-    // push mode
-    int push_mode = EP_PUSH_PLAIN;
-    double drift_tol = 1e-5;
-    uint32_t fallback_K = 0;
-    uint64_t n_fallback = 0;
-
-    // timing
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
-    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
-    std::map<std::string, std::pair<double, uint64_t>> timed;
-
-    std::string err;
-
-    ep_status fail(ep_status code, const char *fmt, ...)
-    {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof buf, fmt, ap);
-        va_end(ap);
-        err = buf;
-        return code;
-    }
-    ep_status hipfail(const char *what, hipError_t e)
-    {
-        return fail(EP_EHIP, "%s: %s", what, hipGetErrorString(e));
-    }
-};
-
-#define HIPCHK(ctx, expr)                                   \
-    do {                                                    \
-        hipError_t e_ = (expr);                             \
-        if (e_ != hipSuccess) return (ctx)->hipfail(#expr, e_); \
-    } while (0)
-
-namespace {
-
-// Timed launch bracket: records events around `launch` when timing is on.
-template <typename F>
-hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
-{
-    if (!c->timing) return launch();
-    std::pair<hipEvent_t, hipEvent_t> ev;
-    if (!c->event_pool.empty()) {
-        ev = c->event_pool.back();
-        c->event_pool.pop_back();
-    } else {
-        hipError_t e = hipEventCreate(&ev.first);
-        if (e != hipSuccess) return e;
-        e = hipEventCreate(&ev.second);
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipEventRecord(ev.first, c->stream);
-    if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(ev.second, c->stream);
-    if (e != hipSuccess) return e;
-    c->pending.emplace_back(name, ev);
-    return hipSuccess;
-}
+namespace etd {
 
 hipError_t collect_timing(ep_ctx *c)
 {
@@ -212,23 +78,7 @@ ep_status refresh_field(ep_ctx *c)
     return EP_OK;
 }
 
-void free_all(ep_ctx *c)
-{
-    for (void *p : {(void *)c->own_zR, (void *)c->own_zV, (void *)c->hist,
-                    (void *)c->etab, (void *)c->rho64, (void *)c->E64, (void *)c->Psi64,
-                    (void *)c->fscal, (void *)c->tab.sub, (void *)c->tab.endrot,
-                    (void *)c->stageR, (void *)c->stageV, (void *)c->mpartial, (void *)c->mout,
-                    (void *)c->mcount, (void *)c->mout_count})
-        if (p) (void)hipFree(p);
-    for (auto &p : c->pending) c->event_pool.push_back(p.second);
-    for (auto &ev : c->event_pool) {
-        (void)hipEventDestroy(ev.first);
-        (void)hipEventDestroy(ev.second);
-    }
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
-}
-
-}  // namespace
+}  // namespace etd
 
 extern "C" {
 
@@ -402,6 +252,11 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
         c->field_valid = false;
         return EP_OK;
     }
+    if (c->push_mode == EP_PUSH_LEARNED) {
+        if (field != EP_FIELD_DUFFING)
+            return c->fail(EP_EINVAL, "ep_step: the learned push supports the Duffing field");
+        return learned_steps(c, dt, eps, n_steps);
+    }
     if (field == EP_FIELD_POISSON && !c->field_valid) {
         ep_status s = refresh_field(c);
         if (s != EP_OK) return s;
@@ -475,6 +330,10 @@ ep_status ep_moments_get(ep_ctx *c, double eps, int32_t field, ep_moments *out)
     HIPCHK(c, hipMemcpyAsync(q, c->mout, sizeof q, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(cnt, c->mout_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(fs, c->fscal, sizeof fs, hipMemcpyDeviceToHost, c->stream));
+    unsigned long long fallbacks = 0;
+    if (c->mlp.d_total)
+        HIPCHK(c, hipMemcpyAsync(&fallbacks, c->mlp.d_total, sizeof fallbacks,
+                                 hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const double charge = c->w * (double)c->n;
     out->t = c->t;
@@ -489,7 +348,7 @@ ep_status ep_moments_get(ep_ctx *c, double eps, int32_t field, ep_moments *out)
     out->n_steps = c->n_steps;
     out->n_offmesh = field == EP_FIELD_POISSON ? cnt[0] : 0;
     out->n_nan = cnt[1];
-    out->n_fallback = c->n_fallback;
+    out->n_fallback = fallbacks;
     return EP_OK;
 }
 
@@ -548,11 +407,16 @@ ep_status ep_set_push_mode(ep_ctx *c, int32_t push, double drift_tol, uint32_t f
     if (!c) return EP_EINVAL;
     if (push != EP_PUSH_PLAIN && push != EP_PUSH_LEARNED)
         return c->fail(EP_EINVAL, "ep_set_push_mode: unknown push mode");
-    if (push == EP_PUSH_LEARNED)
-        return c->fail(EP_ENOTRAINED, "ep_set_push_mode: no corrector network loaded");
+    if (push == EP_PUSH_LEARNED) {
+        if (c->mlp.n_in == 0)
+            return c->fail(EP_ENOTRAINED, "ep_set_push_mode: no corrector network loaded");
+        if (!(drift_tol >= 0.0) || fallback_substeps == 0)
+            return c->fail(EP_EINVAL, "ep_set_push_mode: need drift_tol >= 0 and "
+                                      "fallback_substeps >= 1");
+        c->drift_tol = drift_tol;
+        c->fallback_K = fallback_substeps;
+    }
     c->push_mode = push;
-    (void)drift_tol;
-    (void)fallback_substeps;
     return EP_OK;
 }
 

@@ -1,0 +1,60 @@
+"""What the trained corrector gains over the method without it.
+
+Runs the equal-error comparison (paper_1404_1160_amd.compare) at a reduced
+size and checks:
+  * the comparison's reference (plain push, K_ref substeps) against the exact
+    elliptic solution of the Duffing characteristics;
+  * that training gains over the untrained network (rms-radius error of the
+    network map, no fallback, trained vs random weights);
+and prints the equal-error table: plain K sweep vs learned (with the 1e-5
+energy-drift fallback and without), throughput and rms-radius error.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import duffing
+from paper_1404_1160_amd import EP_FIELD_DUFFING, EP_PUSH_LEARNED, Sim, capi, compare, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_reference_run_matches_exact_solution():
+    R0, V0, w = synth.gaussian(100000, seed=15, sigma=compare.SIGMA)
+    steps = 100
+    with Sim(R0.size, substeps=3200) as s:
+        s.set_particles(R0, V0, w)
+        s.step(compare.DT, compare.EPS, EP_FIELD_DUFFING, steps)
+        R, V = s.particles()
+    Rx, Vx = duffing.solution(R0, V0, compare.EPS, steps * compare.DT)
+    rms, rms_x = np.sqrt(np.mean(R ** 2)), np.sqrt(np.mean(Rx ** 2))
+    assert abs(rms - rms_x) / rms_x < 1e-6
+    assert np.median(np.hypot(R - Rx, V - Vx)) < 1e-5
+
+
+def test_equal_error_comparison():
+    res = compare.equal_error(n_train=1_000_000, n_eval=100_000, steps=100, epochs=6,
+                              plain_Ks=(25, 50, 100, 200), K_ref=1600, log=print)
+    print(json.dumps(res, indent=1))
+    assert res["train"]["loss_last"] < 0.5 * res["train"]["loss_first"]
+    for entry in res["plain"] + res["learned"]:
+        assert np.isfinite(entry["rms_err"]) and entry["particle_steps_per_s"] > 0
+    # errors fall with K for the plain push (second order)
+    errs = [p["rms_err"] for p in res["plain"]]
+    assert errs[-1] < errs[0]
+    # training gains: the trained network map beats the untrained one
+    trained = res["learned"][1]["rms_err"]
+    R0, V0, w = synth.gaussian(100000, seed=15, sigma=compare.SIGMA)
+    with Sim(R0.size, substeps=1) as s:
+        s.set_particles(R0, V0, w)
+        norm = compare.NORM_INIT.copy()
+        norm[3:7] = [res["train"]["mu_delta"], res["train"]["sig_delta"],
+                     res["train"]["mu_kappa"], res["train"]["sig_kappa"]]
+        capi.ep_mlp_set_weights(s.ctx, synth.mlp_init(5, 64, 2, seed=5), norm)
+        capi.ep_set_push_mode(s.ctx, EP_PUSH_LEARNED, 1e300, 100)
+        s.step(compare.DT, compare.EPS, EP_FIELD_DUFFING, 100)
+        R, _ = s.particles()
+    untrained = abs(np.sqrt(np.mean(R ** 2)) - res["rms_ref"]) / res["rms_ref"]
+    print("rms error: trained %.3e, untrained %.3e" % (trained, untrained))
+    assert trained < 0.5 * untrained

@@ -129,3 +129,21 @@ def test_learned_step_fallback_limits():
     R2, V2, fb, _ = mlp.learned_step(p_bad, R, V, dt, eps, norm, pot,
                                      _duffing_fallback(dt, eps, 40), 1.0)
     assert fb.all() and np.array_equal(R2, Rp)
+
+
+def test_fine_labels_match_exact_step():
+    """P9: training labels from the plain push at K = 800 (eps = 1e-3, dt = 0.05,
+    N(0, 1.5) beam) against the exact elliptic step's polar labels: phase
+    error median < 5e-7, 99th percentile < 1e-5, max < 5e-5 (the far tail,
+    |y| ~ 7); amplitude error < 5e-6.  The corrector's own phase error is
+    ~1e-4."""
+    R, V, _ = synth.gaussian(2000, seed=9, sigma=1.5)
+    dt, eps = 0.05, 1e-3
+    Rf, Vf = oracle.push(R, V, dt, eps, 800, field=oracle.FIELD_DUFFING)
+    Rx, Vx = duffing.solution(R, V, eps, dt)
+    d, k = mlp.polar_labels(R, V, Rf, Vf, dt, eps)
+    dx, kx = mlp.polar_labels(R, V, Rx, Vx, dt, eps)
+    ed = np.abs(d - dx)
+    assert np.median(ed) < 5e-7 and np.percentile(ed, 99) < 1e-5 and ed.max() < 5e-5, (
+        np.median(ed), ed.max())
+    assert np.max(np.abs(k - kx)) < 5e-6
