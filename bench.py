@@ -9,9 +9,13 @@ fused kernel) and the exact-integer prefix-sum Poisson solve for the next step
 
 Output: one JSON line (see the repository's documentation for the fields),
 with
-  roofline     -- dominant kernel (push_poisson), algorithmic bytes 16 B per
-                  particle-step / its mean duration from HIP events recorded
-                  on the library's stream, vs the 8 TB/s HBM peak;
+  roofline     -- dominant kernel (push_poisson for the atomic deposit),
+                  algorithmic bytes per launch (16 B per particle) / its mean
+                  duration from HIP events recorded on the library's stream
+                  around every launch, vs the 8 TB/s HBM peak;
+  kernels      -- every kernel of the step with its mean duration;
+  deposit_comparison -- a short run with the other deposit (sort-by-cell
+                  segmented reduction vs LDS-privatised atomics);
   cpu_baseline -- the FP64 CPU oracle timed on this host on a bounded sample;
   learned_vs_plain -- the equal-error comparison of the learned corrector
                   (Duffing field, eps = 1e-3, dt = 0.05, trained on 1e7
@@ -50,6 +54,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run an 800 MB device copy (for HBM counter scaling)")
+    ap.add_argument("--no-deposit-comparison", action="store_true",
+                    help="skip the short run with the other deposit")
+    ap.add_argument("--comparison-steps", type=int, default=50)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the plain-vs-learned equal-error comparison")
     ap.add_argument("--learned-train", type=int, default=10_000_000)
@@ -101,6 +108,52 @@ def cpu_baseline(n_full, cells, eps, dt, K, seconds):
                 n, steps, K, cells, el)}
 
 
+# algorithmic HBM bytes per particle of each particle kernel (FP32 state and
+# u32 ids; the mesh is LDS/L2 resident)
+KERNEL_BYTES = {"push_poisson": 16, "sort_count": 8, "sort_scatter": 24, "sort_reduce": 8}
+STEP_KERNELS = ("push_poisson", "mesh_solve", "sort_count", "sort_offsets", "sort_scatter",
+                "sort_reduce")
+
+
+def run_pic(args, deposit, steps, warmup, R0, V0, w):
+    """Time `steps` Poisson steps; returns (particle-steps/s, ms/step, kernel table, moments)."""
+    from paper_1404_1160_amd import EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED, EP_FIELD_POISSON, Sim, capi
+
+    n = R0.size
+    dep = EP_DEPOSIT_SORTED if deposit == "sorted" else EP_DEPOSIT_ATOMIC
+    sim = Sim(n, n_cells=args.cells, substeps=args.substeps, deposit=dep, device=0)
+    sim.set_particles(R0, V0, w)
+    for _ in range(warmup):
+        sim.step(args.dt, args.eps, EP_FIELD_POISSON, 1)
+    sim.sync()
+    capi.ep_timing_enable(sim.ctx, True)
+    sim.sync()
+    t0 = time.perf_counter()
+    done = 0
+    mom = None
+    while done < steps:
+        chunk = min(args.moments_every, steps - done)
+        sim.step(args.dt, args.eps, EP_FIELD_POISSON, chunk)
+        done += chunk
+        if done % args.moments_every == 0:
+            mom = sim.moments(args.eps, EP_FIELD_POISSON)
+    sim.sync()
+    elapsed = time.perf_counter() - t0
+    kernels = {}
+    for name in STEP_KERNELS:
+        ms, cnt = capi.ep_timing_get(sim.ctx, name)
+        if cnt:
+            k = {"ms_per_launch": ms / cnt, "launches": cnt}
+            if name in KERNEL_BYTES:
+                k["bytes_per_launch"] = KERNEL_BYTES[name] * n
+                k["GB_per_s"] = KERNEL_BYTES[name] * n / (ms / cnt / 1e3) / 1e9
+            kernels[name] = k
+    if mom is None:
+        mom = sim.moments(args.eps, EP_FIELD_POISSON)
+    sim.close()
+    return n * steps / elapsed, elapsed / steps * 1e3, kernels, mom
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -109,22 +162,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-
-    from paper_1404_1160_amd import (EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED, EP_FIELD_POISSON, Sim,
-                                     capi, synth)
+    from paper_1404_1160_amd import capi, synth
 
     capi.lib()   # fails loudly if the HIP library is missing
     n = args.n
     t0 = time.perf_counter()
     R0, V0, w = synth.gaussian_truncated(n, seed=13)
-    gen_s = time.perf_counter() - t0
-    deposit = EP_DEPOSIT_SORTED if args.deposit == "sorted" else EP_DEPOSIT_ATOMIC
-    sim = Sim(n, n_cells=args.cells, substeps=args.substeps, deposit=deposit, device=0)
-    sim.set_particles(R0, V0, w)
-    del R0, V0
-    print("bench: %d particles loaded (generation %.1f s)" % (n, gen_s), file=sys.stderr,
-          flush=True)
+    print("bench: %d particles generated in %.1f s" % (n, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         import torch
@@ -135,31 +180,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        sim.step(args.dt, args.eps, EP_FIELD_POISSON, 1)
-    sim.sync()
-    capi.ep_timing_enable(sim.ctx, True)
-    sim.sync()
-    t0 = time.perf_counter()
-    done = 0
-    mom = None
-    while done < args.steps:
-        chunk = min(args.moments_every, args.steps - done)
-        sim.step(args.dt, args.eps, EP_FIELD_POISSON, chunk)
-        done += chunk
-        if done % args.moments_every == 0:
-            mom = sim.moments(args.eps, EP_FIELD_POISSON)
-    sim.sync()
-    elapsed = time.perf_counter() - t0
-    push_ms, push_count = capi.ep_timing_get(sim.ctx, "push_poisson")
-    solve_ms, solve_count = capi.ep_timing_get(sim.ctx, "mesh_solve")
-    if mom is None:
-        mom = sim.moments(args.eps, EP_FIELD_POISSON)
-    sim.close()
-
-    value = n * args.steps / elapsed
-    push_avg_s = push_ms / max(push_count, 1) / 1e3
-    achieved = BYTES_PER_PARTICLE_STEP * n / push_avg_s / 1e9
+    value, ms_step, kernels, mom = run_pic(args, args.deposit, args.steps, args.warmup, R0, V0, w)
+    bw = {k: v for k, v in kernels.items() if "GB_per_s" in v}
+    dom = max(bw, key=lambda k: bw[k]["ms_per_launch"] * bw[k]["launches"])
+    achieved = bw[dom]["GB_per_s"]
     line = {
         "metric": "particle-steps/s at 1e8 particles (plain push, Vlasov-Poisson)",
         "value": value,
@@ -167,7 +191,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -177,15 +201,23 @@ def main():
                    "n_particles": n, "n_cells": args.cells, "eps": args.eps, "dt": args.dt,
                    "substeps": args.substeps, "deposit": args.deposit,
                    "moments_every": args.moments_every,
-                   "precision": "FP32 push/deposit, FP64 phase, exact-integer charge scan"},
+                   "precision": "FP32 particle state; FP64 phase and in-register push "
+                                "arithmetic; exact-integer charge scan"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n),
-                     "kernel": "push_poisson", "kernel_ms": push_avg_s * 1e3,
-                     "launches": push_count,
-                     "bytes_per_launch": BYTES_PER_PARTICLE_STEP * n},
-        "mesh_solve_ms": solve_ms / max(solve_count, 1),
+                     "kernel": dom, "kernel_ms": bw[dom]["ms_per_launch"],
+                     "launches": bw[dom]["launches"],
+                     "bytes_per_launch": bw[dom]["bytes_per_launch"]},
+        "kernels": kernels,
         "moments": {k: mom[k] for k in ("t", "rms_radius", "energy", "n_offmesh", "n_nan")},
     }
+    if not args.no_deposit_comparison:
+        other = "sorted" if args.deposit == "atomic" else "atomic"
+        v2, ms2, k2, _ = run_pic(args, other, args.comparison_steps, 3, R0, V0, w)
+        line["deposit_comparison"] = {
+            args.deposit: {"particle_steps_per_s": value, "ms_per_step": ms_step},
+            other: {"particle_steps_per_s": v2, "ms_per_step": ms2, "kernels": k2}}
+    del R0, V0
     if not args.no_learned:
         from paper_1404_1160_amd import compare
         print("bench: learned-vs-plain comparison", file=sys.stderr, flush=True)

@@ -2,7 +2,10 @@
 
 Every ``csrc/*.hip`` file is compiled for ``--offload-arch=gfx950`` and linked
 into one shared library next to this file.  Packed FP32 instructions are
-disabled for the device code.
+disabled for the device code, and floating-point contraction is off: every
+fused multiply-add is an explicit fma() in the source, so the same expression
+rounds the same way in every kernel it is inlined into (the deposit of the
+fused push kernel and of the sorted deposit must agree to the bit).
 """
 import glob
 import os
@@ -15,7 +18,7 @@ LIB = os.path.join(HERE, "libetdpic.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I" + INCLUDE]
 

@@ -106,6 +106,11 @@ struct ep_ctx {
         return m;
     }
 
+    // sorted deposit: second particle buffer (cell order), ids, count tables
+    float *sR = nullptr, *sV = nullptr;
+    unsigned *ids = nullptr, *ids2 = nullptr, *inv = nullptr;
+    unsigned *counts = nullptr, *total = nullptr, *starts = nullptr;
+
     // per-chunk substep tables
     StepTables tab{};
     size_t tab_cap = 0;
@@ -187,6 +192,7 @@ inline hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
 hipError_t collect_timing(ep_ctx *c);
 ep_status ensure_tables(ep_ctx *c, size_t entries, size_t steps);
 ep_status refresh_field(ep_ctx *c);
+ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K);
 void free_learned(ep_ctx *c);
 // Learned push of n_steps steps (Duffing field); defined with the learned API.
 ep_status learned_steps(ep_ctx *c, double dt, double eps, uint64_t n_steps);

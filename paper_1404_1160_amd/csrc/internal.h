@@ -59,6 +59,39 @@ size_t push_lds_bytes_for(int nr);
 
 hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &ma);
 
+// ------------------------------------------------------------ sorted deposit
+
+struct SortArgs {
+    const float *zR, *zV;      // state before the step (particle order)
+    const unsigned *ids;       // particle ids in that order
+    int64_t n;
+    const double4 *sub;        // substep table of the step
+    const double2 *endrot;     // rotation to the lab frame at the end of the step
+    int K;
+    double inv_hr;
+    const float2 *etab;        // frozen field
+    const double *fscal;
+    int nr;
+    unsigned *counts;          // [grid][nr+1]
+    unsigned *total;           // [nr+1]
+    unsigned *starts;          // [nr+1]
+    float *oR, *oV;            // state after the step, cell order
+    unsigned *oid;
+    unsigned long long *hist;  // [nr+1] fixed-point node charges
+};
+
+hipError_t setup_sort_lds(int nr);
+hipError_t launch_sort_count(hipStream_t st, const SortArgs &a, int grid);
+hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid);
+hipError_t launch_sort_scatter(hipStream_t st, const SortArgs &a, int grid);
+hipError_t launch_sort_reduce(hipStream_t st, const SortArgs &a, const float *zR, const float *zV,
+                              int n_cu);
+hipError_t launch_iota(hipStream_t st, unsigned *ids, int64_t first, int64_t n);
+hipError_t launch_inverse(hipStream_t st, const unsigned *ids, int64_t n, unsigned *inv);
+hipError_t launch_gather_out(hipStream_t st, const float *zR, const float *zV,
+                             const unsigned *inv, int64_t first, int64_t count, double c,
+                             double s, double *R, double *V);
+
 // ------------------------------------------------------------ learned corrector
 
 constexpr int kH = 64;    // hidden width

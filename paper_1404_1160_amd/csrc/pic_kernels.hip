@@ -31,13 +31,11 @@
 // integers: the trapezoid prefix sum of the node charges is an exact integer
 // scan.
 
-#include "internal.h"
+#include "pic_device.h"
 
 namespace etd {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr double kFixOne = 4294967296.0;              // 2^32
-constexpr double kFixScale = 2.3283064365386963e-10;  // 2^-32
 
 // ------------------------------------------------------------ phase tables
 
@@ -166,64 +164,6 @@ hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
 
 // ------------------------------------------------------------ mesh solve
 
-// Wave (64-lane) and block scans and sums with a fixed combination order, so
-// FP64 results are reproducible run to run.
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_scan(T v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const T u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
-    }
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Exclusive prefix of v over the block (wtot: LDS scratch of >= 16 entries).
-template <typename T>
-__device__ T block_exclusive_scan(T v, T *wtot)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const T incl = wave_inclusive_scan(v);
-    T excl = __shfl_up(incl, 1, 64);
-    if (lane == 0) excl = T(0);
-    if (lane == 63) wtot[w] = incl;
-    __syncthreads();
-    if (w == 0) {
-        const T t = lane < nw ? wtot[lane] : T(0);
-        const T ti = wave_inclusive_scan(t);
-        T te = __shfl_up(ti, 1, 64);
-        if (lane == 0) te = T(0);
-        if (lane < nw) wtot[lane] = te;
-    }
-    __syncthreads();
-    const T r = wtot[w] + excl;
-    __syncthreads();
-    return r;
-}
-
-template <typename T>
-__device__ T block_sum(T v, T *wtot)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_sum(v);
-    if (lane == 0) wtot[w] = v;
-    __syncthreads();
-    T r = T(0);
-    for (int i = 0; i < nw; ++i) r += wtot[i];
-    __syncthreads();
-    return r;
-}
-
 // One workgroup.  From the fixed-point node charges S_k (units of 2^-32 w):
 //   rho_k = w 2^-32 S_k / h_r                                   (CIC density)
 //   I_k   = sum_{i=1..k} (S_{i-1} + S_i)        exact integer trapezoid scan,
@@ -343,66 +283,6 @@ hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &a)
 }
 
 // ------------------------------------------------------------ Poisson push + deposit
-
-struct MeshView {
-    const float2 *Et;       // LDS: (E_m, E_{m+1} - E_m), m = 0..nr-1
-    unsigned long long *H;  // LDS: fixed-point node charges, nr+1
-    double inv_hr;
-    double half;            // nr/2: on-mesh iff -half <= R/h_r < half
-    int c;                  // centre node
-    double Qb;              // half enclosed charge at the edge
-};
-
-// CIC gather of the frozen field at R; off the mesh (and for NaN) E = Qb / R.
-__device__ __forceinline__ double gather(const MeshView &m, double R)
-{
-    const double x = R * m.inv_hr;
-    if (x >= -m.half && x < m.half) {
-        const double fl = floor(x);
-        const double th = x - fl;
-        const float2 e = m.Et[(int)fl + m.c];
-        return fma(th, (double)e.y, (double)e.x);
-    }
-    return m.Qb / R;
-}
-
-// CIC deposit of one particle at R into the LDS histogram (skipped off-mesh).
-__device__ __forceinline__ void deposit(const MeshView &m, double R)
-{
-    const double x = R * m.inv_hr;
-    if (x >= -m.half && x < m.half) {
-        const double fl = floor(x);
-        const double th = x - fl;   // exact, in [0, 1)
-        const int k = (int)fl + m.c;
-        const unsigned int q = (unsigned int)(th * kFixOne);
-        atomicAdd(&m.H[k], (unsigned long long)(4294967296ull - q));
-        atomicAdd(&m.H[k + 1], (unsigned long long)q);
-    }
-}
-
-template <int NP>
-__device__ __forceinline__ void push_group(const MeshView &m, const double4 *__restrict__ sub,
-                                           int K, double (&zr)[NP], double (&zv)[NP])
-{
-    double ar[NP], av[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) ar[p] = av[p] = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double4 q = sub[k];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const double Rm = fma(q.x, zr[p] + ar[p], q.y * (zv[p] + av[p]));
-            const double E = gather(m, Rm);
-            ar[p] = fma(-q.z, E, ar[p]);
-            av[p] = fma(q.w, E, av[p]);
-        }
-    }
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        zr[p] += ar[p];
-        zv[p] += av[p];
-    }
-}
 
 // One macro step of a tile of particles: load FP32 state, K-substep push in
 // the frozen field (PUSH), store, and deposit the new positions -- rounded

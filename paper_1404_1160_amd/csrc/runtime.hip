@@ -15,6 +15,8 @@ void free_all(ep_ctx *c)
                     (void *)c->etab, (void *)c->rho64, (void *)c->E64, (void *)c->Psi64,
                     (void *)c->fscal, (void *)c->tab.sub, (void *)c->tab.endrot,
                     (void *)c->stageR, (void *)c->stageV, (void *)c->mpartial, (void *)c->mout,
+                    (void *)c->sR, (void *)c->sV, (void *)c->ids, (void *)c->ids2, (void *)c->inv,
+                    (void *)c->counts, (void *)c->total, (void *)c->starts,
                     (void *)c->mcount, (void *)c->mout_count})
         if (p) (void)hipFree(p);
     for (auto &p : c->pending) c->event_pool.push_back(p.second);
@@ -75,6 +77,52 @@ ep_status refresh_field(ep_ctx *c)
            }));
     HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, ma); }));
     c->field_valid = true;
+    return EP_OK;
+}
+
+// One Poisson step with the sorted deposit: count, offsets, scatter into the
+// second buffer (which becomes the state), segmented reduction, solve.
+ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K)
+{
+    if (c->n == 0) {
+        HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, c->mesh()); }));
+        return EP_OK;
+    }
+    const int64_t n4 = (int64_t)c->n >> 2;
+    int64_t g = (n4 + kPushBlock - 1) / kPushBlock;
+    if (g > c->push_grid_cap) g = c->push_grid_cap;
+    if (g < 1) g = 1;
+    const int grid = (int)g;
+    SortArgs a;
+    a.zR = c->zR;
+    a.zV = c->zV;
+    a.ids = c->ids;
+    a.n = (int64_t)c->n;
+    a.sub = sub;
+    a.endrot = endrot;
+    a.K = K;
+    a.inv_hr = 1.0 / c->hr;
+    a.etab = c->etab;
+    a.fscal = c->fscal;
+    a.nr = (int)c->cfg.n_cells;
+    a.counts = c->counts;
+    a.total = c->total;
+    a.starts = c->starts;
+    float *oR = c->zR == c->own_zR ? c->sR : c->own_zR;
+    float *oV = c->zV == c->own_zV ? c->sV : c->own_zV;
+    a.oR = oR;
+    a.oV = oV;
+    a.oid = c->ids2;
+    a.hist = c->hist;
+    HIPCHK(c, timed_launch(c, "sort_count", [&] { return launch_sort_count(c->stream, a, grid); }));
+    HIPCHK(c, timed_launch(c, "sort_offsets", [&] { return launch_sort_offsets(c->stream, a, grid); }));
+    HIPCHK(c, timed_launch(c, "sort_scatter", [&] { return launch_sort_scatter(c->stream, a, grid); }));
+    c->zR = oR;
+    c->zV = oV;
+    std::swap(c->ids, c->ids2);
+    HIPCHK(c, timed_launch(c, "sort_reduce",
+                           [&] { return launch_sort_reduce(c->stream, a, c->zR, c->zV, c->n_cu); }));
+    HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, c->mesh()); }));
     return EP_OK;
 }
 
@@ -155,6 +203,21 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     c->zR = c->own_zR;
     c->zV = c->own_zV;
     const size_t nn = (size_t)cfg->n_cells + 1;
+    if (cfg->deposit == EP_DEPOSIT_SORTED) {
+        if (np >= ((size_t)1 << 32)) {
+            c->fail(EP_EINVAL, "ep_create: the sorted deposit indexes particles with 32 bits");
+            return bail(EP_EINVAL);
+        }
+        CREATE_CHK(dalloc(&c->sR, np_pad));
+        CREATE_CHK(dalloc(&c->sV, np_pad));
+        CREATE_CHK(dalloc(&c->ids, np_pad));
+        CREATE_CHK(dalloc(&c->ids2, np_pad));
+        CREATE_CHK(dalloc(&c->inv, np_pad));
+        CREATE_CHK(dalloc(&c->counts, (size_t)c->push_grid_cap * nn));
+        CREATE_CHK(dalloc(&c->total, nn));
+        CREATE_CHK(dalloc(&c->starts, nn));
+        CREATE_CHK(setup_sort_lds((int)cfg->n_cells));
+    }
     CREATE_CHK(dalloc(&c->hist, nn));
     CREATE_CHK(dalloc(&c->etab, nn));
     CREATE_CHK(dalloc(&c->rho64, nn));
@@ -207,6 +270,7 @@ ep_status ep_set_particles(ep_ctx *c, const double *R, const double *V, uint64_t
                                  c->stream));
         HIPCHK(c, launch_twist_in(c->stream, c->stageR, c->stageV, c->zR + off, c->zV + off,
                                   (int64_t)m, cs, sn));
+        if (c->ids) HIPCHK(c, launch_iota(c->stream, c->ids, (int64_t)off, (int64_t)m));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     c->n = n;
@@ -218,6 +282,9 @@ ep_status ep_set_particles(ep_ctx *c, const double *R, const double *V, uint64_t
 ep_status ep_bind_particles(ep_ctx *c, float *zR_dev, float *zV_dev, uint64_t n, double w)
 {
     if (!c) return EP_EINVAL;
+    if (c->cfg.deposit == EP_DEPOSIT_SORTED)
+        return c->fail(EP_ESTATE, "ep_bind_particles: the sorted deposit reorders particles in "
+                                  "library-owned buffers");
     if (!zR_dev || !zV_dev || n > c->cfg.n_particles || !(w > 0.0) ||
         (reinterpret_cast<uintptr_t>(zR_dev) & 15) || (reinterpret_cast<uintptr_t>(zV_dev) & 15))
         return c->fail(EP_EINVAL, "ep_bind_particles: need 16-byte aligned device arrays, "
@@ -281,6 +348,12 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
         } else {
             const MeshArgs ma = c->mesh();
             for (int j = 0; j < S; ++j) {
+                if (c->cfg.deposit == EP_DEPOSIT_SORTED) {
+                    ep_status st = sorted_step(c, c->tab.sub + (size_t)j * K, c->tab.endrot + j,
+                                               K);
+                    if (st != EP_OK) return st;
+                    continue;
+                }
                 HIPCHK(c, timed_launch(c, "push_poisson", [&] {
                            return launch_push_poisson(c->stream, true, c->zR, c->zV,
                                                       (int64_t)c->n, c->tab.sub + (size_t)j * K,
@@ -365,10 +438,16 @@ ep_status ep_get_particles(ep_ctx *c, double *R, double *V, uint64_t offset, uin
         HIPCHK(c, dalloc(&c->stageV, kStageParticles));
     }
     const double cs = cos(c->phase), sn = sin(c->phase);
+    const bool reordered = c->ids != nullptr;
+    if (reordered) HIPCHK(c, launch_inverse(c->stream, c->ids, (int64_t)c->n, c->inv));
     for (uint64_t done = 0; done < count; done += kStageParticles) {
         const uint64_t m = count - done < kStageParticles ? count - done : kStageParticles;
-        HIPCHK(c, launch_twist_out(c->stream, c->zR + offset + done, c->zV + offset + done,
-                                   c->stageR, c->stageV, (int64_t)m, cs, sn));
+        if (reordered)
+            HIPCHK(c, launch_gather_out(c->stream, c->zR, c->zV, c->inv, (int64_t)(offset + done),
+                                        (int64_t)m, cs, sn, c->stageR, c->stageV));
+        else
+            HIPCHK(c, launch_twist_out(c->stream, c->zR + offset + done, c->zV + offset + done,
+                                       c->stageR, c->stageV, (int64_t)m, cs, sn));
         HIPCHK(c, hipMemcpyAsync(R + done, c->stageR, m * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
         HIPCHK(c, hipMemcpyAsync(V + done, c->stageV, m * sizeof(double), hipMemcpyDeviceToHost,

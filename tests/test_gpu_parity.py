@@ -23,8 +23,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1404_1160_amd import (EP_FIELD_DUFFING, EP_FIELD_POISSON, EP_FIELD_ZERO, Sim, capi,
-                                 synth)
+from paper_1404_1160_amd import (EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED, EP_FIELD_DUFFING,
+                                 EP_FIELD_POISSON, EP_FIELD_ZERO, Sim, capi, synth)
 
 pytestmark = pytest.mark.gpu
 
@@ -154,13 +154,14 @@ def test_deposit_and_solve(nr):
     assert np.all(np.sign(E[nr // 2 + 1:]) >= 0)
 
 
-@pytest.mark.parametrize("K", [1, 4])
-def test_poisson_ten_steps_per_particle(K):
+@pytest.mark.parametrize("K,deposit", [(1, EP_DEPOSIT_ATOMIC), (4, EP_DEPOSIT_ATOMIC),
+                                       (1, EP_DEPOSIT_SORTED), (4, EP_DEPOSIT_SORTED)])
+def test_poisson_ten_steps_per_particle(K, deposit):
     """VP beam, N_r = 256, eps = 0.01, dt = 0.05, ragged particle count."""
     R0, V0, w = synth.gaussian_truncated(20003, seed=12)
     eps, dt, nr = 0.01, 0.05, 256
     Ro, Vo = R0.copy(), V0.copy()
-    with Sim(R0.size, n_cells=nr, substeps=K) as sim:
+    with Sim(R0.size, n_cells=nr, substeps=K, deposit=deposit) as sim:
         sim.set_particles(R0, V0, w)
         for s in range(10):
             sim.step(dt, eps, EP_FIELD_POISSON, 1)
@@ -226,6 +227,31 @@ def test_deterministic_and_order_independent():
     for other in out[1:]:
         for a, b in zip(out[0], other):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nr,K,n", [(256, 2, 100003), (4096, 1, 1000001), (256, 3, 5)])
+def test_sorted_deposit_equals_atomic_bitwise(nr, K, n):
+    """The sort-by-cell segmented reduction adds the same fixed-point weights
+    as the LDS-privatised deposit, so particles (in their original order),
+    charge, field and potential are bitwise identical, off-mesh and NaN
+    particles included."""
+    R0, V0, w = synth.gaussian_truncated(n, seed=19)
+    if n > 10:
+        R0[:4] = [6.0, -7.0, np.nan, 4.999]
+    out = []
+    for dep in (EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED):
+        with Sim(n, n_cells=nr, substeps=K, deposit=dep) as sim:
+            sim.set_particles(R0, V0, w)
+            sim.step(0.05, 0.01, EP_FIELD_POISSON, 4)
+            sim.step(0.1, 0.05, EP_FIELD_DUFFING, 1)      # order-preserving step in between
+            sim.step(0.05, 0.01, EP_FIELD_POISSON, 3)
+            R, V = sim.particles()
+            part = sim.particles(n // 3, min(77, n - n // 3))
+            rho, E, Psi, Qb = sim.field()
+            m = sim.moments(0.01, EP_FIELD_POISSON)
+        out.append((R, V, part[0], part[1], rho, E, Psi, np.array([Qb, m["n_offmesh"], m["n_nan"]])))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b, equal_nan=True)
 
 
 def test_small_and_degenerate_inputs():
