@@ -237,6 +237,22 @@ ep_status ep_mlp_grad(ep_ctx *ctx, const float *X, const float *Y, uint32_t batc
 ep_status ep_mlp_train(ep_ctx *ctx, const ep_train_cfg *cfg, const double *R, const double *V,
                        uint64_t n, ep_train_report *report);
 
+/* ---------------------------------------------------------------- checkpoint
+ * ep_save writes the state of the current time level to `path`: a header
+ * (magic "ETDPIC01", format version, loaded particle count, mesh and substep
+ * configuration, weight, t, phase, step count, push mode, fallback settings),
+ * the FP32 rotating-frame particle arrays in the order they were loaded, and
+ * the corrector's parameters and normalisation if one is loaded.  ep_load
+ * restores such a file into a context whose capacity, mesh and substeps
+ * accept it; the field is recomputed from the particles, so a resumed run
+ * continues bit for bit.  The fallback counter of ep_moments is a statistic,
+ * not state: it is not saved.  Errors: EP_EIO (file cannot be opened, read or
+ * written, or is not a checkpoint of this format), EP_EINVAL (it does not fit
+ * the context), EP_EHIP.  ep_load stores the restored particle count in
+ * *n_particles when that pointer is not null. */
+ep_status ep_save(ep_ctx *ctx, const char *path);
+ep_status ep_load(ep_ctx *ctx, const char *path, uint64_t *n_particles);
+
 /* Synchronise the context's stream; reports asynchronous errors. */
 ep_status ep_sync(ep_ctx *ctx);
 

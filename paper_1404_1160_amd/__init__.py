@@ -57,3 +57,9 @@ class Sim:
 
     def sync(self):
         capi.ep_sync(self.ctx)
+
+    def save(self, path):
+        capi.ep_save(self.ctx, path)
+
+    def load(self, path):
+        self.n = capi.ep_load(self.ctx, path)

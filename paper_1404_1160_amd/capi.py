@@ -25,7 +25,7 @@ EXPORTS = (
     "ep_create", "ep_destroy", "ep_last_error", "ep_set_particles", "ep_bind_particles",
     "ep_step", "ep_moments_get", "ep_get_particles", "ep_get_field", "ep_set_push_mode",
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
-    "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train",
+    "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_save", "ep_load",
 )
 
 
@@ -111,6 +111,8 @@ def lib():
             "ep_mlp_grad": ([vp, pf, pf, u32, pf, pd], i32),
             "ep_mlp_train": ([vp, ctypes.POINTER(ep_train_cfg), pd, pd, u64,
                               ctypes.POINTER(ep_train_report)], i32),
+            "ep_save": ([vp, ctypes.c_char_p], i32),
+            "ep_load": ([vp, ctypes.c_char_p, ctypes.POINTER(u64)], i32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -262,3 +264,14 @@ def ep_mlp_train(ctx, R, V, dt, eps, fine_substeps, batch, epochs, lr, lr_final,
     _check(ctx, lib().ep_mlp_train(ctx, ctypes.byref(cfg), _p(R), _p(V), R.size,
                                    ctypes.byref(rep)))
     return rep.as_dict()
+
+
+def ep_save(ctx, path):
+    _check(ctx, lib().ep_save(ctx, os.fsencode(path)))
+
+
+def ep_load(ctx, path):
+    """Restores a checkpoint; returns the restored particle count."""
+    n = ctypes.c_uint64(0)
+    _check(ctx, lib().ep_load(ctx, os.fsencode(path), ctypes.byref(n)))
+    return int(n.value)

@@ -1,0 +1,158 @@
+// Checkpoint and resume of a context (ep_save / ep_load).
+
+#include "context.h"
+
+using namespace etd;
+
+namespace {
+
+constexpr char kMagic[8] = {'E', 'T', 'D', 'P', 'I', 'C', '0', '1'};
+constexpr uint32_t kVersion = 1;
+
+struct Header {
+    char magic[8];
+    uint32_t version;
+    uint32_t n_cells;
+    uint64_t n;
+    uint32_t substeps;
+    int32_t deposit;
+    double r_max;
+    double w;
+    double t;
+    double phase;
+    uint64_t n_steps;
+    int32_t push_mode;
+    uint32_t fallback_K;
+    double drift_tol;
+    uint32_t mlp_n_in;
+    uint32_t mlp_n_params;
+};
+
+struct File {
+    FILE *f = nullptr;
+    ~File()
+    {
+        if (f) fclose(f);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+ep_status ep_save(ep_ctx *c, const char *path)
+{
+    if (!c) return EP_EINVAL;
+    if (!path) return c->fail(EP_EINVAL, "ep_save: null path");
+    DeviceGuard guard(c->device);
+    Header h{};
+    memcpy(h.magic, kMagic, 8);
+    h.version = kVersion;
+    h.n_cells = c->cfg.n_cells;
+    h.n = c->n;
+    h.substeps = c->cfg.substeps;
+    h.deposit = c->cfg.deposit;
+    h.r_max = c->cfg.r_max;
+    h.w = c->w;
+    h.t = c->t;
+    h.phase = c->phase;
+    h.n_steps = c->n_steps;
+    h.push_mode = c->push_mode;
+    h.fallback_K = c->fallback_K;
+    h.drift_tol = c->drift_tol;
+    h.mlp_n_in = (uint32_t)c->mlp.n_in;
+    h.mlp_n_params = (uint32_t)c->mlp.params.size();
+    // particles in loaded order
+    std::vector<float> zr(c->n), zv(c->n);
+    if (c->n) {
+        if (c->ids) {
+            HIPCHK(c, launch_inverse(c->stream, c->ids, (int64_t)c->n, c->inv));
+            float *tmpR = nullptr, *tmpV = nullptr;
+            HIPCHK(c, dalloc(&tmpR, (size_t)c->n));
+            HIPCHK(c, dalloc(&tmpV, (size_t)c->n));
+            hipError_t e = launch_gather_f32(c->stream, c->zR, c->zV, c->inv, (int64_t)c->n, tmpR,
+                                             tmpV);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(zr.data(), tmpR, c->n * 4, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(zv.data(), tmpV, c->n * 4, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            (void)hipFree(tmpR);
+            (void)hipFree(tmpV);
+            if (e != hipSuccess) return c->hipfail("ep_save: gather particles", e);
+        } else {
+            HIPCHK(c, hipMemcpyAsync(zr.data(), c->zR, c->n * 4, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(zv.data(), c->zV, c->n * 4, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    File out;
+    out.f = fopen(path, "wb");
+    if (!out.f) return c->fail(EP_EIO, "ep_save: cannot open %s", path);
+    bool ok = fwrite(&h, sizeof h, 1, out.f) == 1;
+    if (c->n) {
+        ok = ok && fwrite(zr.data(), 4, c->n, out.f) == c->n;
+        ok = ok && fwrite(zv.data(), 4, c->n, out.f) == c->n;
+    }
+    if (h.mlp_n_in) {
+        ok = ok && fwrite(c->mlp.params.data(), 4, h.mlp_n_params, out.f) == h.mlp_n_params;
+        ok = ok && fwrite(c->mlp.norm, 8, 8, out.f) == 8;
+    }
+    ok = ok && fflush(out.f) == 0;
+    if (!ok) return c->fail(EP_EIO, "ep_save: write to %s failed", path);
+    return EP_OK;
+}
+
+ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
+{
+    if (!c) return EP_EINVAL;
+    if (!path) return c->fail(EP_EINVAL, "ep_load: null path");
+    File in;
+    in.f = fopen(path, "rb");
+    if (!in.f) return c->fail(EP_EIO, "ep_load: cannot open %s", path);
+    Header h{};
+    if (fread(&h, sizeof h, 1, in.f) != 1 || memcmp(h.magic, kMagic, 8) != 0 ||
+        h.version != kVersion)
+        return c->fail(EP_EIO, "ep_load: %s is not a checkpoint of format %u", path, kVersion);
+    if (h.n > c->cfg.n_particles || h.n_cells != c->cfg.n_cells || h.r_max != c->cfg.r_max ||
+        h.substeps != c->cfg.substeps || !(h.w > 0.0) ||
+        (h.mlp_n_in && h.mlp_n_params != (uint32_t)mlp_n_params((int)h.mlp_n_in)))
+        return c->fail(EP_EINVAL, "ep_load: checkpoint does not fit this context (particles, "
+                                  "mesh or substeps differ)");
+    std::vector<float> zr(h.n), zv(h.n), params(h.mlp_n_params);
+    double norm[8] = {0};
+    bool ok = true;
+    if (h.n) {
+        ok = fread(zr.data(), 4, h.n, in.f) == h.n && fread(zv.data(), 4, h.n, in.f) == h.n;
+    }
+    if (ok && h.mlp_n_in)
+        ok = fread(params.data(), 4, h.mlp_n_params, in.f) == h.mlp_n_params &&
+             fread(norm, 8, 8, in.f) == 8;
+    if (!ok) return c->fail(EP_EIO, "ep_load: %s is truncated", path);
+    DeviceGuard guard(c->device);
+    if (h.mlp_n_in) {
+        ep_status s = ep_mlp_set_weights(c, params.data(), h.mlp_n_params, norm);
+        if (s != EP_OK) return s;
+    }
+    c->zR = c->own_zR;
+    c->zV = c->own_zV;
+    if (h.n) {
+        HIPCHK(c, hipMemcpy(c->zR, zr.data(), h.n * 4, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->zV, zv.data(), h.n * 4, hipMemcpyHostToDevice));
+        if (c->ids) HIPCHK(c, launch_iota(c->stream, c->ids, 0, (int64_t)h.n));
+    }
+    c->n = h.n;
+    c->w = h.w;
+    c->t = h.t;
+    c->phase = h.phase;
+    c->n_steps = h.n_steps;
+    c->push_mode = (h.push_mode == EP_PUSH_LEARNED && c->mlp.n_in) ? EP_PUSH_LEARNED : EP_PUSH_PLAIN;
+    c->fallback_K = h.fallback_K;
+    c->drift_tol = h.drift_tol;
+    c->field_valid = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (n_particles) *n_particles = h.n;
+    return EP_OK;
+}
+
+}  // extern "C"

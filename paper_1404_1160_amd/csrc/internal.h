@@ -88,6 +88,8 @@ hipError_t launch_sort_reduce(hipStream_t st, const SortArgs &a, const float *zR
                               int n_cu);
 hipError_t launch_iota(hipStream_t st, unsigned *ids, int64_t first, int64_t n);
 hipError_t launch_inverse(hipStream_t st, const unsigned *ids, int64_t n, unsigned *inv);
+hipError_t launch_gather_f32(hipStream_t st, const float *zR, const float *zV, const unsigned *inv,
+                             int64_t n, float *oR, float *oV);
 hipError_t launch_gather_out(hipStream_t st, const float *zR, const float *zV,
                              const unsigned *inv, int64_t first, int64_t count, double c,
                              double s, double *R, double *V);

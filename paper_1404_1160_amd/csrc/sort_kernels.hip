@@ -233,6 +233,28 @@ __global__ void gather_out_kernel(const float *__restrict__ zR, const float *__r
     }
 }
 
+// z of particles inv[j] in original order j < n (FP32 copies)
+__global__ void gather_f32_kernel(const float *__restrict__ zR, const float *__restrict__ zV,
+                                  const unsigned *__restrict__ inv, int64_t n,
+                                  float *__restrict__ oR, float *__restrict__ oV)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j < n) {
+        const unsigned i = inv[j];
+        oR[j] = zR[i];
+        oV[j] = zV[i];
+    }
+}
+
+hipError_t launch_gather_f32(hipStream_t st, const float *zR, const float *zV, const unsigned *inv,
+                             int64_t n, float *oR, float *oV)
+{
+    if (n <= 0) return hipSuccess;
+    gather_f32_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(zR, zV, inv, n, oR,
+                                                                             oV);
+    return hipGetLastError();
+}
+
 static size_t sort_lds_bytes(int nr)
 {
     return (size_t)nr * sizeof(float2) + (size_t)(nr + 1) * sizeof(unsigned);
