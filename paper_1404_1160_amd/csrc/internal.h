@@ -124,8 +124,11 @@ hipError_t setup_train_lds(int n_in);
 hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const float *X,
                            const float *Y, int64_t first, int batch, const float norm[4],
                            float *gpart, float *lpart, float *grad, float *loss);
-hipError_t launch_mlp_adam(hipStream_t st, float *p, float *m, float *v, const float *g, int np,
-                           float lr, float b1, float b2, float bc1, float bc2, float eps);
+hipError_t launch_mlp_train_step(hipStream_t st, int n_in, float *params, float *m, float *v,
+                                 const float *X, const float *Y, int64_t first, int batch,
+                                 const float norm[4], float *gpart, float *lpart, float *grad,
+                                 float *loss, float lr, float b1, float b2, float bc1, float bc2,
+                                 float eps);
 // Learned Duffing step: network prediction, energy check |dH| <= tol |H|,
 // passing particles updated in place, failing ones appended to queue.
 hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,

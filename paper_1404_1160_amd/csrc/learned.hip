@@ -385,13 +385,12 @@ ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, cons
         const uint64_t b = t % per_epoch;
         const double lr = cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) *
                                               (1.0 + cos(3.141592653589793 * (double)t / (double)T));
-        HIPCHK(c, launch_mlp_grad(c->stream, 5, L.d_params, dX.p, dY.p, (int64_t)(b * batch), batch,
-                                  nf, gpart.p, lpart.p, L.d_grad, dloss.p + t));
         const double bc1 = 1.0 / (1.0 - pow(kAdamB1, (double)(t + 1)));
         const double bc2 = 1.0 / (1.0 - pow(kAdamB2, (double)(t + 1)));
-        HIPCHK(c, launch_mlp_adam(c->stream, L.d_params, L.d_m, L.d_v, L.d_grad, np, (float)lr,
-                                  (float)kAdamB1, (float)kAdamB2, (float)bc1, (float)bc2,
-                                  (float)kAdamEps));
+        HIPCHK(c, launch_mlp_train_step(c->stream, 5, L.d_params, L.d_m, L.d_v, dX.p, dY.p,
+                                        (int64_t)(b * batch), batch, nf, gpart.p, lpart.p,
+                                        L.d_grad, dloss.p + t, (float)lr, (float)kAdamB1,
+                                        (float)kAdamB2, (float)bc1, (float)bc2, (float)kAdamEps));
     }
     HIPCHK(c, hipEventRecord(e2, c->stream));
     std::vector<float> losses((size_t)T);

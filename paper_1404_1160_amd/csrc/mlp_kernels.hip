@@ -13,14 +13,14 @@
 //                              three 64x64x64 products run on BF16 MFMA with
 //                              FP32 accumulation (forward split into hi/lo
 //                              BF16 halves, three MFMAs, for ~16-bit operands)
-//   mlp_grad_reduce_kernel     per-tile gradients summed in tile order
-//   mlp_adam_kernel            Adam on the FP32 master weights
-//   mlp_push_duffing_kernel    inference, 32 particles per wave, W2 fragments
-//                              resident in registers, FP64 energy check,
-//                              failing particles appended to a queue
+//   mlp_grad_reduce_kernel     per-tile gradients summed in a fixed order,
+//                              fused with Adam on the FP32 master weights
+//   mlp_push_duffing_kernel    inference, 32 particles per wave, weights in
+//                              LDS, FP64 energy check, failing particles
+//                              appended to a queue
 //   fallback_duffing_kernel    plain push of the queued particles
 
-#include "internal.h"
+#include "pic_device.h"
 
 namespace etd {
 
@@ -38,22 +38,34 @@ __device__ __forceinline__ float act_grad_h(float h)
     return t * __fsqrt_rn(t);
 }
 
-// FP32 -> BF16 bits, round to nearest even.
-__device__ __forceinline__ unsigned short bf16_bits(float f)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values -> a packed BF16 pair, round to nearest even (one
+// v_cvt_pk_bf16_f32 on gfx950); element 0 in the low half.
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b)
 {
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
 }
 
-__device__ __forceinline__ float bf16_value(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
-
-__device__ __forceinline__ bf16x8 as_bf16x8(const unsigned short (&b)[8])
+// Eight FP32 values as a BF16 MFMA operand (hi), and optionally the BF16 of
+// their remainders (lo = bf16(a - hi), exact subtraction), so that hi + lo
+// carries ~16 significant bits.
+template <bool SPLIT>
+__device__ __forceinline__ void to_bf16x8(const float (&a)[8], bf16x8 &hi, bf16x8 &lo)
 {
-    bf16x8 v;
+    uint4 h, l;
+    unsigned *hp = &h.x, *lp = &l.x;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, b[e]);
-    return v;
+    for (int i = 0; i < 4; ++i) {
+        hp[i] = pack_bf16x2(a[2 * i], a[2 * i + 1]);
+        if (SPLIT)
+            lp[i] = pack_bf16x2(a[2 * i] - __uint_as_float(hp[i] << 16),
+                                a[2 * i + 1] - __uint_as_float(hp[i] & 0xFFFF0000u));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    if (SPLIT) lo = __builtin_bit_cast(bf16x8, l);
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 q) { return __builtin_bit_cast(bf16x8, q); }
@@ -72,23 +84,20 @@ __device__ void mma64_wave(const float *A, int ai, int ak, const float *B, int b
     const int r = lane & 31, g = lane >> 5;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-        unsigned short ah[8], al[8], bh[8], bl[8];
+        float a[8], b[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = kk * 16 + g * 8 + e;
-            const float a = A[(i0 + r) * ai + k * ak];
-            const float b = B[k * bk + (j0 + r) * bj];
-            ah[e] = bf16_bits(a);
-            bh[e] = bf16_bits(b);
-            if (SPLIT) {
-                al[e] = bf16_bits(a - bf16_value(ah[e]));
-                bl[e] = bf16_bits(b - bf16_value(bh[e]));
-            }
+            a[e] = A[(i0 + r) * ai + k * ak];
+            b[e] = B[k * bk + (j0 + r) * bj];
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah), as_bf16x8(bh), acc, 0, 0, 0);
+        bf16x8 ah, al, bh, bl;
+        to_bf16x8<SPLIT>(a, ah, al);
+        to_bf16x8<SPLIT>(b, bh, bl);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
         if (SPLIT) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah), as_bf16x8(bl), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al), as_bf16x8(bh), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
         }
     }
 }
@@ -296,42 +305,58 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     }
 }
 
-// grad[p] = sum over tiles in tile order; loss = sum of lpart / (batch * 2).
+// grad[p] = sum over the per-tile gradients, loss = sum of lpart / (batch * 2).
+// A workgroup of 256 threads takes 64 parameters; the four threads of a
+// parameter sum the tiles t = q, q + 4, ... (q = 0..3) and the four partial
+// sums are added as (s0 + s1) + (s2 + s3): a fixed order, so the result is
+// reproducible.  With ADAM the update of Adam (Kingma & Ba; bias corrections
+// bc1 = 1/(1 - b1^t), bc2 = 1/(1 - b2^t)) is applied to the parameters too.
+struct AdamArgs {
+    float *p, *m, *v;
+    float lr, b1, b2, bc1, bc2, eps;
+};
+
+template <bool ADAM>
 __global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(const float *__restrict__ gpart,
                                                               const float *__restrict__ lpart,
                                                               int tiles, int np, int batch,
                                                               float *__restrict__ grad,
-                                                              float *__restrict__ loss)
+                                                              float *__restrict__ loss, AdamArgs ad)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float part[4][64];
+    __shared__ double lw[4];
+    const int tid = threadIdx.x, pl = tid & 63, q = tid >> 6;
+    const int p = blockIdx.x * 64 + pl;
     if (p < np) {
-        float a = 0.f;
-        for (int t = 0; t < tiles; ++t) a += gpart[(size_t)t * np + p];
-        grad[p] = a;
+        float a0 = 0.f, a1 = 0.f;
+        int t = q;
+        for (; t + 4 < tiles; t += 8) {
+            a0 += gpart[(size_t)t * np + p];
+            a1 += gpart[(size_t)(t + 4) * np + p];
+        }
+        if (t < tiles) a0 += gpart[(size_t)t * np + p];
+        part[q][pl] = a0 + a1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    __syncthreads();
+    if (q == 0 && p < np) {
+        const float gi = (part[0][pl] + part[1][pl]) + (part[2][pl] + part[3][pl]);
+        grad[p] = gi;
+        if (ADAM) {
+            const float mi = fmaf(ad.b1, ad.m[p], (1.f - ad.b1) * gi);
+            const float vi = fmaf(ad.b2, ad.v[p], (1.f - ad.b2) * gi * gi);
+            ad.m[p] = mi;
+            ad.v[p] = vi;
+            ad.p[p] -= ad.lr * (mi * ad.bc1) / (__fsqrt_rn(vi * ad.bc2) + ad.eps);
+        }
+    }
+    if (blockIdx.x == 0) {
         double l = 0.0;
-        for (int t = 0; t < tiles; ++t) l += lpart[t];
-        *loss = (float)(l / (double)(batch * 2));
+        for (int t = tid; t < tiles; t += 256) l += lpart[t];
+        l = wave_sum(l);
+        if ((tid & 63) == 0) lw[tid >> 6] = l;
+        __syncthreads();
+        if (tid == 0) *loss = (float)(((lw[0] + lw[1]) + (lw[2] + lw[3])) / (double)(batch * 2));
     }
-}
-
-// Adam (Kingma & Ba) with bias corrections bc1 = 1/(1 - b1^t), bc2 = 1/(1 - b2^t).
-__global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ p,
-                                                       float *__restrict__ m,
-                                                       float *__restrict__ v,
-                                                       const float *__restrict__ g, int np,
-                                                       float lr, float b1, float b2, float bc1,
-                                                       float bc2, float eps)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    const float gi = g[i];
-    const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
-    const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi * bc1) / (__fsqrt_rn(vi * bc2) + eps);
 }
 
 hipError_t setup_train_lds(int n_in)
@@ -344,9 +369,9 @@ hipError_t setup_train_lds(int n_in)
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const float *X,
-                           const float *Y, int64_t first, int batch, const float norm[4],
-                           float *gpart, float *lpart, float *grad, float *loss)
+static hipError_t launch_train_tiles(hipStream_t st, int n_in, const float *params,
+                                     const float *X, const float *Y, int64_t first, int batch,
+                                     const float norm[4], float *gpart, float *lpart)
 {
     const int tiles = (batch + kTile - 1) / kTile;
     const size_t lds = train_lds_floats(n_in) * sizeof(float);
@@ -356,23 +381,38 @@ hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const 
     else
         mlp_train_kernel<6><<<dim3(tiles), dim3(256), lds, st>>>(
             params, X, Y, first, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int np = mlp_n_params(n_in);
-    mlp_grad_reduce_kernel<<<dim3((np + 255) / 256), dim3(256), 0, st>>>(gpart, lpart, tiles, np,
-                                                                       batch, grad, loss);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_adam(hipStream_t st, float *p, float *m, float *v, const float *g, int np,
-                           float lr, float b1, float b2, float bc1, float bc2, float eps)
+hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const float *X,
+                           const float *Y, int64_t first, int batch, const float norm[4],
+                           float *gpart, float *lpart, float *grad, float *loss)
 {
-    mlp_adam_kernel<<<dim3((np + 255) / 256), dim3(256), 0, st>>>(p, m, v, g, np, lr, b1, b2, bc1,
-                                                                  bc2, eps);
+    hipError_t e = launch_train_tiles(st, n_in, params, X, Y, first, batch, norm, gpart, lpart);
+    if (e != hipSuccess) return e;
+    const int np = mlp_n_params(n_in), tiles = (batch + kTile - 1) / kTile;
+    mlp_grad_reduce_kernel<false><<<dim3((np + 63) / 64), dim3(256), 0, st>>>(
+        gpart, lpart, tiles, np, batch, grad, loss, AdamArgs{});
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_train_step(hipStream_t st, int n_in, float *params, float *m, float *v,
+                                 const float *X, const float *Y, int64_t first, int batch,
+                                 const float norm[4], float *gpart, float *lpart, float *grad,
+                                 float *loss, float lr, float b1, float b2, float bc1, float bc2,
+                                 float eps)
+{
+    hipError_t e = launch_train_tiles(st, n_in, params, X, Y, first, batch, norm, gpart, lpart);
+    if (e != hipSuccess) return e;
+    const int np = mlp_n_params(n_in), tiles = (batch + kTile - 1) / kTile;
+    mlp_grad_reduce_kernel<true><<<dim3((np + 63) / 64), dim3(256), 0, st>>>(
+        gpart, lpart, tiles, np, batch, grad, loss, AdamArgs{params, m, v, lr, b1, b2, bc1, bc2, eps});
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ inference
+
+constexpr unsigned kLocalQueue = 2048;   // LDS fallback-queue entries per workgroup
 
 // One learned step of the Duffing beam.  A workgroup of 4 waves takes 128
 // particles per iteration, 32 per wave; lanes l and l+32 share particle l%32
@@ -381,7 +421,8 @@ hipError_t launch_mlp_adam(hipStream_t st, float *p, float *m, float *v, const f
 // activations are live.  All weights stay in LDS and are read where used.
 // The update and the energy check H = |z|^2/(2 eps) + R^4/4 run in FP64;
 // particles that fail keep their state and are appended to the fallback
-// queue with one global atomic per workgroup iteration.
+// queue: first to a queue in LDS, copied out with one global atomic per
+// workgroup at the end, so that the waves never wait on each other.
 __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
     float *__restrict__ zR, float *__restrict__ zV, int64_t n, MlpInfer net, double2 rot0,
     double2 rot1, double inv2eps, double tol, unsigned *__restrict__ qcount,
@@ -391,8 +432,9 @@ __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
     __shared__ float4 sl1[kH];
     __shared__ float sb2[kH];
     __shared__ float sw3[kOut * kH];
-    __shared__ unsigned s_cnt[4], s_base;
+    __shared__ unsigned s_q[kLocalQueue], s_qn, s_qbase;
     const int tid = threadIdx.x;
+    if (tid == 0) s_qn = 0u;
     for (int i = tid; i < 8 * 64; i += blockDim.x) {
         sAh[i] = net.w2hi[i];
         sAl[i] = net.w2lo[i];
@@ -420,15 +462,14 @@ __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
         f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            unsigned short h[8], l[8];
+            float a[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const float4 w = sl1[kk * 16 + g * 8 + e];
-                const float a = act(fmaf(w.x, x0, fmaf(w.y, x1, w.w)));
-                h[e] = bf16_bits(a);
-                l[e] = bf16_bits(a - bf16_value(h[e]));
+                a[e] = act(fmaf(w.x, x0, fmaf(w.y, x1, w.w)));
             }
-            const bf16x8 bh = as_bf16x8(h), bl = as_bf16x8(l);
+            bf16x8 bh, bl;
+            to_bf16x8<true>(a, bh, bl);
             const bf16x8 Ah0 = as_bf16x8(sAh[kk * 64 + lane]), Al0 = as_bf16x8(sAl[kk * 64 + lane]);
             const bf16x8 Ah1 = as_bf16x8(sAh[(4 + kk) * 64 + lane]);
             const bf16x8 Al1 = as_bf16x8(sAl[(4 + kk) * 64 + lane]);
@@ -468,22 +509,29 @@ __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
             zR[p] = (float)nr;
             zV[p] = (float)nv;
         }
-        // fallback queue: wave ballots, workgroup prefix, one global atomic
-        const unsigned long long fail = __ballot(mine && !ok);
-        if (lane == 0) s_cnt[wave] = (unsigned)__popcll(fail);
-        __syncthreads();
-        if (tid == 0) {
-            const unsigned tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-            s_base = tot ? atomicAdd(qcount, tot) : 0u;
+        // failing particles go to the workgroup's LDS queue (one LDS atomic
+        // per wave); slots beyond its capacity take a global slot directly
+        const bool fail = mine && !ok;
+        const unsigned long long fm = __ballot(fail);
+        if (fm) {
+            unsigned base = 0u;
+            if (lane == 0) base = atomicAdd(&s_qn, (unsigned)__popcll(fm));
+            base = __shfl(base, 0, 64);
+            if (fail) {
+                const unsigned slot = base + (unsigned)__popcll(fm & ((1ull << lane) - 1ull));
+                if (slot < kLocalQueue)
+                    s_q[slot] = (unsigned)p;
+                else
+                    queue[atomicAdd(qcount, 1u)] = (unsigned)p;
+            }
         }
-        __syncthreads();
-        if (mine && !ok) {
-            unsigned slot = s_base + (unsigned)__popcll(fail & ((1ull << lane) - 1ull));
-            for (int w = 0; w < wave; ++w) slot += s_cnt[w];
-            queue[slot] = (unsigned)p;
-        }
-        __syncthreads();
     }
+    // one global atomic per workgroup for its LDS queue
+    __syncthreads();
+    const unsigned nq = s_qn < kLocalQueue ? s_qn : kLocalQueue;
+    if (tid == 0 && nq) s_qbase = atomicAdd(qcount, nq);
+    __syncthreads();
+    for (unsigned i = tid; i < nq; i += blockDim.x) queue[s_qbase + i] = s_q[i];
 }
 
 // Plain push (K substeps, FP64) of the queued particles.
