@@ -20,7 +20,11 @@ with
   learned_vs_plain -- the equal-error comparison of the learned corrector
                   (Duffing field, eps = 1e-3, dt = 0.05, trained on 1e7
                   samples, evaluated on 1e7 particles; see
-                  paper_1404_1160_amd/compare.py).
+                  paper_1404_1160_amd/compare.py);
+  learned_vs_plain_vp -- the same for the Vlasov-Poisson beam (N_r = 4096,
+                  eps = 1e-3, dt = 0.1, 6-input network trained on samples
+                  self-generated from a plain run of a 1e6-particle beam,
+                  evaluated on 1e7 particles).
 """
 import argparse
 import hashlib
@@ -61,6 +65,8 @@ def parse():
                     help="skip the plain-vs-learned equal-error comparison")
     ap.add_argument("--learned-train", type=int, default=10_000_000)
     ap.add_argument("--learned-eval", type=int, default=10_000_000)
+    ap.add_argument("--learned-vp-data", type=int, default=1_000_000,
+                    help="beam size of the self-generated Vlasov-Poisson training run")
     return ap.parse_args()
 
 
@@ -223,6 +229,10 @@ def main():
         print("bench: learned-vs-plain comparison", file=sys.stderr, flush=True)
         line["learned_vs_plain"] = compare.equal_error(
             n_train=args.learned_train, n_eval=args.learned_eval,
+            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        print("bench: learned-vs-plain comparison, Vlasov-Poisson", file=sys.stderr, flush=True)
+        line["learned_vs_plain_vp"] = compare.equal_error_vp(
+            n_eval=args.learned_eval, n_data=args.learned_vp_data,
             log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cells, args.eps, args.dt, args.substeps,

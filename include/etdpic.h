@@ -166,9 +166,11 @@ ep_status ep_get_field(ep_ctx *ctx, double *rho, double *E, double *Psi, double 
 
 /* Select the push (ep_push).  For EP_PUSH_LEARNED: drift_tol is the per-particle
  * relative energy-drift bound |H(y_{n+1}) - H(y_n)| <= drift_tol * H(y_n)
- * (H the frozen-field energy of the step), and fallback_substeps the K used by
- * the plain push for particles that fail it.  Errors: EP_EINVAL,
- * EP_ENOTRAINED. */
+ * (H(y) = |y|^2/(2 eps) + P(R), the frozen-field energy of the step: P = R^4/4
+ * for the Duffing field, the mesh potential Psi^n for the Poisson field), and
+ * fallback_substeps the K used by the plain push for particles that fail it.
+ * ep_step then needs a 5-input network for the Duffing field and a 6-input
+ * one for the Poisson field.  Errors: EP_EINVAL, EP_ENOTRAINED. */
 ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
                            uint32_t fallback_substeps);
 
@@ -181,12 +183,19 @@ ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
  * Its outputs o give the step's Duhamel term (eq. 3.6) in polar form around
  * the exact rotation: delta = mu_d + sig_d o_0, kappa = mu_k + sig_k o_1 and
  *   y_{n+1} = (1 + kappa) r(dt/eps + delta) y_n.
+ * With the amplitude-scaled output map the two outputs are a delta and
+ * a kappa (a = |y_n|: the arc length and the radial displacement beyond the
+ * free rotation), divided by a before the map is applied; they stay bounded
+ * for small orbits in the self-consistent field, whose phase advance grows
+ * like 1/a.  Training labels follow the map of the loaded normalisation.
  * Parameters: one FP32 vector W1[64][n_in], b1[64], W2[64][64], b2[64],
  * W3[2][64], b3[2] (row-major; 4674 values for n_in = 5, 4738 for 6).
- * Normalisation: 8 doubles {s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, 0}. */
+ * Normalisation: 8 doubles {s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, map},
+ * map = 0 (delta, kappa) or 1 (amplitude-scaled). */
 typedef struct {
     double dt, eps;            /* step the corrector is trained for (> 0)            */
-    int32_t field;             /* EP_FIELD_DUFFING                                   */
+    int32_t field;             /* EP_FIELD_DUFFING (given samples) or EP_FIELD_POISSON
+                                  (samples collected with ep_mlp_collect)           */
     uint32_t fine_substeps;    /* K of the plain push that makes the labels (>= 1)  */
     uint32_t batch;            /* samples per Adam step, a multiple of 64            */
     uint32_t epochs;           /* passes over the samples (>= 1)                     */
@@ -228,12 +237,35 @@ ep_status ep_mlp_labels(ep_ctx *ctx, double dt, double eps, uint32_t fine_subste
 ep_status ep_mlp_grad(ep_ctx *ctx, const float *X, const float *Y, uint32_t batch, float *grad,
                       double *loss);
 
-/* Train the network on the GPU: labels of the n samples (R, V) are made with
- * the plain push (cfg->fine_substeps), the normalisation of the labels is set
- * from their mean and standard deviation, and Adam runs cfg->epochs passes in
- * batches of cfg->batch in sample order, starting from the parameters loaded
- * with ep_mlp_set_weights.  Errors: EP_EINVAL, EP_ENOTRAINED, EP_ENOMEM,
- * EP_EHIP. */
+/* Self-generated training samples for the Poisson field (6-input network):
+ * from the context's particles first, first + stride, ... at the current time
+ * level and its field E^n (computed first if stale), the features
+ * (R/s_in, V/s_in, cos phi, sin phi, (dt/eps)/s_t, E^n(R)/s_E), with the
+ * scales of the loaded normalisation, and the labels (delta, kappa) of one
+ * plain step of dt at eps with fine_substeps substeps in the frozen field E^n
+ * (the standard PIC field time level).  The samples are appended to the
+ * context's training set (cleared first if reset != 0); *n_total receives its
+ * size.  Changing the network's input count discards the set.
+ * Errors: EP_EINVAL, EP_ENOTRAINED, EP_ESTATE, EP_ENOMEM, EP_EHIP. */
+ep_status ep_mlp_collect(ep_ctx *ctx, double dt, double eps, uint32_t fine_substeps,
+                         uint64_t first, uint64_t stride, int32_t reset, uint64_t *n_total);
+
+/* Copy rows [first, first + count) of the collected training set out:
+ * X[count][6] features, Y[count][2] raw labels (delta, kappa).
+ * Errors: EP_EINVAL, EP_EHIP. */
+ep_status ep_mlp_get_samples(ep_ctx *ctx, uint64_t first, uint64_t count, float *X, float *Y);
+
+/* Train the network on the GPU, starting from the parameters loaded with
+ * ep_mlp_set_weights.  Duffing field: labels of the n samples (R, V) are made
+ * with the plain push (cfg->fine_substeps) and batches are taken in sample
+ * order; the feature scales become {cfg->s_in, 100, 1}.  Poisson field: R, V
+ * and n are ignored, the collected set is used (feature scales unchanged), and
+ * batch b of an epoch takes the rows b, b + P, b + 2P, ... (P batches per
+ * epoch), so that each batch spans all collected time levels.  The
+ * normalisation of the labels is set from the mean and standard deviation of
+ * the first 65536 labels; Adam runs cfg->epochs passes with a step size
+ * cosine-decayed from lr to lr_final.  Errors: EP_EINVAL, EP_ENOTRAINED,
+ * EP_ENOMEM, EP_EHIP. */
 ep_status ep_mlp_train(ep_ctx *ctx, const ep_train_cfg *cfg, const double *R, const double *V,
                        uint64_t n, ep_train_report *report);
 

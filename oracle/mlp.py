@@ -20,6 +20,13 @@ Duhamel term).  The network gives D in polar form around the exact rotation:
     delta = mu_d + sig_d o_0  (phase advance beyond dt/eps)
     kappa = mu_k + sig_k o_1  (relative change of |y|)
     y_{n+1} = (1 + kappa) r(dt/eps + delta) y_n,   D = y_{n+1} - r(dt/eps) y_n
+or, with the amplitude-scaled map (out_map = 1), the arc length and the
+radial displacement of the step beyond the free rotation,
+    s = mu_d + sig_d o_0 = a delta,   rho = mu_k + sig_k o_1 = a kappa,
+    a = |y_n|, i.e. delta = s / a and kappa = rho / a.
+In the self-consistent field E(0+) = rho(0) > 0 = -E(0-), so the phase
+advance of small orbits grows like 1/a while s and rho stay bounded: the
+scaled targets are the ones a smooth network can fit there.
 Check: the frozen-field energy H^n(y) = (R^2 + V^2)/(2 eps) + P(R), P = R^4/4
 (Duffing) or the mesh potential Psi^n (Poisson), must satisfy
 |H^n(y_{n+1}) - H^n(y_n)| <= tol |H^n(y_n)|; particles that fail take the
@@ -117,17 +124,19 @@ def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 class Norm:
     """Normalisation constants of a trained corrector (stored with its weights)."""
 
-    def __init__(self, s_in=1.5, s_t=100.0, s_E=1.0, mu_d=0.0, sig_d=1.0, mu_k=0.0, sig_k=1.0):
+    def __init__(self, s_in=1.5, s_t=100.0, s_E=1.0, mu_d=0.0, sig_d=1.0, mu_k=0.0, sig_k=1.0,
+                 out_map=0):
         self.s_in, self.s_t, self.s_E = s_in, s_t, s_E
         self.mu_d, self.sig_d, self.mu_k, self.sig_k = mu_d, sig_d, mu_k, sig_k
+        self.out_map = int(out_map)   # 0: (delta, kappa); 1: (a delta, a kappa)
 
     def as_array(self):
         return np.array([self.s_in, self.s_t, self.s_E, self.mu_d, self.sig_d, self.mu_k,
-                         self.sig_k, 0.0])
+                         self.sig_k, float(self.out_map)])
 
     @classmethod
     def from_array(cls, a):
-        return cls(*[float(x) for x in a[:7]])
+        return cls(*[float(x) for x in a[:7]], out_map=int(a[7]))
 
 
 def features(R, V, dt, eps, norm, Egather=None):
@@ -146,24 +155,34 @@ def rotate(phi, R, V):
     return c * R + s * V, -s * R + c * V
 
 
-def apply_polar(R, V, dt, eps, delta, kappa):
-    """y_{n+1} = (1 + kappa) r(dt/eps + delta) y_n."""
+def apply_polar(R, V, dt, eps, delta, kappa, scaled=False):
+    """y_{n+1} = (1 + kappa) r(dt/eps + delta) y_n; with scaled=True the
+    inputs are (a delta, a kappa), a = |y_n| (nothing moves at a = 0)."""
+    if scaled:
+        a = np.hypot(R, V)
+        inv = np.divide(1.0, a, out=np.zeros_like(a), where=a > 0)
+        delta, kappa = delta * inv, kappa * inv
     R1, V1 = rotate(dt / eps + delta, R, V)
     return (1.0 + kappa) * R1, (1.0 + kappa) * V1
 
 
-def polar_labels(R, V, R1, V1, dt, eps):
+def polar_labels(R, V, R1, V1, dt, eps, scaled=False):
     """Inverse of apply_polar: (delta, kappa) that map y_n to y_{n+1}.
     delta is the angle from r(dt/eps) y_n to y_{n+1} in the direction in which
-    r advances (atan2 of the cross and dot products), kappa = |y_{n+1}|/|y_n| - 1."""
+    r advances (atan2 of the cross and dot products), kappa = |y_{n+1}|/|y_n| - 1;
+    scaled=True returns (a delta, |y_{n+1}| - a), a = |y_n|."""
     uR, uV = rotate(dt / eps, R, V)
     delta = np.arctan2(R1 * uV - V1 * uR, R1 * uR + V1 * uV)
-    kappa = np.hypot(R1, V1) / np.hypot(R, V) - 1.0
+    a = np.hypot(R, V)
+    if scaled:
+        return a * delta, np.hypot(R1, V1) - a
+    kappa = np.hypot(R1, V1) / a - 1.0
     return delta, kappa
 
 
 def predict(p, R, V, dt, eps, norm, Egather=None):
-    """Network prediction (delta, kappa) for particles (R, V)."""
+    """Network prediction for particles (R, V): (delta, kappa), or (a delta,
+    a kappa) with the amplitude-scaled map."""
     X = features(R, V, dt, eps, norm, Egather)
     O, _ = forward(p, X)
     return norm.mu_d + norm.sig_d * O[:, 0], norm.mu_k + norm.sig_k * O[:, 1]
@@ -180,7 +199,7 @@ def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=Non
     plain step used for particles that fail the check.  Returns
     (R1, V1, fell_back[bool], ratio = |dH|/|H|)."""
     delta, kappa = predict(p, R, V, dt, eps, norm, Egather)
-    R1, V1 = apply_polar(R, V, dt, eps, delta, kappa)
+    R1, V1 = apply_polar(R, V, dt, eps, delta, kappa, scaled=norm.out_map == 1)
     H0 = energy(R, V, eps, potential)
     H1 = energy(R1, V1, eps, potential)
     ratio = np.abs(H1 - H0) / np.abs(H0)

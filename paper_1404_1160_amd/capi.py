@@ -25,7 +25,8 @@ EXPORTS = (
     "ep_create", "ep_destroy", "ep_last_error", "ep_set_particles", "ep_bind_particles",
     "ep_step", "ep_moments_get", "ep_get_particles", "ep_get_field", "ep_set_push_mode",
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
-    "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_save", "ep_load",
+    "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect", "ep_mlp_get_samples",
+    "ep_save", "ep_load",
 )
 
 
@@ -111,6 +112,8 @@ def lib():
             "ep_mlp_grad": ([vp, pf, pf, u32, pf, pd], i32),
             "ep_mlp_train": ([vp, ctypes.POINTER(ep_train_cfg), pd, pd, u64,
                               ctypes.POINTER(ep_train_report)], i32),
+            "ep_mlp_collect": ([vp, d, d, u32, u64, u64, i32, ctypes.POINTER(u64)], i32),
+            "ep_mlp_get_samples": ([vp, u64, u64, pf, pf], i32),
             "ep_save": ([vp, ctypes.c_char_p], i32),
             "ep_load": ([vp, ctypes.c_char_p, ctypes.POINTER(u64)], i32),
         }
@@ -229,6 +232,11 @@ def ep_mlp_set_weights(ctx, params, norm):
     _check(ctx, lib().ep_mlp_set_weights(ctx, _pf(params), params.size, _p(norm)))
 
 
+def mlp_n_params(n_in):
+    """Parameter count of the n_in -> 64 -> 64 -> 2 corrector."""
+    return 64 * n_in + 64 + 64 * 64 + 64 + 2 * 64 + 2
+
+
 def ep_mlp_get_weights(ctx, n_params):
     params = np.empty(n_params, dtype=np.float32)
     norm = np.empty(8)
@@ -257,13 +265,34 @@ def ep_mlp_grad(ctx, X, Y, n_params):
 
 def ep_mlp_train(ctx, R, V, dt, eps, fine_substeps, batch, epochs, lr, lr_final, s_in,
                  field=EP_FIELD_DUFFING):
-    R = _f64(R)
-    V = _f64(V)
+    """Duffing field: trains on the samples (R, V).  Poisson field: pass
+    R = V = None; trains on the set collected with ep_mlp_collect."""
     cfg = ep_train_cfg(dt, eps, field, fine_substeps, batch, epochs, lr, lr_final, s_in)
     rep = ep_train_report()
-    _check(ctx, lib().ep_mlp_train(ctx, ctypes.byref(cfg), _p(R), _p(V), R.size,
-                                   ctypes.byref(rep)))
+    if R is None:
+        _check(ctx, lib().ep_mlp_train(ctx, ctypes.byref(cfg), None, None, 0, ctypes.byref(rep)))
+    else:
+        R = _f64(R)
+        V = _f64(V)
+        _check(ctx, lib().ep_mlp_train(ctx, ctypes.byref(cfg), _p(R), _p(V), R.size,
+                                       ctypes.byref(rep)))
     return rep.as_dict()
+
+
+def ep_mlp_collect(ctx, dt, eps, fine_substeps, first=0, stride=1, reset=False):
+    """Appends self-generated Poisson-field samples; returns the set's size."""
+    n = ctypes.c_uint64(0)
+    _check(ctx, lib().ep_mlp_collect(ctx, float(dt), float(eps), int(fine_substeps), int(first),
+                                     int(stride), 1 if reset else 0, ctypes.byref(n)))
+    return int(n.value)
+
+
+def ep_mlp_get_samples(ctx, first, count):
+    """Rows [first, first + count) of the collected set: (X [count, 6], Y [count, 2])."""
+    X = np.empty((count, 6), dtype=np.float32)
+    Y = np.empty((count, 2), dtype=np.float32)
+    _check(ctx, lib().ep_mlp_get_samples(ctx, int(first), int(count), _pf(X), _pf(Y)))
+    return X, Y
 
 
 def ep_save(ctx, path):

@@ -1,6 +1,6 @@
 """Equal-error comparison of the plain push and the learned corrector.
 
-Workload (learned corrector on the Duffing field): eps = 1e-3, dt = 0.05,
+Duffing workload (`equal_error`): eps = 1e-3, dt = 0.05,
 R, V ~ N(0, 1.5); the network (5 -> 64 -> 64 -> 2) is trained on the GPU on
 samples labelled by the plain push with K_fine substeps, then both forms push
 an evaluation beam for `steps` steps.  Error = the largest relative
@@ -11,13 +11,21 @@ can pass through zero by chance.  Throughput = particle-steps/s of the whole run
 synchronised GPU work, particles resident in HBM).  The equal-error point is
 the smallest plain K whose error does not exceed the learned form's.
 
+Vlasov-Poisson workload (`equal_error_vp`): the beam R ~ N(0, 1) truncated
+to |R| < 4, V ~ N(0, 1), N_r cells on [-5, 5], eps = 1e-3, dt = 0.1.  The
+6-input network (features plus E^n(R_n)) is trained on self-generated data: a
+separate beam (another seed) is run with the plain push at K_data substeps
+and, every `collect_every` steps, its particles, their field E^n and the
+labels of a K_fine-substep step in that frozen field are collected on the
+GPU.  Reference and error metric as above, with the reference run at K_ref.
+
 Everything here calls the HIP library through its C ABI.
 """
 import time
 
 import numpy as np
 
-from . import EP_FIELD_DUFFING, EP_PUSH_LEARNED, EP_PUSH_PLAIN, Sim, capi, synth
+from . import EP_FIELD_DUFFING, EP_FIELD_POISSON, EP_PUSH_LEARNED, EP_PUSH_PLAIN, Sim, capi, synth
 
 DT, EPS, SIGMA = 0.05, 1e-3, 1.5
 NORM_INIT = np.array([SIGMA, 100.0, 1.0, 0.0, 1.0, 0.0, 1.0, 0.0])
@@ -132,4 +140,128 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
     else:
         out["equal_error"] = {"plain_K": None, "gain": None,
                               "note": "no plain K in the sweep reached the learned error"}
+    return out
+
+
+# ------------------------------------------------------------------ Vlasov-Poisson
+
+VP_DT, VP_EPS, VP_NR = 0.1, 1e-3, 4096
+# feature scales (s_in, s_t, s_E), label normalisation set by training, and
+# the amplitude-scaled output map (bounded targets for small orbits)
+VP_NORM_INIT = np.array([1.0, 100.0, 0.25, 0.0, 1.0, 0.0, 1.0, 1.0])
+
+
+def _vp_history(sim, R0, V0, w, steps, every):
+    sim.set_particles(R0, V0, w)
+    out = [sim.moments(VP_EPS, EP_FIELD_POISSON)["rms_radius"]]
+    for _ in range(steps // every):
+        sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, every)
+        out.append(sim.moments(VP_EPS, EP_FIELD_POISSON)["rms_radius"])
+    return np.array(out)
+
+
+def train_vp(n_data, steps, nr=VP_NR, K_data=400, K_fine=800, collect_every=10, epochs=40,
+             batch=4096, lr=3e-3, lr_final=1e-5, seed=16, init_seed=5, log=None):
+    """Self-generated training: plain run of a separate beam, samples collected
+    every `collect_every` steps; returns (params, norm, report, n_samples)."""
+    R, V, w = synth.gaussian_truncated(n_data, seed=seed)
+    with Sim(n_data, n_cells=nr, substeps=K_data) as sim:
+        sim.set_particles(R, V, w)
+        capi.ep_mlp_set_weights(sim.ctx, synth.mlp_init(6, 64, 2, seed=init_seed), VP_NORM_INIT)
+        total = 0
+        for lvl in range(steps // collect_every):
+            total = capi.ep_mlp_collect(sim.ctx, VP_DT, VP_EPS, K_fine, reset=lvl == 0)
+            sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, collect_every)
+        if log:
+            log("vp: collected %d samples" % total)
+        b = min(batch, max(64, (total // 512) // 64 * 64))
+        rep = capi.ep_mlp_train(sim.ctx, None, None, VP_DT, VP_EPS, K_fine, b, epochs, lr,
+                                lr_final, 1.0, field=EP_FIELD_POISSON)
+        p, norm = capi.ep_mlp_get_weights(sim.ctx, capi.mlp_n_params(6))
+    return p, norm, rep, total
+
+
+def _equal_error_point(plain, entry):
+    match = [q for q in plain if q["rms_err"] <= entry["rms_err"]]
+    if not match:
+        return {"plain_K": None, "gain": None,
+                "note": "no plain K in the sweep reached the learned error"}
+    q = min(match, key=lambda e: e["K"])
+    return {"plain_K": q["K"], "plain_particle_steps_per_s": q["particle_steps_per_s"],
+            "learned_particle_steps_per_s": entry["particle_steps_per_s"],
+            "gain": entry["particle_steps_per_s"] / q["particle_steps_per_s"],
+            "rms_err_learned": entry["rms_err"], "rms_err_plain": q["rms_err"]}
+
+
+def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs=40,
+                   K_fine=800, plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5,
+                   extra_tols=(1e-4, 1e-3), K_fb=100, seed_eval=17, every=10, log=None):
+    """As equal_error, for the Vlasov-Poisson beam; the learned push runs at
+    the drift bound tol (the equal-error point), at extra_tols and without
+    the check."""
+    def say(msg):
+        if log:
+            log(msg)
+
+    Re, Ve, we = synth.gaussian_truncated(n_eval, seed=seed_eval)
+    out = {"workload": {"field": "poisson", "eps": VP_EPS, "dt": VP_DT, "n_cells": nr,
+                        "n_eval": n_eval, "n_data": n_data, "steps": steps, "K_fine": K_fine,
+                        "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb}}
+    with Sim(n_eval, n_cells=nr, substeps=K_ref) as ref:
+        hist_ref = _vp_history(ref, Re, Ve, we, steps, every)
+    out["rms_ref"] = float(hist_ref[-1])
+    say("vp reference K=%d rms %.6f" % (K_ref, hist_ref[-1]))
+
+    def timed(sim):
+        sim.set_particles(Re, Ve, we)
+        sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, 1)   # field and tables ready
+        sim.set_particles(Re, Ve, we)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, steps)
+        sim.sync()
+        return time.perf_counter() - t0
+
+    def error(sim):
+        h = _vp_history(sim, Re, Ve, we, steps, every)
+        return float(np.max(np.abs(h - hist_ref) / hist_ref))
+
+    plain = []
+    for K in plain_Ks:
+        with Sim(n_eval, n_cells=nr, substeps=K) as s:
+            el = timed(s)
+            err = error(s)
+        plain.append({"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err})
+        say("vp plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, plain[-1]["particle_steps_per_s"], err))
+    out["plain"] = plain
+
+    p, norm, rep, n_samples = train_vp(n_data, steps, nr=nr, K_fine=K_fine, epochs=epochs,
+                                       log=log)
+    rep["n_samples"] = n_samples
+    out["train"] = rep
+    say("vp trained on %d samples: loss %.4f -> %.4f in %d steps (%.0f ms)" % (
+        n_samples, rep["loss_first"], rep["loss_last"], rep["steps"], rep["train_ms"]))
+    learned = []
+    with Sim(n_eval, n_cells=nr, substeps=1) as sim:
+        capi.ep_mlp_set_weights(sim.ctx, p, norm)
+        for t in (tol,) + tuple(extra_tols) + (float("inf"),):
+            capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, 1e300 if t == float("inf") else t,
+                                  K_fb)
+            sim.set_particles(Re, Ve, we)
+            f0 = sim.moments(VP_EPS, EP_FIELD_POISSON)["n_fallback"]
+            capi.ep_timing_enable(sim.ctx, True)
+            el = timed(sim)
+            mlp_ms, _ = capi.ep_timing_get(sim.ctx, "mlp_push")
+            capi.ep_timing_enable(sim.ctx, False)
+            f1 = sim.moments(VP_EPS, EP_FIELD_POISSON)["n_fallback"]
+            err = error(sim)
+            learned.append({"drift_tol": None if t == float("inf") else t,
+                            "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
+                            "fallback_rate": (f1 - f0) / (n_eval * (steps + 1)),
+                            "network_particle_steps_per_s": n_eval * (steps + 1) / (mlp_ms / 1e3)})
+            say("vp learned tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
+                t, learned[-1]["particle_steps_per_s"], err, learned[-1]["fallback_rate"]))
+    out["learned"] = learned
+    out["equal_error"] = _equal_error_point(plain, learned[0])
+    out["equal_error_no_check"] = _equal_error_point(plain, learned[-1])
     return out

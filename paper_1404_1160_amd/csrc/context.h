@@ -61,6 +61,10 @@ struct Learned {
     unsigned *d_qcount = nullptr, *d_queue = nullptr;
     unsigned long long *d_total = nullptr;
     uint64_t queue_cap = 0;
+    // training set collected from the context's own particles (features
+    // [t_n][6], raw labels [t_n][2])
+    float *d_tx = nullptr, *d_ty = nullptr;
+    uint64_t t_n = 0, t_cap = 0;
 };
 
 }  // namespace etd
@@ -195,6 +199,6 @@ ep_status refresh_field(ep_ctx *c);
 ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K);
 void free_learned(ep_ctx *c);
 // Learned push of n_steps steps (Duffing field); defined with the learned API.
-ep_status learned_steps(ep_ctx *c, double dt, double eps, uint64_t n_steps);
+ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps);
 
 }  // namespace etd

@@ -113,22 +113,25 @@ struct MlpInfer {
     const float *b2;     // [64]
     const float *w3;     // [2][64]
     float b3_0, b3_1, mu_d, sig_d, mu_k, sig_k;
+    int scaled;          // outputs are (a delta, a kappa), a = |y|, instead of (delta, kappa)
 };
 
+// Labels (delta, kappa), or (a delta, a kappa) with scaled != 0.
 hipError_t launch_gen_labels_duffing(hipStream_t st, const float *R, const float *V, int64_t n,
                                      const double4 *sub, int K, float inv_sin, float c_phi,
-                                     float s_phi, float th_scaled, float *X, float *Y);
+                                     float s_phi, float th_scaled, int scaled, float *X, float *Y);
 hipError_t setup_train_lds(int n_in);
 // Gradient of the MSE loss over samples [first, first + batch) (X: [.][n_in],
 // Y: [.][2] raw labels, norm = {mu_d, 1/sig_d, mu_k, 1/sig_k}).
 hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const float *X,
                            const float *Y, int64_t first, int batch, const float norm[4],
                            float *gpart, float *lpart, float *grad, float *loss);
+// One Adam step on the batch whose sample s is row first + s * sstride.
 hipError_t launch_mlp_train_step(hipStream_t st, int n_in, float *params, float *m, float *v,
-                                 const float *X, const float *Y, int64_t first, int batch,
-                                 const float norm[4], float *gpart, float *lpart, float *grad,
-                                 float *loss, float lr, float b1, float b2, float bc1, float bc2,
-                                 float eps);
+                                 const float *X, const float *Y, int64_t first, int64_t sstride,
+                                 int batch, const float norm[4], float *gpart, float *lpart,
+                                 float *grad, float *loss, float lr, float b1, float b2, float bc1,
+                                 float bc2, float eps);
 // Learned Duffing step: network prediction, energy check |dH| <= tol |H|,
 // passing particles updated in place, failing ones appended to queue.
 hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
@@ -139,6 +142,22 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t
 hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,
                                    const unsigned *qcount, const double4 *sub, int K,
                                    unsigned long long *total, int n_cu);
+hipError_t launch_gen_labels_poisson(hipStream_t st, const float *zR, const float *zV,
+                                     int64_t first, int64_t stride, int64_t count, double2 rot0,
+                                     const MeshArgs &ma, const double4 *sub, int K, float inv_sin,
+                                     float c_phi, float s_phi, float th_scaled, float inv_sE,
+                                     int scaled, float *X, float *Y);
+// Learned step in the frozen Poisson field: 6-input network, energy check
+// with the mesh potential, CIC deposit of the particles that pass.
+hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t n,
+                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
+                                   double tol, unsigned *qcount, unsigned *queue,
+                                   const MeshArgs &ma, double rmax, int n_cu);
+// Plain push + deposit of the queued particles in the frozen Poisson field.
+hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const unsigned *queue,
+                                   const unsigned *qcount, const double4 *sub, int K, double2 er,
+                                   const MeshArgs &ma, unsigned long long *total, int n_cu);
+hipError_t setup_learned_lds(int nr);
 
 hipError_t launch_moments(hipStream_t st, const float *zR, const float *zV, int64_t n,
                           double c, double s, double rmax, double *partial,

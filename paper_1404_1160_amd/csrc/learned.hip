@@ -116,6 +116,7 @@ ep_status prepare_inference(ep_ctx *c, double dt, double eps)
     I.sig_d = (float)L.norm[4];
     I.mu_k = (float)L.norm[5];
     I.sig_k = (float)L.norm[6];
+    I.scaled = L.norm[7] == 1.0 ? 1 : 0;
     L.packed = true;
     L.cached_dt = dt;
     L.cached_eps = eps;
@@ -143,6 +144,15 @@ struct DevBuf {
     }
 };
 
+struct Events {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    ~Events()
+    {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 ep_status upload_fp32(ep_ctx *c, const double *src, uint64_t n, float *dst)
 {
     std::vector<float> tmp(n);
@@ -152,8 +162,8 @@ ep_status upload_fp32(ep_ctx *c, const double *src, uint64_t n, float *dst)
 }
 
 // Features and raw labels of n samples into device arrays X[n][5], Y[n][2].
-ep_status make_labels(ep_ctx *c, double dt, double eps, uint32_t K, double s_in, const double *R,
-                      const double *V, uint64_t n, float *dX, float *dY)
+ep_status make_labels(ep_ctx *c, double dt, double eps, uint32_t K, double s_in, int scaled,
+                      const double *R, const double *V, uint64_t n, float *dX, float *dY)
 {
     DevBuf<float> dR, dV;
     HIPCHK(c, dalloc(&dR.p, (size_t)n));
@@ -167,7 +177,7 @@ ep_status make_labels(ep_ctx *c, double dt, double eps, uint32_t K, double s_in,
     const double phi = fmod(th, kTwoPi);
     HIPCHK(c, launch_gen_labels_duffing(c->stream, dR.p, dV.p, (int64_t)n, c->tab.sub, (int)K,
                                         (float)(1.0 / s_in), (float)cos(phi), (float)sin(phi),
-                                        (float)(th / kTimeScale), dX, dY));
+                                        (float)(th / kTimeScale), scaled, dX, dY));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return EP_OK;
 }
@@ -181,24 +191,31 @@ void free_learned(ep_ctx *c)
     Learned &L = c->mlp;
     for (void *p : {(void *)L.d_params, (void *)L.d_m, (void *)L.d_v, (void *)L.d_grad,
                     (void *)L.d_w2hi, (void *)L.d_w2lo, (void *)L.d_l1, (void *)L.d_b2,
-                    (void *)L.d_w3, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total})
+                    (void *)L.d_w3, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total,
+                    (void *)L.d_tx, (void *)L.d_ty})
         if (p) (void)hipFree(p);
     L = Learned();
 }
 
-ep_status learned_steps(ep_ctx *c, double dt, double eps, uint64_t n_steps)
+ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps)
 {
     Learned &L = c->mlp;
-    if (L.n_in != 5)
-        return c->fail(EP_ENOTRAINED, "ep_step: the learned push needs a 5-input network");
+    const bool vp = field == EP_FIELD_POISSON;
+    if (L.n_in != (vp ? 6 : 5))
+        return c->fail(EP_ENOTRAINED, vp ? "ep_step: the learned push in the Poisson field needs "
+                                           "a 6-input network (E^n(R) feature)"
+                                         : "ep_step: the learned push in the Duffing field needs "
+                                           "a 5-input network");
     ep_status s = prepare_inference(c, dt, eps);
     if (s != EP_OK) return s;
     if ((s = ensure_queue(c)) != EP_OK) return s;
+    if (vp && !c->field_valid && (s = refresh_field(c)) != EP_OK) return s;
     const int K = (int)c->fallback_K;
     const double dphi = fmod(dt / eps, kTwoPi);
     size_t chunk = kTableEntries / (size_t)K;
     if (chunk < 1) chunk = 1;
     if ((s = ensure_tables(c, chunk * (size_t)K, chunk)) != EP_OK) return s;
+    const MeshArgs ma = c->mesh();
     uint64_t done = 0;
     while (done < n_steps) {
         const uint64_t rem = n_steps - done;
@@ -208,25 +225,42 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, uint64_t n_steps)
         for (int j = 0; j < S; ++j) {
             const double p0 = fmod(c->phase + (double)j * dphi, kTwoPi);
             const double p1 = fmod(c->phase + (double)(j + 1) * dphi, kTwoPi);
+            const double2 rot0 = make_double2(cos(p0), sin(p0));
+            const double2 rot1 = make_double2(cos(p1), sin(p1));
+            const double4 *sub = c->tab.sub + (size_t)j * K;
             HIPCHK(c, hipMemsetAsync(L.d_qcount, 0, sizeof(unsigned), c->stream));
-            HIPCHK(c, timed_launch(c, "mlp_push", [&] {
-                       return launch_mlp_push_duffing(
-                           c->stream, c->zR, c->zV, (int64_t)c->n, L.infer,
-                           make_double2(cos(p0), sin(p0)), make_double2(cos(p1), sin(p1)), eps,
-                           c->drift_tol, L.d_qcount, L.d_queue, c->n_cu);
-                   }));
-            HIPCHK(c, timed_launch(c, "fallback_push", [&] {
-                       return launch_fallback_duffing(c->stream, c->zR, c->zV, L.d_queue,
-                                                      L.d_qcount, c->tab.sub + (size_t)j * K, K,
-                                                      L.d_total, c->n_cu);
-                   }));
+            if (vp) {
+                HIPCHK(c, timed_launch(c, "mlp_push", [&] {
+                           return launch_mlp_push_poisson(c->stream, c->zR, c->zV, (int64_t)c->n,
+                                                          L.infer, rot0, rot1, eps, c->drift_tol,
+                                                          L.d_qcount, L.d_queue, ma,
+                                                          c->cfg.r_max, c->n_cu);
+                       }));
+                HIPCHK(c, timed_launch(c, "fallback_push", [&] {
+                           return launch_fallback_poisson(c->stream, c->zR, c->zV, L.d_queue,
+                                                          L.d_qcount, sub, K, rot1, ma, L.d_total,
+                                                          c->n_cu);
+                       }));
+                HIPCHK(c, timed_launch(c, "mesh_solve",
+                                       [&] { return launch_mesh_solve(c->stream, ma); }));
+            } else {
+                HIPCHK(c, timed_launch(c, "mlp_push", [&] {
+                           return launch_mlp_push_duffing(c->stream, c->zR, c->zV, (int64_t)c->n,
+                                                          L.infer, rot0, rot1, eps, c->drift_tol,
+                                                          L.d_qcount, L.d_queue, c->n_cu);
+                       }));
+                HIPCHK(c, timed_launch(c, "fallback_push", [&] {
+                           return launch_fallback_duffing(c->stream, c->zR, c->zV, L.d_queue,
+                                                          L.d_qcount, sub, K, L.d_total, c->n_cu);
+                       }));
+            }
         }
         c->phase = fmod(c->phase + (double)S * dphi, kTwoPi);
         c->t += (double)S * dt;
         c->n_steps += (uint64_t)S;
         done += (uint64_t)S;
     }
-    c->field_valid = false;
+    c->field_valid = vp;
     return EP_OK;
 }
 
@@ -246,6 +280,8 @@ ep_status ep_mlp_set_weights(ep_ctx *c, const float *params, uint32_t n_params, 
                        mlp_n_params(5), mlp_n_params(6));
     if (!(norm[0] > 0.0) || !(norm[1] > 0.0) || !(norm[2] > 0.0))
         return c->fail(EP_EINVAL, "ep_mlp_set_weights: feature scales must be positive");
+    if (norm[7] != 0.0 && norm[7] != 1.0)
+        return c->fail(EP_EINVAL, "ep_mlp_set_weights: norm[7] (output map) must be 0 or 1");
     DeviceGuard guard(c->device);
     ep_status s = ensure_mlp_buffers(c, n_in);
     if (s != EP_OK) return s;
@@ -280,7 +316,7 @@ ep_status ep_mlp_labels(ep_ctx *c, double dt, double eps, uint32_t K, const doub
     DevBuf<float> dX, dY;
     HIPCHK(c, dalloc(&dX.p, (size_t)n * 5));
     HIPCHK(c, dalloc(&dY.p, (size_t)n * 2));
-    ep_status s = make_labels(c, dt, eps, K, 1.0, R, V, n, dX.p, dY.p);
+    ep_status s = make_labels(c, dt, eps, K, 1.0, 0, R, V, n, dX.p, dY.p);
     if (s != EP_OK) return s;
     std::vector<float> Y((size_t)n * 2);
     HIPCHK(c, hipMemcpy(Y.data(), dY.p, Y.size() * sizeof(float), hipMemcpyDeviceToHost));
@@ -324,6 +360,86 @@ ep_status ep_mlp_grad(ep_ctx *c, const float *X, const float *Y, uint32_t batch,
     return EP_OK;
 }
 
+ep_status ep_mlp_collect(ep_ctx *c, double dt, double eps, uint32_t K, uint64_t first,
+                         uint64_t stride, int32_t reset, uint64_t *n_total)
+{
+    if (!c) return EP_EINVAL;
+    Learned &L = c->mlp;
+    if (L.n_in != 6)
+        return c->fail(EP_ENOTRAINED, "ep_mlp_collect: load a 6-input network first (its feature "
+                                      "scales normalise the samples)");
+    if (!(dt > 0.0) || !(eps > 0.0) || !isfinite(dt) || !isfinite(eps) || K == 0 || stride == 0)
+        return c->fail(EP_EINVAL, "ep_mlp_collect: need dt > 0, eps > 0, K >= 1, stride >= 1");
+    if (c->w <= 0.0) return c->fail(EP_ESTATE, "ep_mlp_collect: no particles loaded");
+    DeviceGuard guard(c->device);
+    if (reset) L.t_n = 0;
+    const uint64_t count = first < c->n ? (c->n - first + stride - 1) / stride : 0;
+    if (count) {
+        ep_status s;
+        if (!c->field_valid && (s = refresh_field(c)) != EP_OK) return s;
+        if (L.t_n + count > L.t_cap) {
+            uint64_t cap = L.t_cap * 2;
+            if (cap < L.t_n + count) cap = L.t_n + count;
+            float *nx = nullptr, *ny = nullptr;
+            HIPCHK(c, dalloc(&nx, (size_t)cap * 6));
+            if (dalloc(&ny, (size_t)cap * 2) != hipSuccess) {
+                (void)hipFree(nx);
+                return c->fail(EP_ENOMEM, "ep_mlp_collect: no device memory for %llu samples",
+                               (unsigned long long)cap);
+            }
+            hipError_t e = hipSuccess;
+            if (L.t_n) {
+                e = hipMemcpyAsync(nx, L.d_tx, L.t_n * 6 * sizeof(float), hipMemcpyDeviceToDevice,
+                                   c->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(ny, L.d_ty, L.t_n * 2 * sizeof(float),
+                                       hipMemcpyDeviceToDevice, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            }
+            if (e != hipSuccess) {
+                (void)hipFree(nx);
+                (void)hipFree(ny);
+                return c->hipfail("ep_mlp_collect: grow the sample buffers", e);
+            }
+            if (L.d_tx) (void)hipFree(L.d_tx);
+            if (L.d_ty) (void)hipFree(L.d_ty);
+            L.d_tx = nx;
+            L.d_ty = ny;
+            L.t_cap = cap;
+        }
+        if ((s = ensure_tables(c, K, 1)) != EP_OK) return s;
+        const double th = dt / eps, phi = fmod(th, kTwoPi);
+        HIPCHK(c, launch_phase_table(c->stream, c->tab, 0.0, phi, th / K, dt / K, (int)K, 1));
+        HIPCHK(c, launch_gen_labels_poisson(
+                      c->stream, c->zR, c->zV, (int64_t)first, (int64_t)stride, (int64_t)count,
+                      make_double2(cos(c->phase), sin(c->phase)), c->mesh(), c->tab.sub, (int)K,
+                      (float)(1.0 / L.norm[0]), (float)cos(phi), (float)sin(phi),
+                      (float)(th / L.norm[1]), (float)(1.0 / L.norm[2]), L.norm[7] == 1.0,
+                      L.d_tx + L.t_n * 6,
+                      L.d_ty + L.t_n * 2));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        L.t_n += count;
+    }
+    if (n_total) *n_total = L.t_n;
+    return EP_OK;
+}
+
+ep_status ep_mlp_get_samples(ep_ctx *c, uint64_t first, uint64_t count, float *X, float *Y)
+{
+    if (!c) return EP_EINVAL;
+    Learned &L = c->mlp;
+    if (first > L.t_n || count > L.t_n - first || (count && (!X || !Y)))
+        return c->fail(EP_EINVAL, "ep_mlp_get_samples: rows [%llu, %llu) outside the %llu "
+                                  "collected samples",
+                       (unsigned long long)first, (unsigned long long)(first + count),
+                       (unsigned long long)L.t_n);
+    if (count == 0) return EP_OK;
+    DeviceGuard guard(c->device);
+    HIPCHK(c, hipMemcpy(X, L.d_tx + first * 6, count * 6 * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(Y, L.d_ty + first * 2, count * 2 * sizeof(float), hipMemcpyDeviceToHost));
+    return EP_OK;
+}
+
 ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, const double *V,
                        uint64_t n, ep_train_report *rep)
 {
@@ -331,31 +447,40 @@ ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, cons
     Learned &L = c->mlp;
     if (L.n_in == 0)
         return c->fail(EP_ENOTRAINED, "ep_mlp_train: load initial weights first");
-    if (!cfg || !R || !V || !rep || cfg->field != EP_FIELD_DUFFING || L.n_in != 5 ||
-        !(cfg->dt > 0.0) || !(cfg->eps > 0.0) || cfg->fine_substeps == 0 || cfg->batch == 0 ||
-        cfg->batch % 64 || cfg->batch > n || cfg->epochs == 0 || !(cfg->lr > 0.0) ||
-        !(cfg->lr_final >= 0.0) || !(cfg->s_in > 0.0))
-        return c->fail(EP_EINVAL, "ep_mlp_train: invalid configuration (Duffing field, 5-input "
-                                  "network, batch a multiple of 64 and <= n, positive rates)");
+    const bool vp = cfg && cfg->field == EP_FIELD_POISSON;
+    if (vp) n = L.t_n;
+    if (!cfg || !rep || (cfg->field != EP_FIELD_DUFFING && !vp) || L.n_in != (vp ? 6 : 5) ||
+        (!vp && (!R || !V)) || !(cfg->dt > 0.0) || !(cfg->eps > 0.0) ||
+        cfg->fine_substeps == 0 || cfg->batch == 0 || cfg->batch % 64 || cfg->batch > n ||
+        cfg->epochs == 0 || !(cfg->lr > 0.0) || !(cfg->lr_final >= 0.0) || !(cfg->s_in > 0.0))
+        return c->fail(EP_EINVAL, "ep_mlp_train: invalid configuration (Duffing field with a "
+                                  "5-input network and given samples, or Poisson field with a "
+                                  "6-input network and collected samples; batch a multiple of "
+                                  "64 and <= the sample count; positive rates)");
     DeviceGuard guard(c->device);
-    const int np = mlp_n_params(5);
-    DevBuf<float> dX, dY, gpart, lpart, dloss;
-    HIPCHK(c, dalloc(&dX.p, (size_t)n * 5));
-    HIPCHK(c, dalloc(&dY.p, (size_t)n * 2));
-    hipEvent_t e0, e1, e2;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    HIPCHK(c, hipEventCreate(&e2));
+    const int n_in = L.n_in;
+    const int np = mlp_n_params(n_in);
+    DevBuf<float> gX, gY, gpart, lpart, dloss;
+    const float *dX = L.d_tx, *dY = L.d_ty;
+    Events ev;
+    hipEvent_t &e0 = ev.e[0], &e1 = ev.e[1], &e2 = ev.e[2];
+    for (hipEvent_t &e : ev.e) HIPCHK(c, hipEventCreate(&e));
     HIPCHK(c, hipEventRecord(e0, c->stream));
-    ep_status s = make_labels(c, cfg->dt, cfg->eps, cfg->fine_substeps, cfg->s_in, R, V, n, dX.p,
-                              dY.p);
-    if (s != EP_OK) return s;
+    if (!vp) {
+        HIPCHK(c, dalloc(&gX.p, (size_t)n * 5));
+        HIPCHK(c, dalloc(&gY.p, (size_t)n * 2));
+        ep_status s = make_labels(c, cfg->dt, cfg->eps, cfg->fine_substeps, cfg->s_in,
+                                  L.norm[7] == 1.0, R, V, n, gX.p, gY.p);
+        if (s != EP_OK) return s;
+        dX = gX.p;
+        dY = gY.p;
+    }
     HIPCHK(c, hipEventRecord(e1, c->stream));
 
     // normalisation of the labels from their first samples
     const uint64_t ns = n < kNormSamples ? n : kNormSamples;
     std::vector<float> Yh((size_t)ns * 2);
-    HIPCHK(c, hipMemcpy(Yh.data(), dY.p, Yh.size() * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(Yh.data(), dY, Yh.size() * sizeof(float), hipMemcpyDeviceToHost));
     double m[2] = {0, 0}, q[2] = {0, 0};
     for (uint64_t i = 0; i < ns; ++i)
         for (int j = 0; j < 2; ++j) m[j] += Yh[2 * i + j];
@@ -367,8 +492,17 @@ ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, cons
         sd[j] = sqrt(q[j] / (double)ns);
         if (!(sd[j] > 0.0)) sd[j] = 1.0;
     }
-    const double norm[8] = {cfg->s_in, kTimeScale, 1.0, m[0], sd[0], m[1], sd[1], 0.0};
-    for (int i = 0; i < 8; ++i) L.norm[i] = norm[i];
+    if (!vp) {
+        // the Duffing features were just made with these scales
+        L.norm[0] = cfg->s_in;
+        L.norm[1] = kTimeScale;
+        L.norm[2] = 1.0;
+    }
+    L.norm[3] = m[0];
+    L.norm[4] = sd[0];
+    L.norm[5] = m[1];
+    L.norm[6] = sd[1];
+    L.packed = false;
     const float nf[4] = {(float)m[0], (float)(1.0 / sd[0]), (float)m[1], (float)(1.0 / sd[1])};
 
     const int batch = (int)cfg->batch;
@@ -380,17 +514,21 @@ ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, cons
     HIPCHK(c, dalloc(&dloss.p, (size_t)T));
     HIPCHK(c, hipMemsetAsync(L.d_m, 0, np * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(L.d_v, 0, np * sizeof(float), c->stream));
-    HIPCHK(c, setup_train_lds(5));
+    HIPCHK(c, setup_train_lds(n_in));
     for (uint64_t t = 0; t < T; ++t) {
         const uint64_t b = t % per_epoch;
+        // Duffing: consecutive i.i.d. samples; collected sets: batch b takes
+        // rows b, b + per_epoch, ..., so that each batch spans all snapshots
+        const int64_t first = vp ? (int64_t)b : (int64_t)(b * batch);
+        const int64_t sstride = vp ? (int64_t)per_epoch : 1;
         const double lr = cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) *
                                               (1.0 + cos(3.141592653589793 * (double)t / (double)T));
         const double bc1 = 1.0 / (1.0 - pow(kAdamB1, (double)(t + 1)));
         const double bc2 = 1.0 / (1.0 - pow(kAdamB2, (double)(t + 1)));
-        HIPCHK(c, launch_mlp_train_step(c->stream, 5, L.d_params, L.d_m, L.d_v, dX.p, dY.p,
-                                        (int64_t)(b * batch), batch, nf, gpart.p, lpart.p,
-                                        L.d_grad, dloss.p + t, (float)lr, (float)kAdamB1,
-                                        (float)kAdamB2, (float)bc1, (float)bc2, (float)kAdamEps));
+        HIPCHK(c, launch_mlp_train_step(c->stream, n_in, L.d_params, L.d_m, L.d_v, dX, dY, first,
+                                        sstride, batch, nf, gpart.p, lpart.p, L.d_grad,
+                                        dloss.p + t, (float)lr, (float)kAdamB1, (float)kAdamB2,
+                                        (float)bc1, (float)bc2, (float)kAdamEps));
     }
     HIPCHK(c, hipEventRecord(e2, c->stream));
     std::vector<float> losses((size_t)T);
@@ -402,9 +540,6 @@ ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, cons
     float ms_label = 0.f, ms_train = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms_label, e0, e1));
     HIPCHK(c, hipEventElapsedTime(&ms_train, e1, e2));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
     double lf = 0.0, ll = 0.0;
     for (uint64_t t = 0; t < per_epoch; ++t) {
         lf += losses[t];

@@ -104,6 +104,25 @@ __device__ void mma64_wave(const float *A, int ai, int ak, const float *B, int b
 
 __device__ __forceinline__ int tile_row(int q, int g) { return 8 * (q >> 2) + 4 * g + (q & 3); }
 
+// Polar form of a step from z0 to z1 (rotating frame, so the free rotation is
+// the identity): delta = angle from z0 to z1 in the direction r advances,
+// kappa = |z1| / |z0| - 1; scaled: (|z0| delta, |z1| - |z0|).
+__device__ __forceinline__ void polar_label(double zr0, double zv0, double zr, double zv,
+                                            int scaled, double &delta, double &kappa)
+{
+    const double n0 = sqrt(zr0 * zr0 + zv0 * zv0), n1 = sqrt(zr * zr + zv * zv);
+    delta = kappa = 0.0;
+    if (n0 > 0.0) {
+        delta = atan2(zr * zv0 - zv * zr0, zr * zr0 + zv * zv0);
+        if (scaled) {
+            delta *= n0;
+            kappa = n1 - n0;
+        } else {
+            kappa = n1 / n0 - 1.0;
+        }
+    }
+}
+
 // ------------------------------------------------------------ labels
 
 // Training pairs for the Duffing field.  Each sample y = (R, V) is pushed one
@@ -114,7 +133,7 @@ __device__ __forceinline__ int tile_row(int q, int g) { return 8 * (q >> 2) + 4 
 __global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
     const float *__restrict__ Rs, const float *__restrict__ Vs, int64_t n,
     const double4 *__restrict__ sub, int K, float inv_sin, float c_phi, float s_phi,
-    float th_scaled, float *__restrict__ X, float *__restrict__ Y)
+    float th_scaled, int scaled, float *__restrict__ X, float *__restrict__ Y)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -130,12 +149,8 @@ __global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
     }
     zr += ar;
     zv += av;
-    const double n0 = sqrt(zr0 * zr0 + zv0 * zv0);
-    double delta = 0.0, kappa = 0.0;
-    if (n0 > 0.0) {
-        delta = atan2(zr * zv0 - zv * zr0, zr * zr0 + zv * zv0);
-        kappa = sqrt(zr * zr + zv * zv) / n0 - 1.0;
-    }
+    double delta, kappa;
+    polar_label(zr0, zv0, zr, zv, scaled, delta, kappa);
     float *x = X + i * 5;
     x[0] = R * inv_sin;
     x[1] = V * inv_sin;
@@ -148,11 +163,71 @@ __global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
 
 hipError_t launch_gen_labels_duffing(hipStream_t st, const float *R, const float *V, int64_t n,
                                      const double4 *sub, int K, float inv_sin, float c_phi,
-                                     float s_phi, float th_scaled, float *X, float *Y)
+                                     float s_phi, float th_scaled, int scaled, float *X, float *Y)
 {
     if (n <= 0) return hipSuccess;
     gen_labels_duffing_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
-        R, V, n, sub, K, inv_sin, c_phi, s_phi, th_scaled, X, Y);
+        R, V, n, sub, K, inv_sin, c_phi, s_phi, th_scaled, scaled, X, Y);
+    return hipGetLastError();
+}
+
+// Training pairs from the self-consistent beam: sample j is particle
+// first + j * stride of the context at time t_n (lab frame y_n = r(Phi_n) z).
+// Its label is the plain push with K_fine substeps (FP64) in the frozen field
+// E^n of the current mesh, started from phase 0 (the frozen-field step is
+// autonomous, so the map does not depend on Phi_n).  Features as for the
+// Duffing field plus E^n(R_n) / s_E, gathered as the inference kernel does.
+__global__ __launch_bounds__(256) void gen_labels_poisson_kernel(
+    const float *__restrict__ zR, const float *__restrict__ zV, int64_t first, int64_t stride,
+    int64_t count, double2 rot0, MeshView m, const double *__restrict__ qb,
+    const double4 *__restrict__ sub, int K, float inv_sin, float c_phi, float s_phi,
+    float th_scaled, float inv_sE, int scaled, float *__restrict__ X, float *__restrict__ Y)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    m.Qb = *qb;
+    const int64_t i = first + j * stride;
+    const double zr_ = zR[i], zv_ = zV[i];
+    const double zr0 = fma(rot0.x, zr_, rot0.y * zv_);
+    const double zv0 = fma(-rot0.y, zr_, rot0.x * zv_);
+    const double E0 = gather(m, zr0);
+    double zr = zr0, zv = zv0;
+    {
+        double a[1] = {zr}, b[1] = {zv};
+        push_group<1>(m, sub, K, a, b);
+        zr = a[0];
+        zv = b[0];
+    }
+    double delta, kappa;
+    polar_label(zr0, zv0, zr, zv, scaled, delta, kappa);
+    float *x = X + j * 6;
+    x[0] = (float)zr0 * inv_sin;
+    x[1] = (float)zv0 * inv_sin;
+    x[2] = c_phi;
+    x[3] = s_phi;
+    x[4] = th_scaled;
+    x[5] = (float)E0 * inv_sE;
+    Y[j * 2] = (float)delta;
+    Y[j * 2 + 1] = (float)kappa;
+}
+
+hipError_t launch_gen_labels_poisson(hipStream_t st, const float *zR, const float *zV,
+                                     int64_t first, int64_t stride, int64_t count, double2 rot0,
+                                     const MeshArgs &ma, const double4 *sub, int K, float inv_sin,
+                                     float c_phi, float s_phi, float th_scaled, float inv_sE,
+                                     int scaled, float *X, float *Y)
+{
+    if (count <= 0) return hipSuccess;
+    MeshView m;
+    m.Et = ma.etab;
+    m.H = nullptr;
+    m.inv_hr = 1.0 / ma.hr;
+    m.half = 0.5 * (double)ma.nr;
+    m.c = ma.nr >> 1;
+    m.Qb = 0.0;   // read on the device from fscal
+    gen_labels_poisson_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(
+        zR, zV, first, stride, count, rot0, m, ma.fscal + kQb, sub, K, inv_sin, c_phi, s_phi,
+        th_scaled, inv_sE, scaled, X, Y);
     return hipGetLastError();
 }
 
@@ -166,15 +241,16 @@ static size_t train_lds_floats(int n_in)
     return (size_t)mlp_n_params(n_in) + kTile * n_in + kTile * 2 + 5 * kTile * kLd + kTile * 2;
 }
 
-// Forward and backward of the MSE loss over one tile of 64 samples
-// (first + tile*64 ...), samples at or beyond `batch` masked out.  Labels are
+// Forward and backward of the MSE loss over one tile of 64 samples: sample s
+// of the batch is row first + s * sstride of X and Y, samples at or beyond
+// `batch` masked out.  Labels are
 // normalised on load, Yn = (Y - mu) * inv_sig.  Writes this tile's gradient
 // (flat parameter order) to gpart[tile] and its sum of squared errors to
 // lpart[tile]; the loss is the mean over the batch and both outputs.
 template <int NIN>
 __global__ __launch_bounds__(256) void mlp_train_kernel(
     const float *__restrict__ params, const float *__restrict__ X, const float *__restrict__ Y,
-    int64_t first, int batch, float mu_d, float is_d, float mu_k, float is_k,
+    int64_t first, int64_t sstride, int batch, float mu_d, float is_d, float mu_k, float is_k,
     float *__restrict__ gpart, float *__restrict__ lpart)
 {
     constexpr int NP = kH * NIN + kH + kH * kH + kH + kOut * kH + kOut;
@@ -199,12 +275,13 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     for (int i = tid; i < NP; i += nt) sP[i] = params[i];
     for (int i = tid; i < kH * kH; i += nt) sW2[(i >> 6) * kLd + (i & 63)] = params[oW2 + i];
     for (int i = tid; i < kTile * NIN; i += nt) {
-        const int s = i / NIN;
-        sX[i] = (s_base + s < batch) ? X[(first + s_base) * NIN + i] : 0.f;
+        const int s = i / NIN, f = i - s * NIN;
+        sX[i] = (s_base + s < batch) ? X[(first + (int64_t)(s_base + s) * sstride) * NIN + f] : 0.f;
     }
     for (int i = tid; i < kTile * 2; i += nt) {
         const int s = i >> 1;
-        const float y = (s_base + s < batch) ? Y[(first + s_base) * 2 + i] : 0.f;
+        const float y =
+            (s_base + s < batch) ? Y[(first + (int64_t)(s_base + s) * sstride) * 2 + (i & 1)] : 0.f;
         sY[i] = (i & 1) ? (y - mu_k) * is_k : (y - mu_d) * is_d;
     }
     __syncthreads();
@@ -370,17 +447,18 @@ hipError_t setup_train_lds(int n_in)
 }
 
 static hipError_t launch_train_tiles(hipStream_t st, int n_in, const float *params,
-                                     const float *X, const float *Y, int64_t first, int batch,
-                                     const float norm[4], float *gpart, float *lpart)
+                                     const float *X, const float *Y, int64_t first,
+                                     int64_t sstride, int batch, const float norm[4],
+                                     float *gpart, float *lpart)
 {
     const int tiles = (batch + kTile - 1) / kTile;
     const size_t lds = train_lds_floats(n_in) * sizeof(float);
     if (n_in == 5)
         mlp_train_kernel<5><<<dim3(tiles), dim3(256), lds, st>>>(
-            params, X, Y, first, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
+            params, X, Y, first, sstride, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
     else
         mlp_train_kernel<6><<<dim3(tiles), dim3(256), lds, st>>>(
-            params, X, Y, first, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
+            params, X, Y, first, sstride, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
     return hipGetLastError();
 }
 
@@ -388,7 +466,8 @@ hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const 
                            const float *Y, int64_t first, int batch, const float norm[4],
                            float *gpart, float *lpart, float *grad, float *loss)
 {
-    hipError_t e = launch_train_tiles(st, n_in, params, X, Y, first, batch, norm, gpart, lpart);
+    hipError_t e =
+        launch_train_tiles(st, n_in, params, X, Y, first, 1, batch, norm, gpart, lpart);
     if (e != hipSuccess) return e;
     const int np = mlp_n_params(n_in), tiles = (batch + kTile - 1) / kTile;
     mlp_grad_reduce_kernel<false><<<dim3((np + 63) / 64), dim3(256), 0, st>>>(
@@ -397,12 +476,13 @@ hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const 
 }
 
 hipError_t launch_mlp_train_step(hipStream_t st, int n_in, float *params, float *m, float *v,
-                                 const float *X, const float *Y, int64_t first, int batch,
-                                 const float norm[4], float *gpart, float *lpart, float *grad,
-                                 float *loss, float lr, float b1, float b2, float bc1, float bc2,
-                                 float eps)
+                                 const float *X, const float *Y, int64_t first, int64_t sstride,
+                                 int batch, const float norm[4], float *gpart, float *lpart,
+                                 float *grad, float *loss, float lr, float b1, float b2, float bc1,
+                                 float bc2, float eps)
 {
-    hipError_t e = launch_train_tiles(st, n_in, params, X, Y, first, batch, norm, gpart, lpart);
+    hipError_t e =
+        launch_train_tiles(st, n_in, params, X, Y, first, sstride, batch, norm, gpart, lpart);
     if (e != hipSuccess) return e;
     const int np = mlp_n_params(n_in), tiles = (batch + kTile - 1) / kTile;
     mlp_grad_reduce_kernel<true><<<dim3((np + 63) / 64), dim3(256), 0, st>>>(
@@ -412,29 +492,89 @@ hipError_t launch_mlp_train_step(hipStream_t st, int n_in, float *params, float 
 
 // ------------------------------------------------------------ inference
 
-constexpr unsigned kLocalQueue = 2048;   // LDS fallback-queue entries per workgroup
+constexpr unsigned kWaveQueue = 512;   // LDS fallback-queue entries per wave
 
-// One learned step of the Duffing beam.  A workgroup of 4 waves takes 128
-// particles per iteration, 32 per wave; lanes l and l+32 share particle l%32
-// and split its hidden units.  Layers 1 and 3 run on VALU (FP32), layer 2 on
-// MFMA with split BF16 operands, one 16-wide k step at a time so that few
-// activations are live.  All weights stay in LDS and are read where used.
-// The update and the energy check H = |z|^2/(2 eps) + R^4/4 run in FP64;
-// particles that fail keep their state and are appended to the fallback
-// queue: first to a queue in LDS, copied out with one global atomic per
-// workgroup at the end, so that the waves never wait on each other.
-__global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
+// Fallback queue of one wave: a segment of LDS and a wave-uniform fill count.
+// A full segment is copied to the global queue with one atomic, so waves
+// never wait on each other.
+struct WaveQueue {
+    unsigned *sq;
+    unsigned qn;
+};
+
+__device__ __forceinline__ void wave_queue_flush(WaveQueue &q, unsigned *qcount, unsigned *queue,
+                                                 int lane)
+{
+    if (q.qn == 0u) return;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    unsigned base = 0u;
+    if (lane == 0) base = atomicAdd(qcount, q.qn);
+    base = __shfl(base, 0, 64);
+    for (unsigned i = (unsigned)lane; i < q.qn; i += 64u) queue[base + i] = q.sq[i];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    q.qn = 0u;
+}
+
+__device__ __forceinline__ void wave_queue_push(WaveQueue &q, bool fail, unsigned p,
+                                                unsigned *qcount, unsigned *queue, int lane)
+{
+    const unsigned long long fm = __ballot(fail);
+    if (fm == 0ull) return;
+    const unsigned cnt = (unsigned)__popcll(fm);
+    if (q.qn + cnt > kWaveQueue) wave_queue_flush(q, qcount, queue, lane);
+    if (fail) q.sq[q.qn + (unsigned)__popcll(fm & ((1ull << lane) - 1ull))] = p;
+    q.qn += cnt;
+}
+
+// Frozen-field potential Psi^n(R) with -dPsi/dR = E^n(R): the exact integral
+// of the CIC field from the FP64 node values (piecewise quadratic on each
+// cell); outside the mesh Psi(+-r_max) - Qb ln(|R| / r_max).
+struct PotView {
+    const double *E, *Psi;
+    double hr, inv_hr, half, rmax, Qb;
+    int c, nr;
+};
+
+__device__ __forceinline__ double potential(const PotView &v, double R)
+{
+    const double x = R * v.inv_hr;
+    if (x >= v.half) return v.Psi[v.nr] - v.Qb * log(R / v.rmax);
+    if (x < -v.half) return v.Psi[0] - v.Qb * log(-R / v.rmax);
+    if (!(x == x)) return x;
+    const double fl = floor(x);
+    const int m = (int)fl + v.c;
+    const double d = (x - fl) * v.hr;
+    const double e0 = v.E[m], e1 = v.E[m + 1];
+    return v.Psi[m] - fma(e0, d, (e1 - e0) * (d * d) * (0.5 * v.inv_hr));
+}
+
+// One learned step.  A workgroup of 4 waves takes 128 particles per
+// iteration, 32 per wave; lanes l and l+32 share particle l%32 and split its
+// hidden units.  Layers 1 and 3 run on VALU (FP32), layer 2 on MFMA with
+// split BF16 operands, one 16-wide k step at a time so that few activations
+// are live.  All weights stay in LDS and are read where used.  The update and
+// the energy check run in FP64: H = |z|^2/(2 eps) + P(R) with P = R^4/4
+// (Duffing) or the frozen-field potential Psi^n (Poisson, VP = true).  With
+// the amplitude-scaled output map the outputs are divided by a = |z| first.
+// Particles that fail keep their state and go to the fallback queue.  With
+// VP the sixth feature is E^n(R_n), and the particles that pass are deposited
+// (CIC, fixed point) into an LDS histogram added to the mesh at the end.
+template <bool VP>
+__global__ __launch_bounds__(256) void mlp_push_kernel(
     float *__restrict__ zR, float *__restrict__ zV, int64_t n, MlpInfer net, double2 rot0,
     double2 rot1, double inv2eps, double tol, unsigned *__restrict__ qcount,
-    unsigned *__restrict__ queue)
+    unsigned *__restrict__ queue, MeshView mv, PotView pv, const double *__restrict__ qb,
+    unsigned long long *__restrict__ hist)
 {
     __shared__ uint4 sAh[8 * 64], sAl[8 * 64];
     __shared__ float4 sl1[kH];
     __shared__ float sb2[kH];
     __shared__ float sw3[kOut * kH];
-    __shared__ unsigned s_q[kLocalQueue], s_qn, s_qbase;
+    __shared__ unsigned s_q[4][kWaveQueue];
+    extern __shared__ __align__(16) unsigned char vp_smem[];
     const int tid = threadIdx.x;
-    if (tid == 0) s_qn = 0u;
     for (int i = tid; i < 8 * 64; i += blockDim.x) {
         sAh[i] = net.w2hi[i];
         sAl[i] = net.w2lo[i];
@@ -444,7 +584,13 @@ __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
         sb2[tid] = net.b2[tid];
     }
     if (tid < kOut * kH) sw3[tid] = net.w3[tid];
+    if (VP) {
+        mv.H = reinterpret_cast<unsigned long long *>(vp_smem);
+        for (int i = tid; i <= pv.nr; i += blockDim.x) mv.H[i] = 0ull;
+        mv.Qb = pv.Qb = *qb;
+    }
     const int lane = tid & 63, wave = tid >> 6, r = lane & 31, g = lane >> 5;
+    WaveQueue wq{s_q[wave], 0u};
     __syncthreads();
 
     const int64_t nbg = (n + 127) >> 7;
@@ -458,6 +604,7 @@ __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
         const double R = fma(rot0.x, zr, rot0.y * zv);
         const double Vl = fma(-rot0.y, zr, rot0.x * zv);
         const float x0 = (float)R, x1 = (float)Vl;
+        const float x2 = VP ? (float)gather(mv, R) : 0.f;
 
         f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
@@ -466,7 +613,9 @@ __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const float4 w = sl1[kk * 16 + g * 8 + e];
-                a[e] = act(fmaf(w.x, x0, fmaf(w.y, x1, w.w)));
+                float z = fmaf(w.x, x0, fmaf(w.y, x1, w.w));
+                if (VP) z = fmaf(w.z, x2, z);
+                a[e] = act(z);
             }
             bf16x8 bh, bl;
             to_bf16x8<true>(a, bh, bl);
@@ -493,48 +642,58 @@ __global__ __launch_bounds__(256) void mlp_push_duffing_kernel(
         }
         o0 += __shfl_xor(o0, 32, 64);
         o1 += __shfl_xor(o1, 32, 64);
-        const float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);
+        float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);
         const float kappa = fmaf(net.sig_k, o1 + net.b3_1, net.mu_k);
+        double sc;
+        if (net.scaled) {
+            // outputs are (a delta, a kappa); nothing moves at a = 0
+            const double a = sqrt(fma(zr, zr, zv * zv));
+            const double inv_a = a > 0.0 ? 1.0 / a : 0.0;
+            delta = (float)((double)delta * inv_a);
+            sc = fma((double)kappa, inv_a, 1.0);
+        } else {
+            sc = 1.0 + (double)kappa;
+        }
         float sd, cd;
         sincosf(delta, &sd, &cd);
-        const double sc = 1.0 + (double)kappa;
         const double nr = sc * fma((double)cd, zr, (double)sd * zv);
         const double nv = sc * fma(-(double)sd, zr, (double)cd * zv);
-        const double H0 = (zr * zr + zv * zv) * inv2eps + 0.25 * (R * R) * (R * R);
         const double R1 = fma(rot1.x, nr, rot1.y * nv);
-        const double H1 = (nr * nr + nv * nv) * inv2eps + 0.25 * (R1 * R1) * (R1 * R1);
+        double P0, P1;
+        if (VP) {
+            P0 = potential(pv, R);
+            P1 = potential(pv, R1);
+        } else {
+            P0 = 0.25 * (R * R) * (R * R);
+            P1 = 0.25 * (R1 * R1) * (R1 * R1);
+        }
+        const double H0 = fma(zr * zr + zv * zv, inv2eps, P0);
+        const double H1 = fma(nr * nr + nv * nv, inv2eps, P1);
         const bool ok = fabs(H1 - H0) <= tol * fabs(H0);
         const bool mine = valid && g == 0;
         if (mine && ok) {
-            zR[p] = (float)nr;
-            zV[p] = (float)nv;
+            const float fr = (float)nr, fv = (float)nv;
+            zR[p] = fr;
+            zV[p] = fv;
+            if (VP) deposit(mv, fma(rot1.x, (double)fr, rot1.y * (double)fv));
         }
-        // failing particles go to the workgroup's LDS queue (one LDS atomic
-        // per wave); slots beyond its capacity take a global slot directly
-        const bool fail = mine && !ok;
-        const unsigned long long fm = __ballot(fail);
-        if (fm) {
-            unsigned base = 0u;
-            if (lane == 0) base = atomicAdd(&s_qn, (unsigned)__popcll(fm));
-            base = __shfl(base, 0, 64);
-            if (fail) {
-                const unsigned slot = base + (unsigned)__popcll(fm & ((1ull << lane) - 1ull));
-                if (slot < kLocalQueue)
-                    s_q[slot] = (unsigned)p;
-                else
-                    queue[atomicAdd(qcount, 1u)] = (unsigned)p;
-            }
+        wave_queue_push(wq, mine && !ok, (unsigned)p, qcount, queue, lane);
+    }
+    wave_queue_flush(wq, qcount, queue, lane);
+    if (VP) {
+        __syncthreads();
+        const int nn = pv.nr + 1;
+        const int start = (int)(((unsigned)blockIdx.x * 131u) % (unsigned)nn);
+        for (int i0 = tid; i0 < nn; i0 += blockDim.x) {
+            int i = i0 + start;
+            if (i >= nn) i -= nn;
+            const unsigned long long v = mv.H[i];
+            if (v) atomicAdd(&hist[i], v);
         }
     }
-    // one global atomic per workgroup for its LDS queue
-    __syncthreads();
-    const unsigned nq = s_qn < kLocalQueue ? s_qn : kLocalQueue;
-    if (tid == 0 && nq) s_qbase = atomicAdd(qcount, nq);
-    __syncthreads();
-    for (unsigned i = tid; i < nq; i += blockDim.x) queue[s_qbase + i] = s_q[i];
 }
 
-// Plain push (K substeps, FP64) of the queued particles.
+// Plain push (K substeps, FP64) of the queued particles, Duffing field.
 __global__ __launch_bounds__(256) void fallback_duffing_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K,
@@ -558,6 +717,58 @@ __global__ __launch_bounds__(256) void fallback_duffing_kernel(
     }
 }
 
+// Plain push (K substeps, FP64, field table in LDS) of the queued particles in
+// the frozen Poisson field, then their CIC deposit at the end-of-step phase.
+__global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
+    float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
+    const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K, double2 er,
+    MeshView mv, const float2 *__restrict__ etab, const double *__restrict__ qb, int nr,
+    unsigned long long *__restrict__ hist, unsigned long long *__restrict__ total)
+{
+    extern __shared__ __align__(16) unsigned char fb_smem[];
+    const unsigned count = *qcount;
+    if (count == 0u) return;   // uniform over the grid: no LDS set-up needed
+    const int tid = threadIdx.x;
+    mv.Et = reinterpret_cast<float2 *>(fb_smem);
+    mv.H = reinterpret_cast<unsigned long long *>(fb_smem + (size_t)nr * sizeof(float2));
+    float2 *Et = reinterpret_cast<float2 *>(fb_smem);
+    for (int i = tid; i < nr; i += blockDim.x) Et[i] = etab[i];
+    for (int i = tid; i <= nr; i += blockDim.x) mv.H[i] = 0ull;
+    mv.Qb = *qb;
+    if (blockIdx.x == 0 && tid == 0) *total += count;
+    __syncthreads();
+    for (unsigned i = blockIdx.x * blockDim.x + tid; i < count; i += gridDim.x * blockDim.x) {
+        const unsigned p = queue[i];
+        double a[1] = {(double)zR[p]}, b[1] = {(double)zV[p]};
+        push_group<1>(mv, sub, K, a, b);
+        const float fr = (float)a[0], fv = (float)b[0];
+        zR[p] = fr;
+        zV[p] = fv;
+        deposit(mv, fma(er.x, (double)fr, er.y * (double)fv));
+    }
+    __syncthreads();
+    const int nn = nr + 1;
+    const int start = (int)(((unsigned)blockIdx.x * 131u) % (unsigned)nn);
+    for (int i0 = tid; i0 < nn; i0 += blockDim.x) {
+        int i = i0 + start;
+        if (i >= nn) i -= nn;
+        const unsigned long long v = mv.H[i];
+        if (v) atomicAdd(&hist[i], v);
+    }
+}
+
+static MeshView mesh_view(const MeshArgs &ma)
+{
+    MeshView m;
+    m.Et = ma.etab;
+    m.H = nullptr;
+    m.inv_hr = 1.0 / ma.hr;
+    m.half = 0.5 * (double)ma.nr;
+    m.c = ma.nr >> 1;
+    m.Qb = 0.0;
+    return m;
+}
+
 hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
                                    const MlpInfer &net, double2 rot0, double2 rot1, double eps,
                                    double tol, unsigned *qcount, unsigned *queue, int n_cu)
@@ -565,8 +776,35 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t
     if (n <= 0) return hipSuccess;
     int64_t grid = (n + 127) / 128;
     if (grid > (int64_t)n_cu * 8) grid = (int64_t)n_cu * 8;
-    mlp_push_duffing_kernel<<<dim3((unsigned)grid), dim3(256), 0, st>>>(
-        zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue);
+    mlp_push_kernel<false><<<dim3((unsigned)grid), dim3(256), 0, st>>>(
+        zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{}, nullptr,
+        nullptr);
+    return hipGetLastError();
+}
+
+static size_t mlp_vp_lds_bytes(int nr) { return (size_t)(nr + 1) * sizeof(unsigned long long); }
+
+hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t n,
+                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
+                                   double tol, unsigned *qcount, unsigned *queue,
+                                   const MeshArgs &ma, double rmax, int n_cu)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t grid = (n + 127) / 128;
+    if (grid > (int64_t)n_cu * 2) grid = (int64_t)n_cu * 2;
+    PotView pv;
+    pv.E = ma.E64;
+    pv.Psi = ma.Psi64;
+    pv.hr = ma.hr;
+    pv.inv_hr = 1.0 / ma.hr;
+    pv.half = 0.5 * (double)ma.nr;
+    pv.rmax = rmax;
+    pv.Qb = 0.0;
+    pv.c = ma.nr >> 1;
+    pv.nr = ma.nr;
+    mlp_push_kernel<true><<<dim3((unsigned)grid), dim3(256), mlp_vp_lds_bytes(ma.nr), st>>>(
+        zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
+        ma.fscal + kQb, ma.hist);
     return hipGetLastError();
 }
 
@@ -577,6 +815,28 @@ hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const u
     fallback_duffing_kernel<<<dim3((unsigned)n_cu * 8), dim3(256), 0, st>>>(zR, zV, queue, qcount,
                                                                          sub, K, total);
     return hipGetLastError();
+}
+
+hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const unsigned *queue,
+                                   const unsigned *qcount, const double4 *sub, int K, double2 er,
+                                   const MeshArgs &ma, unsigned long long *total, int n_cu)
+{
+    const size_t lds = push_lds_bytes_for(ma.nr);
+    fallback_poisson_kernel<<<dim3((unsigned)n_cu), dim3(kPushBlock), lds, st>>>(
+        zR, zV, queue, qcount, sub, K, er, mesh_view(ma), ma.etab, ma.fscal + kQb, ma.nr, ma.hist,
+        total);
+    return hipGetLastError();
+}
+
+hipError_t setup_learned_lds(int nr)
+{
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_push_kernel<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)mlp_vp_lds_bytes(nr));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&fallback_poisson_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)push_lds_bytes_for(nr));
 }
 
 }  // namespace etd

@@ -195,6 +195,7 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     if (per_cu < 1) per_cu = 1;
     c->push_grid_cap = c->n_cu * per_cu;
     CREATE_CHK(setup_mesh_lds((int)cfg->n_cells));
+    CREATE_CHK(setup_learned_lds((int)cfg->n_cells));
 
     const size_t np = (size_t)cfg->n_particles;
     const size_t np_pad = (np + 3) & ~size_t(3);
@@ -319,11 +320,7 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
         c->field_valid = false;
         return EP_OK;
     }
-    if (c->push_mode == EP_PUSH_LEARNED) {
-        if (field != EP_FIELD_DUFFING)
-            return c->fail(EP_EINVAL, "ep_step: the learned push supports the Duffing field");
-        return learned_steps(c, dt, eps, n_steps);
-    }
+    if (c->push_mode == EP_PUSH_LEARNED) return learned_steps(c, dt, eps, field, n_steps);
     if (field == EP_FIELD_POISSON && !c->field_valid) {
         ep_status s = refresh_field(c);
         if (s != EP_OK) return s;

@@ -129,9 +129,11 @@ def _learned_sim(R, V, w, p, norm, tol, K_fb):
     return sim
 
 
-def test_learned_push_without_fallback_is_the_network_map():
+@pytest.mark.parametrize("out_map", [0, 1])
+def test_learned_push_without_fallback_is_the_network_map(out_map):
     R0, V0, w = synth.gaussian(10001, seed=15, sigma=SIG)
     p, norm = _net()
+    norm.out_map = out_map
     sim = _learned_sim(R0, V0, w, p, norm, 1e300, 8)
     R, V = R0.copy(), V0.copy()
     pd = p.astype(np.float64)
@@ -139,7 +141,7 @@ def test_learned_push_without_fallback_is_the_network_map():
     for s in range(3):
         sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
         d, k = mlp.predict(pd, R, V, DT, EPS, norm)
-        R, V = mlp.apply_polar(R, V, DT, EPS, d, k)
+        R, V = mlp.apply_polar(R, V, DT, EPS, d, k, scaled=out_map == 1)
         Rg, Vg = sim.particles()
         err = rel_particle(Rg, Vg, R, V)
         worst = max(worst, err.max())

@@ -58,3 +58,19 @@ def test_equal_error_comparison():
     untrained = abs(np.sqrt(np.mean(R ** 2)) - res["rms_ref"]) / res["rms_ref"]
     print("rms error: trained %.3e, untrained %.3e" % (trained, untrained))
     assert trained < 0.5 * untrained
+
+
+def test_equal_error_comparison_vp():
+    """Vlasov-Poisson: the 6-input corrector trained on self-generated data
+    (reduced sizes).  Training must gain over the untrained network, and the
+    network map (no check) must beat the cheapest plain push in the sweep."""
+    res = compare.equal_error_vp(n_eval=100_000, n_data=100_000, steps=50, nr=1024, epochs=20,
+                                 plain_Ks=(25, 50, 100, 200), K_ref=1600, extra_tols=(),
+                                 log=print)
+    print(json.dumps(res, indent=1))
+    assert res["train"]["loss_last"] < 0.5 * res["train"]["loss_first"]
+    for entry in res["plain"] + res["learned"]:
+        assert np.isfinite(entry["rms_err"]) and entry["particle_steps_per_s"] > 0
+    errs = [p["rms_err"] for p in res["plain"]]
+    assert errs[-1] < errs[0]
+    assert res["learned"][-1]["rms_err"] < errs[0]

@@ -103,6 +103,38 @@ def test_polar_labels_round_trip():
     assert np.all(d3 > -1e-12) and np.max(np.abs(k3)) < 0.02
 
 
+def test_scaled_polar_labels_round_trip_and_scale():
+    """Amplitude-scaled map: (s, rho) = (a delta, a kappa) reproduce the same
+    end point as (delta, kappa); s is the arc length at radius a.  In a
+    frozen self-consistent field the phase advance of small orbits grows like
+    1/a (the field jumps by 2 rho(0) at R = 0) while s stays bounded."""
+    rng = np.random.default_rng(8)
+    R, V, w = synth.gaussian_truncated(4000, seed=8)
+    dt, eps = 0.1, 1e-3
+    d = rng.uniform(-0.5, 0.5, R.size)
+    k = rng.uniform(-0.01, 0.01, R.size)
+    a = np.hypot(R, V)
+    R1, V1 = mlp.apply_polar(R, V, dt, eps, d, k)
+    R2, V2 = mlp.apply_polar(R, V, dt, eps, a * d, a * k, scaled=True)
+    assert np.max(np.hypot(R1 - R2, V1 - V2)) < 1e-12
+    s, rho = mlp.polar_labels(R, V, R1, V1, dt, eps, scaled=True)
+    assert np.max(np.abs(s - a * d)) < 1e-12 and np.max(np.abs(rho - a * k)) < 1e-12
+    # nothing moves at the origin
+    R0, V0 = mlp.apply_polar(np.zeros(1), np.zeros(1), dt, eps, np.ones(1), np.ones(1), True)
+    assert R0[0] == 0.0 and V0[0] == 0.0
+    # frozen Poisson field of the beam, fine plain step
+    nr = 1024
+    rho_n, _ = oracle.deposit(R, w, nr, -5.0, 5.0)
+    E, _, Qb = oracle.poisson(rho_n, nr, -5.0, 5.0)
+    Rf, Vf = oracle.push(R, V, dt, eps, 400, field=oracle.FIELD_POISSON, E=E, Qb=Qb, nr=nr,
+                         rmin=-5.0, rmax=5.0)
+    dl, _ = mlp.polar_labels(R, V, Rf, Vf, dt, eps)
+    sl, _ = mlp.polar_labels(R, V, Rf, Vf, dt, eps, scaled=True)
+    small, mid = a < 0.1, (a > 0.5) & (a < 1.0)
+    assert np.mean(np.abs(dl[small])) > 4 * np.mean(np.abs(dl[mid]))
+    assert np.max(np.abs(sl[small])) < 2 * np.max(np.abs(sl[mid]))
+
+
 def _duffing_fallback(dt, eps, K):
     return lambda R, V: oracle.push(R, V, dt, eps, K, field=oracle.FIELD_DUFFING)
 
