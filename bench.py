@@ -128,7 +128,11 @@ def run_pic(args, deposit, steps, warmup, R0, V0, w):
     n = R0.size
     dep = EP_DEPOSIT_SORTED if deposit == "sorted" else EP_DEPOSIT_ATOMIC
     sim = Sim(n, n_cells=args.cells, substeps=args.substeps, deposit=dep, device=0)
+    sim.sync()
+    t_set = time.perf_counter()
     sim.set_particles(R0, V0, w)
+    sim.sync()
+    t_set = time.perf_counter() - t_set
     for _ in range(warmup):
         sim.step(args.dt, args.eps, EP_FIELD_POISSON, 1)
     sim.sync()
@@ -156,7 +160,15 @@ def run_pic(args, deposit, steps, warmup, R0, V0, w):
             kernels[name] = k
     if mom is None:
         mom = sim.moments(args.eps, EP_FIELD_POISSON)
+    t_get = time.perf_counter()
+    sim.particles()
+    t_get = time.perf_counter() - t_get
     sim.close()
+    # host hand-over through the C ABI (FP64 host arrays <-> FP32 device state),
+    # outside the timed region: the rate if each run started and ended on the host
+    transfer = {"set_particles_s": t_set, "get_particles_s": t_get,
+                "pcie_inclusive_particle_steps_per_s": n * steps / (elapsed + t_set + t_get)}
+    kernels["_transfer"] = transfer
     return n * steps / elapsed, elapsed / steps * 1e3, kernels, mom
 
 
@@ -187,6 +199,7 @@ def main():
         del src, dst
 
     value, ms_step, kernels, mom = run_pic(args, args.deposit, args.steps, args.warmup, R0, V0, w)
+    transfer = kernels.pop("_transfer")
     bw = {k: v for k, v in kernels.items() if "GB_per_s" in v}
     dom = max(bw, key=lambda k: bw[k]["ms_per_launch"] * bw[k]["launches"])
     achieved = bw[dom]["GB_per_s"]
@@ -215,11 +228,13 @@ def main():
                      "launches": bw[dom]["launches"],
                      "bytes_per_launch": bw[dom]["bytes_per_launch"]},
         "kernels": kernels,
+        "host_transfer": transfer,
         "moments": {k: mom[k] for k in ("t", "rms_radius", "energy", "n_offmesh", "n_nan")},
     }
     if not args.no_deposit_comparison:
         other = "sorted" if args.deposit == "atomic" else "atomic"
         v2, ms2, k2, _ = run_pic(args, other, args.comparison_steps, 3, R0, V0, w)
+        k2.pop("_transfer")
         line["deposit_comparison"] = {
             args.deposit: {"particle_steps_per_s": value, "ms_per_step": ms_step},
             other: {"particle_steps_per_s": v2, "ms_per_step": ms2, "kernels": k2}}
