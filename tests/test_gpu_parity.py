@@ -351,3 +351,27 @@ def test_field_replay_vp_1e6():
 def test_field_replay_vp_1e8():
     """N_p = 1e8, N_r = 4096, eps = 1e-3, dt = 0.05, K = 1 (the benchmark shape)."""
     field_replay(100_000_000, 4096, 1e-3, 0.05, 1, 3, 20000, seed=13)
+
+
+def test_statistical_rms_1e8_against_oracle_subsample():
+    """Full physics at scale, pinned statistically: the GPU run at N_p = 1e8
+    (N_r = 4096, eps = 1e-3, dt = 0.05, K = 1) against the oracle's own
+    self-consistent run of the beam's first 1e6 particles (weight 1e-6).  The
+    rms radii agree within 3/sqrt(N_sub) at every recorded step, the sampling
+    noise of the sub-beam."""
+    n, n_sub, steps, every, nr, eps, dt = 100_000_000, 1_000_000, 40, 10, 4096, 1e-3, 0.05
+    R0, V0, w = synth.gaussian_truncated(n, seed=13)
+    Rs, Vs = R0[:n_sub].copy(), V0[:n_sub].copy()
+    gpu = []
+    with Sim(n, n_cells=nr, substeps=1) as sim:
+        sim.set_particles(R0, V0, w)
+        del R0, V0
+        gpu.append(sim.moments(eps, EP_FIELD_POISSON)["rms_radius"])
+        for _ in range(steps // every):
+            sim.step(dt, eps, EP_FIELD_POISSON, every)
+            gpu.append(sim.moments(eps, EP_FIELD_POISSON)["rms_radius"])
+    _, _, mom = oracle.run(Rs, Vs, 1.0 / n_sub, dt, eps, 1, steps, oracle.FIELD_POISSON, nr=nr,
+                           rmin=-RMAX, rmax=RMAX, with_moments=True)
+    orc = mom[::every, 1]
+    rel = np.abs(np.array(gpu) - orc) / orc
+    assert rel.max() <= 3.0 / math.sqrt(n_sub), rel
