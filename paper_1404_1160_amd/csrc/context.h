@@ -80,7 +80,8 @@ struct ep_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int n_cu = 0;
-    int push_grid_cap = 0;
+    int push_grid_cap = 0;           // workgroups of the fused Poisson push
+    int sort_grid_cap = 0;           // workgroups of the sort passes (resident ones)
 
     // particle state (rotating frame, FP32 SoA)
     float *zR = nullptr, *zV = nullptr;

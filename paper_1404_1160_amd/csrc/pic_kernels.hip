@@ -33,6 +33,8 @@
 
 #include "pic_device.h"
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 namespace etd {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -313,32 +315,50 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
     const double2 er = endrot_tab ? endrot_tab[0] : endrot_val;
     __syncthreads();
 
+    // Each thread takes two float4 groups (8 particles) per iteration, with
+    // all four loads in flight before any arithmetic.  The state is streamed
+    // once per step, so loads and stores are nontemporal: they do not displace
+    // the field table and histogram lines that the caches hold.
     const int64_t n4 = n >> 2;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    float4 *zR4 = reinterpret_cast<float4 *>(zR);
-    float4 *zV4 = reinterpret_cast<float4 *>(zV);
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + tid; g < n4; g += stride) {
-        const float4 r4 = zR4[g], v4 = zV4[g];
-        float fr[4] = {r4.x, r4.y, r4.z, r4.w};
-        float fv[4] = {v4.x, v4.y, v4.z, v4.w};
-        if (PUSH) {
-            double zr[4], zv[4];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 2;
+    f32x4 *zR4 = reinterpret_cast<f32x4 *>(zR);
+    f32x4 *zV4 = reinterpret_cast<f32x4 *>(zV);
+    for (int64_t g0 = blockIdx.x * (int64_t)blockDim.x * 2 + tid; g0 < n4; g0 += stride) {
+        f32x4 r4[2], v4[2];
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                zr[p] = fr[p];
-                zv[p] = fv[p];
+        for (int u = 0; u < 2; ++u) {
+            const int64_t i = g0 + (int64_t)u * blockDim.x;
+            if (i < n4) {
+                r4[u] = __builtin_nontemporal_load(&zR4[i]);
+                v4[u] = __builtin_nontemporal_load(&zV4[i]);
             }
-            push_group<4>(m, sub, K, zr, zv);
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                fr[p] = (float)zr[p];
-                fv[p] = (float)zv[p];
-            }
-            zR4[g] = make_float4(fr[0], fr[1], fr[2], fr[3]);
-            zV4[g] = make_float4(fv[0], fv[1], fv[2], fv[3]);
         }
 #pragma unroll
-        for (int p = 0; p < 4; ++p) deposit(m, fma(er.x, (double)fr[p], er.y * (double)fv[p]));
+        for (int u = 0; u < 2; ++u) {
+            const int64_t i = g0 + (int64_t)u * blockDim.x;
+            if (i < n4) {
+                f32x4 fr = r4[u], fv = v4[u];
+                if (PUSH) {
+                    double zr[4], zv[4];
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        zr[p] = fr[p];
+                        zv[p] = fv[p];
+                    }
+                    push_group<4>(m, sub, K, zr, zv);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        fr[p] = (float)zr[p];
+                        fv[p] = (float)zv[p];
+                    }
+                    __builtin_nontemporal_store(fr, &zR4[i]);
+                    __builtin_nontemporal_store(fv, &zV4[i]);
+                }
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    deposit(m, fma(er.x, (double)fr[p], er.y * (double)fv[p]));
+            }
+        }
     }
     // ragged tail: the last n % 4 particles
     const int64_t gt = blockIdx.x * (int64_t)blockDim.x + tid;
@@ -383,7 +403,7 @@ hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, 
     if (n <= 0) return hipSuccess;
     const size_t lds = push_lds_bytes(ma.nr);
     const int64_t n4 = n >> 2;
-    int64_t grid = (n4 + kPushBlock - 1) / kPushBlock;
+    int64_t grid = (n4 + 2 * kPushBlock - 1) / (2 * kPushBlock);
     if (grid > grid_cap) grid = grid_cap;
     if (grid < 1) grid = 1;
     const double inv_hr = 1.0 / ma.hr;

@@ -90,7 +90,7 @@ ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int 
     }
     const int64_t n4 = (int64_t)c->n >> 2;
     int64_t g = (n4 + kPushBlock - 1) / kPushBlock;
-    if (g > c->push_grid_cap) g = c->push_grid_cap;
+    if (g > c->sort_grid_cap) g = c->sort_grid_cap;
     if (g < 1) g = 1;
     const int grid = (int)g;
     SortArgs a;
@@ -193,7 +193,12 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     int per_cu = (int)(lds_cu / lds);
     if (per_cu > 2) per_cu = 2;
     if (per_cu < 1) per_cu = 1;
-    c->push_grid_cap = c->n_cu * per_cu;
+    // The sort passes keep one counter row per workgroup: the resident
+    // workgroups only.  The fused push takes many more workgroups than fit at
+    // once, so that the LDS set-up and histogram flush of some overlap the
+    // streaming of others (16 per CU measured best at 1e8 particles).
+    c->sort_grid_cap = c->n_cu * per_cu;
+    c->push_grid_cap = c->n_cu * 16;
     CREATE_CHK(setup_mesh_lds((int)cfg->n_cells));
     CREATE_CHK(setup_learned_lds((int)cfg->n_cells));
 
@@ -214,7 +219,7 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
         CREATE_CHK(dalloc(&c->ids, np_pad));
         CREATE_CHK(dalloc(&c->ids2, np_pad));
         CREATE_CHK(dalloc(&c->inv, np_pad));
-        CREATE_CHK(dalloc(&c->counts, (size_t)c->push_grid_cap * nn));
+        CREATE_CHK(dalloc(&c->counts, (size_t)c->sort_grid_cap * nn));
         CREATE_CHK(dalloc(&c->total, nn));
         CREATE_CHK(dalloc(&c->starts, nn));
         CREATE_CHK(setup_sort_lds((int)cfg->n_cells));
