@@ -160,6 +160,15 @@ def run_pic(args, deposit, steps, warmup, R0, V0, w):
             kernels[name] = k
     if mom is None:
         mom = sim.moments(args.eps, EP_FIELD_POISSON)
+    # more steps without the timing events (ep_timing_enable clears the table,
+    # read above), for comparison
+    capi.ep_timing_enable(sim.ctx, False)
+    n_plain = min(steps, 200)
+    sim.sync()
+    t1 = time.perf_counter()
+    sim.step(args.dt, args.eps, EP_FIELD_POISSON, n_plain)
+    sim.sync()
+    ms_untimed = (time.perf_counter() - t1) / n_plain * 1e3
     t_get = time.perf_counter()
     sim.particles()
     t_get = time.perf_counter() - t_get
@@ -167,7 +176,8 @@ def run_pic(args, deposit, steps, warmup, R0, V0, w):
     # host hand-over through the C ABI (FP64 host arrays <-> FP32 device state),
     # outside the timed region: the rate if each run started and ended on the host
     transfer = {"set_particles_s": t_set, "get_particles_s": t_get,
-                "pcie_inclusive_particle_steps_per_s": n * steps / (elapsed + t_set + t_get)}
+                "pcie_inclusive_particle_steps_per_s": n * steps / (elapsed + t_set + t_get),
+                "ms_per_step_without_timing_events": ms_untimed}
     kernels["_transfer"] = transfer
     return n * steps / elapsed, elapsed / steps * 1e3, kernels, mom
 

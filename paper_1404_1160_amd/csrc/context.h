@@ -184,12 +184,15 @@ inline hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
         e = hipEventCreate(&ev.second);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = hipEventRecord(ev.first, c->stream);
+    etd::LaunchEvents &le = etd::next_launch_events();
+    le.start = ev.first;
+    le.stop = ev.second;
+    hipError_t e = launch();
+    const bool consumed = le.start == nullptr && le.stop == nullptr;
+    le = etd::LaunchEvents();
     if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(ev.second, c->stream);
-    if (e != hipSuccess) return e;
+    // every timed launcher dispatches through dispatch_k, which takes both
+    if (!consumed) return hipErrorNotSupported;
     c->pending.emplace_back(name, ev);
     return hipSuccess;
 }

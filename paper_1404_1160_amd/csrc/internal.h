@@ -1,10 +1,47 @@
 // Internal launcher declarations shared by the kernels and the host runtime.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace etd {
+
+// Kernel timing: events that the next dispatch of this host thread carries.
+// hipExtLaunchKernel attaches them to the dispatch packet itself, so a timed
+// run adds no marker packets (and no gaps) between kernels.  `start` goes to
+// the first kernel of a timed launcher and `stop` to its last.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents &next_launch_events();
+
+// Launch `kernel`, consuming the pending start event (FIRST) and/or stop
+// event (LAST); with no events pending this is a plain launch.
+template <bool FIRST, bool LAST, typename F, typename... Args>
+inline hipError_t dispatch_k(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                             Args... args)
+{
+    LaunchEvents &ev = next_launch_events();
+    hipEvent_t a = nullptr, b = nullptr;
+    if (FIRST) {
+        a = ev.start;
+        ev.start = nullptr;
+    }
+    if (LAST) {
+        b = ev.stop;
+        ev.stop = nullptr;
+    }
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, a, b, 0u, args...);
+    return hipGetLastError();
+}
+
+template <typename F, typename... Args>
+inline hipError_t dispatch(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                           Args... args)
+{
+    return dispatch_k<true, true>(kernel, grid, block, lds, st, args...);
+}
 
 constexpr int kPushBlock = 1024;       // threads per block of the mesh push kernels
 constexpr int kSolveBlock = 1024;      // threads of the single-block mesh solve

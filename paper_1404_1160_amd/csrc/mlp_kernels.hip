@@ -776,10 +776,9 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t
     if (n <= 0) return hipSuccess;
     int64_t grid = (n + 127) / 128;
     if (grid > (int64_t)n_cu * 8) grid = (int64_t)n_cu * 8;
-    mlp_push_kernel<false><<<dim3((unsigned)grid), dim3(256), 0, st>>>(
-        zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{}, nullptr,
-        nullptr);
-    return hipGetLastError();
+    return dispatch(mlp_push_kernel<false>, dim3((unsigned)grid), dim3(256), 0, st, zR, zV, n, net,
+                    rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{},
+                    (const double *)nullptr, (unsigned long long *)nullptr);
 }
 
 static size_t mlp_vp_lds_bytes(int nr) { return (size_t)(nr + 1) * sizeof(unsigned long long); }
@@ -802,19 +801,17 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
     pv.Qb = 0.0;
     pv.c = ma.nr >> 1;
     pv.nr = ma.nr;
-    mlp_push_kernel<true><<<dim3((unsigned)grid), dim3(256), mlp_vp_lds_bytes(ma.nr), st>>>(
-        zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
-        ma.fscal + kQb, ma.hist);
-    return hipGetLastError();
+    return dispatch(mlp_push_kernel<true>, dim3((unsigned)grid), dim3(256), mlp_vp_lds_bytes(ma.nr),
+                    st, zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma),
+                    pv, (const double *)(ma.fscal + kQb), ma.hist);
 }
 
 hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,
                                    const unsigned *qcount, const double4 *sub, int K,
                                    unsigned long long *total, int n_cu)
 {
-    fallback_duffing_kernel<<<dim3((unsigned)n_cu * 8), dim3(256), 0, st>>>(zR, zV, queue, qcount,
-                                                                         sub, K, total);
-    return hipGetLastError();
+    return dispatch(fallback_duffing_kernel, dim3((unsigned)n_cu * 8), dim3(256), 0, st, zR, zV,
+                    queue, qcount, sub, K, total);
 }
 
 hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const unsigned *queue,
@@ -822,10 +819,9 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
                                    const MeshArgs &ma, unsigned long long *total, int n_cu)
 {
     const size_t lds = push_lds_bytes_for(ma.nr);
-    fallback_poisson_kernel<<<dim3((unsigned)n_cu), dim3(kPushBlock), lds, st>>>(
-        zR, zV, queue, qcount, sub, K, er, mesh_view(ma), ma.etab, ma.fscal + kQb, ma.nr, ma.hist,
-        total);
-    return hipGetLastError();
+    return dispatch(fallback_poisson_kernel, dim3((unsigned)n_cu), dim3(kPushBlock), lds, st, zR, zV,
+                    queue, qcount, sub, K, er, mesh_view(ma), (const float2 *)ma.etab,
+                    (const double *)(ma.fscal + kQb), ma.nr, ma.hist, total);
 }
 
 hipError_t setup_learned_lds(int nr)

@@ -159,9 +159,8 @@ hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
 {
     if (n <= 0 || S <= 0) return hipSuccess;
     const int block = 256;
-    push_duffing_kernel<<<dim3((unsigned)((n + block - 1) / block)), dim3(block), 0, st>>>(
-        zR, zV, n, sub, K, S);
-    return hipGetLastError();
+    return dispatch(push_duffing_kernel, dim3((unsigned)((n + block - 1) / block)), dim3(block), 0,
+                    st, zR, zV, n, sub, K, S);
 }
 
 // ------------------------------------------------------------ mesh solve
@@ -279,9 +278,8 @@ static size_t mesh_lds_bytes(int nr) { return (size_t)2 * (nr + 1) * sizeof(unsi
 
 hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &a)
 {
-    mesh_solve_kernel<<<dim3(1), dim3(kSolveBlock), mesh_lds_bytes(a.nr), st>>>(
-        a.hist, a.nr, a.w, a.hr, a.etab, a.rho64, a.E64, a.Psi64, a.fscal);
-    return hipGetLastError();
+    return dispatch(mesh_solve_kernel, dim3(1), dim3(kSolveBlock), mesh_lds_bytes(a.nr), st, a.hist,
+                    a.nr, a.w, a.hr, a.etab, a.rho64, a.E64, a.Psi64, a.fscal);
 }
 
 // ------------------------------------------------------------ Poisson push + deposit
@@ -409,12 +407,10 @@ hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, 
     const double inv_hr = 1.0 / ma.hr;
     const dim3 g((unsigned)grid), b(kPushBlock);
     if (push)
-        push_poisson_kernel<true><<<g, b, lds, st>>>(zR, zV, n, sub, endrot_tab, endrot_val, K,
-                                                     inv_hr, ma);
-    else
-        push_poisson_kernel<false><<<g, b, lds, st>>>(zR, zV, n, sub, endrot_tab, endrot_val, 0,
-                                                      inv_hr, ma);
-    return hipGetLastError();
+        return dispatch(push_poisson_kernel<true>, g, b, lds, st, zR, zV, n, sub, endrot_tab,
+                        endrot_val, K, inv_hr, ma);
+    return dispatch(push_poisson_kernel<false>, g, b, lds, st, zR, zV, n, sub, endrot_tab,
+                    endrot_val, 0, inv_hr, ma);
 }
 
 size_t push_lds_bytes_for(int nr) { return push_lds_bytes(nr); }

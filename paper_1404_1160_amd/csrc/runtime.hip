@@ -32,6 +32,12 @@ void free_all(ep_ctx *c)
 
 namespace etd {
 
+LaunchEvents &next_launch_events()
+{
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
 hipError_t collect_timing(ep_ctx *c)
 {
     if (c->pending.empty()) return hipSuccess;

@@ -272,38 +272,37 @@ hipError_t setup_sort_lds(int nr)
 
 hipError_t launch_sort_count(hipStream_t st, const SortArgs &a, int grid)
 {
-    sort_pass_kernel<false><<<dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st>>>(
-        a.zR, a.zV, a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
-        nullptr, nullptr, nullptr, nullptr);
-    return hipGetLastError();
+    return dispatch(sort_pass_kernel<false>, dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st,
+                    a.zR, a.zV, a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr,
+                    a.counts, (const unsigned *)nullptr, (float *)nullptr, (float *)nullptr,
+                    (unsigned *)nullptr);
 }
 
 hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid)
 {
     const int nk = a.nr + 1;
-    sort_offsets_kernel<<<dim3((nk + kOffKeys - 1) / kOffKeys), dim3(kOffKeys * kOffChunks), 0,
-                          st>>>(a.counts, grid, nk, a.total);
-    hipError_t e = hipGetLastError();
+    hipError_t e = dispatch_k<true, false>(sort_offsets_kernel, dim3((nk + kOffKeys - 1) / kOffKeys),
+                                           dim3(kOffKeys * kOffChunks), 0, st, a.counts, grid, nk,
+                                           a.total);
     if (e != hipSuccess) return e;
-    sort_starts_kernel<<<dim3(1), dim3(1024), 0, st>>>(a.total, nk, a.starts);
-    return hipGetLastError();
+    return dispatch_k<false, true>(sort_starts_kernel, dim3(1), dim3(1024), 0, st,
+                                   (const unsigned *)a.total, nk, a.starts);
 }
 
 hipError_t launch_sort_scatter(hipStream_t st, const SortArgs &a, int grid)
 {
-    sort_pass_kernel<true><<<dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st>>>(
-        a.zR, a.zV, a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
-        a.starts, a.oR, a.oV, a.oid);
-    return hipGetLastError();
+    return dispatch(sort_pass_kernel<true>, dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st,
+                    a.zR, a.zV, a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr,
+                    a.counts, (const unsigned *)a.starts, a.oR, a.oV, a.oid);
 }
 
 hipError_t launch_sort_reduce(hipStream_t st, const SortArgs &a, const float *zR, const float *zV,
                               int n_cu)
 {
     (void)n_cu;
-    sort_reduce_kernel<<<dim3(a.nr), dim3(256), 0, st>>>(zR, zV, a.starts, a.total, a.endrot,
-                                                         a.inv_hr, a.nr, a.hist);
-    return hipGetLastError();
+    return dispatch(sort_reduce_kernel, dim3(a.nr), dim3(256), 0, st, zR, zV,
+                    (const unsigned *)a.starts, (const unsigned *)a.total, a.endrot, a.inv_hr,
+                    a.nr, a.hist);
 }
 
 hipError_t launch_iota(hipStream_t st, unsigned *ids, int64_t first, int64_t n)
