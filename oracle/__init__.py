@@ -8,6 +8,10 @@ Layout:
   ``pic_oracle.c``  plain C, FP64: CIC deposit, trapezoid Poisson solve, CIC
                     gather, potential, Strang / ETD1 / ETD2RK pushes, moments,
                     whole runs (ctypes bindings below)
+  ``fine_oracle.c`` plain C, FP64: the paper's reference RK4 solver (field
+                    re-solved at every stage) and its improved ETD scheme
+                    (Algorithm 3.4: periods, N_i, o_i, interpolation,
+                    extrapolation)
   ``duffing.py``    exact Duffing solution by Jacobi elliptic functions and the
                     paper's period formulas (appendix A)
   ``mlp.py``        FP64 forward/backward of the learned corrector network
@@ -50,6 +54,11 @@ def lib():
         L.orc_moments.restype = None
         L.orc_run.argtypes = [p, p, i64, d, d, d, i32, i32, i32, i64, i32, d, d, d, p]
         L.orc_run.restype = None
+        L.orc_rk4_run.argtypes = [p, p, i64, d, d, d, i64, i32, d, i32, d, d]
+        L.orc_rk4_run.restype = i32
+        L.orc_improved_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i64, p,
+                                            ctypes.POINTER(ctypes.c_int64)]
+        L.orc_improved_etd_step.restype = i64
         L.orc_threads.argtypes = []
         L.orc_threads.restype = i32
         _lib = L
@@ -130,6 +139,37 @@ def run(R, V, w, dt, eps, K, n_steps, field, scheme=SCHEME_STRANG, nr=0, rmin=0.
     if with_moments:
         return R, V, mom
     return R, V
+
+
+def rk4_run(R, V, w, eps, h, n_steps, field, nr=0, rmin=0.0, rmax=0.0, E0=0.0):
+    """n_steps of the reference RK4 solver (step h); returns new (R, V)."""
+    R = _f64(R).copy()
+    V = _f64(V).copy()
+    if lib().orc_rk4_run(_ptr(R), _ptr(V), R.size, w, eps, h, n_steps, field, E0, nr, rmin,
+                         rmax) != 0:
+        raise MemoryError("orc_rk4_run")
+    return R, V
+
+
+def fine_step(eps):
+    """The paper's reference step 2 pi eps / 100."""
+    return 2.0 * np.pi * eps / 100.0
+
+
+def improved_etd_step(R, V, w, dt, eps, field, nr=0, rmin=0.0, rmax=0.0, E0=0.0, h=None,
+                      max_fine=100000):
+    """One macro step of Algorithm 3.4.  Returns (R, V, T, N, n_unresolved)."""
+    R = _f64(R).copy()
+    V = _f64(V).copy()
+    h = fine_step(eps) if h is None else h
+    T = np.empty(R.size)
+    N = np.empty(R.size, dtype=np.int64)
+    un = lib().orc_improved_etd_step(_ptr(R), _ptr(V), R.size, w, dt, eps, h, field, E0, nr,
+                                     rmin, rmax, max_fine, _ptr(T),
+                                     N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if un < 0:
+        raise MemoryError("orc_improved_etd_step")
+    return R, V, T, N, int(un)
 
 
 def threads():

@@ -1,0 +1,115 @@
+"""Pins of the oracle's reference RK4 solver and improved ETD scheme
+(Algorithm 3.4) against closed forms, the exact Duffing solution and
+invariants.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import duffing
+from paper_1404_1160_amd import synth
+
+NR, RMAX = 256, 5.0
+VP = dict(nr=NR, rmin=-RMAX, rmax=RMAX)
+
+
+def test_rk4_free_rotation_is_the_stability_polynomial():
+    """E = 0: each RK4 step multiplies y by P(hA), A = M/eps, which for M^2 = -I
+    is (1 - z^2/2 + z^4/24) I + (z - z^3/6) M, z = h/eps (textbook RK4
+    stability polynomial of the linear part of eq. 3.1)."""
+    R0, V0, w = synth.gaussian(200, seed=1)
+    eps = 0.05
+    h = oracle.fine_step(eps)
+    z = h / eps
+    a, b = 1 - z * z / 2 + z ** 4 / 24, z - z ** 3 / 6
+    P = np.array([[a, b], [-b, a]])
+    steps = 157
+    Ps = np.linalg.matrix_power(P, steps)
+    R, V = oracle.rk4_run(R0, V0, w, eps, h, steps, oracle.FIELD_ZERO)
+    Rx, Vx = Ps @ np.stack([R0, V0])
+    assert np.max(np.hypot(R - Rx, V - Vx) / np.hypot(R0, V0)) < 1e-13
+
+
+def test_rk4_constant_field_and_duffing_are_fourth_order():
+    R0, V0, w = synth.gaussian(200, seed=2)
+    eps, t = 0.05, 0.8
+    errs = []
+    for steps in (400, 800):
+        h = t / steps
+        R, V = oracle.rk4_run(R0, V0, w, eps, h, steps, oracle.FIELD_DUFFING)
+        Rx, Vx = duffing.solution(R0, V0, eps, t)
+        errs.append(np.max(np.hypot(R - Rx, V - Vx)))
+    assert 12 < errs[0] / errs[1] < 20, errs
+    # constant field: y(t) = (eps E0, 0) + r(t/eps) (y0 - (eps E0, 0))
+    E0, steps = 0.7, 500
+    R, V = oracle.rk4_run(R0, V0, w, eps, t / steps, steps, oracle.FIELD_CONST, E0=E0)
+    c, s = math.cos(t / eps), math.sin(t / eps)
+    Rc = eps * E0 + c * (R0 - eps * E0) + s * V0
+    Vc = -s * (R0 - eps * E0) + c * V0
+    assert np.max(np.hypot(R - Rc, V - Vc)) < 1e-6
+
+
+def test_rk4_coupled_poisson_run_is_symmetric_and_keeps_charge():
+    R0, V0, w = synth.gaussian_truncated(3000, seed=3)
+    eps = 0.01
+    h = oracle.fine_step(eps)
+    Ra, Va = oracle.rk4_run(R0, V0, w, eps, h, 60, oracle.FIELD_POISSON, **VP)
+    Rb, Vb = oracle.rk4_run(-R0, -V0, w, eps, h, 60, oracle.FIELD_POISSON, **VP)
+    assert np.max(np.abs(Ra + Rb)) < 1e-12 and np.max(np.abs(Va + Vb)) < 1e-12
+    rho, off = oracle.deposit(Ra, w, NR, -RMAX, RMAX)
+    assert off == 0 and abs(rho.sum() * (2 * RMAX / NR) - 1.0) < 1e-12
+    # against the plain exponential integrator with many substeps over the
+    # same time (both converge to the characteristics with the field frozen
+    # per RK stage / per step respectively): close, not equal
+    Rp, Vp = oracle.run(R0, V0, w, 60 * h, eps, 400, 1, oracle.FIELD_POISSON, **VP)
+    assert np.sqrt(np.mean((Ra - Rp) ** 2)) < 1e-3
+
+
+def test_periods_match_the_exact_duffing_period_and_the_free_rotation():
+    R0, V0, w = synth.gaussian(500, seed=4)
+    for eps in (0.05, 1e-3):
+        _, _, T, N, un = oracle.improved_etd_step(R0, V0, w, 0.5, eps, oracle.FIELD_DUFFING)
+        assert un == 0
+        assert np.max(np.abs(T / duffing.period(R0, V0, eps) - 1)) < 1e-5
+        _, _, T0, _, _ = oracle.improved_etd_step(R0, V0, w, 0.5, eps, oracle.FIELD_ZERO)
+        assert np.max(np.abs(T0 / (2 * np.pi * eps) - 1)) < 1e-6
+        # dt = N T + o, 0 <= o < T
+        o = 0.5 - N * T
+        assert np.all(o >= 0) and np.all(o < T) and np.all(N >= 1)
+
+
+def test_improved_etd_is_accurate_for_periodic_orbits():
+    """Duffing orbits are periodic, so Approximation 3.1 holds exactly and the
+    scheme reduces to y(t_n + o_i) + N_i (y(t_n + o_i + T_i) - y(t_n + o_i));
+    its error comes only from the period and the interpolation.  Against the
+    exact elliptic solution at dt = 0.5 (the paper's macro step)."""
+    R0, V0, w = synth.gaussian(400, seed=5)
+    for eps in (0.05, 1e-3):
+        R, V, T, N, un = oracle.improved_etd_step(R0, V0, w, 0.5, eps, oracle.FIELD_DUFFING)
+        Rx, Vx = duffing.solution(R0, V0, eps, 0.5)
+        err = np.hypot(R - Rx, V - Vx)
+        # a relative period error dT shifts the phase by 2 pi N dT after N
+        # periods; the quadratic interpolation errors at t_n + o and
+        # t_n + o + T (~ z^3/10 |y|, z = h/eps = 2 pi/100) enter multiplied by N
+        dT = np.abs(T / duffing.period(R0, V0, eps) - 1)
+        z3 = (2 * np.pi / 100) ** 3
+        bound = (2 * np.pi * (N + 1) * dT + (2 * N + 1) * z3 / 10) * np.hypot(Rx, Vx) * 1.5
+        assert np.all(err <= bound), (eps, np.max(err / bound))
+        assert np.median(err / np.maximum(np.hypot(Rx, Vx), 1.0)) < 2e-4
+
+
+def test_improved_etd_vp_step_tracks_the_reference():
+    """Vlasov-Poisson beam, one macro step dt = 10 T of the improved scheme
+    against the reference RK4 run over the same time: the rms radius agrees to
+    the level of the scheme (the periods vary slowly)."""
+    R0, V0, w = synth.gaussian_truncated(4000, seed=6)
+    eps = 0.01
+    dt = 20 * math.pi * eps
+    R, V, T, N, un = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_POISSON, **VP)
+    assert un == 0 and np.all(N >= 8)
+    h = oracle.fine_step(eps)
+    Rr, Vr = oracle.rk4_run(R0, V0, w, eps, h, int(round(dt / h)), oracle.FIELD_POISSON, **VP)
+    rms, rms_r = np.sqrt(np.mean(R ** 2)), np.sqrt(np.mean(Rr ** 2))
+    assert abs(rms / rms_r - 1) < 2e-3
+    assert np.median(np.hypot(R - Rr, V - Vr)) < 0.05
