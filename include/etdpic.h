@@ -61,8 +61,11 @@ typedef enum {
 
 typedef enum {
     EP_PUSH_PLAIN = 0,     /* K-substep midpoint quadrature of the Duhamel term      */
-    EP_PUSH_LEARNED = 1    /* MLP prediction of the Duhamel term, energy-checked,
+    EP_PUSH_LEARNED = 1,   /* MLP prediction of the Duhamel term, energy-checked,
                               with the plain push as fallback                         */
+    EP_PUSH_RK4 = 2,       /* the paper's reference: classic RK4 on eq. 1.4 with a
+                              small step, field re-solved at every stage             */
+    EP_PUSH_IMPROVED_ETD = 3  /* the paper's improved ETD scheme (Algorithm 3.4)     */
 } ep_push;
 
 /* Context configuration (ep_create).
@@ -173,6 +176,32 @@ ep_status ep_get_field(ep_ctx *ctx, double *rho, double *E, double *Psi, double 
  * one for the Poisson field.  Errors: EP_EINVAL, EP_ENOTRAINED. */
 ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
                            uint32_t fallback_substeps);
+
+/* ---------------------------------------------------------------- fine solvers
+ * EP_PUSH_RK4: each macro step dt is K = ceil(dt / h_fine) classic RK4 steps
+ * of size dt / K on y' = (1/eps) M y + (0, E(t, R)) (eq. 1.4, FP64 in the lab
+ * frame); for the Poisson field all particles advance together and the
+ * charge is deposited and the mesh solved again at every stage.
+ * EP_PUSH_IMPROVED_ETD: each macro step is Algorithm 3.4 — per-particle
+ * periods T_i (time between the first and third sign change of V along a
+ * fine RK4 solve from y^n; Remark 3.5), dt = N_i T_i + o_i, a second fine
+ * solve from y^n giving y(t_n + o_i) and y(t_n + o_i + T_i) by quadratic
+ * interpolation through three fine levels (Remark 3.6), and
+ * y^{n+1} = y(t_n + o_i) + N_i (y(t_n + o_i + T_i) - y(t_n + o_i)) (Lemma 3.3).
+ * h_fine <= 0 selects the paper's fine step 2 pi eps / 100 at each ep_step.
+ * max_fine (>= 1) bounds the fine steps of the period search; a particle
+ * without three sign changes by then keeps the free period 2 pi eps and is
+ * counted as unresolved.  The sorted deposit does not support these modes.
+ * Defaults: h_fine = 0, max_fine = 10000.  Errors: EP_EINVAL. */
+ep_status ep_set_fine_solver(ep_ctx *ctx, double h_fine, uint64_t max_fine);
+
+/* After an EP_PUSH_IMPROVED_ETD step: the periods T_i (FP64) and whole
+ * numbers of periods N_i used by the last macro step, for particles
+ * [offset, offset + count) in loaded order, and the number of unresolved
+ * particles of that step (any output may be NULL).  Synchronises.
+ * Errors: EP_EINVAL, EP_ESTATE (no such step yet), EP_EHIP. */
+ep_status ep_get_periods(ep_ctx *ctx, double *T, int64_t *N, uint64_t offset, uint64_t count,
+                         uint64_t *n_unresolved);
 
 /* ---------------------------------------------------------------- learned
  * Learned Duhamel corrector: a 5 -> 64 -> 64 -> 2 network (6 inputs for the

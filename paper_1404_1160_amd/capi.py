@@ -15,7 +15,7 @@ from . import build as _build
 EP_OK, EP_EINVAL, EP_ENOMEM, EP_EHIP, EP_ESTATE, EP_ENOTRAINED, EP_EIO = 0, -1, -2, -3, -4, -5, -6
 EP_FIELD_ZERO, EP_FIELD_DUFFING, EP_FIELD_POISSON = 0, 1, 2
 EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED = 0, 1
-EP_PUSH_PLAIN, EP_PUSH_LEARNED = 0, 1
+EP_PUSH_PLAIN, EP_PUSH_LEARNED, EP_PUSH_RK4, EP_PUSH_IMPROVED_ETD = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EHIP", -4: "EP_ESTATE",
                 -5: "EP_ENOTRAINED", -6: "EP_EIO"}
@@ -26,7 +26,7 @@ EXPORTS = (
     "ep_step", "ep_moments_get", "ep_get_particles", "ep_get_field", "ep_set_push_mode",
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
     "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect", "ep_mlp_get_samples",
-    "ep_save", "ep_load",
+    "ep_save", "ep_load", "ep_set_fine_solver", "ep_get_periods",
 )
 
 
@@ -114,6 +114,9 @@ def lib():
                               ctypes.POINTER(ep_train_report)], i32),
             "ep_mlp_collect": ([vp, d, d, u32, u64, u64, i32, ctypes.POINTER(u64)], i32),
             "ep_mlp_get_samples": ([vp, u64, u64, pf, pf], i32),
+            "ep_set_fine_solver": ([vp, d, u64], i32),
+            "ep_get_periods": ([vp, pd, ctypes.POINTER(ctypes.c_int64), u64, u64,
+                                ctypes.POINTER(u64)], i32),
             "ep_save": ([vp, ctypes.c_char_p], i32),
             "ep_load": ([vp, ctypes.c_char_p, ctypes.POINTER(u64)], i32),
         }
@@ -293,6 +296,21 @@ def ep_mlp_get_samples(ctx, first, count):
     Y = np.empty((count, 2), dtype=np.float32)
     _check(ctx, lib().ep_mlp_get_samples(ctx, int(first), int(count), _pf(X), _pf(Y)))
     return X, Y
+
+
+def ep_set_fine_solver(ctx, h_fine=0.0, max_fine=10000):
+    """Fine step of the reference RK4 and improved-ETD modes (<= 0: 2 pi eps/100)."""
+    _check(ctx, lib().ep_set_fine_solver(ctx, float(h_fine), int(max_fine)))
+
+
+def ep_get_periods(ctx, count, offset=0):
+    """(T [count] FP64, N [count] int64, n_unresolved) of the last improved-ETD step."""
+    T = np.empty(count)
+    N = np.empty(count, dtype=np.int64)
+    un = ctypes.c_uint64(0)
+    _check(ctx, lib().ep_get_periods(ctx, _p(T), N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     int(offset), int(count), ctypes.byref(un)))
+    return T, N, int(un.value)
 
 
 def ep_save(ctx, path):

@@ -150,6 +150,7 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
     c->fallback_K = h.fallback_K;
     c->drift_tol = h.drift_tol;
     c->field_valid = false;
+    c->periods_valid = false;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (n_particles) *n_particles = h.n;
     return EP_OK;

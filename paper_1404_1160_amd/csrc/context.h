@@ -132,6 +132,13 @@ struct ep_ctx {
     double t = 0.0, phase = 0.0;
     uint64_t n_steps = 0;
 
+    // fine solvers (reference RK4, improved ETD)
+    double h_fine = 0.0;
+    uint64_t max_fine = 10000;
+    etd::FineArgs fine{};
+    uint64_t fine_cap = 0;
+    bool periods_valid = false;
+
     // push mode
     int push_mode = EP_PUSH_PLAIN;
     double drift_tol = 1e-5;
@@ -204,5 +211,8 @@ ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int 
 void free_learned(ep_ctx *c);
 // Learned push of n_steps steps (Duffing field); defined with the learned API.
 ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps);
+// Reference RK4 or improved ETD steps (push modes EP_PUSH_RK4 / _IMPROVED_ETD).
+ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps);
+void free_fine(ep_ctx *c);
 
 }  // namespace etd

@@ -1,0 +1,196 @@
+// Host side of the paper's own solvers: the reference RK4 solver and the
+// improved ETD scheme (Algorithm 3.4), push modes EP_PUSH_RK4 and
+// EP_PUSH_IMPROVED_ETD of ep_step.
+
+#include "context.h"
+
+using namespace etd;
+
+namespace {
+
+constexpr long long kSearchChunk = 16;   // period-search steps between progress checks
+
+ep_status ensure_fine(ep_ctx *c, bool coupled)
+{
+    FineArgs &a = c->fine;
+    if (c->fine_cap >= c->n && a.T && (!coupled || a.yR)) return EP_OK;
+    free_fine(c);
+    const size_t n = (size_t)(c->n ? c->n : 1);
+    HIPCHK(c, dalloc(&a.T, n));
+    HIPCHK(c, dalloc(&a.N, n));
+    HIPCHK(c, dalloc(&a.done, (size_t)3));
+    a.last = a.done + 1;
+    a.unresolved = a.done + 2;
+    if (coupled) {
+        for (double **p : {&a.yR, &a.yV, &a.sR, &a.sV, &a.aR, &a.aV, &a.pR, &a.pV, &a.cR, &a.cV,
+                           &a.dR, &a.dV, &a.t1, &a.o})
+            HIPCHK(c, dalloc(p, n));
+        HIPCHK(c, dalloc(&a.cnt, n));
+    }
+    c->fine_cap = c->n;
+    return EP_OK;
+}
+
+uint64_t read_counter(ep_ctx *c, const unsigned long long *d, hipError_t &e)
+{
+    unsigned long long v = 0;
+    e = hipMemcpyAsync(&v, d, sizeof v, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return v;
+}
+
+// Field of the start level (FP64 positions y) into the mesh.
+ep_status start_field(ep_ctx *c, const MeshArgs &ma)
+{
+    HIPCHK(c, timed_launch(c, "fine_deposit", [&] {
+               return launch_fine_deposit(c->stream, c->fine.yR, (int64_t)c->n, ma,
+                                          c->push_grid_cap);
+           }));
+    HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, ma); }));
+    return EP_OK;
+}
+
+// One coupled RK4 step to level L: four stages, each followed by a solve.
+ep_status coupled_step(ep_ctx *c, int mode, double h, double eps, long long L, const MeshArgs &ma)
+{
+    for (int stage = 1; stage <= 4; ++stage) {
+        HIPCHK(c, timed_launch(c, "fine_stage", [&] {
+                   return launch_rk4_stage(c->stream, stage, mode, c->fine, (int64_t)c->n, h, eps,
+                                           L, ma, c->push_grid_cap);
+               }));
+        HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, ma); }));
+    }
+    return EP_OK;
+}
+
+}  // namespace
+
+namespace etd {
+
+void free_fine(ep_ctx *c)
+{
+    FineArgs &a = c->fine;
+    for (void *p : {(void *)a.yR, (void *)a.yV, (void *)a.sR, (void *)a.sV, (void *)a.aR,
+                    (void *)a.aV, (void *)a.pR, (void *)a.pV, (void *)a.cR, (void *)a.cV,
+                    (void *)a.dR, (void *)a.dV, (void *)a.t1, (void *)a.T, (void *)a.o,
+                    (void *)a.cnt, (void *)a.N, (void *)a.done})
+        if (p) (void)hipFree(p);
+    a = FineArgs();
+    c->fine_cap = 0;
+    c->periods_valid = false;
+}
+
+ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps)
+{
+    const bool ietd = c->push_mode == EP_PUSH_IMPROVED_ETD;
+    const bool coupled = field == EP_FIELD_POISSON;
+    const double h = c->h_fine > 0.0 ? c->h_fine : kTwoPi * eps / 100.0;
+    const double dphi = fmod(dt / eps, kTwoPi);
+    ep_status s = ensure_fine(c, coupled);
+    if (s != EP_OK) return s;
+    const MeshArgs ma = c->mesh();
+    const int64_t n = (int64_t)c->n;
+    FineArgs &a = c->fine;
+    hipError_t e = hipSuccess;
+    for (uint64_t step = 0; step < n_steps; ++step) {
+        const double p0 = c->phase, p1 = fmod(c->phase + dphi, kTwoPi);
+        const double2 rot0 = make_double2(cos(p0), sin(p0)), rot1 = make_double2(cos(p1), sin(p1));
+        if (!ietd) {
+            long long K = (long long)ceil(dt / h - 1e-9);
+            if (K < 1) K = 1;
+            const double hk = dt / (double)K;
+            if (!coupled) {
+                HIPCHK(c, timed_launch(c, "rk4_duffing", [&] {
+                           return launch_rk4_duffing(c->stream, c->zR, c->zV, n, hk, eps, K, rot0,
+                                                     rot1);
+                       }));
+            } else {
+                HIPCHK(c, launch_fine_begin(c->stream, a, c->zR, c->zV, n, rot0, 0, eps));
+                if ((s = start_field(c, ma)) != EP_OK) return s;
+                for (long long L = 1; L <= K; ++L)
+                    if ((s = coupled_step(c, 0, hk, eps, L, ma)) != EP_OK) return s;
+                HIPCHK(c, launch_fine_end(c->stream, a, c->zR, c->zV, n, rot1, 0));
+            }
+        } else if (!coupled) {
+            HIPCHK(c, hipMemsetAsync(a.unresolved, 0, sizeof(unsigned long long), c->stream));
+            HIPCHK(c, timed_launch(c, "ietd_duffing", [&] {
+                       return launch_ietd_duffing(c->stream, c->zR, c->zV, n, dt, h, eps,
+                                                  (long long)c->max_fine, rot0, rot1, a.T, a.N,
+                                                  a.unresolved);
+                   }));
+        } else {
+            // (a) period search, all particles in lock step until every one
+            // has its third sign change of V (or max_fine steps)
+            HIPCHK(c, hipMemsetAsync(a.done, 0, 3 * sizeof(unsigned long long), c->stream));
+            HIPCHK(c, launch_fine_begin(c->stream, a, c->zR, c->zV, n, rot0, 1, eps));
+            if ((s = start_field(c, ma)) != EP_OK) return s;
+            long long L = 0;
+            while (L < (long long)c->max_fine) {
+                long long chunk = kSearchChunk;
+                if (chunk > (long long)c->max_fine - L) chunk = (long long)c->max_fine - L;
+                for (long long j = 0; j < chunk; ++j)
+                    if ((s = coupled_step(c, 1, h, eps, ++L, ma)) != EP_OK) return s;
+                const uint64_t done = read_counter(c, a.done, e);
+                if (e != hipSuccess) return c->hipfail("ep_step: period search", e);
+                if (done >= c->n) break;
+            }
+            // (b) dt = N T + o, and the last fine level the captures need
+            HIPCHK(c, launch_ietd_split(c->stream, a, n, dt, h));
+            const uint64_t last = read_counter(c, a.last, e);
+            if (e != hipSuccess) return c->hipfail("ep_step: split", e);
+            // (c) second solve from y^n with the captures, (d) combination
+            HIPCHK(c, launch_fine_begin(c->stream, a, c->zR, c->zV, n, rot0, 2, eps));
+            if ((s = start_field(c, ma)) != EP_OK) return s;
+            for (long long Lc = 1; Lc <= (long long)last; ++Lc)
+                if ((s = coupled_step(c, 2, h, eps, Lc, ma)) != EP_OK) return s;
+            HIPCHK(c, launch_fine_end(c->stream, a, c->zR, c->zV, n, rot1, 1));
+        }
+        c->phase = p1;
+        c->t += dt;
+        c->n_steps += 1;
+    }
+    c->periods_valid = ietd && n_steps > 0;
+    c->field_valid = false;
+    return EP_OK;
+}
+
+}  // namespace etd
+
+extern "C" {
+
+ep_status ep_set_fine_solver(ep_ctx *c, double h_fine, uint64_t max_fine)
+{
+    if (!c) return EP_EINVAL;
+    if (!(h_fine == h_fine) || !isfinite(h_fine) || max_fine == 0)
+        return c->fail(EP_EINVAL, "ep_set_fine_solver: need a finite h_fine and max_fine >= 1");
+    c->h_fine = h_fine;
+    c->max_fine = max_fine;
+    return EP_OK;
+}
+
+ep_status ep_get_periods(ep_ctx *c, double *T, int64_t *N, uint64_t offset, uint64_t count,
+                         uint64_t *n_unresolved)
+{
+    if (!c) return EP_EINVAL;
+    if (!c->periods_valid)
+        return c->fail(EP_ESTATE, "ep_get_periods: no improved-ETD step since the particles "
+                                  "were set");
+    if (offset > c->n || count > c->n - offset)
+        return c->fail(EP_EINVAL, "ep_get_periods: range outside the %llu particles",
+                       (unsigned long long)c->n);
+    DeviceGuard guard(c->device);
+    if (count && T)
+        HIPCHK(c, hipMemcpyAsync(T, c->fine.T + offset, count * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+    if (count && N)
+        HIPCHK(c, hipMemcpyAsync(N, c->fine.N + offset, count * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, c->stream));
+    unsigned long long un = 0;
+    HIPCHK(c, hipMemcpyAsync(&un, c->fine.unresolved, sizeof un, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (n_unresolved) *n_unresolved = un;
+    return EP_OK;
+}
+
+}  // extern "C"

@@ -196,6 +196,38 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
                                    const MeshArgs &ma, unsigned long long *total, int n_cu);
 hipError_t setup_learned_lds(int nr);
 
+// ------------------------------------------------------------ fine solvers
+// Per-particle FP64 state of the lock-step fine solves (Poisson field).
+struct FineArgs {
+    double *yR, *yV;            // current fine level
+    double *sR, *sV;            // RK4 stage state
+    double *aR, *aV;            // RK4 accumulator k1 + 2 k2 + 2 k3
+    double *pR, *pV;            // level L-2 (captures)
+    double *cR, *cV, *dR, *dV;  // captured y(t_n + o) and y(t_n + o + T)
+    double *t1, *T, *o;         // first sign change, period, remainder
+    int *cnt;                   // sign changes found
+    long long *N;               // whole periods
+    unsigned long long *done, *last, *unresolved;  // [1] each
+};
+hipError_t launch_rk4_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double h,
+                              double eps, long long steps, double2 rot0, double2 rot1);
+hipError_t launch_ietd_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double dt,
+                               double h, double eps, long long max_fine, double2 rot0,
+                               double2 rot1, double *T, long long *N,
+                               unsigned long long *unresolved);
+// stage 1-4 of the coupled RK4 step to level L; mode 0 reference, 1 period
+// search, 2 captures
+hipError_t launch_rk4_stage(hipStream_t st, int stage, int mode, const FineArgs &a, int64_t n,
+                            double h, double eps, long long L, const MeshArgs &ma, int grid_cap);
+hipError_t launch_fine_deposit(hipStream_t st, const double *yR, int64_t n, const MeshArgs &ma,
+                               int grid_cap);
+hipError_t launch_fine_begin(hipStream_t st, const FineArgs &a, const float *zR, const float *zV,
+                             int64_t n, double2 rot0, int mode, double eps);
+hipError_t launch_ietd_split(hipStream_t st, const FineArgs &a, int64_t n, double dt, double h);
+hipError_t launch_fine_end(hipStream_t st, const FineArgs &a, float *zR, float *zV, int64_t n,
+                           double2 rot1, int ietd);
+hipError_t setup_fine_lds(int nr);
+
 hipError_t launch_moments(hipStream_t st, const float *zR, const float *zV, int64_t n,
                           double c, double s, double rmax, double *partial,
                           unsigned long long *pcount, int grid, double *out,

@@ -25,6 +25,7 @@ void free_all(ep_ctx *c)
         (void)hipEventDestroy(ev.second);
     }
     free_learned(c);
+    free_fine(c);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
@@ -207,6 +208,7 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     c->push_grid_cap = c->n_cu * 16;
     CREATE_CHK(setup_mesh_lds((int)cfg->n_cells));
     CREATE_CHK(setup_learned_lds((int)cfg->n_cells));
+    CREATE_CHK(setup_fine_lds((int)cfg->n_cells));
 
     const size_t np = (size_t)cfg->n_particles;
     const size_t np_pad = (np + 3) & ~size_t(3);
@@ -288,6 +290,7 @@ ep_status ep_set_particles(ep_ctx *c, const double *R, const double *V, uint64_t
     c->n = n;
     c->w = w;
     c->field_valid = false;
+    c->periods_valid = false;
     return EP_OK;
 }
 
@@ -306,6 +309,7 @@ ep_status ep_bind_particles(ep_ctx *c, float *zR_dev, float *zV_dev, uint64_t n,
     c->n = n;
     c->w = w;
     c->field_valid = false;
+    c->periods_valid = false;
     return EP_OK;
 }
 
@@ -332,6 +336,8 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
         return EP_OK;
     }
     if (c->push_mode == EP_PUSH_LEARNED) return learned_steps(c, dt, eps, field, n_steps);
+    if (c->push_mode == EP_PUSH_RK4 || c->push_mode == EP_PUSH_IMPROVED_ETD)
+        return fine_steps(c, dt, eps, field, n_steps);
     if (field == EP_FIELD_POISSON && !c->field_valid) {
         ep_status s = refresh_field(c);
         if (s != EP_OK) return s;
@@ -492,8 +498,13 @@ ep_status ep_get_field(ep_ctx *c, double *rho, double *E, double *Psi, double *Q
 ep_status ep_set_push_mode(ep_ctx *c, int32_t push, double drift_tol, uint32_t fallback_substeps)
 {
     if (!c) return EP_EINVAL;
-    if (push != EP_PUSH_PLAIN && push != EP_PUSH_LEARNED)
+    if (push != EP_PUSH_PLAIN && push != EP_PUSH_LEARNED && push != EP_PUSH_RK4 &&
+        push != EP_PUSH_IMPROVED_ETD)
         return c->fail(EP_EINVAL, "ep_set_push_mode: unknown push mode");
+    if ((push == EP_PUSH_RK4 || push == EP_PUSH_IMPROVED_ETD) &&
+        c->cfg.deposit == EP_DEPOSIT_SORTED)
+        return c->fail(EP_EINVAL, "ep_set_push_mode: the fine solvers do not support the sorted "
+                                  "deposit");
     if (push == EP_PUSH_LEARNED) {
         if (c->mlp.n_in == 0)
             return c->fail(EP_ENOTRAINED, "ep_set_push_mode: no corrector network loaded");

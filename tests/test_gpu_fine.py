@@ -1,0 +1,132 @@
+"""The paper's own solvers on the GPU against the FP64 oracle: the reference
+RK4 solver (EP_PUSH_RK4) and the improved ETD scheme (Algorithm 3.4,
+EP_PUSH_IMPROVED_ETD), for the Duffing and the self-consistent field.
+
+Tolerances: per particle 1e-6 max(|y|, 1) (FP32 storage of the state between
+macro steps, FP64 arithmetic on both sides; for the Poisson field the GPU
+gathers from its FP32 field table).  Periods: relative 1e-9 (Duffing, same
+FP64 arithmetic) and 1e-6 (Poisson).  N_i is an integer decided by
+floor(dt / T_i): compared exactly where dt / T_i is not within 1e-6 of a
+whole number; the particles where it is are checked to be valid either way.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1404_1160_amd import (EP_DEPOSIT_SORTED, EP_FIELD_DUFFING, EP_FIELD_POISSON,
+                                 EP_PUSH_IMPROVED_ETD, EP_PUSH_RK4, Sim, capi, synth)
+
+pytestmark = pytest.mark.gpu
+
+NR, RMAX = 256, 5.0
+VP = dict(nr=NR, rmin=-RMAX, rmax=RMAX)
+
+
+def rel(Rg, Vg, Ro, Vo):
+    return np.hypot(Rg - Ro, Vg - Vo) / np.maximum(np.hypot(Ro, Vo), 1.0)
+
+
+def _sim(R0, V0, w, mode, nr=NR, **fine):
+    sim = Sim(R0.size, n_cells=nr, substeps=1)
+    sim.set_particles(R0, V0, w)
+    capi.ep_set_push_mode(sim.ctx, mode)
+    capi.ep_set_fine_solver(sim.ctx, **fine)
+    return sim
+
+
+def test_rk4_duffing_matches_oracle():
+    R0, V0, w = synth.gaussian(10001, seed=51)
+    eps, dt = 0.05, 0.1
+    h = oracle.fine_step(eps)
+    K = math.ceil(dt / h - 1e-9)
+    with _sim(R0, V0, w, EP_PUSH_RK4) as sim:
+        R, V = R0, V0
+        for s in range(3):
+            sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+            Ro, Vo = oracle.rk4_run(R, V, w, eps, dt / K, K, oracle.FIELD_DUFFING)
+            Rg, Vg = sim.particles()
+            assert rel(Rg, Vg, Ro, Vo).max() <= 1e-6, s
+            R, V = Rg, Vg
+
+
+def test_rk4_poisson_matches_oracle():
+    R0, V0, w = synth.gaussian_truncated(20001, seed=52)
+    eps = 0.01
+    h = oracle.fine_step(eps)
+    dt = 12 * h
+    with _sim(R0, V0, w, EP_PUSH_RK4) as sim:
+        R, V = R0, V0
+        for s in range(2):
+            sim.step(dt, eps, EP_FIELD_POISSON, 1)
+            Ro, Vo = oracle.rk4_run(R, V, w, eps, dt / 12, 12, oracle.FIELD_POISSON, **VP)
+            Rg, Vg = sim.particles()
+            assert rel(Rg, Vg, Ro, Vo).max() <= 1e-6, s
+            R, V = Rg, Vg
+
+
+def _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, t_tol):
+    assert np.max(np.abs(Tg / To - 1)) <= t_tol
+    x = dt / To
+    clear = np.abs(x - np.round(x)) > 1e-6
+    assert np.array_equal(Ng[clear], No[clear])
+    assert np.all(np.abs(Ng - No) <= 1)
+    err = rel(Rg, Vg, Ro, Vo)
+    same = Ng == No
+    return err[same].max()
+
+
+def test_improved_etd_duffing_matches_oracle():
+    R0, V0, w = synth.gaussian(10001, seed=53)
+    for eps, dt in ((0.05, 0.5), (1e-3, 0.5)):
+        with _sim(R0, V0, w, EP_PUSH_IMPROVED_ETD) as sim:
+            sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+            Rg, Vg = sim.particles()
+            Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
+        Ro, Vo, To, No, uno = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING)
+        assert un == uno == 0
+        worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, 1e-9)
+        assert worst <= 1e-6, (eps, worst)
+
+
+def test_improved_etd_poisson_matches_oracle():
+    R0, V0, w = synth.gaussian_truncated(4001, seed=54)
+    eps = 0.01
+    dt = 20 * math.pi * eps
+    with _sim(R0, V0, w, EP_PUSH_IMPROVED_ETD) as sim:
+        sim.step(dt, eps, EP_FIELD_POISSON, 1)
+        Rg, Vg = sim.particles()
+        Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
+    Ro, Vo, To, No, uno = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_POISSON, **VP)
+    assert un == uno == 0
+    worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, 1e-6)
+    assert worst <= 1e-5, worst
+
+
+def test_improved_etd_unresolved_particle_keeps_the_free_period():
+    R0, V0, w = synth.gaussian(1001, seed=55)
+    R0[7] = V0[7] = 0.0          # stays at rest: V never changes sign
+    eps, dt = 0.05, 0.5
+    with _sim(R0, V0, w, EP_PUSH_IMPROVED_ETD, max_fine=400) as sim:
+        sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+        Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
+        Rg, Vg = sim.particles()
+    _, _, To, No, uno = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING,
+                                                 max_fine=400)
+    assert un == uno == 1
+    assert Tg[7] == pytest.approx(2 * math.pi * eps, rel=1e-15) and Rg[7] == 0 and Vg[7] == 0
+
+
+def test_fine_modes_reject_sorted_deposit_and_early_period_query():
+    with Sim(16, n_cells=NR, deposit=EP_DEPOSIT_SORTED) as sim:
+        with pytest.raises(capi.EtdpicError) as e:
+            capi.ep_set_push_mode(sim.ctx, EP_PUSH_IMPROVED_ETD)
+        assert e.value.status == capi.EP_EINVAL
+    R0, V0, w = synth.gaussian(100, seed=56)
+    with _sim(R0, V0, w, EP_PUSH_IMPROVED_ETD) as sim:
+        with pytest.raises(capi.EtdpicError) as e:
+            capi.ep_get_periods(sim.ctx, 10)
+        assert e.value.status == capi.EP_ESTATE
+        with pytest.raises(capi.EtdpicError):
+            capi.ep_set_fine_solver(sim.ctx, 0.0, 0)
