@@ -24,7 +24,11 @@ with
   learned_vs_plain_vp -- the same for the Vlasov-Poisson beam (N_r = 4096,
                   eps = 1e-3, dt = 0.1, 6-input network trained on samples
                   self-generated from a plain run of a 1e6-particle beam,
-                  evaluated on 1e7 particles).
+                  evaluated on 1e7 particles);
+  paper_schemes -- the paper's improved ETD scheme (Algorithm 3.4) and the
+                  plain push against its RK4 reference on its initial beam
+                  (eq. 2.7), eps = 1e-3, dt = 0.5 (Duffing 1e6 particles,
+                  Vlasov-Poisson 1e5).
 """
 import argparse
 import hashlib
@@ -63,6 +67,8 @@ def parse():
     ap.add_argument("--comparison-steps", type=int, default=50)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the plain-vs-learned equal-error comparison")
+    ap.add_argument("--no-paper-schemes", action="store_true",
+                    help="skip the reference-RK4 / improved-ETD measurement")
     ap.add_argument("--learned-train", type=int, default=10_000_000)
     ap.add_argument("--learned-eval", type=int, default=10_000_000)
     ap.add_argument("--learned-vp-data", type=int, default=1_000_000,
@@ -242,6 +248,14 @@ def main():
         "moments": {k: mom[k] for k in ("t", "rms_radius", "energy", "n_offmesh", "n_nan")},
     }
     if not args.no_deposit_comparison:
+        # the other eps of the at-scale configuration, same beam and mesh
+        other_eps = 1e-2 if args.eps != 1e-2 else 1e-3
+        a2 = argparse.Namespace(**vars(args))
+        a2.eps = other_eps
+        v3, ms3, k3, _ = run_pic(a2, args.deposit, args.comparison_steps, 3, R0, V0, w)
+        k3.pop("_transfer")
+        line["eps_comparison"] = {"eps": other_eps, "particle_steps_per_s": v3,
+                                  "ms_per_step": ms3, "kernels": k3}
         other = "sorted" if args.deposit == "atomic" else "atomic"
         v2, ms2, k2, _ = run_pic(args, other, args.comparison_steps, 3, R0, V0, w)
         k2.pop("_transfer")
@@ -258,6 +272,13 @@ def main():
         print("bench: learned-vs-plain comparison, Vlasov-Poisson", file=sys.stderr, flush=True)
         line["learned_vs_plain_vp"] = compare.equal_error_vp(
             n_eval=args.learned_eval, n_data=args.learned_vp_data,
+            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    if not args.no_paper_schemes:
+        from paper_1404_1160_amd import compare
+        print("bench: the paper's schemes (reference RK4, improved ETD)", file=sys.stderr,
+              flush=True)
+        line["paper_schemes"] = compare.paper_schemes(
+            n_duffing=1_000_000, n_vp=100_000, steps_duffing=20, steps_vp=2,
             log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cells, args.eps, args.dt, args.substeps,

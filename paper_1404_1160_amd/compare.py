@@ -265,3 +265,64 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     out["equal_error"] = _equal_error_point(plain, learned[0])
     out["equal_error_no_check"] = _equal_error_point(plain, learned[-1])
     return out
+
+
+# ------------------------------------------------------------ the paper's own schemes
+
+def _run_scheme(R0, V0, w, field, mode, dt, eps, steps, nr=VP_NR, substeps=1):
+    """Returns (R, V, seconds, extra) after `steps` macro steps of `mode`."""
+    with Sim(R0.size, n_cells=nr, substeps=substeps) as sim:
+        sim.set_particles(R0, V0, w)
+        capi.ep_set_push_mode(sim.ctx, mode)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.step(dt, eps, field, steps)
+        sim.sync()
+        el = time.perf_counter() - t0
+        extra = {}
+        if mode == capi.EP_PUSH_IMPROVED_ETD:
+            T, N, un = capi.ep_get_periods(sim.ctx, R0.size)
+            extra = {"N_median": float(np.median(N)), "N_min": int(N.min()),
+                     "N_max": int(N.max()), "unresolved": un}
+        R, V = sim.particles()
+    return R, V, el, extra
+
+
+def paper_schemes(n_duffing=1_000_000, n_vp=100_000, eps=1e-3, dt=0.5, steps_duffing=20,
+                  steps_vp=4, plain_K=(100, 400), nr=1024, log=None):
+    """The improved ETD scheme (Algorithm 3.4) and the plain exponential
+    integrator against the paper's reference (RK4 with step 2 pi eps / 100,
+    field re-solved at every stage), on the paper's initial beam (eq. 2.7),
+    eps = 1e-3, dt = 0.5: particle-steps/s (macro steps) and the relative
+    rms-radius and median particle errors at the end against the reference."""
+    def say(msg):
+        if log:
+            log(msg)
+
+    out = {}
+    for field, name, n, steps in ((EP_FIELD_DUFFING, "duffing", n_duffing, steps_duffing),
+                                  (EP_FIELD_POISSON, "poisson", n_vp, steps_vp)):
+        R0, V0, w = synth.paper_f0(n, seed=18)
+        Rr, Vr, el_ref, _ = _run_scheme(R0, V0, w, field, capi.EP_PUSH_RK4, dt, eps, steps, nr)
+        rms_ref = float(np.sqrt(np.mean(Rr ** 2)))
+        res = {"n": n, "steps": steps, "t_end": steps * dt, "eps": eps, "dt": dt,
+               "reference": {"scheme": "RK4, step 2 pi eps/100",
+                             "particle_steps_per_s": n * steps / el_ref}}
+
+        def score(R, V, el):
+            return {"particle_steps_per_s": n * steps / el,
+                    "rms_err": abs(float(np.sqrt(np.mean(R ** 2))) - rms_ref) / rms_ref,
+                    "median_particle_err": float(np.median(np.hypot(R - Rr, V - Vr)))}
+
+        R, V, el, extra = _run_scheme(R0, V0, w, field, capi.EP_PUSH_IMPROVED_ETD, dt, eps, steps,
+                                      nr)
+        res["improved_etd"] = dict(score(R, V, el), **extra)
+        for K in plain_K:
+            R, V, el, _ = _run_scheme(R0, V0, w, field, capi.EP_PUSH_PLAIN, dt, eps, steps, nr,
+                                      substeps=K)
+            res["plain_K%d" % K] = score(R, V, el)
+        say("%s: reference %.3e, improved ETD %.3e particle-steps/s (rms err %.2e)" % (
+            name, res["reference"]["particle_steps_per_s"],
+            res["improved_etd"]["particle_steps_per_s"], res["improved_etd"]["rms_err"]))
+        out[name] = res
+    return out
