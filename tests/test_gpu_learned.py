@@ -6,10 +6,11 @@ Tolerances:
   * gradients (BF16 MFMA products, FP32 accumulation) against the FP64 oracle
     at the same FP32 weights and inputs: per tensor relative Frobenius error
     <= 2^-6 and cosine >= 0.9995
-  * learned step without fallback: the network runs in FP32 with split-BF16
-    layer-2 operands (each operand kept to ~2^-16 relative), so the outputs
-    o carry errors ~1e-5 |o|; a particle's error is sig_d |d o| |y|: the test
-    bound is 5e-5 max(|y|, 1) for sig_d = 0.05
+  * learned step without fallback: layer 2 multiplies split-BF16 weights
+    (~2^-16) by activations rounded to BF16 (relative 2^-9); summed over 64
+    hidden units with weights ~0.1-0.2 this gives output errors up to ~2e-3
+    in o, and a particle's error is sig_d |d o| (scaled map) or
+    sig_d |d o| |y|: the test bound is 3e-4 max(|y|, 1) for sig_d = 0.05
   * fallback: the plain push, per particle 1e-6 as for the plain path.
 """
 import math
@@ -145,7 +146,7 @@ def test_learned_push_without_fallback_is_the_network_map(out_map):
         Rg, Vg = sim.particles()
         err = rel_particle(Rg, Vg, R, V)
         worst = max(worst, err.max())
-        assert err.max() <= 5e-5, (s, err.max())
+        assert err.max() <= 3e-4, (s, err.max())
         R, V = Rg, Vg      # continue from the GPU state: compare one step at a time
     assert sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"] == 0
     sim.close()
@@ -198,7 +199,7 @@ def test_check_decisions_agree_with_oracle():
     assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
     err = rel_particle(Rg, Vg, Ro, Vo)
     assert np.max(err[clear & fb]) <= 1e-6
-    assert np.max(err[clear & ~fb]) <= 5e-5
+    assert np.max(err[clear & ~fb]) <= 3e-4
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
 
 

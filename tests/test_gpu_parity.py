@@ -191,6 +191,26 @@ def test_poisson_full_run_moments():
                 assert rel <= TOL_RUN, (s, key, m[key], mom[s, col])
 
 
+def test_poisson_full_run_moments_at_config_size():
+    """The Vlasov-Poisson configuration at its own size: N_p = 1e6, N_r = 256,
+    eps = 0.01, dt = 0.05, 2000 steps, K = 1: rms radius and energy within
+    1e-4 of the oracle every 250 steps."""
+    R0, V0, w = synth.gaussian_truncated(1_000_000, seed=12)
+    eps, dt, nr, K, n = 0.01, 0.05, 256, 1, 2000
+    _, _, mom = oracle.run(R0, V0, w, dt, eps, K, n, oracle.FIELD_POISSON, nr=nr, rmin=-RMAX,
+                           rmax=RMAX, with_moments=True)
+    with Sim(R0.size, n_cells=nr, substeps=K) as sim:
+        sim.set_particles(R0, V0, w)
+        for s in range(0, n + 1, 250):
+            if s:
+                sim.step(dt, eps, EP_FIELD_POISSON, 250)
+            m = sim.moments(eps, EP_FIELD_POISSON)
+            for key, col in (("rms_radius", 1), ("energy", 2)):
+                rel = abs(m[key] - mom[s, col]) / abs(mom[s, col])
+                assert rel <= TOL_RUN, (s, key, m[key], mom[s, col])
+            assert m["n_nan"] == 0
+
+
 def test_poisson_changing_dt_and_eps_mid_run():
     R0, V0, w = synth.gaussian_truncated(5001, seed=13)
     nr, K = 256, 2
