@@ -65,7 +65,9 @@ typedef enum {
                               with the plain push as fallback                         */
     EP_PUSH_RK4 = 2,       /* the paper's reference: classic RK4 on eq. 1.4 with a
                               small step, field re-solved at every stage             */
-    EP_PUSH_IMPROVED_ETD = 3  /* the paper's improved ETD scheme (Algorithm 3.4)     */
+    EP_PUSH_IMPROVED_ETD = 3, /* the paper's improved ETD scheme (Algorithm 3.4)     */
+    EP_PUSH_CLASSIC_ETD = 4,  /* Algorithm 2.1 with the fast period 2 pi eps          */
+    EP_PUSH_MODIFIED_ETD = 5  /* Algorithm 2.1 with the mean of the particles' periods */
 } ep_push;
 
 /* Context configuration (ep_create).
@@ -188,6 +190,10 @@ ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
  * solve from y^n giving y(t_n + o_i) and y(t_n + o_i + T_i) by quadratic
  * interpolation through three fine levels (Remark 3.6), and
  * y^{n+1} = y(t_n + o_i) + N_i (y(t_n + o_i + T_i) - y(t_n + o_i)) (Lemma 3.3).
+ * EP_PUSH_CLASSIC_ETD / EP_PUSH_MODIFIED_ETD: Algorithm 2.1 with a common
+ * period P (2 pi eps, or the mean of the periods T_i found as above):
+ * dt = N P + o, y(t_n + P) by ceil(P / h_fine) equal RK4 steps, y(t_n + N P) =
+ * y^n + N (y(t_n + P) - y^n), then ceil(o / h_fine) equal steps over o.
  * h_fine <= 0 selects the paper's fine step 2 pi eps / 100 at each ep_step.
  * max_fine (>= 1) bounds the fine steps of the period search; a particle
  * without three sign changes by then keeps the free period 2 pi eps and is
@@ -195,8 +201,9 @@ ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
  * Defaults: h_fine = 0, max_fine = 10000.  Errors: EP_EINVAL. */
 ep_status ep_set_fine_solver(ep_ctx *ctx, double h_fine, uint64_t max_fine);
 
-/* After an EP_PUSH_IMPROVED_ETD step: the periods T_i (FP64) and whole
- * numbers of periods N_i used by the last macro step, for particles
+/* After an EP_PUSH_IMPROVED_ETD or EP_PUSH_MODIFIED_ETD step: the periods
+ * T_i (FP64) and whole numbers of periods N_i (the common N for the modified
+ * scheme) used by the last macro step, for particles
  * [offset, offset + count) in loaded order, and the number of unresolved
  * particles of that step (any output may be NULL).  Synchronises.
  * Errors: EP_EINVAL, EP_ESTATE (no such step yet), EP_EHIP. */

@@ -9,9 +9,10 @@ Layout:
                     gather, potential, Strang / ETD1 / ETD2RK pushes, moments,
                     whole runs (ctypes bindings below)
   ``fine_oracle.c`` plain C, FP64: the paper's reference RK4 solver (field
-                    re-solved at every stage) and its improved ETD scheme
+                    re-solved at every stage), its improved ETD scheme
                     (Algorithm 3.4: periods, N_i, o_i, interpolation,
-                    extrapolation)
+                    extrapolation) and the classic / modified ETD scheme
+                    (Algorithm 2.1 with 2 pi eps or the mean period)
   ``duffing.py``    exact Duffing solution by Jacobi elliptic functions and the
                     paper's period formulas (appendix A)
   ``mlp.py``        FP64 forward/backward of the learned corrector network
@@ -59,6 +60,9 @@ def lib():
         L.orc_improved_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i64, p,
                                             ctypes.POINTER(ctypes.c_int64)]
         L.orc_improved_etd_step.restype = i64
+        L.orc_classic_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i32, i64,
+                                           p, p]
+        L.orc_classic_etd_step.restype = i64
         L.orc_threads.argtypes = []
         L.orc_threads.restype = i32
         _lib = L
@@ -170,6 +174,24 @@ def improved_etd_step(R, V, w, dt, eps, field, nr=0, rmin=0.0, rmax=0.0, E0=0.0,
     if un < 0:
         raise MemoryError("orc_improved_etd_step")
     return R, V, T, N, int(un)
+
+
+def classic_etd_step(R, V, w, dt, eps, field, modified, nr=0, rmin=0.0, rmax=0.0, E0=0.0,
+                     h=None, max_fine=100000):
+    """One macro step of Algorithm 2.1 with the period 2 pi eps (modified =
+    False) or the particles' mean period (modified = True).
+    Returns (R, V, P, T, n_unresolved); T is the periods (modified) or None."""
+    R = _f64(R).copy()
+    V = _f64(V).copy()
+    h = fine_step(eps) if h is None else h
+    T = np.empty(R.size)
+    P = ctypes.c_double(0.0)
+    un = lib().orc_classic_etd_step(_ptr(R), _ptr(V), R.size, w, dt, eps, h, field, E0, nr, rmin,
+                                    rmax, 1 if modified else 0, max_fine, _ptr(T),
+                                    ctypes.byref(P))
+    if un < 0:
+        raise MemoryError("orc_classic_etd_step")
+    return R, V, P.value, (T if modified else None), int(un)
 
 
 def threads():

@@ -22,6 +22,13 @@
  *    (d) y_i^{n+1} = y_i(t_n + o_i) + N_i (y_i(t_n + o_i + T_i) - y_i(t_n + o_i))
  *        (Lemma 3.3).
  *
+ * 3. The classic ETD scheme (Algorithm 2.1) with a common fast period P, and
+ *    its modified form, P = the mean over the particles of their periods T_i
+ *    (section 2): dt = N P + o; a reference solve over P from y^n gives
+ *    y(t_n + P); y(t_n + N P) = y^n + N (y(t_n + P) - y^n) (its step 2); a
+ *    reference solve over o from there gives y^{n+1}.  The solves over P and
+ *    o take ceil(P / h) and ceil(o / h) equal steps (at least one for o > 0).
+ *
  * Readings where the paper is silent:
  *   - a sign change of V between fine levels k and k+1 is (V_k < 0) !=
  *     (V_{k+1} < 0); its time is found by linear interpolation of V between
@@ -162,6 +169,107 @@ static int64_t near_level(double tau, double h)
 {
     int64_t j = (int64_t)floor(tau / h + 0.5);
     return j < 1 ? 1 : j;
+}
+
+/* Period search: the reference solve from (R, V) until every particle's
+ * velocity has changed sign three times or max_fine steps; T[i] receives the
+ * time from the first to the third change (2 pi eps if not found).  Returns
+ * the number of unresolved particles.  buf: 3n doubles, cnt: n ints (zeroed
+ * here), work: 6n doubles. */
+static int64_t period_search(const double *R, const double *V, int64_t n, double eps, double h,
+                             field_ctx *f, int64_t max_fine, double *T, double *buf, int *cnt,
+                             double *work)
+{
+    const size_t nn = (size_t)n;
+    double *Rw = buf, *Vw = buf + nn, *t1 = buf + 2 * nn;
+    double *Vp = work + 4 * nn;   /* the part of work rk4_step leaves alone */
+    memcpy(Rw, R, sizeof(double) * nn);
+    memcpy(Vw, V, sizeof(double) * nn);
+    memset(cnt, 0, sizeof(int) * nn);
+    for (int64_t i = 0; i < n; ++i) T[i] = 2.0 * M_PI * eps;
+    int64_t done = 0, steps = 0;
+    while (done < n && steps < max_fine) {
+        memcpy(Vp, Vw, sizeof(double) * nn);
+        rk4_step(Rw, Vw, n, eps, h, f, work);
+        for (int64_t i = 0; i < n; ++i) {
+            if (cnt[i] >= 3 || (Vp[i] < 0.0) == (Vw[i] < 0.0)) continue;
+            const double ts = (double)steps * h + h * Vp[i] / (Vp[i] - Vw[i]);
+            cnt[i] += 1;
+            if (cnt[i] == 1) t1[i] = ts;
+            if (cnt[i] == 3) {
+                T[i] = ts - t1[i];
+                ++done;
+            }
+        }
+        ++steps;
+    }
+    return n - done;
+}
+
+/* Reference solve over a duration d in ceil(d / h) equal steps. */
+static void solve_for(double *R, double *V, int64_t n, double eps, double d, double h,
+                      field_ctx *f, double *work)
+{
+    if (!(d > 0.0)) return;
+    int64_t K = (int64_t)ceil(d / h - 1e-9);
+    if (K < 1) K = 1;
+    const double hk = d / (double)K;
+    for (int64_t k = 0; k < K; ++k) rk4_step(R, V, n, eps, hk, f, work);
+}
+
+/* One macro step of the classic ETD scheme (Algorithm 2.1) with the period
+ * 2 pi eps (modified = 0) or with the mean period of the particles
+ * (modified = 1; T receives the periods).  *P_out receives the period used.
+ * Returns the number of unresolved particles (modified), or -1 without
+ * memory. */
+int64_t orc_classic_etd_step(double *R, double *V, int64_t n, double w, double dt, double eps,
+                             double h, int kind, double E0, int nr, double rmin, double rmax,
+                             int modified, int64_t max_fine, double *T, double *P_out)
+{
+    if (n <= 0) return 0;
+    field_ctx f;
+    const size_t nn = (size_t)n;
+    double *work = (double *)malloc(sizeof(double) * 6 * nn);
+    double *buf = (double *)malloc(sizeof(double) * 5 * nn);
+    int *cnt = (int *)calloc(nn, sizeof(int));
+    if (!work || !buf || !cnt || field_init(&f, kind, E0, w, nr, rmin, rmax) != 0) {
+        free(work);
+        free(buf);
+        free(cnt);
+        return -1;
+    }
+    double P = 2.0 * M_PI * eps;
+    int64_t unresolved = 0;
+    if (modified) {
+        unresolved = period_search(R, V, n, eps, h, &f, max_fine, T, buf, cnt, work);
+        double sum = 0.0;
+        for (int64_t i = 0; i < n; ++i) sum += T[i];
+        P = sum / (double)n;
+    }
+    double q = floor(dt / P), o = dt - q * P;
+    if (o < 0.0) {
+        q -= 1.0;
+        o += P;
+    }
+    if (o >= P) {
+        q += 1.0;
+        o -= P;
+    }
+    double *Rp = buf + 3 * nn, *Vp = buf + 4 * nn;
+    memcpy(Rp, R, sizeof(double) * nn);
+    memcpy(Vp, V, sizeof(double) * nn);
+    solve_for(Rp, Vp, n, eps, P, h, &f, work);                 /* y(t_n + P)   */
+    for (int64_t i = 0; i < n; ++i) {                           /* y(t_n + N P) */
+        R[i] = R[i] + q * (Rp[i] - R[i]);
+        V[i] = V[i] + q * (Vp[i] - V[i]);
+    }
+    solve_for(R, V, n, eps, o, h, &f, work);                    /* y(t_{n+1})   */
+    if (P_out) *P_out = P;
+    field_free(&f);
+    free(work);
+    free(buf);
+    free(cnt);
+    return unresolved;
 }
 
 /* One macro step of the improved ETD scheme (Algorithm 3.4).  On return R, V

@@ -15,7 +15,8 @@ from . import build as _build
 EP_OK, EP_EINVAL, EP_ENOMEM, EP_EHIP, EP_ESTATE, EP_ENOTRAINED, EP_EIO = 0, -1, -2, -3, -4, -5, -6
 EP_FIELD_ZERO, EP_FIELD_DUFFING, EP_FIELD_POISSON = 0, 1, 2
 EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED = 0, 1
-EP_PUSH_PLAIN, EP_PUSH_LEARNED, EP_PUSH_RK4, EP_PUSH_IMPROVED_ETD = 0, 1, 2, 3
+(EP_PUSH_PLAIN, EP_PUSH_LEARNED, EP_PUSH_RK4, EP_PUSH_IMPROVED_ETD, EP_PUSH_CLASSIC_ETD,
+ EP_PUSH_MODIFIED_ETD) = 0, 1, 2, 3, 4, 5
 
 STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EHIP", -4: "EP_ESTATE",
                 -5: "EP_ENOTRAINED", -6: "EP_EIO"}

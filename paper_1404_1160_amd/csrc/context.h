@@ -138,6 +138,7 @@ struct ep_ctx {
     etd::FineArgs fine{};
     uint64_t fine_cap = 0;
     bool periods_valid = false;
+    double last_period = 0.0;        // common period P of the last classic/modified ETD step
 
     // push mode
     int push_mode = EP_PUSH_PLAIN;

@@ -1,6 +1,7 @@
-// Host side of the paper's own solvers: the reference RK4 solver and the
-// improved ETD scheme (Algorithm 3.4), push modes EP_PUSH_RK4 and
-// EP_PUSH_IMPROVED_ETD of ep_step.
+// Host side of the paper's own solvers: the reference RK4 solver, the
+// improved ETD scheme (Algorithm 3.4) and the classic / modified ETD scheme
+// (Algorithm 2.1), push modes EP_PUSH_RK4, EP_PUSH_IMPROVED_ETD,
+// EP_PUSH_CLASSIC_ETD and EP_PUSH_MODIFIED_ETD of ep_step.
 
 #include "context.h"
 
@@ -9,6 +10,7 @@ using namespace etd;
 namespace {
 
 constexpr long long kSearchChunk = 16;   // period-search steps between progress checks
+constexpr int kRedBlocks = 256;          // partial sums of the mean-period reduction
 
 ep_status ensure_fine(ep_ctx *c, bool coupled)
 {
@@ -21,6 +23,7 @@ ep_status ensure_fine(ep_ctx *c, bool coupled)
     HIPCHK(c, dalloc(&a.done, (size_t)3));
     a.last = a.done + 1;
     a.unresolved = a.done + 2;
+    HIPCHK(c, dalloc(&a.red, (size_t)(kRedBlocks + 1)));
     if (coupled) {
         for (double **p : {&a.yR, &a.yV, &a.sR, &a.sV, &a.aR, &a.aV, &a.pR, &a.pV, &a.cR, &a.cV,
                            &a.dR, &a.dV, &a.t1, &a.o})
@@ -63,6 +66,30 @@ ep_status coupled_step(ep_ctx *c, int mode, double h, double eps, long long L, c
     return EP_OK;
 }
 
+// Period search in lock step from the state z at phase rot0: until every
+// particle has its third sign change of V, or max_fine fine steps.
+ep_status coupled_period_search(ep_ctx *c, double h, double eps, double2 rot0, const MeshArgs &ma)
+{
+    FineArgs &a = c->fine;
+    const int64_t n = (int64_t)c->n;
+    hipError_t e = hipSuccess;
+    ep_status s;
+    HIPCHK(c, hipMemsetAsync(a.done, 0, 3 * sizeof(unsigned long long), c->stream));
+    HIPCHK(c, launch_fine_begin(c->stream, a, c->zR, c->zV, n, rot0, 1, eps));
+    if ((s = start_field(c, ma)) != EP_OK) return s;
+    long long L = 0;
+    while (L < (long long)c->max_fine) {
+        long long chunk = kSearchChunk;
+        if (chunk > (long long)c->max_fine - L) chunk = (long long)c->max_fine - L;
+        for (long long j = 0; j < chunk; ++j)
+            if ((s = coupled_step(c, 1, h, eps, ++L, ma)) != EP_OK) return s;
+        const uint64_t done = read_counter(c, a.done, e);
+        if (e != hipSuccess) return c->hipfail("ep_step: period search", e);
+        if (done >= c->n) break;
+    }
+    return EP_OK;
+}
+
 }  // namespace
 
 namespace etd {
@@ -73,7 +100,7 @@ void free_fine(ep_ctx *c)
     for (void *p : {(void *)a.yR, (void *)a.yV, (void *)a.sR, (void *)a.sV, (void *)a.aR,
                     (void *)a.aV, (void *)a.pR, (void *)a.pV, (void *)a.cR, (void *)a.cV,
                     (void *)a.dR, (void *)a.dV, (void *)a.t1, (void *)a.T, (void *)a.o,
-                    (void *)a.cnt, (void *)a.N, (void *)a.done})
+                    (void *)a.cnt, (void *)a.N, (void *)a.done, (void *)a.red})
         if (p) (void)hipFree(p);
     a = FineArgs();
     c->fine_cap = 0;
@@ -83,6 +110,8 @@ void free_fine(ep_ctx *c)
 ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps)
 {
     const bool ietd = c->push_mode == EP_PUSH_IMPROVED_ETD;
+    const bool modified = c->push_mode == EP_PUSH_MODIFIED_ETD;
+    const bool classic = modified || c->push_mode == EP_PUSH_CLASSIC_ETD;
     const bool coupled = field == EP_FIELD_POISSON;
     const double h = c->h_fine > 0.0 ? c->h_fine : kTwoPi * eps / 100.0;
     const double dphi = fmod(dt / eps, kTwoPi);
@@ -95,7 +124,61 @@ ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n
     for (uint64_t step = 0; step < n_steps; ++step) {
         const double p0 = c->phase, p1 = fmod(c->phase + dphi, kTwoPi);
         const double2 rot0 = make_double2(cos(p0), sin(p0)), rot1 = make_double2(cos(p1), sin(p1));
-        if (!ietd) {
+        if (classic) {
+            // Algorithm 2.1 with P = 2 pi eps, or with the mean period
+            double P = kTwoPi * eps;
+            if (modified) {
+                HIPCHK(c, hipMemsetAsync(a.done, 0, 3 * sizeof(unsigned long long), c->stream));
+                if (!coupled) {
+                    HIPCHK(c, timed_launch(c, "period_duffing", [&] {
+                               return launch_period_duffing(c->stream, c->zR, c->zV, n, h, eps,
+                                                            (long long)c->max_fine, rot0, a.T,
+                                                            a.unresolved);
+                           }));
+                } else {
+                    if ((s = coupled_period_search(c, h, eps, rot0, ma)) != EP_OK) return s;
+                    HIPCHK(c, launch_ietd_split(c->stream, a, n, dt, h));   // counts unresolved
+                }
+                HIPCHK(c, launch_sum(c->stream, a.T, n, a.red, kRedBlocks, a.red + kRedBlocks));
+                double sum = 0.0;
+                HIPCHK(c, hipMemcpyAsync(&sum, a.red + kRedBlocks, sizeof sum,
+                                         hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                P = sum / (double)n;
+            }
+            double q = floor(dt / P), o = dt - q * P;
+            if (o < 0.0) {
+                q -= 1.0;
+                o += P;
+            }
+            if (o >= P) {
+                q += 1.0;
+                o -= P;
+            }
+            long long K1 = (long long)ceil(P / h - 1e-9);
+            if (K1 < 1) K1 = 1;
+            long long K2 = o > 0.0 ? (long long)ceil(o / h - 1e-9) : 0;
+            if (o > 0.0 && K2 < 1) K2 = 1;
+            const double hP = P / (double)K1, ho = K2 ? o / (double)K2 : 0.0;
+            if (!coupled) {
+                HIPCHK(c, timed_launch(c, "cetd_duffing", [&] {
+                           return launch_cetd_duffing(c->stream, c->zR, c->zV, n, hP, K1, ho, K2,
+                                                      q, eps, rot0, rot1);
+                       }));
+            } else {
+                HIPCHK(c, launch_fine_begin(c->stream, a, c->zR, c->zV, n, rot0, 3, eps));
+                if ((s = start_field(c, ma)) != EP_OK) return s;
+                for (long long L = 1; L <= K1; ++L)
+                    if ((s = coupled_step(c, 0, hP, eps, L, ma)) != EP_OK) return s;
+                HIPCHK(c, launch_cetd_combine(c->stream, a, n, q));
+                if ((s = start_field(c, ma)) != EP_OK) return s;
+                for (long long L = 1; L <= K2; ++L)
+                    if ((s = coupled_step(c, 0, ho, eps, L, ma)) != EP_OK) return s;
+                HIPCHK(c, launch_fine_end(c->stream, a, c->zR, c->zV, n, rot1, 0));
+            }
+            if (modified) HIPCHK(c, launch_fill_ll(c->stream, a.N, n, (long long)q));
+            c->last_period = P;
+        } else if (!ietd) {
             long long K = (long long)ceil(dt / h - 1e-9);
             if (K < 1) K = 1;
             const double hk = dt / (double)K;
@@ -118,22 +201,10 @@ ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n
                                                   (long long)c->max_fine, rot0, rot1, a.T, a.N,
                                                   a.unresolved);
                    }));
-        } else {
+        } else if (ietd) {
             // (a) period search, all particles in lock step until every one
             // has its third sign change of V (or max_fine steps)
-            HIPCHK(c, hipMemsetAsync(a.done, 0, 3 * sizeof(unsigned long long), c->stream));
-            HIPCHK(c, launch_fine_begin(c->stream, a, c->zR, c->zV, n, rot0, 1, eps));
-            if ((s = start_field(c, ma)) != EP_OK) return s;
-            long long L = 0;
-            while (L < (long long)c->max_fine) {
-                long long chunk = kSearchChunk;
-                if (chunk > (long long)c->max_fine - L) chunk = (long long)c->max_fine - L;
-                for (long long j = 0; j < chunk; ++j)
-                    if ((s = coupled_step(c, 1, h, eps, ++L, ma)) != EP_OK) return s;
-                const uint64_t done = read_counter(c, a.done, e);
-                if (e != hipSuccess) return c->hipfail("ep_step: period search", e);
-                if (done >= c->n) break;
-            }
+            if ((s = coupled_period_search(c, h, eps, rot0, ma)) != EP_OK) return s;
             // (b) dt = N T + o, and the last fine level the captures need
             HIPCHK(c, launch_ietd_split(c->stream, a, n, dt, h));
             const uint64_t last = read_counter(c, a.last, e);
@@ -149,7 +220,7 @@ ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n
         c->t += dt;
         c->n_steps += 1;
     }
-    c->periods_valid = ietd && n_steps > 0;
+    c->periods_valid = (ietd || modified) && n_steps > 0;
     c->field_valid = false;
     return EP_OK;
 }

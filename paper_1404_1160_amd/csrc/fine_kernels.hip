@@ -169,6 +169,121 @@ hipError_t launch_ietd_duffing(hipStream_t st, float *zR, float *zV, int64_t n, 
                     T, N, unresolved);
 }
 
+// Periods only (the modified ETD scheme needs their mean first).
+__global__ __launch_bounds__(256) void period_duffing_kernel(
+    const float *__restrict__ zR, const float *__restrict__ zV, int64_t n, double h, double ie,
+    long long max_fine, double T_free, double2 rot0, double *__restrict__ Tout,
+    unsigned long long *__restrict__ unresolved)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double zr = zR[i], zv = zV[i];
+    double R = fma(rot0.x, zr, rot0.y * zv), V = fma(-rot0.y, zr, rot0.x * zv);
+    double t1 = 0.0, T = T_free;
+    int cnt = 0;
+    for (long long k = 0; k < max_fine && cnt < 3; ++k) {
+        const double Vp = V;
+        rk4_duffing(R, V, h, ie);
+        if ((Vp < 0.0) != (V < 0.0)) {
+            const double ts = (double)k * h + h * Vp / (Vp - V);
+            if (++cnt == 1) t1 = ts;
+            if (cnt == 3) T = ts - t1;
+        }
+    }
+    if (cnt < 3) atomicAdd(unresolved, 1ull);
+    Tout[i] = T;
+}
+
+// Classic ETD step (Algorithm 2.1) with the common period P = dt - N o:
+// K1 equal steps over P give y(t_n + P); y(t_n + N P) = y^n + N (y(t_n + P)
+// - y^n); K2 equal steps over o give y^{n+1}.
+__global__ __launch_bounds__(256) void cetd_duffing_kernel(float *__restrict__ zR,
+                                                           float *__restrict__ zV, int64_t n,
+                                                           double hP, long long K1, double ho,
+                                                           long long K2, double q, double ie,
+                                                           double2 rot0, double2 rot1)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double zr = zR[i], zv = zV[i];
+    const double R0 = fma(rot0.x, zr, rot0.y * zv), V0 = fma(-rot0.y, zr, rot0.x * zv);
+    double R = R0, V = V0;
+    for (long long k = 0; k < K1; ++k) rk4_duffing(R, V, hP, ie);
+    R = fma(q, R - R0, R0);
+    V = fma(q, V - V0, V0);
+    for (long long k = 0; k < K2; ++k) rk4_duffing(R, V, ho, ie);
+    zR[i] = (float)fma(rot1.x, R, -rot1.y * V);
+    zV[i] = (float)fma(rot1.y, R, rot1.x * V);
+}
+
+// Sum of x[0..n) in a fixed order: per-block partial sums (strided per
+// thread, then the block's fixed-order tree), then one block adds the
+// partials in index order.
+__global__ __launch_bounds__(256) void sum_partial_kernel(const double *__restrict__ x, int64_t n,
+                                                          double *__restrict__ partial)
+{
+    __shared__ double wt[4];
+    double a = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a += x[i];
+    a = block_sum<double>(a, wt);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(256) void sum_final_kernel(const double *__restrict__ partial, int g,
+                                                        double *__restrict__ out)
+{
+    __shared__ double wt[4];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < g; i += blockDim.x) a += partial[i];
+    a = block_sum<double>(a, wt);
+    if (threadIdx.x == 0) *out = a;
+}
+
+__global__ __launch_bounds__(256) void fill_ll_kernel(long long *__restrict__ x, int64_t n,
+                                                      long long v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+hipError_t launch_period_duffing(hipStream_t st, const float *zR, const float *zV, int64_t n,
+                                 double h, double eps, long long max_fine, double2 rot0, double *T,
+                                 unsigned long long *unresolved)
+{
+    if (n <= 0) return hipSuccess;
+    return dispatch(period_duffing_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, zR,
+                    zV, n, h, 1.0 / eps, max_fine, 2.0 * 3.141592653589793 * eps, rot0, T,
+                    unresolved);
+}
+
+hipError_t launch_cetd_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double hP,
+                               long long K1, double ho, long long K2, double q, double eps,
+                               double2 rot0, double2 rot1)
+{
+    if (n <= 0) return hipSuccess;
+    return dispatch(cetd_duffing_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, zR,
+                    zV, n, hP, K1, ho, K2, q, 1.0 / eps, rot0, rot1);
+}
+
+hipError_t launch_sum(hipStream_t st, const double *x, int64_t n, double *partial, int g,
+                      double *out)
+{
+    sum_partial_kernel<<<dim3((unsigned)g), dim3(256), 0, st>>>(x, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sum_final_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_ll(hipStream_t st, long long *x, int64_t n, long long v)
+{
+    if (n <= 0) return hipSuccess;
+    fill_ll_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(x, n, v);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ Poisson (lock step)
 
 // Stage kernel of the coupled RK4 step from level L-1 to level L (t = L h).
@@ -323,6 +438,10 @@ __global__ __launch_bounds__(256) void fine_begin_kernel(FineArgs a, const float
         a.cnt[i] = 0;
         a.T[i] = T_free;
     }
+    if (mode == 3) {   // classic ETD: keep y^n
+        a.pR[i] = R;
+        a.pV[i] = V;
+    }
     if (mode == 2) {
         a.pR[i] = R;
         a.pV[i] = V;
@@ -331,6 +450,23 @@ __global__ __launch_bounds__(256) void fine_begin_kernel(FineArgs a, const float
         a.dR[i] = R;
         a.dV[i] = V;
     }
+}
+
+// Classic ETD, step 2: y(t_n + N P) = y^n + N (y(t_n + P) - y^n), y^n in p.
+__global__ __launch_bounds__(256) void cetd_combine_kernel(FineArgs a, int64_t n, double q)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double R0 = a.pR[i], V0 = a.pV[i];
+    a.yR[i] = fma(q, a.yR[i] - R0, R0);
+    a.yV[i] = fma(q, a.yV[i] - V0, V0);
+}
+
+hipError_t launch_cetd_combine(hipStream_t st, const FineArgs &a, int64_t n, double q)
+{
+    if (n <= 0) return hipSuccess;
+    cetd_combine_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(a, n, q);
+    return hipGetLastError();
 }
 
 // After the period search: split dt, and the last fine level the captures need.

@@ -208,6 +208,7 @@ struct FineArgs {
     int *cnt;                   // sign changes found
     long long *N;               // whole periods
     unsigned long long *done, *last, *unresolved;  // [1] each
+    double *red;                // 257: partial sums of a fixed-order reduction, result
 };
 hipError_t launch_rk4_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double h,
                               double eps, long long steps, double2 rot0, double2 rot1);
@@ -227,6 +228,17 @@ hipError_t launch_ietd_split(hipStream_t st, const FineArgs &a, int64_t n, doubl
 hipError_t launch_fine_end(hipStream_t st, const FineArgs &a, float *zR, float *zV, int64_t n,
                            double2 rot1, int ietd);
 hipError_t setup_fine_lds(int nr);
+hipError_t launch_period_duffing(hipStream_t st, const float *zR, const float *zV, int64_t n,
+                                 double h, double eps, long long max_fine, double2 rot0, double *T,
+                                 unsigned long long *unresolved);
+hipError_t launch_cetd_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double hP,
+                               long long K1, double ho, long long K2, double q, double eps,
+                               double2 rot0, double2 rot1);
+// fixed-order sum of x[0..n) into *out (partial: g doubles)
+hipError_t launch_sum(hipStream_t st, const double *x, int64_t n, double *partial, int g,
+                      double *out);
+hipError_t launch_fill_ll(hipStream_t st, long long *x, int64_t n, long long v);
+hipError_t launch_cetd_combine(hipStream_t st, const FineArgs &a, int64_t n, double q);
 
 hipError_t launch_moments(hipStream_t st, const float *zR, const float *zV, int64_t n,
                           double c, double s, double rmax, double *partial,

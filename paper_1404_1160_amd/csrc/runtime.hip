@@ -336,8 +336,7 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
         return EP_OK;
     }
     if (c->push_mode == EP_PUSH_LEARNED) return learned_steps(c, dt, eps, field, n_steps);
-    if (c->push_mode == EP_PUSH_RK4 || c->push_mode == EP_PUSH_IMPROVED_ETD)
-        return fine_steps(c, dt, eps, field, n_steps);
+    if (c->push_mode >= EP_PUSH_RK4) return fine_steps(c, dt, eps, field, n_steps);
     if (field == EP_FIELD_POISSON && !c->field_valid) {
         ep_status s = refresh_field(c);
         if (s != EP_OK) return s;
@@ -498,11 +497,9 @@ ep_status ep_get_field(ep_ctx *c, double *rho, double *E, double *Psi, double *Q
 ep_status ep_set_push_mode(ep_ctx *c, int32_t push, double drift_tol, uint32_t fallback_substeps)
 {
     if (!c) return EP_EINVAL;
-    if (push != EP_PUSH_PLAIN && push != EP_PUSH_LEARNED && push != EP_PUSH_RK4 &&
-        push != EP_PUSH_IMPROVED_ETD)
+    if (push < EP_PUSH_PLAIN || push > EP_PUSH_MODIFIED_ETD)
         return c->fail(EP_EINVAL, "ep_set_push_mode: unknown push mode");
-    if ((push == EP_PUSH_RK4 || push == EP_PUSH_IMPROVED_ETD) &&
-        c->cfg.deposit == EP_DEPOSIT_SORTED)
+    if (push >= EP_PUSH_RK4 && c->cfg.deposit == EP_DEPOSIT_SORTED)
         return c->fail(EP_EINVAL, "ep_set_push_mode: the fine solvers do not support the sorted "
                                   "deposit");
     if (push == EP_PUSH_LEARNED) {

@@ -130,3 +130,37 @@ def test_fine_modes_reject_sorted_deposit_and_early_period_query():
         assert e.value.status == capi.EP_ESTATE
         with pytest.raises(capi.EtdpicError):
             capi.ep_set_fine_solver(sim.ctx, 0.0, 0)
+
+
+@pytest.mark.parametrize("modified", [False, True])
+def test_classic_and_modified_etd_duffing_match_oracle(modified):
+    R0, V0, w = synth.gaussian(10001, seed=57)
+    eps, dt = 1e-3, 0.5
+    mode = capi.EP_PUSH_MODIFIED_ETD if modified else capi.EP_PUSH_CLASSIC_ETD
+    with _sim(R0, V0, w, mode) as sim:
+        sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+        Rg, Vg = sim.particles()
+        if modified:
+            Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
+    Ro, Vo, P, To, uno = oracle.classic_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING,
+                                                 modified)
+    assert rel(Rg, Vg, Ro, Vo).max() <= 1e-6
+    if modified:
+        assert un == uno == 0
+        assert np.max(np.abs(Tg / To - 1)) <= 1e-9
+        assert abs(Tg.mean() / P - 1) <= 1e-12 and np.all(Ng == math.floor(dt / P))
+
+
+def test_modified_etd_poisson_matches_oracle():
+    R0, V0, w = synth.gaussian_truncated(4001, seed=58)
+    eps = 0.01
+    dt = 20 * math.pi * eps
+    with _sim(R0, V0, w, capi.EP_PUSH_MODIFIED_ETD) as sim:
+        sim.step(dt, eps, EP_FIELD_POISSON, 1)
+        Rg, Vg = sim.particles()
+        Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
+    Ro, Vo, P, To, uno = oracle.classic_etd_step(R0, V0, w, dt, eps, oracle.FIELD_POISSON, True,
+                                                 **VP)
+    assert un == uno == 0
+    assert np.max(np.abs(Tg / To - 1)) <= 1e-6 and np.all(Ng == math.floor(dt / P))
+    assert rel(Rg, Vg, Ro, Vo).max() <= 1e-5

@@ -113,3 +113,36 @@ def test_improved_etd_vp_step_tracks_the_reference():
     rms, rms_r = np.sqrt(np.mean(R ** 2)), np.sqrt(np.mean(Rr ** 2))
     assert abs(rms / rms_r - 1) < 2e-3
     assert np.median(np.hypot(R - Rr, V - Vr)) < 0.05
+
+
+def test_classic_etd_free_rotation_and_mean_period():
+    """E = 0: Algorithm 2.1 with P = 2 pi eps is the exact rotation up to the
+    reference solver's error over one period, multiplied by N; the modified
+    form finds P = 2 pi eps from the periods."""
+    R0, V0, w = synth.gaussian(500, seed=8)
+    eps, dt = 1e-3, 0.5
+    c, s = math.cos(dt / eps), math.sin(dt / eps)
+    for modified in (False, True):
+        R, V, P, T, un = oracle.classic_etd_step(R0, V0, w, dt, eps, oracle.FIELD_ZERO, modified)
+        assert un == 0 and abs(P / (2 * math.pi * eps) - 1) < 1e-6
+        err = np.hypot(R - (c * R0 + s * V0), V - (-s * R0 + c * V0))
+        assert np.max(err / np.hypot(R0, V0)) < 5e-4
+
+
+def test_paper_claims_classic_modified_improved():
+    """Section 2 and section 3: on the Duffing beam (periods differ from
+    particle to particle) with dt = 0.5 >> 2 pi eps, eps = 1e-3, the classic
+    scheme is inaccurate, the mean period helps, and the per-particle periods
+    of Algorithm 3.4 make the step accurate (errors against the exact
+    solution)."""
+    R0, V0, w = synth.gaussian(1000, seed=9)
+    eps, dt = 1e-3, 0.5
+    Rx, Vx = duffing.solution(R0, V0, eps, dt)
+
+    def med(R, V):
+        return np.median(np.hypot(R - Rx, V - Vx))
+
+    ec = med(*oracle.classic_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING, False)[:2])
+    em = med(*oracle.classic_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING, True)[:2])
+    ei = med(*oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING)[:2])
+    assert ei < em / 100 and em < ec, (ec, em, ei)
