@@ -280,6 +280,7 @@ def main():
         line["paper_schemes"] = compare.paper_schemes(
             n_duffing=1_000_000, n_vp=100_000, steps_duffing=20, steps_vp=2,
             log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        line["period_diagnostics"] = compare.period_diagnostics()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cells, args.eps, args.dt, args.substeps,
                                             args.cpu_seconds)

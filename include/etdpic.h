@@ -201,6 +201,12 @@ ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
  * Defaults: h_fine = 0, max_fine = 10000.  Errors: EP_EINVAL. */
 ep_status ep_set_fine_solver(ep_ctx *ctx, double h_fine, uint64_t max_fine);
 
+/* The periods T_i of the current state, without stepping (the paper's period
+ * diagnostics, section 2): the same fine-solve search as Algorithm 3.4 uses,
+ * for the Duffing or the Poisson field; ep_get_periods then returns them with
+ * N_i = 0.  Errors: EP_EINVAL, EP_ESTATE, EP_ENOMEM, EP_EHIP. */
+ep_status ep_compute_periods(ep_ctx *ctx, double eps, int32_t field, uint64_t *n_unresolved);
+
 /* After an EP_PUSH_IMPROVED_ETD or EP_PUSH_MODIFIED_ETD step: the periods
  * T_i (FP64) and whole numbers of periods N_i (the common N for the modified
  * scheme) used by the last macro step, for particles

@@ -27,7 +27,7 @@ EXPORTS = (
     "ep_step", "ep_moments_get", "ep_get_particles", "ep_get_field", "ep_set_push_mode",
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
     "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect", "ep_mlp_get_samples",
-    "ep_save", "ep_load", "ep_set_fine_solver", "ep_get_periods",
+    "ep_save", "ep_load", "ep_set_fine_solver", "ep_get_periods", "ep_compute_periods",
 )
 
 
@@ -116,6 +116,7 @@ def lib():
             "ep_mlp_collect": ([vp, d, d, u32, u64, u64, i32, ctypes.POINTER(u64)], i32),
             "ep_mlp_get_samples": ([vp, u64, u64, pf, pf], i32),
             "ep_set_fine_solver": ([vp, d, u64], i32),
+            "ep_compute_periods": ([vp, d, i32, ctypes.POINTER(u64)], i32),
             "ep_get_periods": ([vp, pd, ctypes.POINTER(ctypes.c_int64), u64, u64,
                                 ctypes.POINTER(u64)], i32),
             "ep_save": ([vp, ctypes.c_char_p], i32),
@@ -302,6 +303,13 @@ def ep_mlp_get_samples(ctx, first, count):
 def ep_set_fine_solver(ctx, h_fine=0.0, max_fine=10000):
     """Fine step of the reference RK4 and improved-ETD modes (<= 0: 2 pi eps/100)."""
     _check(ctx, lib().ep_set_fine_solver(ctx, float(h_fine), int(max_fine)))
+
+
+def ep_compute_periods(ctx, eps, field):
+    """Periods of the current state (no step); returns the unresolved count."""
+    un = ctypes.c_uint64(0)
+    _check(ctx, lib().ep_compute_periods(ctx, float(eps), int(field), ctypes.byref(un)))
+    return int(un.value)
 
 
 def ep_get_periods(ctx, count, offset=0):

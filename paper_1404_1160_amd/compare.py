@@ -281,8 +281,9 @@ def _run_scheme(R0, V0, w, field, mode, dt, eps, steps, nr=VP_NR, substeps=1, h_
 
 def paper_schemes(n_duffing=1_000_000, n_vp=100_000, eps=1e-3, dt=0.5, steps_duffing=20,
                   steps_vp=4, plain_K=(100, 400), nr=1024, ref_refine=4, log=None):
-    """The improved ETD scheme (Algorithm 3.4) and the plain exponential
-    integrator against the paper's reference solver (RK4, field re-solved at
+    """The improved ETD scheme (Algorithm 3.4), the classic and modified ETD
+    schemes (Algorithm 2.1) and the plain exponential integrator against the
+    paper's reference solver (RK4, field re-solved at
     every stage) on the paper's initial beam (eq. 2.7), eps = 1e-3, dt = 0.5:
     particle-steps/s (macro steps) and the relative rms-radius and median
     particle errors at the end against the reference.  The reference runs
@@ -317,6 +318,10 @@ def paper_schemes(n_duffing=1_000_000, n_vp=100_000, eps=1e-3, dt=0.5, steps_duf
         R, V, el, extra = _run_scheme(R0, V0, w, field, capi.EP_PUSH_IMPROVED_ETD, dt, eps, steps,
                                       nr)
         res["improved_etd"] = dict(score(R, V, el), **extra)
+        for name_m, mode in (("classic_etd", capi.EP_PUSH_CLASSIC_ETD),
+                             ("modified_etd", capi.EP_PUSH_MODIFIED_ETD)):
+            R, V, el, _ = _run_scheme(R0, V0, w, field, mode, dt, eps, steps, nr)
+            res[name_m] = score(R, V, el)
         for K in plain_K:
             R, V, el, _ = _run_scheme(R0, V0, w, field, capi.EP_PUSH_PLAIN, dt, eps, steps, nr,
                                       substeps=K)
@@ -325,4 +330,29 @@ def paper_schemes(n_duffing=1_000_000, n_vp=100_000, eps=1e-3, dt=0.5, steps_duf
             name, res["reference"]["particle_steps_per_s"],
             res["improved_etd"]["particle_steps_per_s"], res["improved_etd"]["rms_err"]))
         out[name] = res
+    return out
+
+
+def period_diagnostics(n=100_000, eps=0.01, t_end=5.0, dt=0.05, K=4, nr=1024):
+    """The paper's period and modulus diagnostics (section 2) on its initial
+    beam (eq. 2.7) at eps = 0.01: the Duffing periods against 2 pi eps, and in
+    the self-consistent field the periods and moduli at t_end (plain push)
+    against those at t = 0."""
+    from . import diagnostics
+    R0, V0, w = synth.paper_f0(n, seed=19)
+    out = {"n": n, "eps": eps}
+    with Sim(n, n_cells=nr, substeps=K) as sim:
+        sim.set_particles(R0, V0, w)
+        d, _ = diagnostics.period_summary(sim, eps, EP_FIELD_DUFFING)
+        out["duffing_periods"] = {k: v for k, v in d.items() if "histogram" not in k and "edges" not in k}
+        sim.set_particles(R0, V0, w)
+        d0, T0 = diagnostics.period_summary(sim, eps, EP_FIELD_POISSON)
+        sim.step(dt, eps, EP_FIELD_POISSON, int(round(t_end / dt)))
+        d1, T1 = diagnostics.period_summary(sim, eps, EP_FIELD_POISSON)
+        R, V = sim.particles()
+    out["poisson_periods_t0"] = {k: v for k, v in d0.items() if "histogram" not in k and "edges" not in k}
+    out["poisson_periods_t_end"] = {k: v for k, v in d1.items() if "histogram" not in k and "edges" not in k}
+    out["poisson_period_change"] = diagnostics.period_change(T0, T1)
+    out["poisson_modulus_change"] = diagnostics.modulus_change(R0, V0, R, V)
+    out["t_end"] = t_end
     return out

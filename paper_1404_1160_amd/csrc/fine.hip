@@ -239,6 +239,41 @@ ep_status ep_set_fine_solver(ep_ctx *c, double h_fine, uint64_t max_fine)
     return EP_OK;
 }
 
+ep_status ep_compute_periods(ep_ctx *c, double eps, int32_t field, uint64_t *n_unresolved)
+{
+    if (!c) return EP_EINVAL;
+    if (!(eps > 0.0) || !isfinite(eps) || (field != EP_FIELD_DUFFING && field != EP_FIELD_POISSON))
+        return c->fail(EP_EINVAL, "ep_compute_periods: need eps > 0 and the Duffing or Poisson "
+                                  "field");
+    if (c->w <= 0.0) return c->fail(EP_ESTATE, "ep_compute_periods: no particles loaded");
+    if (c->cfg.deposit == EP_DEPOSIT_SORTED)
+        return c->fail(EP_EINVAL, "ep_compute_periods: not with the sorted deposit");
+    DeviceGuard guard(c->device);
+    const bool coupled = field == EP_FIELD_POISSON;
+    ep_status s = ensure_fine(c, coupled);
+    if (s != EP_OK) return s;
+    FineArgs &a = c->fine;
+    const int64_t n = (int64_t)c->n;
+    const double h = c->h_fine > 0.0 ? c->h_fine : kTwoPi * eps / 100.0;
+    const double2 rot0 = make_double2(cos(c->phase), sin(c->phase));
+    HIPCHK(c, hipMemsetAsync(a.done, 0, 3 * sizeof(unsigned long long), c->stream));
+    if (!coupled) {
+        HIPCHK(c, launch_period_duffing(c->stream, c->zR, c->zV, n, h, eps, (long long)c->max_fine,
+                                        rot0, a.T, a.unresolved));
+    } else {
+        if ((s = coupled_period_search(c, h, eps, rot0, c->mesh())) != EP_OK) return s;
+        HIPCHK(c, launch_ietd_split(c->stream, a, n, 0.0, h));   // counts unresolved
+        c->field_valid = false;
+    }
+    HIPCHK(c, launch_fill_ll(c->stream, a.N, n, 0));
+    unsigned long long un = 0;
+    HIPCHK(c, hipMemcpyAsync(&un, a.unresolved, sizeof un, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->periods_valid = true;
+    if (n_unresolved) *n_unresolved = un;
+    return EP_OK;
+}
+
 ep_status ep_get_periods(ep_ctx *c, double *T, int64_t *N, uint64_t offset, uint64_t count,
                          uint64_t *n_unresolved)
 {

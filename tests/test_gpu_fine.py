@@ -164,3 +164,39 @@ def test_modified_etd_poisson_matches_oracle():
     assert un == uno == 0
     assert np.max(np.abs(Tg / To - 1)) <= 1e-6 and np.all(Ng == math.floor(dt / P))
     assert rel(Rg, Vg, Ro, Vo).max() <= 1e-5
+
+
+def test_compute_periods_match_oracle_and_exact_periods():
+    from oracle import duffing
+    R0, V0, w = synth.gaussian(5001, seed=59)
+    eps = 0.01
+    with _sim(R0, V0, w, capi.EP_PUSH_PLAIN) as sim:
+        assert capi.ep_compute_periods(sim.ctx, eps, EP_FIELD_DUFFING) == 0
+        Tg, Ng, _ = capi.ep_get_periods(sim.ctx, R0.size)
+        Rg, Vg = sim.particles()
+    assert np.array_equal(Rg, R0) and np.array_equal(Vg, V0) and np.all(Ng == 0)
+    assert np.max(np.abs(Tg / duffing.period(R0, V0, eps) - 1)) < 1e-5
+    R1, V1, w1 = synth.gaussian_truncated(4001, seed=60)
+    with _sim(R1, V1, w1, capi.EP_PUSH_PLAIN) as sim:
+        assert capi.ep_compute_periods(sim.ctx, eps, EP_FIELD_POISSON) == 0
+        Tg, _, _ = capi.ep_get_periods(sim.ctx, R1.size)
+    _, _, To, _, _ = oracle.improved_etd_step(R1, V1, w1, 0.1, eps, oracle.FIELD_POISSON, **VP)
+    assert np.max(np.abs(Tg / To - 1)) <= 1e-6
+
+
+def test_period_diagnostics_of_the_papers_beam(golden):
+    """The paper's initial beam (eq. 2.7) in the Duffing field at eps = 0.01:
+    every period lies in the window the paper reports, just below 2 pi eps."""
+    from paper_1404_1160_amd import diagnostics
+    R0, V0, w = synth.paper_f0(20000, seed=61)
+    eps = golden["duffing_period_window_eps_0.01"]["eps"]   # window 2 pi eps - 1.5 eps^2 .. 2 pi eps
+    with _sim(R0, V0, w, capi.EP_PUSH_PLAIN) as sim:
+        sim.n = R0.size
+        summ, T = diagnostics.period_summary(sim, eps, EP_FIELD_DUFFING)
+    lo, hi = 2 * math.pi * eps - 1.5 * eps ** 2, 2 * math.pi * eps
+    # the search itself is good to ~1.3e-7 relative (free rotation: linear
+    # interpolation of the sign change, RK4 phase error), which matters for the
+    # smallest orbits, whose periods approach 2 pi eps from below
+    tol = 3e-7 * hi
+    assert summ["unresolved"] == 0 and lo - tol < T.min() and T.max() < hi + tol
+    assert summ["mean_over_2pi_eps"] < 1.0
