@@ -60,8 +60,6 @@ def parse():
     ap.add_argument("--moments-every", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run an 800 MB device copy (for HBM counter scaling)")
     ap.add_argument("--no-deposit-comparison", action="store_true",
                     help="skip the short run with the other deposit")
     ap.add_argument("--comparison-steps", type=int, default=50)
@@ -92,6 +90,14 @@ def measured_traffic(n):
     if c.get("kernel_source_sha256_16") != kernel_hash() or c.get("n_particles") != n:
         return None
     return c.get("bytes_per_launch")
+
+
+def device_copy_bandwidth(n):
+    """Achieved bandwidth of a plain device copy of the particle state's size
+    (8 B per particle read and written), as a practical ceiling beside the
+    8 TB/s peak: GB/s counting read plus written bytes."""
+    from paper_1404_1160_amd import capi
+    return capi.ep_copy_bandwidth(8 * n, reps=10)
 
 
 def cpu_baseline(n_full, cells, eps, dt, K, seconds):
@@ -205,14 +211,7 @@ def main():
     print("bench: %d particles generated in %.1f s" % (n, time.perf_counter() - t0),
           file=sys.stderr, flush=True)
 
-    if args.copy_calibration:
-        import torch
-        src = torch.empty(n * 2, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_gbs = device_copy_bandwidth(n)
 
     value, ms_step, kernels, mom = run_pic(args, args.deposit, args.steps, args.warmup, R0, V0, w)
     transfer = kernels.pop("_transfer")
@@ -242,7 +241,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n),
                      "kernel": dom, "kernel_ms": bw[dom]["ms_per_launch"],
                      "launches": bw[dom]["launches"],
-                     "bytes_per_launch": bw[dom]["bytes_per_launch"]},
+                     "bytes_per_launch": bw[dom]["bytes_per_launch"],
+                     "device_copy_GB_per_s": copy_gbs,
+                     "frac_of_device_copy": achieved / copy_gbs},
         "kernels": kernels,
         "host_transfer": transfer,
         "moments": {k: mom[k] for k in ("t", "rms_radius", "energy", "n_offmesh", "n_nan")},

@@ -80,7 +80,10 @@ typedef enum {
  *   deposit     : ep_deposit.
  *   device      : HIP device ordinal.
  *   hip_stream  : hipStream_t to queue work on, or NULL for a library-owned
- *                 stream (created at default priority). */
+ *                 stream (created at default priority).  A caller's stream
+ *                 (and bound arrays, ep_bind_particles) must come from the
+ *                 same HIP runtime the library is linked with: a framework
+ *                 that ships its own copy of the runtime cannot share them. */
 typedef struct {
     uint64_t n_particles;
     uint32_t n_cells;
@@ -326,6 +329,13 @@ ep_status ep_mlp_train(ep_ctx *ctx, const ep_train_cfg *cfg, const double *R, co
  * *n_particles when that pointer is not null. */
 ep_status ep_save(ep_ctx *ctx, const char *path);
 ep_status ep_load(ep_ctx *ctx, const char *path, uint64_t *n_particles);
+
+/* Achieved bandwidth of a plain device-to-device copy of `bytes` on `device`
+ * (reps timed copies after 3 untimed ones), counting bytes read plus bytes
+ * written: a practical ceiling to compare the particle kernels with.  Needs
+ * no context; allocates and frees two buffers of `bytes`.
+ * Errors: EP_EINVAL, EP_ENOMEM, EP_EHIP. */
+ep_status ep_copy_bandwidth(int32_t device, uint64_t bytes, int32_t reps, double *gb_per_s);
 
 /* Synchronise the context's stream; reports asynchronous errors. */
 ep_status ep_sync(ep_ctx *ctx);

@@ -28,6 +28,7 @@ EXPORTS = (
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
     "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect", "ep_mlp_get_samples",
     "ep_save", "ep_load", "ep_set_fine_solver", "ep_get_periods", "ep_compute_periods",
+    "ep_copy_bandwidth",
 )
 
 
@@ -116,6 +117,7 @@ def lib():
             "ep_mlp_collect": ([vp, d, d, u32, u64, u64, i32, ctypes.POINTER(u64)], i32),
             "ep_mlp_get_samples": ([vp, u64, u64, pf, pf], i32),
             "ep_set_fine_solver": ([vp, d, u64], i32),
+            "ep_copy_bandwidth": ([i32, u64, i32, pd], i32),
             "ep_compute_periods": ([vp, d, i32, ctypes.POINTER(u64)], i32),
             "ep_get_periods": ([vp, pd, ctypes.POINTER(ctypes.c_int64), u64, u64,
                                 ctypes.POINTER(u64)], i32),
@@ -303,6 +305,13 @@ def ep_mlp_get_samples(ctx, first, count):
 def ep_set_fine_solver(ctx, h_fine=0.0, max_fine=10000):
     """Fine step of the reference RK4 and improved-ETD modes (<= 0: 2 pi eps/100)."""
     _check(ctx, lib().ep_set_fine_solver(ctx, float(h_fine), int(max_fine)))
+
+
+def ep_copy_bandwidth(n_bytes, reps=10, device=0):
+    """GB/s (read + written) of a plain device copy of n_bytes."""
+    out = ctypes.c_double(0.0)
+    _check(None, lib().ep_copy_bandwidth(int(device), int(n_bytes), int(reps), ctypes.byref(out)))
+    return out.value
 
 
 def ep_compute_periods(ctx, eps, field):

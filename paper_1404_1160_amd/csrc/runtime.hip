@@ -515,6 +515,39 @@ ep_status ep_set_push_mode(ep_ctx *c, int32_t push, double drift_tol, uint32_t f
     return EP_OK;
 }
 
+ep_status ep_copy_bandwidth(int32_t device, uint64_t bytes, int32_t reps, double *gb_per_s)
+{
+    if (!gb_per_s || bytes == 0 || reps < 1) return EP_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EP_EINVAL;
+    DeviceGuard guard(device);
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ep_status st = EP_EHIP;
+    float ms = 0.f;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        st = EP_ENOMEM;
+        goto done;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+    for (int i = 0; i < 3; ++i)
+        if (hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, nullptr) != hipSuccess) goto done;
+    if (hipEventRecord(e0, nullptr) != hipSuccess) goto done;
+    for (int i = 0; i < reps; ++i)
+        if (hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, nullptr) != hipSuccess) goto done;
+    if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.f))
+        goto done;
+    *gb_per_s = 2.0 * (double)bytes * reps / ((double)ms / 1e3) / 1e9;
+    st = EP_OK;
+done:
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return st;
+}
+
 ep_status ep_timing_enable(ep_ctx *c, int32_t on)
 {
     if (!c) return EP_EINVAL;
