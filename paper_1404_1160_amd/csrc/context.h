@@ -53,7 +53,8 @@ struct Learned {
     // inference constants for (dt, eps) = cached_dt, cached_eps
     uint4 *d_w2hi = nullptr, *d_w2lo = nullptr;
     float4 *d_l1 = nullptr;
-    float *d_b2 = nullptr, *d_w3 = nullptr;
+    float *d_b2 = nullptr;
+    uint4 *d_w3f = nullptr;
     bool packed = false;
     double cached_dt = -1.0, cached_eps = -1.0;
     MlpInfer infer{};

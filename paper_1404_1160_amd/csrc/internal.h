@@ -148,7 +148,9 @@ struct MlpInfer {
     const float4 *l1;    // [64] (w_R, w_V, w_E, b1'): layer 1 with the constant
                          //      features folded into the bias
     const float *b2;     // [64]
-    const float *w3;     // [2][64]
+    const uint4 *w3f;    // [2][4 k steps][64 lanes] BF16 x 8: W3 as MFMA A-fragments
+                         //   (hi, then lo), rows 0, 1 the outputs, k in the
+                         //   order the layer-2 results sit in the lanes
     float b3_0, b3_1, mu_d, sig_d, mu_k, sig_k;
     int scaled;          // outputs are (a delta, a kappa), a = |y|, instead of (delta, kappa)
 };

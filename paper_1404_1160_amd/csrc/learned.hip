@@ -59,7 +59,7 @@ ep_status ensure_mlp_buffers(ep_ctx *c, int n_in)
     HIPCHK(c, dalloc(&L.d_w2lo, (size_t)8 * 64));
     HIPCHK(c, dalloc(&L.d_l1, (size_t)kH));
     HIPCHK(c, dalloc(&L.d_b2, (size_t)kH));
-    HIPCHK(c, dalloc(&L.d_w3, (size_t)kOut * kH));
+    HIPCHK(c, dalloc(&L.d_w3f, (size_t)2 * 4 * 64));
     HIPCHK(c, dalloc(&L.d_qcount, (size_t)1));
     HIPCHK(c, dalloc(&L.d_total, (size_t)1));
     HIPCHK(c, hipMemsetAsync(L.d_total, 0, sizeof(unsigned long long), c->stream));
@@ -103,13 +103,32 @@ ep_status prepare_inference(ep_ctx *c, double dt, double eps)
     HIPCHK(c, hipMemcpy(L.d_w2lo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(L.d_l1, l1.data(), l1.size() * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(L.d_b2, P + o.b2, kH * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_w3, P + o.W3, kOut * kH * sizeof(float), hipMemcpyHostToDevice));
+    // W3 as A-fragments of the layer-3 MFMA: row i < 2 is output i; k step kk,
+    // lane group g, element e stands for hidden unit
+    //   32 (kk / 2) + 16 (kk % 2) + (e < 4 ? 4 g + e : 8 + 4 g + e - 4),
+    // the unit whose layer-2 result lane (., g) holds in accumulator element
+    // 8 (kk % 2) + e -- so the activations enter the MFMA from the lanes'
+    // own registers.
+    std::vector<uint16_t> w3h((size_t)4 * 64 * 8), w3l((size_t)4 * 64 * 8);
+    for (int kk = 0; kk < 4; ++kk)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 8; ++e) {
+                const int i = lane & 31, g = lane >> 5;
+                const int u = 32 * (kk >> 1) + 16 * (kk & 1) + (e < 4 ? 4 * g + e : 8 + 4 * g + e - 4);
+                const float w = i < kOut ? P[o.W3 + i * kH + u] : 0.f;
+                const uint16_t h = host_bf16(w);
+                const size_t at = ((size_t)kk * 64 + lane) * 8 + e;
+                w3h[at] = h;
+                w3l[at] = host_bf16(w - host_bf16_value(h));
+            }
+    HIPCHK(c, hipMemcpy(L.d_w3f, w3h.data(), w3h.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_w3f + 4 * 64, w3l.data(), w3l.size() * 2, hipMemcpyHostToDevice));
     MlpInfer &I = L.infer;
     I.w2hi = L.d_w2hi;
     I.w2lo = L.d_w2lo;
     I.l1 = L.d_l1;
     I.b2 = L.d_b2;
-    I.w3 = L.d_w3;
+    I.w3f = L.d_w3f;
     I.b3_0 = P[o.b3];
     I.b3_1 = P[o.b3 + 1];
     I.mu_d = (float)L.norm[3];
@@ -191,7 +210,7 @@ void free_learned(ep_ctx *c)
     Learned &L = c->mlp;
     for (void *p : {(void *)L.d_params, (void *)L.d_m, (void *)L.d_v, (void *)L.d_grad,
                     (void *)L.d_w2hi, (void *)L.d_w2lo, (void *)L.d_l1, (void *)L.d_b2,
-                    (void *)L.d_w3, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total,
+                    (void *)L.d_w3f, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total,
                     (void *)L.d_tx, (void *)L.d_ty})
         if (p) (void)hipFree(p);
     L = Learned();

@@ -552,9 +552,10 @@ __device__ __forceinline__ double potential(const PotView &v, double R)
 
 // One learned step.  A workgroup of 4 waves takes 128 particles per
 // iteration, 32 per wave; lanes l and l+32 share particle l%32 and split its
-// hidden units.  Layers 1 and 3 run on VALU (FP32), layer 2 on MFMA, one
-// 16-wide k step at a time so that few activations are live: W2 as split BF16
-// (hi + lo, ~16 bits, two MFMAs) times the activations rounded to BF16.  The
+// hidden units.  Layer 1 runs on VALU (FP32), layers 2 and 3 on MFMA, one
+// 16-wide k step at a time so that few activations are live: W2 and W3 as
+// split BF16 (hi + lo, ~16 bits, two MFMAs) times the activations rounded to
+// BF16; the layer-3 operand order is that of the layer-2 results in the lanes.  The
 // activations' own lo halves would cost more VALU work than they are worth:
 // their rounding (2^-9) stays far below the network's approximation error.  All weights stay in LDS and are read where used.  The update and
 // the energy check run in FP64: H = |z|^2/(2 eps) + P(R) with P = R^4/4
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
     __shared__ uint4 sAh[8 * 64], sAl[8 * 64];
     __shared__ float4 sl1[kH];
     __shared__ float sb2[kH];
-    __shared__ float sw3[kOut * kH];
+    __shared__ uint4 sW3[2 * 4 * 64];
     __shared__ unsigned s_q[4][kWaveQueue];
     extern __shared__ __align__(16) unsigned char vp_smem[];
     const int tid = threadIdx.x;
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
         sl1[tid] = net.l1[tid];
         sb2[tid] = net.b2[tid];
     }
-    if (tid < kOut * kH) sw3[tid] = net.w3[tid];
+    for (int i = tid; i < 2 * 4 * 64; i += blockDim.x) sW3[i] = net.w3f[i];
     if (VP) {
         mv.H = reinterpret_cast<unsigned long long *>(vp_smem);
         for (int i = tid; i <= pv.nr; i += blockDim.x) mv.H[i] = 0ull;
@@ -629,19 +630,27 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al0, bh, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al1, bh, acc1, 0, 0, 0);
         }
-        float o0 = 0.f, o1 = 0.f;
+        // layer 3 on MFMA: the layer-2 results (rounded to BF16) are already
+        // in B-operand order in each lane; W3 (split BF16) is the A operand;
+        // lanes 0-31 receive the two outputs of their particle
+        f32x16 acc3 = {};
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int u0 = tile_row(q, g), u1 = 32 + tile_row(q, g);
-            const float h0 = act(acc0[q] + sb2[u0]);
-            const float h1 = act(acc1[q] + sb2[u1]);
-            o0 = fmaf(sw3[u0], h0, o0);
-            o1 = fmaf(sw3[kH + u0], h0, o1);
-            o0 = fmaf(sw3[u1], h1, o0);
-            o1 = fmaf(sw3[kH + u1], h1, o1);
+        for (int kk = 0; kk < 4; ++kk) {
+            float hv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int q = 8 * (kk & 1) + e;
+                const int u = 32 * (kk >> 1) + tile_row(q, g);
+                hv[e] = act((kk < 2 ? acc0[q] : acc1[q]) + sb2[u]);
+            }
+            bf16x8 bh, bl;
+            to_bf16x8<false>(hv, bh, bl);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(sW3[kk * 64 + lane]), bh, acc3,
+                                                           0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(sW3[256 + kk * 64 + lane]), bh,
+                                                           acc3, 0, 0, 0);
         }
-        o0 += __shfl_xor(o0, 32, 64);
-        o1 += __shfl_xor(o1, 32, 64);
+        const float o0 = acc3[0], o1 = acc3[1];
         float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);
         const float kappa = fmaf(net.sig_k, o1 + net.b3_1, net.mu_k);
         double sc;
