@@ -42,8 +42,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 16   # read + write zR, zV (FP32)
-COUNTERS = os.path.join(ROOT, "profiles", "push_poisson_1e8_nr4096_counters.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1404_1160_amd", "csrc", "pic_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "push_poisson_1e8_nr4096_hbm_counters.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1404_1160_amd", "csrc", f)
+                  for f in ("pic_kernels.hip", "internal.h")]
 
 
 def parse():
@@ -75,21 +76,34 @@ def parse():
 
 
 def kernel_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(n):
-    """HBM bytes per push launch from committed rocprofv3 counter runs, or None
-    if they were taken on another version of the kernel source."""
+def measured_traffic(n, cells, substeps):
+    """HBM bytes per push launch (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    same counter's reading for a device copy of known size) from the committed
+    rocprofv3 counter summary, or None if it was taken on another version of
+    the kernel source or at another size of the workload."""
+    fields = {}
     try:
         with open(COUNTERS) as f:
-            c = json.load(f)
-    except (OSError, ValueError):
+            for line in f:
+                key, sep, val = line.strip().partition(": ")
+                if sep and key in ("kernel_source_sha256_16", "n_particles", "n_cells",
+                                   "substeps", "bytes_per_launch"):
+                    fields[key] = val.strip()
+    except OSError:
         return None
-    if c.get("kernel_source_sha256_16") != kernel_hash() or c.get("n_particles") != n:
+    if fields.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    return c.get("bytes_per_launch")
+    if (fields.get("n_particles"), fields.get("n_cells"), fields.get("substeps")) != (
+            str(n), str(cells), str(substeps)) or "bytes_per_launch" not in fields:
+        return None
+    return int(fields["bytes_per_launch"])
 
 
 def device_copy_bandwidth(n):
@@ -218,6 +232,7 @@ def main():
     bw = {k: v for k, v in kernels.items() if "GB_per_s" in v}
     dom = max(bw, key=lambda k: bw[k]["ms_per_launch"] * bw[k]["launches"])
     achieved = bw[dom]["GB_per_s"]
+    traffic = (measured_traffic(n, args.cells, args.substeps) if dom == "push_poisson" else None)
     line = {
         "metric": "particle-steps/s at 1e8 particles (plain push, Vlasov-Poisson)",
         "value": value,
@@ -238,10 +253,12 @@ def main():
                    "precision": "FP32 particle state; FP64 phase and in-register push "
                                 "arithmetic; exact-integer charge scan"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dom, "kernel_ms": bw[dom]["ms_per_launch"],
                      "launches": bw[dom]["launches"],
                      "bytes_per_launch": bw[dom]["bytes_per_launch"],
+                     "traffic_over_algorithmic": (traffic / bw[dom]["bytes_per_launch"]
+                                                  if traffic else None),
                      "device_copy_GB_per_s": copy_gbs,
                      "frac_of_device_copy": achieved / copy_gbs},
         "kernels": kernels,

@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libetdpic.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+CLI_SRC = os.path.join(HERE, "cli", "etdpic_run.c")
+ROCM_LIB = "/opt/rocm/lib"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
@@ -42,7 +44,19 @@ def build(verbose: bool = False) -> str:
     if verbose and msgs:
         print("\n".join(msgs))
     os.replace(tmp, LIB)
+    build_cli()
     return LIB
+
+
+def build_cli() -> str:
+    """Compile the command-line driver ``etdpic_run`` (host C, gcc) against the library."""
+    out = os.path.join(HERE, "etdpic_run")
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=gnu99", "-Wall", "-I" + INCLUDE, CLI_SRC, "-o", tmp,
+           "-L" + HERE, "-letdpic", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath-link," + ROCM_LIB, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
 
 
 def is_built() -> bool:
