@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 16   # read + write zR, zV (FP32)
 COUNTERS = os.path.join(ROOT, "profiles", "push_poisson_1e8_nr4096_hbm_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1404_1160_amd", "csrc", f)
-                  for f in ("pic_kernels.hip", "internal.h")]
+                  for f in ("pic_kernels.hip", "pic_device.h", "internal.h")]
 
 
 def parse():

@@ -22,6 +22,10 @@ ROCM_LIB = "/opt/rocm/lib"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: the learned-inference kernel
+         # feeds every layer's results straight into VALU activations, and
+         # AGPR accumulators would cost one copy instruction per element
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-Wall", "-Wno-unused-result", "-I" + INCLUDE]
 
 

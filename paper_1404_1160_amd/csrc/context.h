@@ -51,9 +51,8 @@ struct Learned {
     double norm[8] = {0};
     float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
     // inference constants for (dt, eps) = cached_dt, cached_eps
-    uint4 *d_w2hi = nullptr, *d_w2lo = nullptr;
-    float4 *d_l1 = nullptr;
-    float *d_b2 = nullptr;
+    uint4 *d_w1f = nullptr, *d_w2f = nullptr;
+    float4 *d_b2 = nullptr;
     uint4 *d_w3f = nullptr;
     bool packed = false;
     double cached_dt = -1.0, cached_eps = -1.0;

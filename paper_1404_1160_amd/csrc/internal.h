@@ -143,15 +143,17 @@ __host__ __device__ constexpr int mlp_n_params(int n_in)
 
 // Inference constants of a trained network for one (dt, eps).
 struct MlpInfer {
-    const uint4 *w2hi;   // [8 fragments][64 lanes] BF16 x 8: high parts of W2
-    const uint4 *w2lo;   //                                   low parts
-    const float4 *l1;    // [64] (w_R, w_V, w_E, b1'): layer 1 with the constant
-                         //      features folded into the bias
-    const float *b2;     // [64]
-    const uint4 *w3f;    // [2][4 k steps][64 lanes] BF16 x 8: W3 as MFMA A-fragments
-                         //   (hi, then lo), rows 0, 1 the outputs, k in the
-                         //   order the layer-2 results sit in the lanes
+    // FP16 MFMA A-fragments (uint4 = 8 FP16 values of one lane).  Hidden unit
+    // order in k: step kk, lane group g, element e stands for unit
+    //   32 (kk / 2) + 16 (kk % 2) + 8 (e / 4) + 4 g + e % 4,
+    // the unit whose result lane (., g) holds in accumulator element
+    // 8 (kk % 2) + e of tile kk / 2.
+    const uint4 *w1f;    // [2 tiles][64 lanes] layer 1 / 64, features folded (see kernel)
+    const uint4 *w2f;    // [8 = 4 mt + kk][64 lanes] W2 / 64
+    const float4 *b2;    // [16] b2 / 64
+    const uint4 *w3f;    // [4 kk][64 lanes] W3, rows 0, 1 the outputs, the rest zero
     float b3_0, b3_1, mu_d, sig_d, mu_k, sig_k;
+    float xmax;          // features are clamped to +-xmax
     int scaled;          // outputs are (a delta, a kappa), a = |y|, instead of (delta, kappa)
 };
 

@@ -12,20 +12,43 @@ constexpr double kAdamB1 = 0.9, kAdamB2 = 0.999, kAdamEps = 1e-8;
 constexpr double kTimeScale = 100.0;   // s_t: feature scale of dt/eps
 constexpr uint32_t kNormSamples = 65536;
 
-uint16_t host_bf16(float f)
+// FP32 -> FP16 bits, round to nearest even (subnormals, overflow to inf).
+uint16_t host_f16(float f)
 {
-    uint32_t u;
-    memcpy(&u, &f, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    uint32_t x;
+    memcpy(&x, &f, 4);
+    const uint32_t sign = (x >> 16) & 0x8000u, ax = x & 0x7FFFFFFFu;
+    if (ax > 0x7F800000u) return (uint16_t)(sign | 0x7E00u);
+    if (ax >= 0x477FF000u) return (uint16_t)(sign | 0x7C00u);
+    if (ax < 0x38800000u) {
+        float v;
+        memcpy(&v, &ax, 4);
+        return (uint16_t)(sign | (uint32_t)nearbyintf(v * 16777216.0f));
+    }
+    const uint32_t m = ax + 0xFFFu + ((ax >> 13) & 1u) - (112u << 23);
+    return (uint16_t)(sign | (m >> 13));
 }
 
-float host_bf16_value(uint16_t b)
+float host_f16_value(uint16_t h)
 {
-    const uint32_t u = (uint32_t)b << 16;
-    float f;
-    memcpy(&f, &u, 4);
-    return f;
+    const uint32_t e = (h >> 10) & 0x1Fu, m = h & 0x3FFu;
+    float v;
+    if (e == 0) {
+        v = (float)m * (1.0f / 16777216.0f);
+    } else if (e == 31) {
+        v = m ? NAN : INFINITY;
+    } else {
+        const uint32_t b = ((e + 112u) << 23) | (m << 13);
+        memcpy(&v, &b, 4);
+    }
+    return (h & 0x8000u) ? -v : v;
+}
+
+// w as FP16 hi + lo (lo = f16(w - hi), ~22 significant bits together)
+void split_f16(float w, uint16_t &hi, uint16_t &lo)
+{
+    hi = host_f16(w);
+    lo = host_f16(w - host_f16_value(hi));
 }
 
 struct Offsets {
@@ -55,11 +78,10 @@ ep_status ensure_mlp_buffers(ep_ctx *c, int n_in)
     HIPCHK(c, dalloc(&L.d_m, np));
     HIPCHK(c, dalloc(&L.d_v, np));
     HIPCHK(c, dalloc(&L.d_grad, np));
-    HIPCHK(c, dalloc(&L.d_w2hi, (size_t)8 * 64));
-    HIPCHK(c, dalloc(&L.d_w2lo, (size_t)8 * 64));
-    HIPCHK(c, dalloc(&L.d_l1, (size_t)kH));
-    HIPCHK(c, dalloc(&L.d_b2, (size_t)kH));
-    HIPCHK(c, dalloc(&L.d_w3f, (size_t)2 * 4 * 64));
+    HIPCHK(c, dalloc(&L.d_w2f, (size_t)8 * 64));
+    HIPCHK(c, dalloc(&L.d_w1f, (size_t)2 * 64));
+    HIPCHK(c, dalloc(&L.d_b2, (size_t)kH / 4));
+    HIPCHK(c, dalloc(&L.d_w3f, (size_t)4 * 64));
     HIPCHK(c, dalloc(&L.d_qcount, (size_t)1));
     HIPCHK(c, dalloc(&L.d_total, (size_t)1));
     HIPCHK(c, hipMemsetAsync(L.d_total, 0, sizeof(unsigned long long), c->stream));
@@ -67,66 +89,91 @@ ep_status ensure_mlp_buffers(ep_ctx *c, int n_in)
     return EP_OK;
 }
 
-// Inference constants for one (dt, eps): W2 as split-BF16 MFMA A-fragments
-// (fragment f = 4 mt + kk, lane l: W2[32 mt + l%32][16 kk + 8 (l/32) + e],
-// e = 0..7), layer 1 with the constant features folded into the bias.
+// Hidden unit that MFMA operand slot (k step kk, lane group g, element e)
+// stands for: the unit whose result lane (., g) holds in accumulator element
+// 8 (kk % 2) + e of tile kk / 2, so that one layer's results are the next
+// layer's B operand as they sit in the lanes.
+int slot_unit(int kk, int g, int e)
+{
+    return 32 * (kk >> 1) + 16 * (kk & 1) + 8 * (e >> 2) + 4 * g + (e & 3);
+}
+
+// Inference constants for one (dt, eps), as FP16 MFMA A-fragments (lane l:
+// row l % 32, k = 8 (l / 32) + e of the step): layer 1 as split FP16 with the
+// constant features folded into the bias, W2 and the biases scaled by 1/64
+// (the activation takes z / 64), W2 and W3 in FP16 in slot_unit order.  Fails if a
+// pre-activation could leave the activation's FP16 range.
 ep_status prepare_inference(ep_ctx *c, double dt, double eps)
 {
     Learned &L = c->mlp;
     if (L.packed && L.cached_dt == dt && L.cached_eps == eps) return EP_OK;
     const Offsets o = offsets(L.n_in);
     const float *P = L.params.data();
-    std::vector<uint16_t> hi((size_t)8 * 64 * 8), lo((size_t)8 * 64 * 8);
-    for (int mt = 0; mt < 2; ++mt)
-        for (int kk = 0; kk < 4; ++kk)
-            for (int lane = 0; lane < 64; ++lane)
-                for (int e = 0; e < 8; ++e) {
-                    const int i = mt * 32 + (lane & 31), k = kk * 16 + 8 * (lane >> 5) + e;
-                    const float w = P[o.W2 + i * kH + k];
-                    const uint16_t h = host_bf16(w);
-                    const size_t at = ((size_t)(mt * 4 + kk) * 64 + lane) * 8 + e;
-                    hi[at] = h;
-                    lo[at] = host_bf16(w - host_bf16_value(h));
-                }
+    constexpr double kPre = 1.0 / 64.0, kUMax = 255.0;   // |z / 64| < 255: u^2 finite
     const double s_in = L.norm[0], s_t = L.norm[1], s_E = L.norm[2];
     const double th = dt / eps;
     const double phi = fmod(th, kTwoPi);
-    std::vector<float4> l1(kH);
+
+    // layer 1: per unit (w_R, w_V, w_E, b') / 64
+    std::vector<uint16_t> w1((size_t)2 * 64 * 8, 0);
+    double xmax = 30000.0;   // keeps the features' FP16 parts finite
     for (int u = 0; u < kH; ++u) {
         const float *w = P + o.W1 + u * L.n_in;
         const double b = (double)P[o.b1 + u] + (double)w[2] * cos(phi) + (double)w[3] * sin(phi) +
                          (double)w[4] * th / s_t;
-        l1[u] = make_float4((float)(w[0] / s_in), (float)(w[1] / s_in),
-                            L.n_in == 6 ? (float)(w[5] / s_E) : 0.f, (float)b);
+        const double wf[4] = {w[0] / s_in * kPre, w[1] / s_in * kPre,
+                              L.n_in == 6 ? w[5] / s_E * kPre : 0.0, b * kPre};
+        const double room = kUMax - fabs(wf[3]), slope = fabs(wf[0]) + fabs(wf[1]) + fabs(wf[2]);
+        if (!(room > 0.0))
+            return c->fail(EP_EINVAL, "network bias too large for the FP16 inference path");
+        if (slope > 0.0) xmax = fmin(xmax, room / slope);
+        const int t = u >> 5, i = u & 31;
+        for (int f = 0; f < 4; ++f) {
+            uint16_t hi, lo;
+            split_f16((float)wf[f], hi, lo);
+            w1[((size_t)t * 64 + i) * 8 + f] = hi;                 // g = 0: hi x (x_hi, 1)
+            if (f < 3) w1[((size_t)t * 64 + i) * 8 + 4 + f] = hi;  //        hi x x_lo
+            w1[((size_t)t * 64 + 32 + i) * 8 + f] = lo;            // g = 1: lo x (x_hi, 1)
+        }
     }
-    HIPCHK(c, hipMemcpy(L.d_w2hi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_w2lo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_l1, l1.data(), l1.size() * sizeof(float4), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_b2, P + o.b2, kH * sizeof(float), hipMemcpyHostToDevice));
-    // W3 as A-fragments of the layer-3 MFMA: row i < 2 is output i; k step kk,
-    // lane group g, element e stands for hidden unit
-    //   32 (kk / 2) + 16 (kk % 2) + (e < 4 ? 4 g + e : 8 + 4 g + e - 4),
-    // the unit whose layer-2 result lane (., g) holds in accumulator element
-    // 8 (kk % 2) + e -- so the activations enter the MFMA from the lanes'
-    // own registers.
-    std::vector<uint16_t> w3h((size_t)4 * 64 * 8), w3l((size_t)4 * 64 * 8);
+    if (!(xmax >= 1.0))
+        return c->fail(EP_EINVAL, "network weights too large for the FP16 inference path");
+
+    // layer 2
+    std::vector<uint16_t> w2((size_t)8 * 64 * 8);
+    for (int mt = 0; mt < 2; ++mt)
+        for (int kk = 0; kk < 4; ++kk)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    const int i = mt * 32 + (lane & 31), k = slot_unit(kk, lane >> 5, e);
+                    w2[((size_t)(mt * 4 + kk) * 64 + lane) * 8 + e] =
+                        host_f16((float)(P[o.W2 + i * kH + k] * kPre));
+                }
+    std::vector<float> b2(kH);
+    for (int j = 0; j < kH; ++j) {
+        double bound = fabs((double)P[o.b2 + j]);
+        for (int k = 0; k < kH; ++k) bound += fabs((double)P[o.W2 + j * kH + k]);
+        if (!(bound * kPre < kUMax))
+            return c->fail(EP_EINVAL, "network weights too large for the FP16 inference path");
+        b2[j] = (float)(P[o.b2 + j] * kPre);
+    }
+    // layer 3: rows 0 and 1 are the outputs, the rest zero
+    std::vector<uint16_t> w3((size_t)4 * 64 * 8, 0);
     for (int kk = 0; kk < 4; ++kk)
         for (int lane = 0; lane < 64; ++lane)
             for (int e = 0; e < 8; ++e) {
-                const int i = lane & 31, g = lane >> 5;
-                const int u = 32 * (kk >> 1) + 16 * (kk & 1) + (e < 4 ? 4 * g + e : 8 + 4 * g + e - 4);
-                const float w = i < kOut ? P[o.W3 + i * kH + u] : 0.f;
-                const uint16_t h = host_bf16(w);
-                const size_t at = ((size_t)kk * 64 + lane) * 8 + e;
-                w3h[at] = h;
-                w3l[at] = host_bf16(w - host_bf16_value(h));
+                const int i = lane & 31;
+                if (i < kOut)
+                    w3[((size_t)kk * 64 + lane) * 8 + e] =
+                        host_f16(P[o.W3 + i * kH + slot_unit(kk, lane >> 5, e)]);
             }
-    HIPCHK(c, hipMemcpy(L.d_w3f, w3h.data(), w3h.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_w3f + 4 * 64, w3l.data(), w3l.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_w1f, w1.data(), w1.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_w2f, w2.data(), w2.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_b2, b2.data(), kH * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(L.d_w3f, w3.data(), w3.size() * 2, hipMemcpyHostToDevice));
     MlpInfer &I = L.infer;
-    I.w2hi = L.d_w2hi;
-    I.w2lo = L.d_w2lo;
-    I.l1 = L.d_l1;
+    I.w1f = L.d_w1f;
+    I.w2f = L.d_w2f;
     I.b2 = L.d_b2;
     I.w3f = L.d_w3f;
     I.b3_0 = P[o.b3];
@@ -135,6 +182,7 @@ ep_status prepare_inference(ep_ctx *c, double dt, double eps)
     I.sig_d = (float)L.norm[4];
     I.mu_k = (float)L.norm[5];
     I.sig_k = (float)L.norm[6];
+    I.xmax = (float)xmax;
     I.scaled = L.norm[7] == 1.0 ? 1 : 0;
     L.packed = true;
     L.cached_dt = dt;
@@ -209,7 +257,7 @@ void free_learned(ep_ctx *c)
 {
     Learned &L = c->mlp;
     for (void *p : {(void *)L.d_params, (void *)L.d_m, (void *)L.d_v, (void *)L.d_grad,
-                    (void *)L.d_w2hi, (void *)L.d_w2lo, (void *)L.d_l1, (void *)L.d_b2,
+                    (void *)L.d_w2f, (void *)L.d_w1f, (void *)L.d_b2,
                     (void *)L.d_w3f, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total,
                     (void *)L.d_tx, (void *)L.d_ty})
         if (p) (void)hipFree(p);

@@ -70,6 +70,40 @@ __device__ __forceinline__ void to_bf16x8(const float (&a)[8], bf16x8 &hi, bf16x
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 q) { return __builtin_bit_cast(bf16x8, q); }
 
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f16x8 as_f16x8(uint4 q) { return __builtin_bit_cast(f16x8, q); }
+
+extern "C" __device__ _Float16 __ocml_rsqrt_f16(_Float16);
+
+// The activation of two pre-activations given as u = z / 64 (FP32), in
+// packed FP16: act(z) = z / sqrt(1 + z^2) = u / sqrt(u^2 + 2^-12).  The 1/64
+// keeps u^2 finite for |z| < 16320 and 2^-12 a normal FP16 number; the
+// inference weights carry the factor.  Inputs are rounded to nearest once;
+// the result has ~11 significant bits.
+__device__ __forceinline__ f16x2 act_pair(float a, float b)
+{
+    const f16x2 u = {(_Float16)a, (_Float16)b};
+    const f16x2 c = {(_Float16)0x1p-12f, (_Float16)0x1p-12f};
+    const f16x2 t = __builtin_elementwise_fma(u, u, c);
+    const f16x2 r = {__ocml_rsqrt_f16(t.x), __ocml_rsqrt_f16(t.y)};
+    return u * r;
+}
+
+// Eight activations of accumulator elements q0 .. q0 + 7 as an FP16 operand.
+__device__ __forceinline__ f16x8 act_operand(const f32x16 &acc, int q0)
+{
+    f16x8 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const f16x2 h = act_pair(acc[q0 + 2 * i], acc[q0 + 2 * i + 1]);
+        v[2 * i] = h.x;
+        v[2 * i + 1] = h.y;
+    }
+    return v;
+}
+
 // Wave-level 32x32 tile of a 64x64x64 product from FP32 LDS operands:
 //   acc(i, j) += sum_k A(i0 + i, k) B(k, j0 + j),
 //   A(i, k) = A[i*ai + k*ak],  B(k, j) = B[k*bk + j*bj].
@@ -551,19 +585,32 @@ __device__ __forceinline__ double potential(const PotView &v, double R)
 }
 
 // One learned step.  A workgroup of 4 waves takes 128 particles per
-// iteration, 32 per wave; lanes l and l+32 share particle l%32 and split its
-// hidden units.  Layer 1 runs on VALU (FP32), layers 2 and 3 on MFMA, one
-// 16-wide k step at a time so that few activations are live: W2 and W3 as
-// split BF16 (hi + lo, ~16 bits, two MFMAs) times the activations rounded to
-// BF16; the layer-3 operand order is that of the layer-2 results in the lanes.  The
-// activations' own lo halves would cost more VALU work than they are worth:
-// their rounding (2^-9) stays far below the network's approximation error.  All weights stay in LDS and are read where used.  The update and
-// the energy check run in FP64: H = |z|^2/(2 eps) + P(R) with P = R^4/4
-// (Duffing) or the frozen-field potential Psi^n (Poisson, VP = true).  With
-// the amplitude-scaled output map the outputs are divided by a = |z| first.
-// Particles that fail keep their state and go to the fallback queue.  With
-// VP the sixth feature is E^n(R_n), and the particles that pass are deposited
-// (CIC, fixed point) into an LDS histogram added to the mesh at the end.
+// iteration, 32 per wave; lanes l and l+32 share particle l%32.  All three
+// layers run on FP16 MFMA (32x32x16) with FP32 accumulation, the activations
+// in packed FP16 between them:
+//   layer 1  one MFMA per 32 hidden units; k slots 0-7 hold the features as
+//            FP16 hi parts, the constant 1 (bias) and the features' lo parts
+//            against the weights' hi parts, slots 8-15 the weights' lo parts
+//            against the features' hi parts -- ~22-bit products;
+//   layer 2  W2 in FP16 times the activations, accumulators started at the
+//            bias;
+//   layer 3  W3 in FP16 times the activations, lanes 0-31 receive the two
+//            outputs of their particle.
+// FP16 weights (2^-12 relative) in layers 2 and 3 cost no measurable accuracy
+// next to the activations' own FP16 rounding; splitting them into hi + lo
+// halves, as in layer 1, doubled those layers' MFMAs for nothing.
+// The results of one layer are the next layer's B operand without any data
+// movement: the k order of W2 and W3 is permuted at upload to the order in
+// which the accumulator elements sit in the lanes.  Features are clamped to
+// +-xmax (set from the weights so that no pre-activation can leave the FP16
+// activation's range).  All weights stay in LDS and are read where used.  The
+// update and the energy check run in FP64: H = |z|^2/(2 eps) + P(R) with
+// P = R^4/4 (Duffing) or the frozen-field potential Psi^n (Poisson,
+// VP = true).  With the amplitude-scaled output map the outputs are divided
+// by a = |z| first.  Particles that fail keep their state and go to the
+// fallback queue.  With VP the sixth feature is E^n(R_n), and the particles
+// that pass are deposited (CIC, fixed point) into an LDS histogram added to
+// the mesh at the end.
 template <bool VP>
 __global__ __launch_bounds__(256) void mlp_push_kernel(
     float *__restrict__ zR, float *__restrict__ zV, int64_t n, MlpInfer net, double2 rot0,
@@ -571,22 +618,17 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
     unsigned *__restrict__ queue, MeshView mv, PotView pv, const double *__restrict__ qb,
     unsigned long long *__restrict__ hist)
 {
-    __shared__ uint4 sAh[8 * 64], sAl[8 * 64];
-    __shared__ float4 sl1[kH];
-    __shared__ float sb2[kH];
-    __shared__ uint4 sW3[2 * 4 * 64];
+    __shared__ uint4 sW2[8 * 64];
+    __shared__ uint4 sW1[2 * 64];
+    __shared__ float4 sb2[kH / 4];
+    __shared__ uint4 sW3[4 * 64];
     __shared__ unsigned s_q[4][kWaveQueue];
     extern __shared__ __align__(16) unsigned char vp_smem[];
     const int tid = threadIdx.x;
-    for (int i = tid; i < 8 * 64; i += blockDim.x) {
-        sAh[i] = net.w2hi[i];
-        sAl[i] = net.w2lo[i];
-    }
-    if (tid < kH) {
-        sl1[tid] = net.l1[tid];
-        sb2[tid] = net.b2[tid];
-    }
-    for (int i = tid; i < 2 * 4 * 64; i += blockDim.x) sW3[i] = net.w3f[i];
+    for (int i = tid; i < 8 * 64; i += blockDim.x) sW2[i] = net.w2f[i];
+    if (tid < 2 * 64) sW1[tid] = net.w1f[tid];
+    if (tid < kH / 4) sb2[tid] = net.b2[tid];
+    for (int i = tid; i < 4 * 64; i += blockDim.x) sW3[i] = net.w3f[i];
     if (VP) {
         mv.H = reinterpret_cast<unsigned long long *>(vp_smem);
         for (int i = tid; i <= pv.nr; i += blockDim.x) mv.H[i] = 0ull;
@@ -606,49 +648,52 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
         const double zv = valid ? (double)zV[p] : 0.0;
         const double R = fma(rot0.x, zr, rot0.y * zv);
         const double Vl = fma(-rot0.y, zr, rot0.x * zv);
-        const float x0 = (float)R, x1 = (float)Vl;
-        const float x2 = VP ? (float)gather(mv, R) : 0.f;
+        // features, clamped, as FP16 hi + lo
+        float xf[3] = {(float)R, (float)Vl, VP ? (float)gather(mv, R) : 0.f};
+        _Float16 xh[3], xl[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float x = fminf(fmaxf(xf[i], -net.xmax), net.xmax);
+            xh[i] = (_Float16)x;
+            xl[i] = g == 0 ? (_Float16)(x - (float)xh[i]) : (_Float16)0.f;
+        }
+        const f16x8 xb = {xh[0], xh[1], xh[2], (_Float16)1.f, xl[0], xl[1], xl[2], (_Float16)0.f};
 
-        f32x16 acc0 = {}, acc1 = {};
+        // layer 1: pre-activations / 64 of units 0-31 and 32-63
+        const f32x16 zero = {};
+        const f32x16 u0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW1[lane]), xb, zero,
+                                                                 0, 0, 0);
+        const f32x16 u1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW1[64 + lane]), xb,
+                                                                 zero, 0, 0, 0);
+        // layer 2, accumulators started at b2 / 64
+        f32x16 acc0, acc1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float4 c0 = sb2[2 * j + g], c1 = sb2[8 + 2 * j + g];
+            acc0[4 * j] = c0.x;
+            acc0[4 * j + 1] = c0.y;
+            acc0[4 * j + 2] = c0.z;
+            acc0[4 * j + 3] = c0.w;
+            acc1[4 * j] = c1.x;
+            acc1[4 * j + 1] = c1.y;
+            acc1[4 * j + 2] = c1.z;
+            acc1[4 * j + 3] = c1.w;
+        }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            float a[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float4 w = sl1[kk * 16 + g * 8 + e];
-                float z = fmaf(w.x, x0, fmaf(w.y, x1, w.w));
-                if (VP) z = fmaf(w.z, x2, z);
-                a[e] = act(z);
-            }
-            bf16x8 bh, bl;
-            to_bf16x8<false>(a, bh, bl);
-            const bf16x8 Ah0 = as_bf16x8(sAh[kk * 64 + lane]), Al0 = as_bf16x8(sAl[kk * 64 + lane]);
-            const bf16x8 Ah1 = as_bf16x8(sAh[(4 + kk) * 64 + lane]);
-            const bf16x8 Al1 = as_bf16x8(sAl[(4 + kk) * 64 + lane]);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah0, bh, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah1, bh, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al0, bh, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al1, bh, acc1, 0, 0, 0);
+            const f16x8 b = act_operand(kk < 2 ? u0 : u1, 8 * (kk & 1));
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW2[kk * 64 + lane]), b, acc0,
+                                                          0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW2[(4 + kk) * 64 + lane]), b,
+                                                          acc1, 0, 0, 0);
         }
-        // layer 3 on MFMA: the layer-2 results (rounded to BF16) are already
-        // in B-operand order in each lane; W3 (split BF16) is the A operand;
-        // lanes 0-31 receive the two outputs of their particle
+        // layer 3
         f32x16 acc3 = {};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            float hv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int q = 8 * (kk & 1) + e;
-                const int u = 32 * (kk >> 1) + tile_row(q, g);
-                hv[e] = act((kk < 2 ? acc0[q] : acc1[q]) + sb2[u]);
-            }
-            bf16x8 bh, bl;
-            to_bf16x8<false>(hv, bh, bl);
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(sW3[kk * 64 + lane]), bh, acc3,
-                                                           0, 0, 0);
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(sW3[256 + kk * 64 + lane]), bh,
-                                                           acc3, 0, 0, 0);
+            const f16x8 b = act_operand(kk < 2 ? acc0 : acc1, 8 * (kk & 1));
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW3[kk * 64 + lane]), b, acc3,
+                                                          0, 0, 0);
         }
         const float o0 = acc3[0], o1 = acc3[1];
         float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);

@@ -6,11 +6,14 @@ Tolerances:
   * gradients (BF16 MFMA products, FP32 accumulation) against the FP64 oracle
     at the same FP32 weights and inputs: per tensor relative Frobenius error
     <= 2^-6 and cosine >= 0.9995
-  * learned step without fallback: layer 2 multiplies split-BF16 weights
-    (~2^-16) by activations rounded to BF16 (relative 2^-9); summed over 64
-    hidden units with weights ~0.1-0.2 this gives output errors up to ~2e-3
-    in o, and a particle's error is sig_d |d o| (scaled map) or
-    sig_d |d o| |y|: the test bound is 3e-4 max(|y|, 1) for sig_d = 0.05
+  * learned step without fallback: FP16 MFMA operands in all three layers
+    (layer-1 weights and features split into FP16 hi + lo, ~2^-22; W2 and
+    W3 rounded to FP16, 2^-12 relative); each activation carries ~3 FP16
+    roundings (2^-12 relative each: the pre-activation, the inverse square
+    root, the product).  Summed over 64 hidden units with weights ~0.1-0.2
+    this gives output errors up to ~1e-3 in o, and a particle's error is
+    sig_d |d o| (scaled map) or sig_d |d o| |y|, ~5e-5 for sig_d = 0.05: the
+    test bound is 1e-4 max(|y|, 1)
   * fallback: the plain push, per particle 1e-6 as for the plain path.
 """
 import math
@@ -146,7 +149,7 @@ def test_learned_push_without_fallback_is_the_network_map(out_map):
         Rg, Vg = sim.particles()
         err = rel_particle(Rg, Vg, R, V)
         worst = max(worst, err.max())
-        assert err.max() <= 3e-4, (s, err.max())
+        assert err.max() <= 1e-4, (s, err.max())
         R, V = Rg, Vg      # continue from the GPU state: compare one step at a time
     assert sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"] == 0
     sim.close()
@@ -199,7 +202,7 @@ def test_check_decisions_agree_with_oracle():
     assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
     err = rel_particle(Rg, Vg, Ro, Vo)
     assert np.max(err[clear & fb]) <= 1e-6
-    assert np.max(err[clear & ~fb]) <= 3e-4
+    assert np.max(err[clear & ~fb]) <= 1e-4
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
 
 

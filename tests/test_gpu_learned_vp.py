@@ -6,8 +6,8 @@ particles that pass are deposited by the learned kernel, the others are
 pushed and deposited by the plain fallback.  Training samples are
 self-generated from the context's own particles (ep_mlp_collect).
 
-Tolerances as for the Duffing corrector: 3e-4 max(|y|, 1) for the network map
-(BF16 activations into layer 2), the plain-push bound 1e-6 for fallback particles and
+Tolerances as for the Duffing corrector: 1e-4 max(|y|, 1) for the network map
+(FP16 operands in all three layers), the plain-push bound 1e-6 for fallback particles and
 labels (a label is checked through the state it maps to), field after a step
 2e-6 max|E|.  All cases call the HIP library through its C ABI.
 """
@@ -98,7 +98,7 @@ def test_learned_push_without_fallback_is_the_network_map(out_map):
         sim.step(DT, EPS, EP_FIELD_POISSON, 1)
         Rg, Vg = sim.particles()
         err = rel_particle(Rg, Vg, Ro, Vo)
-        assert err.max() <= 3e-4, (s, err.max())
+        assert err.max() <= 1e-4, (s, err.max())
         # the learned kernel deposited the new positions
         _, Eg_, _, _ = sim.field()
         Eo, _, _ = _field(Rg, w)
@@ -145,7 +145,7 @@ def test_check_decisions_agree_with_oracle():
     assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
     err = rel_particle(Rg, Vg, Ro, Vo)
     assert np.max(err[clear & fb]) <= 1e-6
-    assert np.max(err[clear & ~fb]) <= 3e-4
+    assert np.max(err[clear & ~fb]) <= 1e-4
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
 
 
