@@ -747,32 +747,91 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
     }
 }
 
+// Fallback kernels keep the substep coefficients in LDS up to this many
+// substeps (64 KB); beyond it they read them from global memory.
+constexpr int kFallbackLdsK = 2048;
+
+// LDS of the Poisson fallback: field table and histogram, as in the mesh push
+// kernel, then the coefficient table at a 32-byte boundary.
+__host__ __device__ constexpr size_t fallback_table_offset(int nr)
+{
+    return ((size_t)nr * sizeof(float2) + (size_t)(nr + 1) * sizeof(unsigned long long) + 31) &
+           ~(size_t)31;
+}
+
+// K substeps of the plain push of one particle.  A fallback kernel holds few
+// particles, so its loop is bound by latency: the substep coefficients are
+// read eight substeps at a time (one wait per eight table reads instead of
+// one per substep).  Same arithmetic in the same order as the plain push
+// kernels, so a fallback particle gets exactly the plain push.
+template <typename Field>
+__device__ __forceinline__ void push_staged(const double4 *__restrict__ t, int K, Field field,
+                                            double &zr, double &zv)
+{
+    double ar = 0.0, av = 0.0;
+    const auto substep = [&](const double4 &q) {
+        const double Rm = fma(q.x, zr + ar, q.y * (zv + av));
+        const double E = field(Rm);
+        ar = fma(-q.z, E, ar);
+        av = fma(q.w, E, av);
+    };
+    int k = 0;
+    for (; k + 8 <= K; k += 8) {
+        double4 q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = t[k + j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) substep(q[j]);
+    }
+    for (; k < K; ++k) substep(t[k]);
+    zr += ar;
+    zv += av;
+}
+
+// Copies the K substep coefficients into LDS (K <= kFallbackLdsK).
+__device__ __forceinline__ double4 *stage_table(unsigned char *smem, const double4 *sub, int K)
+{
+    double4 *t = reinterpret_cast<double4 *>(smem);
+    for (int i = threadIdx.x; i < K; i += blockDim.x) t[i] = sub[i];
+    return t;
+}
+
 // Plain push (K substeps, FP64) of the queued particles, Duffing field.
+// Workgroups past the queue's end return at once; the others stage the
+// coefficient table in LDS when it fits (K <= kFallbackLdsK).
 __global__ __launch_bounds__(256) void fallback_duffing_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K,
     unsigned long long *__restrict__ total)
 {
+    extern __shared__ __align__(16) unsigned char fbd_smem[];
     const unsigned count = *qcount;
     if (blockIdx.x == 0 && threadIdx.x == 0) *total += count;
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += gridDim.x * blockDim.x) {
-        const unsigned p = queue[i];
-        double zr = zR[p], zv = zV[p], ar = 0.0, av = 0.0;
-        for (int k = 0; k < K; ++k) {
-            const double4 q = sub[k];
-            const double Rm = fma(q.x, zr + ar, q.y * (zv + av));
-            const double E = -(Rm * Rm) * Rm;
-            ar = fma(-q.z, E, ar);
-            av = fma(q.w, E, av);
+    if ((unsigned)blockIdx.x * blockDim.x >= count) return;   // uniform over the workgroup
+    const auto duffing = [](double R) { return -(R * R) * R; };
+    const auto run = [&](const double4 *t) {
+        for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
+             i += gridDim.x * blockDim.x) {
+            const unsigned p = queue[i];
+            double zr = zR[p], zv = zV[p];
+            push_staged(t, K, duffing, zr, zv);
+            zR[p] = (float)zr;
+            zV[p] = (float)zv;
         }
-        zR[p] = (float)(zr + ar);
-        zV[p] = (float)(zv + av);
+    };
+    // two loops, so that each one's table reads use their own address space
+    if (K <= kFallbackLdsK) {
+        const double4 *t = stage_table(fbd_smem, sub, K);
+        __syncthreads();
+        run(t);
+    } else {
+        run(sub);
     }
 }
 
-// Plain push (K substeps, FP64, field table in LDS) of the queued particles in
-// the frozen Poisson field, then their CIC deposit at the end-of-step phase.
+// Plain push (K substeps, FP64, field table and, when it fits, the substep
+// coefficients in LDS) of the queued particles in the frozen Poisson field,
+// then their CIC deposit at the end-of-step phase.
 __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K, double2 er,
@@ -781,7 +840,9 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
 {
     extern __shared__ __align__(16) unsigned char fb_smem[];
     const unsigned count = *qcount;
-    if (count == 0u) return;   // uniform over the grid: no LDS set-up needed
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total += count;
+    // uniform over the workgroup: an empty workgroup has nothing to deposit
+    if ((unsigned)blockIdx.x * blockDim.x >= count) return;
     const int tid = threadIdx.x;
     mv.Et = reinterpret_cast<float2 *>(fb_smem);
     mv.H = reinterpret_cast<unsigned long long *>(fb_smem + (size_t)nr * sizeof(float2));
@@ -789,17 +850,27 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     for (int i = tid; i < nr; i += blockDim.x) Et[i] = etab[i];
     for (int i = tid; i <= nr; i += blockDim.x) mv.H[i] = 0ull;
     mv.Qb = *qb;
-    if (blockIdx.x == 0 && tid == 0) *total += count;
+    const bool staged = K <= kFallbackLdsK;
+    const double4 *t = staged ? stage_table(fb_smem + fallback_table_offset(nr), sub, K) : nullptr;
     __syncthreads();
-    for (unsigned i = blockIdx.x * blockDim.x + tid; i < count; i += gridDim.x * blockDim.x) {
-        const unsigned p = queue[i];
-        double a[1] = {(double)zR[p]}, b[1] = {(double)zV[p]};
-        push_group<1>(mv, sub, K, a, b);
-        const float fr = (float)a[0], fv = (float)b[0];
-        zR[p] = fr;
-        zV[p] = fv;
-        deposit(mv, fma(er.x, (double)fr, er.y * (double)fv));
-    }
+    const auto field = [&mv](double R) { return gather(mv, R); };
+    const auto run = [&](const double4 *tab) {
+        for (unsigned i = blockIdx.x * blockDim.x + tid; i < count;
+             i += gridDim.x * blockDim.x) {
+            const unsigned p = queue[i];
+            double zr = zR[p], zv = zV[p];
+            push_staged(tab, K, field, zr, zv);
+            const float fr = (float)zr, fv = (float)zv;
+            zR[p] = fr;
+            zV[p] = fv;
+            deposit(mv, fma(er.x, (double)fr, er.y * (double)fv));
+        }
+    };
+    // two loops, so that each one's table reads use their own address space
+    if (staged)
+        run(t);
+    else
+        run(sub);
     __syncthreads();
     const int nn = nr + 1;
     const int start = (int)(((unsigned)blockIdx.x * 131u) % (unsigned)nn);
@@ -864,7 +935,8 @@ hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const u
                                    const unsigned *qcount, const double4 *sub, int K,
                                    unsigned long long *total, int n_cu)
 {
-    return dispatch(fallback_duffing_kernel, dim3((unsigned)n_cu * 8), dim3(256), 0, st, zR, zV,
+    const size_t lds = K <= kFallbackLdsK ? (size_t)K * sizeof(double4) : 0;
+    return dispatch(fallback_duffing_kernel, dim3((unsigned)n_cu * 8), dim3(256), lds, st, zR, zV,
                     queue, qcount, sub, K, total);
 }
 
@@ -872,7 +944,9 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
                                    const unsigned *qcount, const double4 *sub, int K, double2 er,
                                    const MeshArgs &ma, unsigned long long *total, int n_cu)
 {
-    const size_t lds = push_lds_bytes_for(ma.nr);
+    const size_t lds = K <= kFallbackLdsK
+                           ? fallback_table_offset(ma.nr) + (size_t)K * sizeof(double4)
+                           : push_lds_bytes_for(ma.nr);
     return dispatch(fallback_poisson_kernel, dim3((unsigned)n_cu), dim3(kPushBlock), lds, st, zR, zV,
                     queue, qcount, sub, K, er, mesh_view(ma), (const float2 *)ma.etab,
                     (const double *)(ma.fscal + kQb), ma.nr, ma.hist, total);
@@ -884,9 +958,13 @@ hipError_t setup_learned_lds(int nr)
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)mlp_vp_lds_bytes(nr));
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fallback_duffing_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kFallbackLdsK * sizeof(double4)));
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&fallback_poisson_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)push_lds_bytes_for(nr));
+                               (int)(fallback_table_offset(nr) + kFallbackLdsK * sizeof(double4)));
 }
 
 }  // namespace etd

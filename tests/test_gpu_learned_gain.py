@@ -6,6 +6,8 @@ size and checks:
     elliptic solution of the Duffing characteristics;
   * that training gains over the untrained network (rms-radius error of the
     network map, no fallback, trained vs random weights);
+  * that at the at-scale Duffing workload the learned push beats the plain
+    push of equal rms-radius error in throughput;
 and prints the equal-error table: plain K sweep vs learned (with the 1e-5
 energy-drift fallback and without), throughput and rms-radius error.
 """
@@ -58,6 +60,18 @@ def test_equal_error_comparison():
     untrained = abs(np.sqrt(np.mean(R ** 2)) - res["rms_ref"]) / res["rms_ref"]
     print("rms error: trained %.3e, untrained %.3e" % (trained, untrained))
     assert trained < 0.5 * untrained
+
+
+def test_learned_beats_plain_at_equal_error():
+    """At the at-scale Duffing workload (eps = 1e-3, dt = 0.05, R, V ~ N(0, 1.5),
+    200 steps, network trained on 1e7 fine-push labels; 2e6 evaluation
+    particles here) the learned push is faster than the cheapest plain push
+    whose rms-radius error is as small, with the 1e-5 energy check and
+    without it."""
+    res = compare.equal_error(n_train=10_000_000, n_eval=2_000_000, log=print)
+    print(json.dumps({k: res[k] for k in ("equal_error", "equal_error_no_check")}, indent=1))
+    for key in ("equal_error", "equal_error_no_check"):
+        assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
 
 
 def test_equal_error_comparison_vp():
