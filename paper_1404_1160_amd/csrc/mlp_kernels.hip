@@ -584,7 +584,12 @@ __device__ __forceinline__ double potential(const PotView &v, double R)
     return v.Psi[m] - fma(e0, d, (e1 - e0) * (d * d) * (0.5 * v.inv_hr));
 }
 
-// One learned step.  A workgroup of 4 waves takes 128 particles per
+// Waves per workgroup of the inference kernel.  With the Poisson field a
+// workgroup holds a (N_r + 1)-entry histogram in LDS, which allows two
+// workgroups per CU: eight waves each keep four waves on every SIMD.
+constexpr int kWavesDuffing = 4, kWavesPoisson = 8;
+
+// One learned step.  A workgroup of WAVES waves takes 32 WAVES particles per
 // iteration, 32 per wave; lanes l and l+32 share particle l%32.  All three
 // layers run on FP16 MFMA (32x32x16) with FP32 accumulation, the activations
 // in packed FP16 between them:
@@ -611,8 +616,8 @@ __device__ __forceinline__ double potential(const PotView &v, double R)
 // fallback queue.  With VP the sixth feature is E^n(R_n), and the particles
 // that pass are deposited (CIC, fixed point) into an LDS histogram added to
 // the mesh at the end.
-template <bool VP>
-__global__ __launch_bounds__(256) void mlp_push_kernel(
+template <bool VP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
     float *__restrict__ zR, float *__restrict__ zV, int64_t n, MlpInfer net, double2 rot0,
     double2 rot1, double inv2eps, double tol, unsigned *__restrict__ qcount,
     unsigned *__restrict__ queue, MeshView mv, PotView pv, const double *__restrict__ qb,
@@ -622,7 +627,7 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
     __shared__ uint4 sW1[2 * 64];
     __shared__ float4 sb2[kH / 4];
     __shared__ uint4 sW3[4 * 64];
-    __shared__ unsigned s_q[4][kWaveQueue];
+    __shared__ unsigned s_q[WAVES][kWaveQueue];
     extern __shared__ __align__(16) unsigned char vp_smem[];
     const int tid = threadIdx.x;
     for (int i = tid; i < 8 * 64; i += blockDim.x) sW2[i] = net.w2f[i];
@@ -638,11 +643,12 @@ __global__ __launch_bounds__(256) void mlp_push_kernel(
     WaveQueue wq{s_q[wave], 0u};
     __syncthreads();
 
-    const int64_t nbg = (n + 127) >> 7;
+    constexpr int kGroup = 32 * WAVES;   // particles per workgroup iteration
+    const int64_t nbg = (n + kGroup - 1) / kGroup;
     for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
         // keep the LDS reads below inside the loop (no hoisting into registers)
         asm volatile("" ::: "memory");
-        const int64_t p = bg * 128 + wave * 32 + r;
+        const int64_t p = bg * kGroup + wave * 32 + r;
         const bool valid = p < n;
         const double zr = valid ? (double)zR[p] : 0.0;
         const double zv = valid ? (double)zV[p] : 0.0;
@@ -899,9 +905,10 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t
                                    double tol, unsigned *qcount, unsigned *queue, int n_cu)
 {
     if (n <= 0) return hipSuccess;
-    int64_t grid = (n + 127) / 128;
+    int64_t grid = (n + 32 * kWavesDuffing - 1) / (32 * kWavesDuffing);
     if (grid > (int64_t)n_cu * 8) grid = (int64_t)n_cu * 8;
-    return dispatch(mlp_push_kernel<false>, dim3((unsigned)grid), dim3(256), 0, st, zR, zV, n, net,
+    return dispatch(mlp_push_kernel<false, kWavesDuffing>, dim3((unsigned)grid),
+                    dim3(64 * kWavesDuffing), 0, st, zR, zV, n, net,
                     rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{},
                     (const double *)nullptr, (unsigned long long *)nullptr);
 }
@@ -914,7 +921,7 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
                                    const MeshArgs &ma, double rmax, int n_cu)
 {
     if (n <= 0) return hipSuccess;
-    int64_t grid = (n + 127) / 128;
+    int64_t grid = (n + 32 * kWavesPoisson - 1) / (32 * kWavesPoisson);
     if (grid > (int64_t)n_cu * 2) grid = (int64_t)n_cu * 2;
     PotView pv;
     pv.E = ma.E64;
@@ -926,7 +933,8 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
     pv.Qb = 0.0;
     pv.c = ma.nr >> 1;
     pv.nr = ma.nr;
-    return dispatch(mlp_push_kernel<true>, dim3((unsigned)grid), dim3(256), mlp_vp_lds_bytes(ma.nr),
+    return dispatch(mlp_push_kernel<true, kWavesPoisson>, dim3((unsigned)grid),
+                    dim3(64 * kWavesPoisson), mlp_vp_lds_bytes(ma.nr),
                     st, zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma),
                     pv, (const double *)(ma.fscal + kQb), ma.hist);
 }
@@ -954,7 +962,7 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
 
 hipError_t setup_learned_lds(int nr)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_push_kernel<true>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_push_kernel<true, kWavesPoisson>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)mlp_vp_lds_bytes(nr));
     if (e != hipSuccess) return e;
