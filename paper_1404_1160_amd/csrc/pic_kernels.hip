@@ -288,7 +288,7 @@ hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &a)
 // the frozen field (PUSH), store, and deposit the new positions -- rounded
 // to the stored FP32 state, so that a later deposit of the same state gives
 // the same charge bit for bit.
-template <bool PUSH>
+template <bool PUSH, int U>
 __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
     float *__restrict__ zR, float *__restrict__ zV, int64_t n, const double4 *__restrict__ sub,
     const double2 *__restrict__ endrot_tab, double2 endrot_val, int K, double inv_hr, MeshArgs ma)
@@ -313,18 +313,18 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
     const double2 er = endrot_tab ? endrot_tab[0] : endrot_val;
     __syncthreads();
 
-    // Each thread takes two float4 groups (8 particles) per iteration, with
-    // all four loads in flight before any arithmetic.  The state is streamed
+    // Each thread takes U float4 groups (4 U particles) per iteration, with
+    // all their loads in flight before any arithmetic.  The state is streamed
     // once per step, so loads and stores are nontemporal: they do not displace
     // the field table and histogram lines that the caches hold.
     const int64_t n4 = n >> 2;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * U;
     f32x4 *zR4 = reinterpret_cast<f32x4 *>(zR);
     f32x4 *zV4 = reinterpret_cast<f32x4 *>(zV);
-    for (int64_t g0 = blockIdx.x * (int64_t)blockDim.x * 2 + tid; g0 < n4; g0 += stride) {
-        f32x4 r4[2], v4[2];
+    for (int64_t g0 = blockIdx.x * (int64_t)blockDim.x * U + tid; g0 < n4; g0 += stride) {
+        f32x4 r4[U], v4[U];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t i = g0 + (int64_t)u * blockDim.x;
             if (i < n4) {
                 r4[u] = __builtin_nontemporal_load(&zR4[i]);
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
             }
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t i = g0 + (int64_t)u * blockDim.x;
             if (i < n4) {
                 f32x4 fr = r4[u], fv = v4[u];
@@ -401,24 +401,36 @@ hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, 
     if (n <= 0) return hipSuccess;
     const size_t lds = push_lds_bytes(ma.nr);
     const int64_t n4 = n >> 2;
-    int64_t grid = (n4 + 2 * kPushBlock - 1) / (2 * kPushBlock);
+    // Two float4 groups per thread keep more loads in flight where the state
+    // stream is long; a short one would leave CUs without a workgroup (grid_cap
+    // is 16 workgroups per CU: below 2 per CU, take one group per thread).
+    const int64_t g2 = (n4 + 2 * kPushBlock - 1) / (2 * kPushBlock);
+    const bool two = g2 >= (int64_t)grid_cap / 8;
+    int64_t grid = two ? g2 : (n4 + kPushBlock - 1) / kPushBlock;
     if (grid > grid_cap) grid = grid_cap;
     if (grid < 1) grid = 1;
     const double inv_hr = 1.0 / ma.hr;
     const dim3 g((unsigned)grid), b(kPushBlock);
-    if (push)
-        return dispatch(push_poisson_kernel<true>, g, b, lds, st, zR, zV, n, sub, endrot_tab,
+    if (push) {
+        if (two)
+            return dispatch(push_poisson_kernel<true, 2>, g, b, lds, st, zR, zV, n, sub,
+                            endrot_tab, endrot_val, K, inv_hr, ma);
+        return dispatch(push_poisson_kernel<true, 1>, g, b, lds, st, zR, zV, n, sub, endrot_tab,
                         endrot_val, K, inv_hr, ma);
-    return dispatch(push_poisson_kernel<false>, g, b, lds, st, zR, zV, n, sub, endrot_tab,
+    }
+    if (two)
+        return dispatch(push_poisson_kernel<false, 2>, g, b, lds, st, zR, zV, n, sub, endrot_tab,
+                        endrot_val, 0, inv_hr, ma);
+    return dispatch(push_poisson_kernel<false, 1>, g, b, lds, st, zR, zV, n, sub, endrot_tab,
                     endrot_val, 0, inv_hr, ma);
 }
 
 size_t push_lds_bytes_for(int nr) { return push_lds_bytes(nr); }
 
-template <bool P>
+template <bool P, int U>
 static hipError_t raise_lds(int lds)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<P>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<P, U>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
@@ -426,8 +438,10 @@ hipError_t setup_mesh_lds(int nr)
 {
     const int lds = (int)push_lds_bytes(nr);
     hipError_t e;
-    if ((e = raise_lds<true>(lds)) != hipSuccess) return e;
-    if ((e = raise_lds<false>(lds)) != hipSuccess) return e;
+    if ((e = raise_lds<true, 1>(lds)) != hipSuccess) return e;
+    if ((e = raise_lds<true, 2>(lds)) != hipSuccess) return e;
+    if ((e = raise_lds<false, 1>(lds)) != hipSuccess) return e;
+    if ((e = raise_lds<false, 2>(lds)) != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&mesh_solve_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)mesh_lds_bytes(nr));

@@ -49,9 +49,9 @@ __device__ __forceinline__ void step_one(const MeshView &m, const double4 *__res
 
 }  // namespace
 
-// Particles are visited in the same order as by the fused push kernel
-// (float4 groups with a grid stride, then the ragged tail) so that both
-// passes assign each particle to the same workgroup.
+// Both passes visit the particles in the same order (float4 groups with a
+// grid stride, then the ragged tail), so that they assign each particle to
+// the same workgroup.
 template <bool SCATTER>
 __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     const float *__restrict__ zR, const float *__restrict__ zV, const unsigned *__restrict__ ids,

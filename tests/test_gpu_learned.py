@@ -180,6 +180,28 @@ def test_nan_weight_forces_fallback():
     sim.close()
 
 
+def test_weights_outside_the_fp16_range_are_rejected():
+    """A network whose pre-activations could leave the FP16 activation's range
+    (|z| >= 16320) is refused with EP_EINVAL when a step needs it; the state
+    is left untouched, and a network in range works afterwards."""
+    R0, V0, w = synth.gaussian(1000, seed=19, sigma=SIG)
+    p, norm = _net()
+    o_b2 = 64 * 5 + 64 + 64 * 64          # first layer-2 bias
+    o_b1 = 64 * 5                         # first layer-1 bias
+    for off in (o_b2, o_b1):
+        bad = p.copy()
+        bad[off] = 2.0e4
+        sim = _learned_sim(R0, V0, w, bad, norm, 1e300, 8)
+        with pytest.raises(capi.EtdpicError) as ei:
+            sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+        assert ei.value.status == capi.EP_EINVAL and "FP16" in str(ei.value)
+        Rg, Vg = sim.particles()
+        assert np.array_equal(Rg, R0.astype(np.float32).astype(np.float64))
+        capi.ep_mlp_set_weights(sim.ctx, p, norm.as_array())
+        sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+        sim.close()
+
+
 def test_check_decisions_agree_with_oracle():
     """With tol at the median drift ratio about half the particles take the
     network map and half the plain fallback; where the oracle's ratio is not
