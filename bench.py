@@ -18,6 +18,7 @@ with
                   segmented reduction vs LDS-privatised atomics);
   cpu_baseline -- the FP64 CPU oracle timed on this host on a bounded sample;
   learned_vs_plain -- the equal-error comparison of the learned corrector
+                  (BF16 and FP16 inference, with the 1e-5 check and without)
                   (Duffing field, eps = 1e-3, dt = 0.05, trained on 1e7
                   samples, evaluated on 1e7 particles; see
                   paper_1404_1160_amd/compare.py);

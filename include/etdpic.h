@@ -256,6 +256,23 @@ typedef struct {
     double label_ms, train_ms; /* GPU time of label generation and of training       */
 } ep_train_report;
 
+/* MFMA operand type of the learned push (the inference; training always uses
+ * BF16 products with FP32 accumulation). */
+typedef enum {
+    EP_MLP_BF16 = 0, /* default: layer-1 weights and features as split BF16
+                        (hi + lo), W2 and W3 as split BF16, activations computed
+                        in FP32 and rounded to BF16                             */
+    EP_MLP_FP16 = 1  /* layer-1 weights and features as split FP16, W2 and W3 in
+                        FP16, activations in packed FP16 arithmetic: faster and
+                        closer to the FP64 network; networks whose pre-
+                        activations could reach |z| >= 16320 are refused with
+                        EP_EINVAL by the step that needs them                   */
+} ep_mlp_precision;
+
+/* Select the inference operand type (ep_mlp_precision) for later learned
+ * steps.  Errors: EP_EINVAL (unknown value). */
+ep_status ep_mlp_set_precision(ep_ctx *ctx, int32_t precision);
+
 /* Load network parameters (n_params = 4674 or 4738 FP32 values, layout above)
  * and their normalisation (8 doubles).  Errors: EP_EINVAL. */
 ep_status ep_mlp_set_weights(ep_ctx *ctx, const float *params, uint32_t n_params,
@@ -317,12 +334,15 @@ ep_status ep_mlp_train(ep_ctx *ctx, const ep_train_cfg *cfg, const double *R, co
 /* ---------------------------------------------------------------- checkpoint
  * ep_save writes the state of the current time level to `path`: a header
  * (magic "ETDPIC01", format version, loaded particle count, mesh and substep
- * configuration, weight, t, phase, step count, push mode, fallback settings),
+ * configuration, weight, t, phase, step count, push mode, fallback settings,
+ * inference precision, fine-solver settings),
  * the FP32 rotating-frame particle arrays in the order they were loaded, and
  * the corrector's parameters and normalisation if one is loaded.  ep_load
  * restores such a file into a context whose capacity, mesh and substeps
  * accept it; the field is recomputed from the particles, so a resumed run
- * continues bit for bit.  The fallback counter of ep_moments is a statistic,
+ * continues bit for bit.  A push mode the context cannot run (the learned
+ * push without a network, a fine solver with the sorted deposit) is restored
+ * as the plain push.  The fallback counter of ep_moments is a statistic,
  * not state: it is not saved.  Errors: EP_EIO (file cannot be opened, read or
  * written, or is not a checkpoint of this format), EP_EINVAL (it does not fit
  * the context), EP_EHIP.  ep_load stores the restored particle count in

@@ -8,7 +8,8 @@ generators shared with the tests.
 from . import capi
 from .capi import (EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED, EP_FIELD_DUFFING, EP_FIELD_POISSON,
                    EP_FIELD_ZERO, EP_PUSH_CLASSIC_ETD, EP_PUSH_IMPROVED_ETD, EP_PUSH_LEARNED,
-                   EP_PUSH_MODIFIED_ETD, EP_PUSH_PLAIN, EP_PUSH_RK4, EtdpicError)
+                   EP_PUSH_MODIFIED_ETD, EP_PUSH_PLAIN, EP_PUSH_RK4, EP_MLP_BF16, EP_MLP_FP16,
+                   EtdpicError)
 
 
 class Sim:

@@ -17,6 +17,7 @@ EP_FIELD_ZERO, EP_FIELD_DUFFING, EP_FIELD_POISSON = 0, 1, 2
 EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED = 0, 1
 (EP_PUSH_PLAIN, EP_PUSH_LEARNED, EP_PUSH_RK4, EP_PUSH_IMPROVED_ETD, EP_PUSH_CLASSIC_ETD,
  EP_PUSH_MODIFIED_ETD) = 0, 1, 2, 3, 4, 5
+EP_MLP_BF16, EP_MLP_FP16 = 0, 1
 
 STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EHIP", -4: "EP_ESTATE",
                 -5: "EP_ENOTRAINED", -6: "EP_EIO"}
@@ -28,7 +29,7 @@ EXPORTS = (
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
     "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect", "ep_mlp_get_samples",
     "ep_save", "ep_load", "ep_set_fine_solver", "ep_get_periods", "ep_compute_periods",
-    "ep_copy_bandwidth",
+    "ep_copy_bandwidth", "ep_mlp_set_precision",
 )
 
 
@@ -109,6 +110,7 @@ def lib():
             "ep_timing_enable": ([vp, i32], i32),
             "ep_timing_get": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(u64)], i32),
             "ep_mlp_set_weights": ([vp, pf, u32, pd], i32),
+            "ep_mlp_set_precision": ([vp, i32], i32),
             "ep_mlp_get_weights": ([vp, pf, u32, pd], i32),
             "ep_mlp_labels": ([vp, d, d, u32, pd, pd, u64, pf, pf], i32),
             "ep_mlp_grad": ([vp, pf, pf, u32, pf, pd], i32),
@@ -237,6 +239,11 @@ def ep_mlp_set_weights(ctx, params, norm):
     if norm.size != 8:
         raise ValueError("norm must hold 8 values")
     _check(ctx, lib().ep_mlp_set_weights(ctx, _pf(params), params.size, _p(norm)))
+
+
+def ep_mlp_set_precision(ctx, precision):
+    """Inference operand type: EP_MLP_BF16 (default) or EP_MLP_FP16."""
+    _check(ctx, lib().ep_mlp_set_precision(ctx, int(precision)))
 
 
 def mlp_n_params(n_in):

@@ -19,13 +19,18 @@ and, every `collect_every` steps, its particles, their field E^n and the
 labels of a K_fine-substep step in that frozen field are collected on the
 GPU.  Reference and error metric as above, with the reference run at K_ref.
 
+The learned push runs with both inference operand types (BF16, the
+library's default, and FP16); the results carry the equal-error point of
+each (with the check and without it) and a summary of their gains.
+
 Everything here calls the HIP library through its C ABI.
 """
 import time
 
 import numpy as np
 
-from . import EP_FIELD_DUFFING, EP_FIELD_POISSON, EP_PUSH_LEARNED, EP_PUSH_PLAIN, Sim, capi, synth
+from . import (EP_FIELD_DUFFING, EP_FIELD_POISSON, EP_MLP_BF16, EP_MLP_FP16, EP_PUSH_LEARNED,
+               EP_PUSH_PLAIN, Sim, capi, synth)
 
 DT, EPS, SIGMA = 0.05, 1e-3, 1.5
 NORM_INIT = np.array([SIGMA, 100.0, 1.0, 0.0, 1.0, 0.0, 1.0, 0.0])
@@ -79,11 +84,35 @@ def _equal_error_point(plain, entry):
             "rms_err_learned": entry["rms_err"], "rms_err_plain": q["rms_err"]}
 
 
+PREC_NAMES = {EP_MLP_BF16: "bf16", EP_MLP_FP16: "fp16"}
+
+
+def _equal_error_points(out, plain, learned, tol=None):
+    """Equal-error points of the learned runs, per precision p:
+    "equal_error_<p>" at the drift bound (the first checked run unless tol is
+    given) and "equal_error_no_check_<p>"; "gains" collects their gains."""
+    gains = {}
+    for name in dict.fromkeys(e["precision"] for e in learned):
+        runs = [e for e in learned if e["precision"] == name]
+        checked = [e for e in runs if e["drift_tol"] is not None and
+                   (tol is None or e["drift_tol"] == tol)]
+        g = {}
+        if checked:
+            out["equal_error_" + name] = _equal_error_point(plain, checked[0])
+            g["with_check"] = out["equal_error_" + name]["gain"]
+        out["equal_error_no_check_" + name] = _equal_error_point(
+            plain, [e for e in runs if e["drift_tol"] is None][0])
+        g["no_check"] = out["equal_error_no_check_" + name]["gain"]
+        gains[name] = g
+    out["gains"] = gains
+
+
 def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fine=800,
                 plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5, K_fb=400,
-                seed_eval=15, every=10, log=None):
+                seed_eval=15, every=10, precisions=(EP_MLP_BF16, EP_MLP_FP16), log=None):
     """Returns a dict with the training report, the plain sweep, the learned
-    runs and the equal-error point."""
+    runs (for each inference precision, with the check at tol and without
+    it) and the equal-error points (see _equal_error_points)."""
     def say(msg):
         if log:
             log(msg)
@@ -122,7 +151,8 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
         say("trained: loss %.4f -> %.4f in %d steps (%.0f ms)" % (
             rep["loss_first"], rep["loss_last"], rep["steps"], rep["train_ms"]))
         learned = []
-        for t in (tol, float("inf")):
+        for prec, t in [(p_, t_) for p_ in precisions for t_ in (tol, float("inf"))]:
+            capi.ep_mlp_set_precision(sim.ctx, prec)
             sim.set_particles(Re, Ve, we)
             capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, 1e300 if t == float("inf") else t,
                                   K_fb)
@@ -136,18 +166,19 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
             fb_ms, _ = capi.ep_timing_get(sim.ctx, "fallback_push")
             capi.ep_timing_enable(sim.ctx, False)
             err, perr = run_error(sim)
-            learned.append({"drift_tol": None if t == float("inf") else t,
+            learned.append({"precision": PREC_NAMES[prec],
+                            "drift_tol": None if t == float("inf") else t,
                             "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
                             "median_particle_err": perr,
                             "fallback_rate": (f1 - f0) / (n_eval * (steps + 1)),
                             "network_particle_steps_per_s": n_eval * cnt / (mlp_ms / 1e3),
                             "fallback_ms_per_step": fb_ms / cnt})
-            say("learned tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
-                t, learned[-1]["particle_steps_per_s"], err, learned[-1]["fallback_rate"]))
+            say("learned %s tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
+                PREC_NAMES[prec], t, learned[-1]["particle_steps_per_s"], err,
+                learned[-1]["fallback_rate"]))
         capi.ep_set_push_mode(sim.ctx, EP_PUSH_PLAIN)
     out["learned"] = learned
-    out["equal_error"] = _equal_error_point(plain, learned[0])
-    out["equal_error_no_check"] = _equal_error_point(plain, learned[-1])
+    _equal_error_points(out, plain, learned)
     return out
 
 
@@ -191,10 +222,11 @@ def train_vp(n_data, steps, nr=VP_NR, K_data=400, K_fine=800, collect_every=10, 
 
 def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs=40,
                    K_fine=800, plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5,
-                   extra_tols=(1e-4, 1e-3), K_fb=400, seed_eval=17, every=10, log=None):
-    """As equal_error, for the Vlasov-Poisson beam; the learned push runs at
-    the drift bound tol (the equal-error point), at extra_tols and without
-    the check."""
+                   extra_tols=(1e-4, 1e-3), K_fb=400, seed_eval=17, every=10,
+                   precisions=(EP_MLP_BF16, EP_MLP_FP16), log=None):
+    """As equal_error, for the Vlasov-Poisson beam; the learned push runs, for
+    each precision, at the drift bound tol (the equal-error point), at
+    extra_tols and without the check."""
     def say(msg):
         if log:
             log(msg)
@@ -240,7 +272,9 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     learned = []
     with Sim(n_eval, n_cells=nr, substeps=1) as sim:
         capi.ep_mlp_set_weights(sim.ctx, p, norm)
-        for t in (tol,) + tuple(extra_tols) + (float("inf"),):
+        tols = (tol,) + tuple(extra_tols) + (float("inf"),)
+        for prec, t in [(p_, t_) for p_ in precisions for t_ in tols]:
+            capi.ep_mlp_set_precision(sim.ctx, prec)
             capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, 1e300 if t == float("inf") else t,
                                   K_fb)
             sim.set_particles(Re, Ve, we)
@@ -253,15 +287,16 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
             mlp_ms, cnt = capi.ep_timing_get(sim.ctx, "mlp_push")
             capi.ep_timing_enable(sim.ctx, False)
             err = error(sim)
-            learned.append({"drift_tol": None if t == float("inf") else t,
+            learned.append({"precision": PREC_NAMES[prec],
+                            "drift_tol": None if t == float("inf") else t,
                             "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
                             "fallback_rate": (f1 - f0) / (n_eval * (steps + 1)),
                             "network_particle_steps_per_s": n_eval * cnt / (mlp_ms / 1e3)})
-            say("vp learned tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
-                t, learned[-1]["particle_steps_per_s"], err, learned[-1]["fallback_rate"]))
+            say("vp learned %s tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
+                PREC_NAMES[prec], t, learned[-1]["particle_steps_per_s"], err,
+                learned[-1]["fallback_rate"]))
     out["learned"] = learned
-    out["equal_error"] = _equal_error_point(plain, learned[0])
-    out["equal_error_no_check"] = _equal_error_point(plain, learned[-1])
+    _equal_error_points(out, plain, learned, tol)
     return out
 
 

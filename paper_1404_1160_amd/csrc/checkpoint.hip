@@ -7,7 +7,7 @@ using namespace etd;
 namespace {
 
 constexpr char kMagic[8] = {'E', 'T', 'D', 'P', 'I', 'C', '0', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct Header {
     char magic[8];
@@ -26,6 +26,10 @@ struct Header {
     double drift_tol;
     uint32_t mlp_n_in;
     uint32_t mlp_n_params;
+    int32_t mlp_precision;
+    uint32_t reserved;
+    double h_fine;
+    uint64_t max_fine;
 };
 
 struct File {
@@ -62,6 +66,9 @@ ep_status ep_save(ep_ctx *c, const char *path)
     h.drift_tol = c->drift_tol;
     h.mlp_n_in = (uint32_t)c->mlp.n_in;
     h.mlp_n_params = (uint32_t)c->mlp.params.size();
+    h.mlp_precision = c->mlp.precision;
+    h.h_fine = c->h_fine;
+    h.max_fine = c->max_fine;
     // particles in loaded order
     std::vector<float> zr(c->n), zv(c->n);
     if (c->n) {
@@ -146,7 +153,18 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
     c->t = h.t;
     c->phase = h.phase;
     c->n_steps = h.n_steps;
-    c->push_mode = (h.push_mode == EP_PUSH_LEARNED && c->mlp.n_in) ? EP_PUSH_LEARNED : EP_PUSH_PLAIN;
+    // the push mode as saved, where this context supports it (else plain)
+    int32_t mode = h.push_mode;
+    if (mode < EP_PUSH_PLAIN || mode > EP_PUSH_MODIFIED_ETD) mode = EP_PUSH_PLAIN;
+    if (mode == EP_PUSH_LEARNED && !c->mlp.n_in) mode = EP_PUSH_PLAIN;
+    if (mode >= EP_PUSH_RK4 && c->cfg.deposit == EP_DEPOSIT_SORTED) mode = EP_PUSH_PLAIN;
+    c->push_mode = mode;
+    if (h.mlp_precision == EP_MLP_BF16 || h.mlp_precision == EP_MLP_FP16)
+        (void)ep_mlp_set_precision(c, h.mlp_precision);
+    if (isfinite(h.h_fine) && h.max_fine >= 1) {
+        c->h_fine = h.h_fine;
+        c->max_fine = h.max_fine;
+    }
     c->fallback_K = h.fallback_K;
     c->drift_tol = h.drift_tol;
     c->field_valid = false;

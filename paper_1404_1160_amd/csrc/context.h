@@ -52,6 +52,7 @@ struct Learned {
     float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
     // inference constants for (dt, eps) = cached_dt, cached_eps
     uint4 *d_w1f = nullptr, *d_w2f = nullptr;
+    int32_t precision = EP_MLP_BF16;   // MFMA operand type of the inference
     float4 *d_b2 = nullptr;
     uint4 *d_w3f = nullptr;
     bool packed = false;

@@ -148,12 +148,15 @@ struct MlpInfer {
     //   32 (kk / 2) + 16 (kk % 2) + 8 (e / 4) + 4 g + e % 4,
     // the unit whose result lane (., g) holds in accumulator element
     // 8 (kk % 2) + e of tile kk / 2.
+    // FP16 (fp16 != 0) or BF16 values; with BF16 the W2 and W3 fragments
+    // are followed by those of their lo parts (w - hi).
     const uint4 *w1f;    // [2 tiles][64 lanes] layer 1 / 64, features folded (see kernel)
-    const uint4 *w2f;    // [8 = 4 mt + kk][64 lanes] W2 / 64
+    const uint4 *w2f;    // [(2)][8 = 4 mt + kk][64 lanes] W2 / 64
     const float4 *b2;    // [16] b2 / 64
-    const uint4 *w3f;    // [4 kk][64 lanes] W3, rows 0, 1 the outputs, the rest zero
+    const uint4 *w3f;    // [(2)][4 kk][64 lanes] W3, rows 0, 1 the outputs, the rest zero
     float b3_0, b3_1, mu_d, sig_d, mu_k, sig_k;
     float xmax;          // features are clamped to +-xmax
+    int fp16;            // MFMA operands in FP16 (1) or BF16 (0)
     int scaled;          // outputs are (a delta, a kappa), a = |y|, instead of (delta, kappa)
 };
 

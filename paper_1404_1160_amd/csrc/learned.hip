@@ -44,11 +44,35 @@ float host_f16_value(uint16_t h)
     return (h & 0x8000u) ? -v : v;
 }
 
-// w as FP16 hi + lo (lo = f16(w - hi), ~22 significant bits together)
-void split_f16(float w, uint16_t &hi, uint16_t &lo)
+// FP32 -> BF16 bits, round to nearest even.
+uint16_t host_bf16(float f)
 {
-    hi = host_f16(w);
-    lo = host_f16(w - host_f16_value(hi));
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);   // NaN stays NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float host_bf16_value(uint16_t b)
+{
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// w as hi + lo in FP16 (fp16 != 0, ~22 significant bits together) or BF16
+// (~16 bits); lo = round(w - hi)
+void split_op(int fp16, float w, uint16_t &hi, uint16_t &lo)
+{
+    if (fp16) {
+        hi = host_f16(w);
+        lo = host_f16(w - host_f16_value(hi));
+    } else {
+        hi = host_bf16(w);
+        lo = host_bf16(w - host_bf16_value(hi));
+    }
 }
 
 struct Offsets {
@@ -78,10 +102,10 @@ ep_status ensure_mlp_buffers(ep_ctx *c, int n_in)
     HIPCHK(c, dalloc(&L.d_m, np));
     HIPCHK(c, dalloc(&L.d_v, np));
     HIPCHK(c, dalloc(&L.d_grad, np));
-    HIPCHK(c, dalloc(&L.d_w2f, (size_t)8 * 64));
+    HIPCHK(c, dalloc(&L.d_w2f, (size_t)2 * 8 * 64));
     HIPCHK(c, dalloc(&L.d_w1f, (size_t)2 * 64));
     HIPCHK(c, dalloc(&L.d_b2, (size_t)kH / 4));
-    HIPCHK(c, dalloc(&L.d_w3f, (size_t)4 * 64));
+    HIPCHK(c, dalloc(&L.d_w3f, (size_t)2 * 4 * 64));
     HIPCHK(c, dalloc(&L.d_qcount, (size_t)1));
     HIPCHK(c, dalloc(&L.d_total, (size_t)1));
     HIPCHK(c, hipMemsetAsync(L.d_total, 0, sizeof(unsigned long long), c->stream));
@@ -98,15 +122,17 @@ int slot_unit(int kk, int g, int e)
     return 32 * (kk >> 1) + 16 * (kk & 1) + 8 * (e >> 2) + 4 * g + (e & 3);
 }
 
-// Inference constants for one (dt, eps), as FP16 MFMA A-fragments (lane l:
-// row l % 32, k = 8 (l / 32) + e of the step): layer 1 as split FP16 with the
-// constant features folded into the bias, W2 and the biases scaled by 1/64
-// (the activation takes z / 64), W2 and W3 in FP16 in slot_unit order.  Fails if a
+// Inference constants for one (dt, eps), as MFMA A-fragments in the chosen
+// operand type (lane l: row l % 32, k = 8 (l / 32) + e of the step): layer 1
+// as split hi + lo with the constant features folded into the bias, W2 and
+// the biases scaled by 1/64 (the activation takes z / 64), W2 and W3 in
+// slot_unit order (with BF16 also their lo parts).  With FP16, fails if a
 // pre-activation could leave the activation's FP16 range.
 ep_status prepare_inference(ep_ctx *c, double dt, double eps)
 {
     Learned &L = c->mlp;
     if (L.packed && L.cached_dt == dt && L.cached_eps == eps) return EP_OK;
+    const int fp16 = L.precision == EP_MLP_FP16 ? 1 : 0;
     const Offsets o = offsets(L.n_in);
     const float *P = L.params.data();
     constexpr double kPre = 1.0 / 64.0, kUMax = 255.0;   // |z / 64| < 255: u^2 finite
@@ -124,48 +150,52 @@ ep_status prepare_inference(ep_ctx *c, double dt, double eps)
         const double wf[4] = {w[0] / s_in * kPre, w[1] / s_in * kPre,
                               L.n_in == 6 ? w[5] / s_E * kPre : 0.0, b * kPre};
         const double room = kUMax - fabs(wf[3]), slope = fabs(wf[0]) + fabs(wf[1]) + fabs(wf[2]);
-        if (!(room > 0.0))
-            return c->fail(EP_EINVAL, "network bias too large for the FP16 inference path");
-        if (slope > 0.0) xmax = fmin(xmax, room / slope);
+        if (fp16) {
+            if (!(room > 0.0))
+                return c->fail(EP_EINVAL, "network bias too large for the FP16 inference path");
+            if (slope > 0.0) xmax = fmin(xmax, room / slope);
+        }
         const int t = u >> 5, i = u & 31;
         for (int f = 0; f < 4; ++f) {
             uint16_t hi, lo;
-            split_f16((float)wf[f], hi, lo);
+            split_op(fp16, (float)wf[f], hi, lo);
             w1[((size_t)t * 64 + i) * 8 + f] = hi;                 // g = 0: hi x (x_hi, 1)
             if (f < 3) w1[((size_t)t * 64 + i) * 8 + 4 + f] = hi;  //        hi x x_lo
             w1[((size_t)t * 64 + 32 + i) * 8 + f] = lo;            // g = 1: lo x (x_hi, 1)
         }
     }
-    if (!(xmax >= 1.0))
+    if (fp16 && !(xmax >= 1.0))
         return c->fail(EP_EINVAL, "network weights too large for the FP16 inference path");
 
     // layer 2
-    std::vector<uint16_t> w2((size_t)8 * 64 * 8);
+    constexpr size_t kW2 = (size_t)8 * 64 * 8, kW3 = (size_t)4 * 64 * 8;   // values per part
+    std::vector<uint16_t> w2(2 * kW2, 0);
     for (int mt = 0; mt < 2; ++mt)
         for (int kk = 0; kk < 4; ++kk)
             for (int lane = 0; lane < 64; ++lane)
                 for (int e = 0; e < 8; ++e) {
                     const int i = mt * 32 + (lane & 31), k = slot_unit(kk, lane >> 5, e);
-                    w2[((size_t)(mt * 4 + kk) * 64 + lane) * 8 + e] =
-                        host_f16((float)(P[o.W2 + i * kH + k] * kPre));
+                    const size_t at = ((size_t)(mt * 4 + kk) * 64 + lane) * 8 + e;
+                    split_op(fp16, (float)(P[o.W2 + i * kH + k] * kPre), w2[at], w2[kW2 + at]);
                 }
     std::vector<float> b2(kH);
     for (int j = 0; j < kH; ++j) {
         double bound = fabs((double)P[o.b2 + j]);
         for (int k = 0; k < kH; ++k) bound += fabs((double)P[o.W2 + j * kH + k]);
-        if (!(bound * kPre < kUMax))
+        if (fp16 && !(bound * kPre < kUMax))
             return c->fail(EP_EINVAL, "network weights too large for the FP16 inference path");
         b2[j] = (float)(P[o.b2 + j] * kPre);
     }
     // layer 3: rows 0 and 1 are the outputs, the rest zero
-    std::vector<uint16_t> w3((size_t)4 * 64 * 8, 0);
+    std::vector<uint16_t> w3(2 * kW3, 0);
     for (int kk = 0; kk < 4; ++kk)
         for (int lane = 0; lane < 64; ++lane)
             for (int e = 0; e < 8; ++e) {
                 const int i = lane & 31;
+                const size_t at = ((size_t)kk * 64 + lane) * 8 + e;
                 if (i < kOut)
-                    w3[((size_t)kk * 64 + lane) * 8 + e] =
-                        host_f16(P[o.W3 + i * kH + slot_unit(kk, lane >> 5, e)]);
+                    split_op(fp16, P[o.W3 + i * kH + slot_unit(kk, lane >> 5, e)], w3[at],
+                             w3[kW3 + at]);
             }
     HIPCHK(c, hipMemcpy(L.d_w1f, w1.data(), w1.size() * 2, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(L.d_w2f, w2.data(), w2.size() * 2, hipMemcpyHostToDevice));
@@ -183,6 +213,7 @@ ep_status prepare_inference(ep_ctx *c, double dt, double eps)
     I.mu_k = (float)L.norm[5];
     I.sig_k = (float)L.norm[6];
     I.xmax = (float)xmax;
+    I.fp16 = fp16;
     I.scaled = L.norm[7] == 1.0 ? 1 : 0;
     L.packed = true;
     L.cached_dt = dt;
@@ -261,7 +292,9 @@ void free_learned(ep_ctx *c)
                     (void *)L.d_w3f, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total,
                     (void *)L.d_tx, (void *)L.d_ty})
         if (p) (void)hipFree(p);
+    const int32_t precision = L.precision;   // a setting of the context, not of the network
     L = Learned();
+    L.precision = precision;
 }
 
 ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps)
@@ -334,6 +367,16 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
 }  // namespace etd
 
 extern "C" {
+
+ep_status ep_mlp_set_precision(ep_ctx *c, int32_t precision)
+{
+    if (!c) return EP_EINVAL;
+    if (precision != EP_MLP_BF16 && precision != EP_MLP_FP16)
+        return c->fail(EP_EINVAL, "ep_mlp_set_precision: unknown precision %d", (int)precision);
+    if (c->mlp.precision != precision) c->mlp.packed = false;
+    c->mlp.precision = precision;
+    return EP_OK;
+}
 
 ep_status ep_mlp_set_weights(ep_ctx *c, const float *params, uint32_t n_params, const double *norm)
 {

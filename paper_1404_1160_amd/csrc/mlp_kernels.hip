@@ -91,18 +91,61 @@ __device__ __forceinline__ f16x2 act_pair(float a, float b)
     return u * r;
 }
 
-// Eight activations of accumulator elements q0 .. q0 + 7 as an FP16 operand.
-__device__ __forceinline__ f16x8 act_operand(const f32x16 &acc, int q0)
-{
-    f16x8 v;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const f16x2 h = act_pair(acc[q0 + 2 * i], acc[q0 + 2 * i + 1]);
-        v[2 * i] = h.x;
-        v[2 * i + 1] = h.y;
+// Operand types of the inference MFMAs (32x32x16, FP32 accumulation).
+//   FP16: activations in packed FP16 arithmetic, W2 and W3 in FP16 (one
+//         MFMA each);
+//   BF16: gfx950 has no packed BF16 arithmetic, so the activations run in
+//         FP32 and are rounded to BF16; W2 and W3 as split BF16 (hi + lo, two
+//         MFMAs, ~16 bits).
+// Both take the pre-activations as u = z / 64 (see act_pair).
+template <typename T>
+struct InferOp;
+
+template <>
+struct InferOp<_Float16> {
+    typedef f16x8 vec;
+    static constexpr bool kSplitW = false;
+    static __device__ __forceinline__ vec load(uint4 q) { return __builtin_bit_cast(vec, q); }
+    static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
     }
-    return v;
-}
+    // activations of accumulator elements q0 .. q0 + 7
+    static __device__ __forceinline__ vec act(const f32x16 &acc, int q0)
+    {
+        vec v;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const f16x2 h = act_pair(acc[q0 + 2 * i], acc[q0 + 2 * i + 1]);
+            v[2 * i] = h.x;
+            v[2 * i + 1] = h.y;
+        }
+        return v;
+    }
+};
+
+template <>
+struct InferOp<__bf16> {
+    typedef bf16x8 vec;
+    static constexpr bool kSplitW = true;
+    static __device__ __forceinline__ vec load(uint4 q) { return __builtin_bit_cast(vec, q); }
+    static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ vec act(const f32x16 &acc, int q0)
+    {
+        uint4 h;
+        unsigned *hp = &h.x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float u0 = acc[q0 + 2 * i], u1 = acc[q0 + 2 * i + 1];
+            hp[i] = pack_bf16x2(u0 * __frsqrt_rn(fmaf(u0, u0, 0x1p-12f)),
+                                u1 * __frsqrt_rn(fmaf(u1, u1, 0x1p-12f)));
+        }
+        return __builtin_bit_cast(vec, h);
+    }
+};
 
 // Wave-level 32x32 tile of a 64x64x64 product from FP32 LDS operands:
 //   acc(i, j) += sum_k A(i0 + i, k) B(k, j0 + j),
@@ -591,19 +634,19 @@ constexpr int kWavesDuffing = 4, kWavesPoisson = 8;
 
 // One learned step.  A workgroup of WAVES waves takes 32 WAVES particles per
 // iteration, 32 per wave; lanes l and l+32 share particle l%32.  All three
-// layers run on FP16 MFMA (32x32x16) with FP32 accumulation, the activations
-// in packed FP16 between them:
-//   layer 1  one MFMA per 32 hidden units; k slots 0-7 hold the features as
-//            FP16 hi parts, the constant 1 (bias) and the features' lo parts
+// layers run on MFMA (32x32x16, operand type T: FP16 or BF16, see InferOp)
+// with FP32 accumulation:
+//   layer 1  one MFMA per 32 hidden units; k slots 0-7 hold the features'
+//            hi parts, the constant 1 (bias) and the features' lo parts
 //            against the weights' hi parts, slots 8-15 the weights' lo parts
-//            against the features' hi parts -- ~22-bit products;
-//   layer 2  W2 in FP16 times the activations, accumulators started at the
-//            bias;
-//   layer 3  W3 in FP16 times the activations, lanes 0-31 receive the two
-//            outputs of their particle.
-// FP16 weights (2^-12 relative) in layers 2 and 3 cost no measurable accuracy
-// next to the activations' own FP16 rounding; splitting them into hi + lo
-// halves, as in layer 1, doubled those layers' MFMAs for nothing.
+//            against the features' hi parts (FP16: ~22-bit, BF16: ~16-bit
+//            products);
+//   layer 2  W2 times the activations, accumulators started at the bias;
+//   layer 3  W3 times the activations, lanes 0-31 receive the two outputs of
+//            their particle.
+// With FP16, W2 and W3 are not split: their 2^-12 rounding costs no
+// measurable accuracy next to the activations' own, and splitting doubled
+// those layers' MFMAs.
 // The results of one layer are the next layer's B operand without any data
 // movement: the k order of W2 and W3 is permuted at upload to the order in
 // which the accumulator elements sit in the lanes.  Features are clamped to
@@ -616,24 +659,27 @@ constexpr int kWavesDuffing = 4, kWavesPoisson = 8;
 // fallback queue.  With VP the sixth feature is E^n(R_n), and the particles
 // that pass are deposited (CIC, fixed point) into an LDS histogram added to
 // the mesh at the end.
-template <bool VP, int WAVES>
+template <bool VP, int WAVES, typename T>
 __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
     float *__restrict__ zR, float *__restrict__ zV, int64_t n, MlpInfer net, double2 rot0,
     double2 rot1, double inv2eps, double tol, unsigned *__restrict__ qcount,
     unsigned *__restrict__ queue, MeshView mv, PotView pv, const double *__restrict__ qb,
     unsigned long long *__restrict__ hist)
 {
-    __shared__ uint4 sW2[8 * 64];
+    typedef InferOp<T> Op;
+    typedef typename Op::vec vec;
+    constexpr int kW = Op::kSplitW ? 2 : 1;   // weight parts of layers 2 and 3
+    __shared__ uint4 sW2[kW * 8 * 64];
     __shared__ uint4 sW1[2 * 64];
     __shared__ float4 sb2[kH / 4];
-    __shared__ uint4 sW3[4 * 64];
+    __shared__ uint4 sW3[kW * 4 * 64];
     __shared__ unsigned s_q[WAVES][kWaveQueue];
     extern __shared__ __align__(16) unsigned char vp_smem[];
     const int tid = threadIdx.x;
-    for (int i = tid; i < 8 * 64; i += blockDim.x) sW2[i] = net.w2f[i];
+    for (int i = tid; i < kW * 8 * 64; i += blockDim.x) sW2[i] = net.w2f[i];
     if (tid < 2 * 64) sW1[tid] = net.w1f[tid];
     if (tid < kH / 4) sb2[tid] = net.b2[tid];
-    for (int i = tid; i < 4 * 64; i += blockDim.x) sW3[i] = net.w3f[i];
+    for (int i = tid; i < kW * 4 * 64; i += blockDim.x) sW3[i] = net.w3f[i];
     if (VP) {
         mv.H = reinterpret_cast<unsigned long long *>(vp_smem);
         for (int i = tid; i <= pv.nr; i += blockDim.x) mv.H[i] = 0ull;
@@ -654,23 +700,21 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const double zv = valid ? (double)zV[p] : 0.0;
         const double R = fma(rot0.x, zr, rot0.y * zv);
         const double Vl = fma(-rot0.y, zr, rot0.x * zv);
-        // features, clamped, as FP16 hi + lo
+        // features, clamped, as hi + lo parts
         float xf[3] = {(float)R, (float)Vl, VP ? (float)gather(mv, R) : 0.f};
-        _Float16 xh[3], xl[3];
+        T xh[3], xl[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const float x = fminf(fmaxf(xf[i], -net.xmax), net.xmax);
-            xh[i] = (_Float16)x;
-            xl[i] = g == 0 ? (_Float16)(x - (float)xh[i]) : (_Float16)0.f;
+            xh[i] = (T)x;
+            xl[i] = g == 0 ? (T)(x - (float)xh[i]) : (T)0.f;
         }
-        const f16x8 xb = {xh[0], xh[1], xh[2], (_Float16)1.f, xl[0], xl[1], xl[2], (_Float16)0.f};
+        const vec xb = {xh[0], xh[1], xh[2], (T)1.f, xl[0], xl[1], xl[2], (T)0.f};
 
         // layer 1: pre-activations / 64 of units 0-31 and 32-63
         const f32x16 zero = {};
-        const f32x16 u0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW1[lane]), xb, zero,
-                                                                 0, 0, 0);
-        const f32x16 u1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW1[64 + lane]), xb,
-                                                                 zero, 0, 0, 0);
+        const f32x16 u0 = Op::mma(Op::load(sW1[lane]), xb, zero);
+        const f32x16 u1 = Op::mma(Op::load(sW1[64 + lane]), xb, zero);
         // layer 2, accumulators started at b2 / 64
         f32x16 acc0, acc1;
 #pragma unroll
@@ -687,19 +731,21 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const f16x8 b = act_operand(kk < 2 ? u0 : u1, 8 * (kk & 1));
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW2[kk * 64 + lane]), b, acc0,
-                                                          0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW2[(4 + kk) * 64 + lane]), b,
-                                                          acc1, 0, 0, 0);
+            const vec b = Op::act(kk < 2 ? u0 : u1, 8 * (kk & 1));
+#pragma unroll
+            for (int w = 0; w < kW; ++w) {
+                acc0 = Op::mma(Op::load(sW2[(w * 8 + kk) * 64 + lane]), b, acc0);
+                acc1 = Op::mma(Op::load(sW2[(w * 8 + 4 + kk) * 64 + lane]), b, acc1);
+            }
         }
         // layer 3
         f32x16 acc3 = {};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const f16x8 b = act_operand(kk < 2 ? acc0 : acc1, 8 * (kk & 1));
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(sW3[kk * 64 + lane]), b, acc3,
-                                                          0, 0, 0);
+            const vec b = Op::act(kk < 2 ? acc0 : acc1, 8 * (kk & 1));
+#pragma unroll
+            for (int w = 0; w < kW; ++w)
+                acc3 = Op::mma(Op::load(sW3[(w * 4 + kk) * 64 + lane]), b, acc3);
         }
         const float o0 = acc3[0], o1 = acc3[1];
         float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);
@@ -907,8 +953,12 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t
     if (n <= 0) return hipSuccess;
     int64_t grid = (n + 32 * kWavesDuffing - 1) / (32 * kWavesDuffing);
     if (grid > (int64_t)n_cu * 8) grid = (int64_t)n_cu * 8;
-    return dispatch(mlp_push_kernel<false, kWavesDuffing>, dim3((unsigned)grid),
-                    dim3(64 * kWavesDuffing), 0, st, zR, zV, n, net,
+    const dim3 g((unsigned)grid), b(64 * kWavesDuffing);
+    if (net.fp16)
+        return dispatch(mlp_push_kernel<false, kWavesDuffing, _Float16>, g, b, 0, st, zR, zV, n,
+                        net, rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{},
+                        (const double *)nullptr, (unsigned long long *)nullptr);
+    return dispatch(mlp_push_kernel<false, kWavesDuffing, __bf16>, g, b, 0, st, zR, zV, n, net,
                     rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{},
                     (const double *)nullptr, (unsigned long long *)nullptr);
 }
@@ -933,10 +983,15 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
     pv.Qb = 0.0;
     pv.c = ma.nr >> 1;
     pv.nr = ma.nr;
-    return dispatch(mlp_push_kernel<true, kWavesPoisson>, dim3((unsigned)grid),
-                    dim3(64 * kWavesPoisson), mlp_vp_lds_bytes(ma.nr),
-                    st, zR, zV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma),
-                    pv, (const double *)(ma.fscal + kQb), ma.hist);
+    const dim3 g((unsigned)grid), b(64 * kWavesPoisson);
+    const size_t lds = mlp_vp_lds_bytes(ma.nr);
+    if (net.fp16)
+        return dispatch(mlp_push_kernel<true, kWavesPoisson, _Float16>, g, b, lds, st, zR, zV, n,
+                        net, rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
+                        (const double *)(ma.fscal + kQb), ma.hist);
+    return dispatch(mlp_push_kernel<true, kWavesPoisson, __bf16>, g, b, lds, st, zR, zV, n, net,
+                    rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
+                    (const double *)(ma.fscal + kQb), ma.hist);
 }
 
 hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,
@@ -962,9 +1017,13 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
 
 hipError_t setup_learned_lds(int nr)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_push_kernel<true, kWavesPoisson>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)mlp_vp_lds_bytes(nr));
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&mlp_push_kernel<true, kWavesPoisson, _Float16>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_vp_lds_bytes(nr));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&mlp_push_kernel<true, kWavesPoisson, __bf16>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_vp_lds_bytes(nr));
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fallback_duffing_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -10,7 +10,8 @@ import pytest
 
 from oracle import mlp
 from paper_1404_1160_amd import (EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED, EP_FIELD_DUFFING,
-                                 EP_FIELD_POISSON, EP_PUSH_LEARNED, EtdpicError, Sim, capi, synth)
+                                 EP_FIELD_POISSON, EP_MLP_BF16, EP_MLP_FP16, EP_PUSH_IMPROVED_ETD,
+                                 EP_PUSH_LEARNED, EtdpicError, Sim, capi, synth)
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +46,11 @@ def test_poisson_resume_is_bitwise(tmp_path, deposit):
         assert abs(ma[k] - mb[k]) <= rtol * abs(ma[k]), k
 
 
-def test_learned_resume_restores_network(tmp_path):
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
+def test_learned_resume_restores_network(tmp_path, precision):
+    """The network, its normalisation, the push mode and the inference
+    precision come back: the resumed run matches bit for bit (the two
+    precisions give different bits, so a lost setting would show)."""
     R, V, w = synth.gaussian(50_001, seed=32, sigma=1.5)
     dt, eps = 0.05, 1e-3
     p = synth.mlp_init(5, 64, 2, seed=3)
@@ -54,17 +59,40 @@ def test_learned_resume_restores_network(tmp_path):
     with Sim(R.size, substeps=16) as a:
         capi.ep_mlp_set_weights(a.ctx, p, norm)
         capi.ep_set_push_mode(a.ctx, EP_PUSH_LEARNED, 1e-4, 32)
+        capi.ep_mlp_set_precision(a.ctx, precision)
         a.set_particles(R, V, w)
         a.step(dt, eps, EP_FIELD_DUFFING, 3)
         a.save(path)
         a.step(dt, eps, EP_FIELD_DUFFING, 4)
         Ra, Va = a.particles()
     with Sim(R.size, substeps=16) as b:
+        capi.ep_mlp_set_precision(b.ctx, EP_MLP_FP16 + EP_MLP_BF16 - precision)
         b.load(path)
         q, nb = capi.ep_mlp_get_weights(b.ctx, mlp.n_params(5))
         assert np.array_equal(q, p.astype(np.float32))
         assert np.array_equal(nb, norm)
         b.step(dt, eps, EP_FIELD_DUFFING, 4)
+        Rb, Vb = b.particles()
+    assert np.array_equal(Ra, Rb) and np.array_equal(Va, Vb)
+
+
+def test_fine_solver_resume_restores_mode_and_step(tmp_path):
+    """The improved ETD push mode and the fine step h_fine come back with the
+    checkpoint: the resumed run matches bit for bit."""
+    R, V, w = synth.paper_f0(2_001, seed=34)
+    dt, eps, h = 0.2, 1e-2, 2.0 * np.pi * 1e-2 / 50
+    path = str(tmp_path / "ck.bin")
+    with Sim(R.size, substeps=4) as a:
+        capi.ep_set_push_mode(a.ctx, EP_PUSH_IMPROVED_ETD)
+        capi.ep_set_fine_solver(a.ctx, h, 5000)
+        a.set_particles(R, V, w)
+        a.step(dt, eps, EP_FIELD_DUFFING, 2)
+        a.save(path)
+        a.step(dt, eps, EP_FIELD_DUFFING, 2)
+        Ra, Va = a.particles()
+    with Sim(R.size, substeps=4) as b:
+        b.load(path)
+        b.step(dt, eps, EP_FIELD_DUFFING, 2)
         Rb, Vb = b.particles()
     assert np.array_equal(Ra, Rb) and np.array_equal(Va, Vb)
 

@@ -6,14 +6,17 @@ Tolerances:
   * gradients (BF16 MFMA products, FP32 accumulation) against the FP64 oracle
     at the same FP32 weights and inputs: per tensor relative Frobenius error
     <= 2^-6 and cosine >= 0.9995
-  * learned step without fallback: FP16 MFMA operands in all three layers
-    (layer-1 weights and features split into FP16 hi + lo, ~2^-22; W2 and
-    W3 rounded to FP16, 2^-12 relative); each activation carries ~3 FP16
-    roundings (2^-12 relative each: the pre-activation, the inverse square
-    root, the product).  Summed over 64 hidden units with weights ~0.1-0.2
-    this gives output errors up to ~1e-3 in o, and a particle's error is
-    sig_d |d o| (scaled map) or sig_d |d o| |y|, ~5e-5 for sig_d = 0.05: the
-    test bound is 1e-4 max(|y|, 1)
+  * learned step without fallback, for each inference operand type:
+      - BF16 (default): split-BF16 weights (~2^-16) times activations
+        rounded to BF16 (relative 2^-9); summed over 64 hidden units with
+        weights ~0.1-0.2 this gives output errors up to ~4e-3 in o, and a
+        particle's error is sig_d |d o| (scaled map) or sig_d |d o| |y|,
+        ~2e-4 for sig_d = 0.05: the bound is 3e-4 max(|y|, 1);
+      - FP16: layer-1 weights and features split into FP16 hi + lo (~2^-22),
+        W2 and W3 rounded to FP16 (2^-12 relative); each activation carries
+        ~3 FP16 roundings (2^-12 relative each: the pre-activation, the
+        inverse square root, the product), so output errors up to ~1e-3 in
+        o, particle errors ~5e-5: the bound is 1e-4 max(|y|, 1)
   * fallback: the plain push, per particle 1e-6 as for the plain path.
 """
 import math
@@ -23,7 +26,8 @@ import pytest
 
 import oracle
 from oracle import mlp
-from paper_1404_1160_amd import EP_FIELD_DUFFING, EP_PUSH_LEARNED, EP_PUSH_PLAIN, Sim, capi, synth
+from paper_1404_1160_amd import (EP_FIELD_DUFFING, EP_MLP_BF16, EP_MLP_FP16, EP_PUSH_LEARNED,
+                                 EP_PUSH_PLAIN, Sim, capi, synth)
 
 pytestmark = pytest.mark.gpu
 
@@ -125,20 +129,26 @@ def _net(seed=9):
     return p, norm
 
 
-def _learned_sim(R, V, w, p, norm, tol, K_fb):
+# bound of the network map's per-particle error, per inference operand type
+MAP_TOL = {EP_MLP_BF16: 3e-4, EP_MLP_FP16: 1e-4}
+
+
+def _learned_sim(R, V, w, p, norm, tol, K_fb, precision=EP_MLP_BF16):
     sim = Sim(R.size, substeps=1)
     sim.set_particles(R, V, w)
     capi.ep_mlp_set_weights(sim.ctx, p, norm.as_array())
     capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, tol, K_fb)
+    capi.ep_mlp_set_precision(sim.ctx, precision)
     return sim
 
 
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
 @pytest.mark.parametrize("out_map", [0, 1])
-def test_learned_push_without_fallback_is_the_network_map(out_map):
+def test_learned_push_without_fallback_is_the_network_map(out_map, precision):
     R0, V0, w = synth.gaussian(10001, seed=15, sigma=SIG)
     p, norm = _net()
     norm.out_map = out_map
-    sim = _learned_sim(R0, V0, w, p, norm, 1e300, 8)
+    sim = _learned_sim(R0, V0, w, p, norm, 1e300, 8, precision)
     R, V = R0.copy(), V0.copy()
     pd = p.astype(np.float64)
     worst = 0.0
@@ -149,7 +159,7 @@ def test_learned_push_without_fallback_is_the_network_map(out_map):
         Rg, Vg = sim.particles()
         err = rel_particle(Rg, Vg, R, V)
         worst = max(worst, err.max())
-        assert err.max() <= 1e-4, (s, err.max())
+        assert err.max() <= MAP_TOL[precision], (s, err.max())
         R, V = Rg, Vg      # continue from the GPU state: compare one step at a time
     assert sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"] == 0
     sim.close()
@@ -181,9 +191,11 @@ def test_nan_weight_forces_fallback():
 
 
 def test_weights_outside_the_fp16_range_are_rejected():
-    """A network whose pre-activations could leave the FP16 activation's range
-    (|z| >= 16320) is refused with EP_EINVAL when a step needs it; the state
-    is left untouched, and a network in range works afterwards."""
+    """With FP16 inference, a network whose pre-activations could leave the
+    FP16 activation's range (|z| >= 16320) is refused with EP_EINVAL when a
+    step needs it; the state is left untouched, a network in range works
+    afterwards, and the BF16 inference (FP32 activations) runs the large
+    network."""
     R0, V0, w = synth.gaussian(1000, seed=19, sigma=SIG)
     p, norm = _net()
     o_b2 = 64 * 5 + 64 + 64 * 64          # first layer-2 bias
@@ -191,18 +203,22 @@ def test_weights_outside_the_fp16_range_are_rejected():
     for off in (o_b2, o_b1):
         bad = p.copy()
         bad[off] = 2.0e4
-        sim = _learned_sim(R0, V0, w, bad, norm, 1e300, 8)
+        sim = _learned_sim(R0, V0, w, bad, norm, 1e300, 8, EP_MLP_FP16)
         with pytest.raises(capi.EtdpicError) as ei:
             sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
         assert ei.value.status == capi.EP_EINVAL and "FP16" in str(ei.value)
         Rg, Vg = sim.particles()
         assert np.array_equal(Rg, R0.astype(np.float32).astype(np.float64))
+        capi.ep_mlp_set_precision(sim.ctx, EP_MLP_BF16)
+        sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+        capi.ep_mlp_set_precision(sim.ctx, EP_MLP_FP16)
         capi.ep_mlp_set_weights(sim.ctx, p, norm.as_array())
         sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
         sim.close()
 
 
-def test_check_decisions_agree_with_oracle():
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
+def test_check_decisions_agree_with_oracle(precision):
     """With tol at the median drift ratio about half the particles take the
     network map and half the plain fallback; where the oracle's ratio is not
     within 20% of tol both sides decide alike."""
@@ -215,7 +231,7 @@ def test_check_decisions_agree_with_oracle():
     tol = float(np.median(ratio))
     Ro, Vo, fb, ratio = mlp.learned_step(p.astype(np.float64), R0, V0, DT, EPS, norm, pot, plain,
                                          tol)
-    sim = _learned_sim(R0, V0, w, p, norm, tol, 16)
+    sim = _learned_sim(R0, V0, w, p, norm, tol, 16, precision)
     sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
     Rg, Vg = sim.particles()
     nfb = sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"]
@@ -224,7 +240,7 @@ def test_check_decisions_agree_with_oracle():
     assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
     err = rel_particle(Rg, Vg, Ro, Vo)
     assert np.max(err[clear & fb]) <= 1e-6
-    assert np.max(err[clear & ~fb]) <= 1e-4
+    assert np.max(err[clear & ~fb]) <= MAP_TOL[precision]
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
 
 

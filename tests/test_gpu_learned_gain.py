@@ -66,12 +66,18 @@ def test_learned_beats_plain_at_equal_error():
     """At the at-scale Duffing workload (eps = 1e-3, dt = 0.05, R, V ~ N(0, 1.5),
     200 steps, network trained on 1e7 fine-push labels; 2e6 evaluation
     particles here) the learned push is faster than the cheapest plain push
-    whose rms-radius error is as small, with the 1e-5 energy check and
-    without it."""
+    whose rms-radius error is as small: with FP16 inference with the 1e-5
+    energy check and without it, with BF16 inference without the check."""
     res = compare.equal_error(n_train=10_000_000, n_eval=2_000_000, log=print)
-    print(json.dumps({k: res[k] for k in ("equal_error", "equal_error_no_check")}, indent=1))
-    for key in ("equal_error", "equal_error_no_check"):
+    keys = [k for k in res if k.startswith("equal_error")]
+    print(json.dumps({k: res[k] for k in keys}, indent=1))
+    # FP16 inference, the closer of the two operand types to the FP64 network
+    for key in ("equal_error_fp16", "equal_error_no_check_fp16"):
         assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
+    # BF16 inference: its larger rounding makes 8 % of the predictions fail
+    # the 1e-5 check; without the check it beats the plain push as well
+    key = "equal_error_no_check_bf16"
+    assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
 
 
 def test_equal_error_comparison_vp():
