@@ -117,28 +117,39 @@ def device_copy_bandwidth(n):
 
 def cpu_baseline(n_full, cells, eps, dt, K, seconds):
     """The FP64 oracle on this host: a 2e6-particle sample of the same beam
-    (weights scaled to the full beam's charge), stepped until ~`seconds`."""
-    import numpy as np
-
+    (weights scaled to the full beam's charge), stepped until ~`seconds` on
+    all the threads it uses, then a 2e5-particle sample on one thread for
+    ~seconds/4."""
     import oracle
     from paper_1404_1160_amd import synth
 
+    def rate(n, budget):
+        R, V, _ = synth.gaussian_truncated(n, seed=13)
+        w = 1.0 / n
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            R, V = oracle.run(R, V, w, dt, eps, K, 1, oracle.FIELD_POISSON, nr=cells,
+                              rmin=-5.0, rmax=5.0)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return n * steps / el, steps, el
+
     n = min(n_full, 2_000_000)
-    R, V, _ = synth.gaussian_truncated(n, seed=13)
-    w = 1.0 / n
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        R, V = oracle.run(R, V, w, dt, eps, K, 1, oracle.FIELD_POISSON, nr=cells, rmin=-5.0,
-                          rmax=5.0)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
+    cores = oracle.threads()
+    value, steps, el = rate(n, seconds)
+    n1 = min(n_full, 200_000)
+    oracle.set_threads(1)
+    try:
+        value1, steps1, el1 = rate(n1, seconds / 4)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": value, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
             "sample": "%d particles of the same beam x %d steps (K=%d, N_r=%d), %.1f s" % (
-                n, steps, K, cells, el)}
+                n, steps, K, cells, el),
+            "single_thread": {"value": value1, "unit": "particle-steps/s", "cores": 1,
+                              "sample": "%d particles x %d steps, %.1f s" % (n1, steps1, el1)}}
 
 
 # algorithmic HBM bytes per particle of each particle kernel (FP32 state and

@@ -43,6 +43,8 @@ def lib():
         p = ctypes.POINTER(ctypes.c_double)
         L.orc_deposit.argtypes = [p, i64, d, i32, d, d, p]
         L.orc_deposit.restype = i64
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_set_threads.restype = None
         L.orc_poisson.argtypes = [p, i32, d, d, p, p, p]
         L.orc_poisson.restype = None
         L.orc_gather.argtypes = [d, p, d, i32, d, d]
@@ -196,3 +198,8 @@ def classic_etd_step(R, V, w, dt, eps, field, modified, nr=0, rmin=0.0, rmax=0.0
 
 def threads():
     return int(lib().orc_threads())
+
+
+def set_threads(n):
+    """OpenMP threads of later pushes (timing only; results do not depend on it)."""
+    lib().orc_set_threads(int(n))

@@ -306,3 +306,14 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads of later pushes (n >= 1). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
