@@ -155,7 +155,7 @@ def cpu_baseline(n_full, cells, eps, dt, K, seconds):
 # algorithmic HBM bytes per particle of each particle kernel (FP32 state and
 # u32 ids; the mesh is LDS/L2 resident)
 KERNEL_BYTES = {"push_poisson": 16, "sort_count": 8, "sort_scatter": 24, "sort_reduce": 8}
-STEP_KERNELS = ("push_poisson", "mesh_solve", "sort_count", "sort_offsets", "sort_scatter",
+STEP_KERNELS = ("push_poisson", "mesh_solve", "potential", "sort_count", "sort_offsets", "sort_scatter",
                 "sort_reduce")
 
 

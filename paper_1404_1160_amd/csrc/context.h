@@ -96,6 +96,7 @@ struct ep_ctx {
     float2 *etab = nullptr;
     double *rho64 = nullptr, *E64 = nullptr, *Psi64 = nullptr, *fscal = nullptr;
     bool field_valid = false;
+    bool potential_valid = false;   // Psi64 and the field energy belong to the field
 
     MeshArgs mesh() const
     {
@@ -209,6 +210,12 @@ inline hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
 hipError_t collect_timing(ep_ctx *c);
 ep_status ensure_tables(ep_ctx *c, size_t entries, size_t steps);
 ep_status refresh_field(ep_ctx *c);
+// Field of the accumulated charge; with potential also Psi and the field
+// energy, which only the learned Poisson push, the moments and ep_get_field
+// read.
+ep_status solve_mesh(ep_ctx *c, const MeshArgs &ma, bool potential);
+// Psi and the field energy of the current field, if a solve left them out.
+ep_status ensure_potential(ep_ctx *c);
 ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K);
 void free_learned(ep_ctx *c);
 // Learned push of n_steps steps (Duffing field); defined with the learned API.

@@ -49,8 +49,7 @@ ep_status start_field(ep_ctx *c, const MeshArgs &ma)
                return launch_fine_deposit(c->stream, c->fine.yR, (int64_t)c->n, ma,
                                           c->push_grid_cap);
            }));
-    HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, ma); }));
-    return EP_OK;
+    return solve_mesh(c, ma, false);
 }
 
 // One coupled RK4 step to level L: four stages, each followed by a solve.
@@ -61,7 +60,7 @@ ep_status coupled_step(ep_ctx *c, int mode, double h, double eps, long long L, c
                    return launch_rk4_stage(c->stream, stage, mode, c->fine, (int64_t)c->n, h, eps,
                                            L, ma, c->push_grid_cap);
                }));
-        HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, ma); }));
+        if (ep_status s = solve_mesh(c, ma, false); s != EP_OK) return s;
     }
     return EP_OK;
 }

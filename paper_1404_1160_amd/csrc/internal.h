@@ -94,7 +94,12 @@ hipError_t launch_push_poisson(hipStream_t st, bool push, float *zR, float *zV, 
 hipError_t setup_mesh_lds(int nr);
 size_t push_lds_bytes_for(int nr);
 
-hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &ma);
+// Field of the accumulated charge; with potential also Psi and the field
+// energy (else they are left as they were).
+hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &ma, bool potential);
+// Psi and the field energy of the field in E64 (the same bits as a solve
+// with potential).
+hipError_t launch_potential(hipStream_t st, const MeshArgs &ma);
 
 // ------------------------------------------------------------ sorted deposit
 

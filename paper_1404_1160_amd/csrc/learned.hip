@@ -309,7 +309,7 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
     ep_status s = prepare_inference(c, dt, eps);
     if (s != EP_OK) return s;
     if ((s = ensure_queue(c)) != EP_OK) return s;
-    if (vp && !c->field_valid && (s = refresh_field(c)) != EP_OK) return s;
+    if (vp && (s = c->field_valid ? ensure_potential(c) : refresh_field(c)) != EP_OK) return s;
     const int K = (int)c->fallback_K;
     const double dphi = fmod(dt / eps, kTwoPi);
     size_t chunk = kTableEntries / (size_t)K;
@@ -341,8 +341,8 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
                                                           L.d_qcount, sub, K, rot1, ma, L.d_total,
                                                           c->n_cu);
                        }));
-                HIPCHK(c, timed_launch(c, "mesh_solve",
-                                       [&] { return launch_mesh_solve(c->stream, ma); }));
+                // the next learned step checks energies with this field's potential
+                if (ep_status s2 = solve_mesh(c, ma, true); s2 != EP_OK) return s2;
             } else {
                 HIPCHK(c, timed_launch(c, "mlp_push", [&] {
                            return launch_mlp_push_duffing(c->stream, c->zR, c->zV, (int64_t)c->n,

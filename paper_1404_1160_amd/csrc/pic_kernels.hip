@@ -171,25 +171,21 @@ hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
 //           so P_k = int_{x_0}^{x_k} rho = w 2^-33 I_k
 //   Q_j   = (P_{c+j} - P_{c-j}) / 2 = w 2^-34 (I_{c+j} - I_{c-j})
 //   E_k   = Q_{|k-c|} / x_k  (k != c),  E_c = 0,  Qb = w 2^-34 I_nr
-//   Psi_k = -int_0^{x_k} E  (trapezoid of the node values)
-//   field energy int_0^{r_max} x E^2 dx (trapezoid)
 // and the FP32 gather table (E_m, E_{m+1} - E_m).  Clears hist for the next
 // accumulation.  Node arrays live in the caller's LDS (2 (nr+1) u64): S and
-// I as u64, then E as FP64 in the storage of S and the potential's prefix in
-// the storage of I.  Elementwise passes run node-contiguous across threads;
-// the two scans run over contiguous per-thread chunks.
-__device__ void mesh_solve_block(unsigned char *smem, unsigned long long *__restrict__ hist,
-                                 int nr, double w, double hr, float2 *__restrict__ etab,
-                                 double *__restrict__ rho64, double *__restrict__ E64,
-                                 double *__restrict__ Psi64, double *__restrict__ fscal)
+// I as u64, then E as FP64 in the storage of S.  Elementwise passes run
+// node-contiguous across threads; the scan runs over contiguous per-thread
+// chunks.  Leaves E in LDS (first nr+1 doubles) for solve_potential_block.
+__device__ void solve_field_block(unsigned char *smem, unsigned long long *__restrict__ hist,
+                                  int nr, double w, double hr, float2 *__restrict__ etab,
+                                  double *__restrict__ rho64, double *__restrict__ E64,
+                                  double *__restrict__ fscal)
 {
     const int nn = nr + 1;
     unsigned long long *S = reinterpret_cast<unsigned long long *>(smem);
     double *Ed = reinterpret_cast<double *>(smem);
     unsigned long long *I = S + nn;
-    double *Fd = reinterpret_cast<double *>(I);
     __shared__ unsigned long long wu[kSolveBlock / 64];
-    __shared__ double wd[kSolveBlock / 64];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int c = nr >> 1;
     const double rho_scale = w * kFixScale / hr;
@@ -237,12 +233,36 @@ __device__ void mesh_solve_block(unsigned char *smem, unsigned long long *__rest
     }
     __syncthreads();
 
-    double fe = 0.0;
 #pragma unroll 1
     for (int k = tid; k < nr; k += nt) {
         const double e0 = Ed[k], e1 = Ed[k + 1];
         etab[k] = make_float2((float)e0, (float)(e1 - e0));
+    }
+}
+
+// From the node field E in LDS (first nr+1 doubles of smem; the next nr+1
+// are scratch), with every thread past a barrier since E was written:
+//   Psi_k = -int_0^{x_k} E  (trapezoid of the node values)
+//   field energy int_0^{r_max} x E^2 dx (trapezoid)
+// in a fixed summation order, so that the potential kernel and the full solve
+// give the same bits.
+__device__ void solve_potential_block(unsigned char *smem, int nr, double hr,
+                                      double *__restrict__ Psi64, double *__restrict__ fscal)
+{
+    const int nn = nr + 1;
+    const double *Ed = reinterpret_cast<const double *>(smem);
+    double *Fd = reinterpret_cast<double *>(smem) + nn;
+    __shared__ double wd[kSolveBlock / 64];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int c = nr >> 1;
+    const int chunk = (nn + nt - 1) / nt;
+    const int k0 = min(tid * chunk, nn), k1 = min(k0 + chunk, nn);
+
+    double fe = 0.0;
+#pragma unroll 1
+    for (int k = tid; k < nr; k += nt) {
         if (k >= c) {
+            const double e0 = Ed[k], e1 = Ed[k + 1];
             const double x0 = (double)(k - c) * hr, x1 = (double)(k + 1 - c) * hr;
             fe += hr * (x0 * e0 * e0 + x1 * e1 * e1) * 0.5;
         }
@@ -265,21 +285,46 @@ __device__ void mesh_solve_block(unsigned char *smem, unsigned long long *__rest
     if (tid == 0) fscal[kFieldEnergy] = fe;
 }
 
+// The field (and with POT its potential and energy) of the accumulated charge.
+template <bool POT>
 __global__ __launch_bounds__(kSolveBlock) void mesh_solve_kernel(
     unsigned long long *__restrict__ hist, int nr, double w, double hr, float2 *__restrict__ etab,
     double *__restrict__ rho64, double *__restrict__ E64, double *__restrict__ Psi64,
     double *__restrict__ fscal)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    mesh_solve_block(smem, hist, nr, w, hr, etab, rho64, E64, Psi64, fscal);
+    solve_field_block(smem, hist, nr, w, hr, etab, rho64, E64, fscal);
+    if (POT) solve_potential_block(smem, nr, hr, Psi64, fscal);
+}
+
+// The potential and field energy of the field in E64.
+__global__ __launch_bounds__(kSolveBlock) void potential_kernel(const double *__restrict__ E64,
+                                                                int nr, double hr,
+                                                                double *__restrict__ Psi64,
+                                                                double *__restrict__ fscal)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *Ed = reinterpret_cast<double *>(smem);
+    for (int k = threadIdx.x; k <= nr; k += blockDim.x) Ed[k] = E64[k];
+    __syncthreads();
+    solve_potential_block(smem, nr, hr, Psi64, fscal);
 }
 
 static size_t mesh_lds_bytes(int nr) { return (size_t)2 * (nr + 1) * sizeof(unsigned long long); }
 
-hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &a)
+hipError_t launch_mesh_solve(hipStream_t st, const MeshArgs &a, bool potential)
 {
-    return dispatch(mesh_solve_kernel, dim3(1), dim3(kSolveBlock), mesh_lds_bytes(a.nr), st, a.hist,
-                    a.nr, a.w, a.hr, a.etab, a.rho64, a.E64, a.Psi64, a.fscal);
+    if (potential)
+        return dispatch(mesh_solve_kernel<true>, dim3(1), dim3(kSolveBlock), mesh_lds_bytes(a.nr),
+                        st, a.hist, a.nr, a.w, a.hr, a.etab, a.rho64, a.E64, a.Psi64, a.fscal);
+    return dispatch(mesh_solve_kernel<false>, dim3(1), dim3(kSolveBlock), mesh_lds_bytes(a.nr), st,
+                    a.hist, a.nr, a.w, a.hr, a.etab, a.rho64, a.E64, a.Psi64, a.fscal);
+}
+
+hipError_t launch_potential(hipStream_t st, const MeshArgs &a)
+{
+    return dispatch(potential_kernel, dim3(1), dim3(kSolveBlock), mesh_lds_bytes(a.nr), st,
+                    (const double *)a.E64, a.nr, a.hr, a.Psi64, a.fscal);
 }
 
 // ------------------------------------------------------------ Poisson push + deposit
@@ -442,9 +487,13 @@ hipError_t setup_mesh_lds(int nr)
     if ((e = raise_lds<true, 2>(lds)) != hipSuccess) return e;
     if ((e = raise_lds<false, 1>(lds)) != hipSuccess) return e;
     if ((e = raise_lds<false, 2>(lds)) != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&mesh_solve_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)mesh_lds_bytes(nr));
+    for (const void *k : {reinterpret_cast<const void *>(&mesh_solve_kernel<true>),
+                          reinterpret_cast<const void *>(&mesh_solve_kernel<false>),
+                          reinterpret_cast<const void *>(&potential_kernel)})
+        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)mesh_lds_bytes(nr))) != hipSuccess)
+            return e;
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------ moments

@@ -82,8 +82,25 @@ ep_status refresh_field(ep_ctx *c)
                return launch_push_poisson(c->stream, false, c->zR, c->zV, (int64_t)c->n,
                                           nullptr, nullptr, er, 0, ma, c->push_grid_cap);
            }));
-    HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, ma); }));
+    ep_status s = solve_mesh(c, ma, true);
+    if (s != EP_OK) return s;
     c->field_valid = true;
+    return EP_OK;
+}
+
+ep_status solve_mesh(ep_ctx *c, const MeshArgs &ma, bool potential)
+{
+    HIPCHK(c, timed_launch(c, "mesh_solve",
+                           [&] { return launch_mesh_solve(c->stream, ma, potential); }));
+    c->potential_valid = potential;
+    return EP_OK;
+}
+
+ep_status ensure_potential(ep_ctx *c)
+{
+    if (c->potential_valid) return EP_OK;
+    HIPCHK(c, timed_launch(c, "potential", [&] { return launch_potential(c->stream, c->mesh()); }));
+    c->potential_valid = true;
     return EP_OK;
 }
 
@@ -92,8 +109,7 @@ ep_status refresh_field(ep_ctx *c)
 ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K)
 {
     if (c->n == 0) {
-        HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, c->mesh()); }));
-        return EP_OK;
+        return solve_mesh(c, c->mesh(), false);
     }
     const int64_t n4 = (int64_t)c->n >> 2;
     int64_t g = (n4 + kPushBlock - 1) / kPushBlock;
@@ -129,8 +145,7 @@ ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int 
     std::swap(c->ids, c->ids2);
     HIPCHK(c, timed_launch(c, "sort_reduce",
                            [&] { return launch_sort_reduce(c->stream, a, c->zR, c->zV, c->n_cu); }));
-    HIPCHK(c, timed_launch(c, "mesh_solve", [&] { return launch_mesh_solve(c->stream, c->mesh()); }));
-    return EP_OK;
+    return solve_mesh(c, c->mesh(), false);
 }
 
 }  // namespace etd
@@ -373,8 +388,7 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
                                                       c->tab.endrot + j, make_double2(1.0, 0.0),
                                                       K, ma, c->push_grid_cap);
                        }));
-                HIPCHK(c, timed_launch(c, "mesh_solve",
-                                       [&] { return launch_mesh_solve(c->stream, ma); }));
+                if (ep_status s = solve_mesh(c, ma, false); s != EP_OK) return s;
             }
         }
         c->phase = fmod(c->phase + (double)S * dphi, kTwoPi);
@@ -402,8 +416,8 @@ ep_status ep_moments_get(ep_ctx *c, double eps, int32_t field, ep_moments *out)
         return c->fail(EP_EINVAL, "ep_moments_get: need eps > 0 and a valid field model");
     if (c->w <= 0.0) return c->fail(EP_ESTATE, "ep_moments_get: no particles loaded");
     DeviceGuard guard(c->device);
-    if (field == EP_FIELD_POISSON && !c->field_valid) {
-        ep_status s = refresh_field(c);
+    if (field == EP_FIELD_POISSON) {
+        ep_status s = c->field_valid ? ensure_potential(c) : refresh_field(c);
         if (s != EP_OK) return s;
     }
     const int grid = moments_grid((int64_t)c->n);
@@ -479,8 +493,8 @@ ep_status ep_get_field(ep_ctx *c, double *rho, double *E, double *Psi, double *Q
                        c->cfg.n_cells + 1);
     if (c->w <= 0.0) return c->fail(EP_ESTATE, "ep_get_field: no particles loaded");
     DeviceGuard guard(c->device);
-    if (!c->field_valid) {
-        ep_status s = refresh_field(c);
+    {
+        ep_status s = c->field_valid ? ensure_potential(c) : refresh_field(c);
         if (s != EP_OK) return s;
     }
     const size_t bytes = (size_t)n_nodes * sizeof(double);
