@@ -767,8 +767,13 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const double R1 = fma(rot1.x, nr, rot1.y * nv);
         double P0, P1;
         if (VP) {
-            P0 = potential(pv, R);
-            P1 = potential(pv, R1);
+            // the two lanes of a particle evaluate one potential each: lane
+            // l + 32 the old position, lane l (the only one whose network
+            // outputs, and so R1, are valid) the new one
+            const double Pm = potential(pv, g ? R : R1);
+            const double Po = __shfl_xor(Pm, 32, 64);
+            P0 = g ? Pm : Po;
+            P1 = g ? Po : Pm;
         } else {
             P0 = 0.25 * (R * R) * (R * R);
             P1 = 0.25 * (R1 * R1) * (R1 * R1);
