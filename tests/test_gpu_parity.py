@@ -154,6 +154,31 @@ def test_deposit_and_solve(nr):
     assert np.all(np.sign(E[nr // 2 + 1:]) >= 0)
 
 
+@pytest.mark.parametrize("deposit", [EP_DEPOSIT_ATOMIC, EP_DEPOSIT_SORTED])
+def test_potential_after_field_only_solves(deposit):
+    """Plain steps solve the field without its potential; the potential and
+    field energy that ep_get_field and the moments then compute on demand
+    belong to the current field: Psi against the oracle's solve of the
+    GPU's own particles, and the moments' field energy against the
+    trapezoid of x E^2 over the returned node field."""
+    nr = 256
+    R0, V0, w = synth.gaussian_truncated(50001, seed=21)
+    with Sim(R0.size, n_cells=nr, substeps=2, deposit=deposit) as sim:
+        sim.set_particles(R0, V0, w)
+        sim.step(0.05, 0.01, EP_FIELD_POISSON, 5)
+        m = sim.moments(0.01, EP_FIELD_POISSON)
+        rho, E, Psi, Qb = sim.field()
+        Rg, _ = sim.particles()
+    rho_o, E_o, Psi_o, Qb_o, _ = _oracle_field(Rg, w, nr)
+    assert np.max(np.abs(E - E_o)) <= 2e-6 * np.max(np.abs(E_o))
+    assert np.max(np.abs(Psi - Psi_o)) <= 2e-6 * np.max(np.abs(Psi_o))
+    hr = 2 * RMAX / nr
+    x = (np.arange(nr + 1) - nr // 2) * hr
+    right = slice(nr // 2, nr + 1)
+    fe = np.trapezoid(x[right] * E[right] ** 2, dx=hr)
+    assert abs(m["potential"] - fe) <= 1e-12 * fe
+
+
 @pytest.mark.parametrize("K,deposit", [(1, EP_DEPOSIT_ATOMIC), (4, EP_DEPOSIT_ATOMIC),
                                        (1, EP_DEPOSIT_SORTED), (4, EP_DEPOSIT_SORTED)])
 def test_poisson_ten_steps_per_particle(K, deposit):
