@@ -42,13 +42,12 @@ def test_rk4_duffing_matches_oracle():
     h = oracle.fine_step(eps)
     K = math.ceil(dt / h - 1e-9)
     with _sim(R0, V0, w, EP_PUSH_RK4) as sim:
-        R, V = R0, V0
+        Ro, Vo = R0, V0
         for s in range(3):
             sim.step(dt, eps, EP_FIELD_DUFFING, 1)
-            Ro, Vo = oracle.rk4_run(R, V, w, eps, dt / K, K, oracle.FIELD_DUFFING)
+            Ro, Vo = oracle.rk4_run(Ro, Vo, w, eps, dt / K, K, oracle.FIELD_DUFFING)
             Rg, Vg = sim.particles()
             assert rel(Rg, Vg, Ro, Vo).max() <= 1e-6, s
-            R, V = Rg, Vg
 
 
 def test_rk4_poisson_matches_oracle():
@@ -57,13 +56,12 @@ def test_rk4_poisson_matches_oracle():
     h = oracle.fine_step(eps)
     dt = 12 * h
     with _sim(R0, V0, w, EP_PUSH_RK4) as sim:
-        R, V = R0, V0
+        Ro, Vo = R0, V0
         for s in range(2):
             sim.step(dt, eps, EP_FIELD_POISSON, 1)
-            Ro, Vo = oracle.rk4_run(R, V, w, eps, dt / 12, 12, oracle.FIELD_POISSON, **VP)
+            Ro, Vo = oracle.rk4_run(Ro, Vo, w, eps, dt / 12, 12, oracle.FIELD_POISSON, **VP)
             Rg, Vg = sim.particles()
             assert rel(Rg, Vg, Ro, Vo).max() <= 1e-6, s
-            R, V = Rg, Vg
 
 
 def _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, t_tol):

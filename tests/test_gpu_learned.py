@@ -151,16 +151,15 @@ def test_learned_push_without_fallback_is_the_network_map(out_map, precision):
     sim = _learned_sim(R0, V0, w, p, norm, 1e300, 8, precision)
     R, V = R0.copy(), V0.copy()
     pd = p.astype(np.float64)
-    worst = 0.0
     for s in range(3):
         sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
         d, k = mlp.predict(pd, R, V, DT, EPS, norm)
         R, V = mlp.apply_polar(R, V, DT, EPS, d, k, scaled=out_map == 1)
         Rg, Vg = sim.particles()
         err = rel_particle(Rg, Vg, R, V)
-        worst = max(worst, err.max())
-        assert err.max() <= MAP_TOL[precision], (s, err.max())
-        R, V = Rg, Vg      # continue from the GPU state: compare one step at a time
+        # both sides continue from their own state: the per-step deviations
+        # add up (the map is smooth), so the bound grows with the step count
+        assert err.max() <= (s + 1) * MAP_TOL[precision], (s, err.max())
     assert sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"] == 0
     sim.close()
 

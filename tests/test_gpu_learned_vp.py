@@ -69,17 +69,25 @@ def test_collected_labels_match_oracle():
         capi.ep_mlp_set_weights(sim.ctx, synth.mlp_init(6, 64, 2, seed=3), norm.as_array())
         count = capi.ep_mlp_collect(sim.ctx, DT, EPS, K, first=3, stride=7, reset=True)
         X, Y = capi.ep_mlp_get_samples(sim.ctx, 0, count)
-        R, V = sim.particles()
-        _, E, _, Qb = sim.field()
         # a second collection appends
         assert capi.ep_mlp_collect(sim.ctx, DT, EPS, K, first=0, stride=1000) == count + 21
     idx = np.arange(3, n, 7)
     assert count == idx.size
+    # the oracle's own two plain steps from the same beam give the state and
+    # field the samples were collected from (the GPU state is their FP32
+    # rounding, well inside the bounds below)
+    R, V = oracle.run(R0, V0, w, DT, EPS, 4, 2, oracle.FIELD_POISSON, nr=NR, rmin=-RMAX,
+                      rmax=RMAX)
+    E, _, Qb = _field(R, w)
     Rs, Vs = R[idx], V[idx]
     Rf, Vf = oracle.push(Rs, Vs, DT, EPS, K, E=E, Qb=Qb, **POIS)
     Eg = oracle.gather(Rs, E, Qb, NR, -RMAX, RMAX)
     Xo = mlp.features(Rs, Vs, DT, EPS, norm, Egather=Eg)
-    assert np.max(np.abs(X - Xo) / np.maximum(np.abs(Xo), 1.0)) <= 2e-6
+    # features: 2e-6 as for the same state; the field feature E/s_E also
+    # carries the field's own bound, 2e-6 max|E| (FP32 against FP64 positions)
+    tol = np.full(Xo.shape[1], 2e-6)
+    tol[5] += 2e-6 * np.max(np.abs(E)) / norm.s_E
+    assert np.all(np.max(np.abs(X - Xo) / np.maximum(np.abs(Xo), 1.0), axis=0) <= tol)
     # each label, applied to its sample, gives the oracle's fine step
     R1, V1 = mlp.apply_polar(Rs, Vs, DT, EPS, Y[:, 0].astype(np.float64),
                              Y[:, 1].astype(np.float64), scaled=True)
@@ -94,21 +102,27 @@ def test_learned_push_without_fallback_is_the_network_map(out_map, precision):
     p = synth.mlp_init(6, 64, 2, seed=9)
     norm = _norm(out_map=out_map)
     sim, w = _learned_sim(20001, 42, p, norm, 1e300, 8, precision=precision)
+    R, V, _ = synth.gaussian_truncated(20001, seed=42)
     pd = p.astype(np.float64)
     for s in range(3):
-        R, V = sim.particles()
+        # the oracle's map from its own state, in its own field
         E, _, Qb = _field(R, w)
         Eg = oracle.gather(R, E, Qb, NR, -RMAX, RMAX)
         d, k = mlp.predict(pd, R, V, DT, EPS, norm, Egather=Eg)
-        Ro, Vo = mlp.apply_polar(R, V, DT, EPS, d, k, scaled=out_map == 1)
+        R, V = mlp.apply_polar(R, V, DT, EPS, d, k, scaled=out_map == 1)
         sim.step(DT, EPS, EP_FIELD_POISSON, 1)
         Rg, Vg = sim.particles()
-        err = rel_particle(Rg, Vg, Ro, Vo)
-        assert err.max() <= MAP_TOL[precision], (s, err.max())
-        # the learned kernel deposited the new positions
+        err = rel_particle(Rg, Vg, R, V)
+        # per-step deviations add up (the map and the field are smooth), so
+        # the bound grows with the step count
+        assert err.max() <= (s + 1) * MAP_TOL[precision], (s, err.max())
+        # the learned kernel deposited the new positions: its field is the one
+        # a fresh context deposits from the same particles
         _, Eg_, _, _ = sim.field()
-        Eo, _, _ = _field(Rg, w)
-        assert np.max(np.abs(Eg_ - Eo)) <= 2e-6 * np.max(np.abs(Eo))
+        with Sim(Rg.size, n_cells=NR) as fresh:
+            fresh.set_particles(Rg, Vg, w)
+            _, Ef, _, _ = fresh.field()
+        assert np.max(np.abs(Eg_ - Ef)) <= 2e-6 * np.max(np.abs(Ef))
     assert sim.moments(EPS, EP_FIELD_POISSON)["n_fallback"] == 0
     sim.close()
 
@@ -179,9 +193,10 @@ def test_gradients_six_inputs_match_oracle():
 
 def test_training_on_collected_samples_matches_oracle_training():
     """Samples from three time levels of a plain run; a whole training run on
-    the GPU against the FP64 oracle's run on the same samples and batch order
-    (batch b of an epoch = rows b, b + P, ...): first- and last-epoch mean
-    losses agree to 2%, and the loss falls."""
+    the GPU against the FP64 oracle's run on the samples it collects itself
+    from the same beam, in the same batch order (batch b of an epoch = rows
+    b, b + P, ...): first- and last-epoch mean losses agree to 2%, and the
+    loss falls."""
     n, batch, epochs, lr, lr_final = 24000, 256, 6, 3e-3, 1e-5
     R0, V0, w = synth.gaussian_truncated(n, seed=46)
     norm = _norm()
@@ -200,12 +215,29 @@ def test_training_on_collected_samples_matches_oracle_training():
     P = total // batch
     assert rep["steps"] == epochs * P and np.all(np.isfinite(pg))
     assert np.array_equal(normg[:3], norm.as_array()[:3])
-    Yd = Y.astype(np.float64)
+    # the reported normalisation is that of the samples the GPU trained on
+    Yg = Y.astype(np.float64)
+    assert np.allclose([rep["mu_delta"], rep["mu_kappa"]], Yg[:65536].mean(0), rtol=1e-5,
+                       atol=1e-9)
+    assert np.allclose([rep["sig_delta"], rep["sig_kappa"]], Yg[:65536].std(0), rtol=1e-5)
+    # the oracle collects its own samples the same way from the same beam:
+    # at each level the particles lvl, lvl + 3, ... of its own plain run, the
+    # features in its own field and the labels of a 32-substep push in it
+    R, V = R0, V0
+    Xs, Ys = [], []
+    for lvl in range(3):
+        E, _, Qb = _field(R, w)
+        idx = np.arange(lvl, n, 3)
+        Rs, Vs = R[idx], V[idx]
+        Eg = oracle.gather(Rs, E, Qb, NR, -RMAX, RMAX)
+        Xs.append(mlp.features(Rs, Vs, DT, EPS, norm, Egather=Eg))
+        Rf, Vf = oracle.push(Rs, Vs, DT, EPS, 32, E=E, Qb=Qb, **POIS)
+        Ys.append(np.stack(mlp.polar_labels(Rs, Vs, Rf, Vf, DT, EPS, scaled=True), 1))
+        R, V = oracle.run(R, V, w, DT, EPS, 8, 2, oracle.FIELD_POISSON, nr=NR, rmin=-RMAX,
+                          rmax=RMAX)
+    Xd, Yd = np.concatenate(Xs), np.concatenate(Ys)
     mu, sd = Yd[:65536].mean(0), Yd[:65536].std(0)
-    assert np.allclose([rep["mu_delta"], rep["mu_kappa"]], mu, rtol=1e-5, atol=1e-9)
-    assert np.allclose([rep["sig_delta"], rep["sig_kappa"]], sd, rtol=1e-5)
     Yn = (Yd - mu) / sd
-    Xd = X.astype(np.float64)
     q = p0.astype(np.float64)
     m = np.zeros_like(q)
     v = np.zeros_like(q)
