@@ -59,8 +59,8 @@ def lib():
         L.orc_run.restype = None
         L.orc_rk4_run.argtypes = [p, p, i64, d, d, d, i64, i32, d, i32, d, d]
         L.orc_rk4_run.restype = i32
-        L.orc_improved_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i64, p,
-                                            ctypes.POINTER(ctypes.c_int64)]
+        L.orc_improved_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i64, i32,
+                                            p, ctypes.POINTER(ctypes.c_int64)]
         L.orc_improved_etd_step.restype = i64
         L.orc_classic_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i32, i64,
                                            p, p]
@@ -163,15 +163,18 @@ def fine_step(eps):
 
 
 def improved_etd_step(R, V, w, dt, eps, field, nr=0, rmin=0.0, rmax=0.0, E0=0.0, h=None,
-                      max_fine=100000):
-    """One macro step of Algorithm 3.4.  Returns (R, V, T, N, n_unresolved)."""
+                      max_fine=100000, T=None):
+    """One macro step of Algorithm 3.4.  Returns (R, V, T, N, n_unresolved).
+    With T given (the periods of a previous step, in the given field where
+    they are constant) the period search is skipped."""
     R = _f64(R).copy()
     V = _f64(V).copy()
     h = fine_step(eps) if h is None else h
-    T = np.empty(R.size)
+    given = T is not None
+    T = _f64(T).copy() if given else np.empty(R.size)
     N = np.empty(R.size, dtype=np.int64)
     un = lib().orc_improved_etd_step(_ptr(R), _ptr(V), R.size, w, dt, eps, h, field, E0, nr,
-                                     rmin, rmax, max_fine, _ptr(T),
+                                     rmin, rmax, max_fine, 1 if given else 0, _ptr(T),
                                      N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     if un < 0:
         raise MemoryError("orc_improved_etd_step")

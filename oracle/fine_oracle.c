@@ -278,7 +278,7 @@ int64_t orc_classic_etd_step(double *R, double *V, int64_t n, double w, double d
  * max_fine fine steps (they use 2 pi eps), or -1 without memory. */
 int64_t orc_improved_etd_step(double *R, double *V, int64_t n, double w, double dt, double eps,
                               double h, int kind, double E0, int nr, double rmin, double rmax,
-                              int64_t max_fine, double *T, int64_t *N)
+                              int64_t max_fine, int periods_given, double *T, int64_t *N)
 {
     if (n <= 0) return 0;
     field_ctx f;
@@ -299,11 +299,14 @@ int64_t orc_improved_etd_step(double *R, double *V, int64_t n, double w, double 
     double *ta = buf + 15 * nn;
     const double two_pi_eps = 2.0 * M_PI * eps;
 
-    /* (a) periods */
+    /* (a) periods; skipped when T holds them already (the given field keeps
+       each particle's period constant, so the paper computes them at the
+       first macro step only) */
     memcpy(Rw, R, sizeof(double) * nn);
     memcpy(Vw, V, sizeof(double) * nn);
-    int64_t done = 0, steps = 0;
-    for (int64_t i = 0; i < n; ++i) T[i] = two_pi_eps;
+    int64_t done = periods_given ? n : 0, steps = 0;
+    if (!periods_given)
+        for (int64_t i = 0; i < n; ++i) T[i] = two_pi_eps;
     while (done < n && steps < max_fine) {
         memcpy(Vp, Vw, sizeof(double) * nn);
         rk4_step(Rw, Vw, n, eps, h, &f, work);

@@ -99,6 +99,37 @@ def test_improved_etd_is_accurate_for_periodic_orbits():
         assert np.median(err / np.maximum(np.hypot(Rx, Vx), 1.0)) < 2e-4
 
 
+def test_improved_etd_with_given_periods():
+    """In the given field the periods are constant, and Algorithm 3.4 may take
+    them from a previous step.  With the exact elliptic periods given, the
+    period term of the error bound above vanishes and only the
+    interpolation term is left; with the step's own searched periods given,
+    the step is the one that searches them, bit for bit; and a second step
+    that reuses the first step's periods stays within the bound of two steps
+    against the exact solution."""
+    R0, V0, w = synth.gaussian(400, seed=6)
+    for eps in (0.05, 1e-3):
+        Tx = duffing.period(R0, V0, eps)
+        R, V, T, N, un = oracle.improved_etd_step(R0, V0, w, 0.5, eps, oracle.FIELD_DUFFING,
+                                                  T=Tx)
+        assert un == 0 and np.array_equal(T, Tx)
+        Rx, Vx = duffing.solution(R0, V0, eps, 0.5)
+        z3 = (2 * np.pi / 100) ** 3
+        bound = ((2 * N + 1) * z3 / 10) * np.hypot(Rx, Vx) * 1.5
+        err = np.hypot(R - Rx, V - Vx)
+        assert np.all(err <= bound), (eps, np.max(err / bound))
+        Rs, Vs, Ts, Ns, _ = oracle.improved_etd_step(R0, V0, w, 0.5, eps, oracle.FIELD_DUFFING)
+        Rg, Vg, Tg, Ng, _ = oracle.improved_etd_step(R0, V0, w, 0.5, eps, oracle.FIELD_DUFFING,
+                                                     T=Ts)
+        assert np.array_equal(Rg, Rs) and np.array_equal(Vg, Vs) and np.array_equal(Ng, Ns)
+        R2, V2, _, N2, _ = oracle.improved_etd_step(Rs, Vs, w, 0.5, eps, oracle.FIELD_DUFFING,
+                                                    T=Ts)
+        Rx2, Vx2 = duffing.solution(R0, V0, eps, 1.0)
+        dT = np.abs(Ts / Tx - 1)
+        bound2 = 2 * (2 * np.pi * (N + 1) * dT + (2 * N + 1) * z3 / 10) * np.hypot(Rx2, Vx2) * 1.5
+        assert np.all(np.hypot(R2 - Rx2, V2 - Vx2) <= bound2), eps
+
+
 def test_improved_etd_vp_step_tracks_the_reference():
     """Vlasov-Poisson beam, one macro step dt = 10 T of the improved scheme
     against the reference RK4 run over the same time: the rms radius agrees to
