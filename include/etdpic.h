@@ -201,8 +201,18 @@ ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
  * max_fine (>= 1) bounds the fine steps of the period search; a particle
  * without three sign changes by then keeps the free period 2 pi eps and is
  * counted as unresolved.  The sorted deposit does not support these modes.
- * Defaults: h_fine = 0, max_fine = 10000.  Errors: EP_EINVAL. */
-ep_status ep_set_fine_solver(ep_ctx *ctx, double h_fine, uint64_t max_fine);
+ * periods_once (0 or 1): in the Duffing field each particle's period is
+ * constant (section 3), so with periods_once = 1 an improved ETD step reuses
+ * the periods found by the preceding improved ETD, modified ETD or
+ * ep_compute_periods call on the same particles, with the same eps and fine
+ * step, when no other step came in between; it then runs only the capture
+ * solve, and ep_get_periods keeps reporting the unresolved count of the
+ * search that found them.  The self-consistent field searches at every step.
+ * Calling ep_set_fine_solver drops the kept periods.
+ * Defaults: h_fine = 0, max_fine = 10000, periods_once = 1.  Errors:
+ * EP_EINVAL. */
+ep_status ep_set_fine_solver(ep_ctx *ctx, double h_fine, uint64_t max_fine,
+                             int32_t periods_once);
 
 /* The periods T_i of the current state, without stepping (the paper's period
  * diagnostics, section 2): the same fine-solve search as Algorithm 3.4 uses,
@@ -336,8 +346,11 @@ ep_status ep_mlp_train(ep_ctx *ctx, const ep_train_cfg *cfg, const double *R, co
  * (magic "ETDPIC01", format version, loaded particle count, mesh and substep
  * configuration, weight, t, phase, step count, push mode, fallback settings,
  * inference precision, fine-solver settings),
- * the FP32 rotating-frame particle arrays in the order they were loaded, and
- * the corrector's parameters and normalisation if one is loaded.  ep_load
+ * the FP32 rotating-frame particle arrays in the order they were loaded, the
+ * corrector's parameters and normalisation if one is loaded, and the periods
+ * T_i and N_i of the last improved or modified ETD step (or ep_compute_periods
+ * call) if they belong to the saved particles, so that a resumed improved ETD
+ * run reuses them as the uninterrupted run does.  ep_load
  * restores such a file into a context whose capacity, mesh and substeps
  * accept it; the field is recomputed from the particles, so a resumed run
  * continues bit for bit.  A push mode the context cannot run (the learned

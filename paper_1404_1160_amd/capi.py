@@ -118,7 +118,7 @@ def lib():
                               ctypes.POINTER(ep_train_report)], i32),
             "ep_mlp_collect": ([vp, d, d, u32, u64, u64, i32, ctypes.POINTER(u64)], i32),
             "ep_mlp_get_samples": ([vp, u64, u64, pf, pf], i32),
-            "ep_set_fine_solver": ([vp, d, u64], i32),
+            "ep_set_fine_solver": ([vp, d, u64, i32], i32),
             "ep_copy_bandwidth": ([i32, u64, i32, pd], i32),
             "ep_compute_periods": ([vp, d, i32, ctypes.POINTER(u64)], i32),
             "ep_get_periods": ([vp, pd, ctypes.POINTER(ctypes.c_int64), u64, u64,
@@ -309,9 +309,11 @@ def ep_mlp_get_samples(ctx, first, count):
     return X, Y
 
 
-def ep_set_fine_solver(ctx, h_fine=0.0, max_fine=10000):
-    """Fine step of the reference RK4 and improved-ETD modes (<= 0: 2 pi eps/100)."""
-    _check(ctx, lib().ep_set_fine_solver(ctx, float(h_fine), int(max_fine)))
+def ep_set_fine_solver(ctx, h_fine=0.0, max_fine=10000, periods_once=True):
+    """Fine step of the reference RK4 and improved-ETD modes (<= 0: 2 pi eps/100),
+    the period-search bound, and whether Duffing improved-ETD steps reuse the
+    periods found once."""
+    _check(ctx, lib().ep_set_fine_solver(ctx, float(h_fine), int(max_fine), int(periods_once)))
 
 
 def ep_copy_bandwidth(n_bytes, reps=10, device=0):

@@ -7,7 +7,7 @@ using namespace etd;
 namespace {
 
 constexpr char kMagic[8] = {'E', 'T', 'D', 'P', 'I', 'C', '0', '1'};
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 
 struct Header {
     char magic[8];
@@ -30,6 +30,13 @@ struct Header {
     uint32_t reserved;
     double h_fine;
     uint64_t max_fine;
+    int32_t periods_once;
+    int32_t periods_saved;      // 1: the periods T_i and N_i follow the particles
+    int32_t periods_duffing;    // 1: reusable Duffing periods
+    uint32_t reserved2;
+    double periods_eps;
+    double periods_h;
+    uint64_t periods_unresolved;
 };
 
 struct File {
@@ -69,6 +76,25 @@ ep_status ep_save(ep_ctx *c, const char *path)
     h.mlp_precision = c->mlp.precision;
     h.h_fine = c->h_fine;
     h.max_fine = c->max_fine;
+    h.periods_once = c->periods_once ? 1 : 0;
+    // periods of the last period-finding step, if they belong to these particles
+    std::vector<double> T;
+    std::vector<int64_t> N;
+    if (c->periods_valid && !c->ids && c->n && c->fine.T) {
+        T.resize(c->n);
+        N.resize(c->n);
+        unsigned long long un = 0;
+        HIPCHK(c, hipMemcpyAsync(T.data(), c->fine.T, c->n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(N.data(), c->fine.N, c->n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&un, c->fine.unresolved, sizeof un, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        h.periods_saved = 1;
+        h.periods_duffing = c->periods_duffing && c->periods_step == c->n_steps ? 1 : 0;
+        h.periods_eps = c->periods_eps;
+        h.periods_h = c->periods_h;
+        h.periods_unresolved = un;
+    }
     // particles in loaded order
     std::vector<float> zr(c->n), zv(c->n);
     if (c->n) {
@@ -105,6 +131,10 @@ ep_status ep_save(ep_ctx *c, const char *path)
         ok = ok && fwrite(c->mlp.params.data(), 4, h.mlp_n_params, out.f) == h.mlp_n_params;
         ok = ok && fwrite(c->mlp.norm, 8, 8, out.f) == 8;
     }
+    if (h.periods_saved) {
+        ok = ok && fwrite(T.data(), 8, c->n, out.f) == c->n;
+        ok = ok && fwrite(N.data(), 8, c->n, out.f) == c->n;
+    }
     ok = ok && fflush(out.f) == 0;
     if (!ok) return c->fail(EP_EIO, "ep_save: write to %s failed", path);
     return EP_OK;
@@ -127,6 +157,8 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
         return c->fail(EP_EINVAL, "ep_load: checkpoint does not fit this context (particles, "
                                   "mesh or substeps differ)");
     std::vector<float> zr(h.n), zv(h.n), params(h.mlp_n_params);
+    std::vector<double> T(h.periods_saved ? h.n : 0);
+    std::vector<int64_t> N(h.periods_saved ? h.n : 0);
     double norm[8] = {0};
     bool ok = true;
     if (h.n) {
@@ -135,6 +167,8 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
     if (ok && h.mlp_n_in)
         ok = fread(params.data(), 4, h.mlp_n_params, in.f) == h.mlp_n_params &&
              fread(norm, 8, 8, in.f) == 8;
+    if (ok && h.periods_saved)
+        ok = fread(T.data(), 8, h.n, in.f) == h.n && fread(N.data(), 8, h.n, in.f) == h.n;
     if (!ok) return c->fail(EP_EIO, "ep_load: %s is truncated", path);
     DeviceGuard guard(c->device);
     if (h.mlp_n_in) {
@@ -167,8 +201,19 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
     }
     c->fallback_K = h.fallback_K;
     c->drift_tol = h.drift_tol;
+    c->periods_once = h.periods_once != 0;
     c->field_valid = false;
     c->periods_valid = false;
+    c->periods_duffing = false;
+    if (h.periods_saved && h.n) {
+        ep_status s = restore_periods(c, T.data(), N.data(), h.periods_unresolved);
+        if (s != EP_OK) return s;
+        c->periods_valid = true;
+        c->periods_duffing = h.periods_duffing != 0;
+        c->periods_eps = h.periods_eps;
+        c->periods_h = h.periods_h;
+        c->periods_step = c->n_steps;
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (n_particles) *n_particles = h.n;
     return EP_OK;

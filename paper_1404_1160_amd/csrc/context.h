@@ -141,6 +141,13 @@ struct ep_ctx {
     uint64_t fine_cap = 0;
     bool periods_valid = false;
     double last_period = 0.0;        // common period P of the last classic/modified ETD step
+    // In the given (Duffing) field each particle's period is constant, so the
+    // periods found once are reused by later improved ETD steps (section 3)
+    // while nothing but period-finding steps has moved the particles.
+    bool periods_once = true;
+    bool periods_duffing = false;    // fine.T holds Duffing periods of the current particles
+    double periods_eps = 0.0, periods_h = 0.0;
+    uint64_t periods_step = 0;       // n_steps when they were last found or used
 
     // push mode
     int push_mode = EP_PUSH_PLAIN;
@@ -223,5 +230,7 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
 // Reference RK4 or improved ETD steps (push modes EP_PUSH_RK4 / _IMPROVED_ETD).
 ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps);
 void free_fine(ep_ctx *c);
+// Duffing periods into fine.T and fine.N (checkpoint restore)
+ep_status restore_periods(ep_ctx *c, const double *T, const int64_t *N, uint64_t unresolved);
 
 }  // namespace etd

@@ -194,11 +194,17 @@ ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n
                 HIPCHK(c, launch_fine_end(c->stream, a, c->zR, c->zV, n, rot1, 0));
             }
         } else if (!coupled) {
-            HIPCHK(c, hipMemsetAsync(a.unresolved, 0, sizeof(unsigned long long), c->stream));
-            HIPCHK(c, timed_launch(c, "ietd_duffing", [&] {
+            // the periods of an earlier search stay valid in the given field;
+            // the unresolved count stays that of the search
+            const bool reuse = c->periods_once && c->periods_valid && c->periods_duffing &&
+                               c->periods_eps == eps && c->periods_h == h &&
+                               c->periods_step == c->n_steps;
+            if (!reuse)
+                HIPCHK(c, hipMemsetAsync(a.unresolved, 0, sizeof(unsigned long long), c->stream));
+            HIPCHK(c, timed_launch(c, reuse ? "ietd_duffing_reuse" : "ietd_duffing", [&] {
                        return launch_ietd_duffing(c->stream, c->zR, c->zV, n, dt, h, eps,
-                                                  (long long)c->max_fine, rot0, rot1, a.T, a.N,
-                                                  a.unresolved);
+                                                  (long long)c->max_fine, rot0, rot1, reuse, a.T,
+                                                  a.N, a.unresolved);
                    }));
         } else if (ietd) {
             // (a) period search, all particles in lock step until every one
@@ -218,9 +224,27 @@ ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n
         c->phase = p1;
         c->t += dt;
         c->n_steps += 1;
+        c->periods_valid = ietd || modified;
+        c->periods_duffing = (ietd || modified) && !coupled;
+        c->periods_eps = eps;
+        c->periods_h = h;
+        c->periods_step = c->n_steps;
     }
-    c->periods_valid = (ietd || modified) && n_steps > 0;
     c->field_valid = false;
+    return EP_OK;
+}
+
+ep_status restore_periods(ep_ctx *c, const double *T, const int64_t *N, uint64_t unresolved)
+{
+    ep_status s = ensure_fine(c, false);
+    if (s != EP_OK) return s;
+    FineArgs &a = c->fine;
+    const unsigned long long un = unresolved;
+    if (c->n) {
+        HIPCHK(c, hipMemcpy(a.T, T, c->n * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(a.N, N, c->n * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, hipMemcpy(a.unresolved, &un, sizeof un, hipMemcpyHostToDevice));
     return EP_OK;
 }
 
@@ -228,13 +252,17 @@ ep_status fine_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n
 
 extern "C" {
 
-ep_status ep_set_fine_solver(ep_ctx *c, double h_fine, uint64_t max_fine)
+ep_status ep_set_fine_solver(ep_ctx *c, double h_fine, uint64_t max_fine, int32_t periods_once)
 {
     if (!c) return EP_EINVAL;
     if (!(h_fine == h_fine) || !isfinite(h_fine) || max_fine == 0)
         return c->fail(EP_EINVAL, "ep_set_fine_solver: need a finite h_fine and max_fine >= 1");
+    if (periods_once != 0 && periods_once != 1)
+        return c->fail(EP_EINVAL, "ep_set_fine_solver: periods_once must be 0 or 1");
     c->h_fine = h_fine;
     c->max_fine = max_fine;
+    c->periods_once = periods_once != 0;
+    c->periods_duffing = false;   // a new max_fine may resolve other periods
     return EP_OK;
 }
 
@@ -269,6 +297,10 @@ ep_status ep_compute_periods(ep_ctx *c, double eps, int32_t field, uint64_t *n_u
     HIPCHK(c, hipMemcpyAsync(&un, a.unresolved, sizeof un, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->periods_valid = true;
+    c->periods_duffing = !coupled;
+    c->periods_eps = eps;
+    c->periods_h = h;
+    c->periods_step = c->n_steps;
     if (n_unresolved) *n_unresolved = un;
     return EP_OK;
 }

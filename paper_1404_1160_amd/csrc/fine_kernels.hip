@@ -89,30 +89,38 @@ __global__ __launch_bounds__(256) void rk4_duffing_kernel(float *__restrict__ zR
     zV[i] = (float)fma(rot1.y, R, rot1.x * V);
 }
 
-// Improved ETD step for the Duffing field, one particle per thread.
+// Improved ETD step for the Duffing field, one particle per thread.  With
+// reuse set, T[i] holds the particle's period from an earlier search (in the
+// given field each particle's period is constant, section 3) and the search
+// is skipped; otherwise the search writes T[i].
 __global__ __launch_bounds__(256) void ietd_duffing_kernel(
     float *__restrict__ zR, float *__restrict__ zV, int64_t n, double dt, double h, double ie,
-    long long max_fine, double T_free, double2 rot0, double2 rot1, double *__restrict__ Tout,
-    long long *__restrict__ Nout, unsigned long long *__restrict__ unresolved)
+    long long max_fine, double T_free, double2 rot0, double2 rot1, int reuse,
+    double *__restrict__ Tio, long long *__restrict__ Nout,
+    unsigned long long *__restrict__ unresolved)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double zr = zR[i], zv = zV[i];
     const double R0 = fma(rot0.x, zr, rot0.y * zv), V0 = fma(-rot0.y, zr, rot0.x * zv);
     const double inv_h = 1.0 / h;
-    // periods
-    double R = R0, V = V0, t1 = 0.0, T = T_free;
-    int cnt = 0;
-    for (long long k = 0; k < max_fine && cnt < 3; ++k) {
-        const double Vp = V;
-        rk4_duffing(R, V, h, ie);
-        if ((Vp < 0.0) != (V < 0.0)) {
-            const double ts = (double)k * h + h * Vp / (Vp - V);
-            if (++cnt == 1) t1 = ts;
-            if (cnt == 3) T = ts - t1;
+    double R = R0, V = V0, T = T_free;
+    if (reuse) {
+        T = Tio[i];
+    } else {
+        double t1 = 0.0;
+        int cnt = 0;
+        for (long long k = 0; k < max_fine && cnt < 3; ++k) {
+            const double Vp = V;
+            rk4_duffing(R, V, h, ie);
+            if ((Vp < 0.0) != (V < 0.0)) {
+                const double ts = (double)k * h + h * Vp / (Vp - V);
+                if (++cnt == 1) t1 = ts;
+                if (cnt == 3) T = ts - t1;
+            }
         }
+        if (cnt < 3) atomicAdd(unresolved, 1ull);
     }
-    if (cnt < 3) atomicAdd(unresolved, 1ull);
     if (!(T > 0.0 && T < 1e300)) T = T_free;   // keeps the capture loop bounded
     long long N;
     double o;
@@ -146,8 +154,8 @@ __global__ __launch_bounds__(256) void ietd_duffing_kernel(
     const double R1 = fma(q, Rb - Ra, Ra), V1 = fma(q, Vb - Va, Va);
     zR[i] = (float)fma(rot1.x, R1, -rot1.y * V1);
     zV[i] = (float)fma(rot1.y, R1, rot1.x * V1);
-    if (Tout) Tout[i] = T;
-    if (Nout) Nout[i] = N;
+    if (!reuse) Tio[i] = T;
+    Nout[i] = N;
 }
 
 hipError_t launch_rk4_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double h,
@@ -160,13 +168,13 @@ hipError_t launch_rk4_duffing(hipStream_t st, float *zR, float *zV, int64_t n, d
 
 hipError_t launch_ietd_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double dt,
                                double h, double eps, long long max_fine, double2 rot0,
-                               double2 rot1, double *T, long long *N,
+                               double2 rot1, bool reuse, double *T, long long *N,
                                unsigned long long *unresolved)
 {
     if (n <= 0) return hipSuccess;
     return dispatch(ietd_duffing_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, zR,
                     zV, n, dt, h, 1.0 / eps, max_fine, 2.0 * 3.141592653589793 * eps, rot0, rot1,
-                    T, N, unresolved);
+                    reuse ? 1 : 0, T, N, unresolved);
 }
 
 // Periods only (the modified ETD scheme needs their mean first).

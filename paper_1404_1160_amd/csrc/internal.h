@@ -224,9 +224,10 @@ struct FineArgs {
 };
 hipError_t launch_rk4_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double h,
                               double eps, long long steps, double2 rot0, double2 rot1);
+// reuse: T already holds the periods and the search is skipped
 hipError_t launch_ietd_duffing(hipStream_t st, float *zR, float *zV, int64_t n, double dt,
                                double h, double eps, long long max_fine, double2 rot0,
-                               double2 rot1, double *T, long long *N,
+                               double2 rot1, bool reuse, double *T, long long *N,
                                unsigned long long *unresolved);
 // stage 1-4 of the coupled RK4 step to level L; mode 0 reference, 1 period
 // search, 2 captures

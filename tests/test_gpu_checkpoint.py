@@ -90,11 +90,16 @@ def test_fine_solver_resume_restores_mode_and_step(tmp_path):
         a.save(path)
         a.step(dt, eps, EP_FIELD_DUFFING, 2)
         Ra, Va = a.particles()
+        Ta, Na, _ = capi.ep_get_periods(a.ctx, R.size)
     with Sim(R.size, substeps=4) as b:
         b.load(path)
+        # the kept periods come back too: the resumed steps reuse them
+        Tl, _, _ = capi.ep_get_periods(b.ctx, R.size)
         b.step(dt, eps, EP_FIELD_DUFFING, 2)
         Rb, Vb = b.particles()
+        Tb, Nb, _ = capi.ep_get_periods(b.ctx, R.size)
     assert np.array_equal(Ra, Rb) and np.array_equal(Va, Vb)
+    assert np.array_equal(Tl, Ta) and np.array_equal(Tb, Ta) and np.array_equal(Nb, Na)
 
 
 def test_load_rejects_mismatch_and_garbage(tmp_path):

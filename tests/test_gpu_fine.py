@@ -88,6 +88,74 @@ def test_improved_etd_duffing_matches_oracle():
         assert worst <= 1e-6, (eps, worst)
 
 
+@pytest.mark.parametrize("once", [True, False])
+def test_improved_etd_duffing_steps_match_oracle(once):
+    """Three macro steps at the paper's eps.  With periods_once the GPU reuses
+    the periods of its first search and the oracle is handed its own
+    first-step periods; without it both search at every step."""
+    R0, V0, w = synth.gaussian(10001, seed=58)
+    eps, dt = 1e-3, 0.5
+    with _sim(R0, V0, w, EP_PUSH_IMPROVED_ETD, periods_once=once) as sim:
+        Ro, Vo, T1 = R0, V0, None
+        for s in range(3):
+            sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+            Rg, Vg = sim.particles()
+            Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
+            Ro, Vo, To, No, uno = oracle.improved_etd_step(Ro, Vo, w, dt, eps,
+                                                           oracle.FIELD_DUFFING,
+                                                           T=T1 if once else None)
+            if once and s == 0:
+                T1 = To
+            assert un == uno == 0, s
+            # searched from FP32-stored against FP64 states after the first step
+            t_tol = 1e-9 if once or s == 0 else 1e-8
+            worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, t_tol)
+            assert worst <= 1e-6, (s, worst)
+            if once and s:
+                assert np.array_equal(Tg, T1g)
+            if s == 0:
+                T1g = Tg
+
+
+def test_improved_etd_period_reuse_rules():
+    """The periods are reused only after an improved ETD step on the same
+    particles with the same eps and fine step: another step in between, a new
+    eps or a call of ep_set_fine_solver makes the next step search again."""
+    R0, V0, w = synth.gaussian(4001, seed=59)
+    eps, dt = 1e-3, 0.5
+
+    def periods():
+        return capi.ep_get_periods(sim.ctx, R0.size)[0]
+
+    with _sim(R0, V0, w, EP_PUSH_IMPROVED_ETD) as sim:
+        sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+        T1 = periods()
+        sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+        assert np.array_equal(periods(), T1)
+        capi.ep_set_push_mode(sim.ctx, capi.EP_PUSH_PLAIN)
+        sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+        capi.ep_set_push_mode(sim.ctx, EP_PUSH_IMPROVED_ETD)
+        sim.step(dt, eps, EP_FIELD_DUFFING, 1)
+        # searched again from where the plain step left the particles (its
+        # single substep over 80 fast periods changes their amplitudes)
+        T3 = periods()
+        T_free = 2 * np.pi * eps
+        assert not np.array_equal(T3, T1)
+        assert np.all((T3 > 0.5 * T_free) & (T3 < (1 + 1e-6) * T_free))
+        sim.step(dt, 2 * eps, EP_FIELD_DUFFING, 1)
+        T4 = periods()
+        assert np.all((T4 > 1.5 * T3) & (T4 < (1 + 1e-6) * 2 * T_free))
+        capi.ep_set_fine_solver(sim.ctx, 0.0, 10000)
+        sim.step(dt, 2 * eps, EP_FIELD_DUFFING, 1)
+        T5 = periods()
+        # a search from another point of the orbit: the same periods up to
+        # the search's own error
+        assert not np.array_equal(T5, T4) and np.max(np.abs(T5 / T4 - 1)) < 1e-3
+        with pytest.raises(capi.EtdpicError) as e:
+            capi.ep_set_fine_solver(sim.ctx, 0.0, 10000, periods_once=2)
+        assert e.value.status == capi.EP_EINVAL
+
+
 def test_improved_etd_poisson_matches_oracle():
     R0, V0, w = synth.gaussian_truncated(4001, seed=54)
     eps = 0.01
