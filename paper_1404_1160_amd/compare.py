@@ -18,6 +18,11 @@ separate beam (another seed) is run with the plain push at K_data substeps
 and, every `collect_every` steps, its particles, their field E^n and the
 labels of a K_fine-substep step in that frozen field are collected on the
 GPU.  Reference and error metric as above, with the reference run at K_ref.
+The labels take K_fine = 12800 substeps here: the CIC field's gradient jumps
+at every node, so the plain push converges slowly in K, and at K = 800 its
+own frozen-field energy error (median 7e-5 relative) exceeds the 1e-5 drift
+bound; a network fitted closely to such labels inherits that error and fails
+the check.
 
 The learned push runs with both inference operand types (BF16, the
 library's default, and FP16); the results carry the equal-error point of
@@ -199,7 +204,7 @@ def _vp_history(sim, R0, V0, w, steps, every):
     return np.array(out)
 
 
-def train_vp(n_data, steps, nr=VP_NR, K_data=400, K_fine=800, collect_every=10, epochs=40,
+def train_vp(n_data, steps, nr=VP_NR, K_data=400, K_fine=12800, collect_every=10, epochs=40,
              batch=4096, lr=3e-3, lr_final=1e-5, seed=16, init_seed=5, log=None):
     """Self-generated training: plain run of a separate beam, samples collected
     every `collect_every` steps; returns (params, norm, report, n_samples)."""
@@ -221,7 +226,7 @@ def train_vp(n_data, steps, nr=VP_NR, K_data=400, K_fine=800, collect_every=10, 
 
 
 def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs=40,
-                   K_fine=800, plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5,
+                   K_fine=12800, plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5,
                    extra_tols=(1e-4, 1e-3), K_fb=400, seed_eval=17, every=10,
                    precisions=(EP_MLP_BF16, EP_MLP_FP16), log=None):
     """As equal_error, for the Vlasov-Poisson beam; the learned push runs, for

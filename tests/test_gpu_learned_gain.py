@@ -93,3 +93,21 @@ def test_equal_error_comparison_vp():
     errs = [p["rms_err"] for p in res["plain"]]
     assert errs[-1] < errs[0]
     assert res["learned"][-1]["rms_err"] < errs[0]
+
+
+def test_learned_vp_beats_plain_at_equal_error():
+    """At the at-scale Vlasov-Poisson workload (N_r = 4096, eps = 1e-3,
+    dt = 0.1, 200 steps; the network trained on samples of a separate beam
+    labelled with K_fine = 12800 substeps; 2e6 evaluation particles here) the
+    learned push with the 1e-5 energy check and the plain fallback is faster
+    than the cheapest plain push whose rms-radius error is as small, with both
+    inference operand types."""
+    res = compare.equal_error_vp(n_eval=2_000_000, n_data=1_000_000, extra_tols=(), log=print)
+    keys = [k for k in res if k.startswith("equal_error")]
+    print(json.dumps({k: res[k] for k in keys}, indent=1))
+    for prec in ("bf16", "fp16"):
+        key = "equal_error_" + prec
+        assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
+        checked = [e for e in res["learned"] if e["precision"] == prec and e["drift_tol"] == 1e-5]
+        assert checked and checked[0]["fallback_rate"] < 0.1, checked
+
