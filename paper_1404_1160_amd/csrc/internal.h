@@ -50,7 +50,8 @@ constexpr int kMomentQuantities = 4;   // sum R^2, sum |z|^2, sum R^4, (unused)
 constexpr int kMomentCounts = 2;       // off-mesh, non-finite
 
 // Scalars of the solved field, stored on the device after each solve.
-enum FieldScalar { kQb = 0, kFieldEnergy = 1, kMeshCharge = 2, kFieldScalars = 4 };
+// kEmax: an upper bound on |E| of the CIC gather anywhere on the mesh
+enum FieldScalar { kQb = 0, kFieldEnergy = 1, kMeshCharge = 2, kEmax = 3, kFieldScalars = 4 };
 
 // Per-substep coefficients of the plain push (FP64): the midpoint phase phi
 // of the substep gives (cos phi, sin phi, h sin phi, h cos phi).

@@ -256,13 +256,13 @@ hipError_t launch_gen_labels_duffing(hipStream_t st, const float *R, const float
 // Duffing field plus E^n(R_n) / s_E, gathered as the inference kernel does.
 __global__ __launch_bounds__(256) void gen_labels_poisson_kernel(
     const float *__restrict__ zR, const float *__restrict__ zV, int64_t first, int64_t stride,
-    int64_t count, double2 rot0, MeshView m, const double *__restrict__ qb,
+    int64_t count, double2 rot0, MeshView m, const double *__restrict__ fscal,
     const double4 *__restrict__ sub, int K, float inv_sin, float c_phi, float s_phi,
     float th_scaled, float inv_sE, int scaled, float *__restrict__ X, float *__restrict__ Y)
 {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= count) return;
-    m.Qb = *qb;
+    m.Qb = fscal[kQb];
     const int64_t i = first + j * stride;
     const double zr_ = zR[i], zv_ = zV[i];
     const double zr0 = fma(rot0.x, zr_, rot0.y * zv_);
@@ -271,7 +271,10 @@ __global__ __launch_bounds__(256) void gen_labels_poisson_kernel(
     double zr = zr0, zv = zv0;
     {
         double a[1] = {zr}, b[1] = {zv};
-        push_group<1>(m, sub, K, a, b);
+        if (fma(zr, zr, zv * zv) < on_mesh_limit2(m, sub, K, fscal[kEmax]))
+            push_group<1, true>(m, sub, K, a, b);
+        else
+            push_group<1>(m, sub, K, a, b);
         zr = a[0];
         zv = b[0];
     }
@@ -303,7 +306,7 @@ hipError_t launch_gen_labels_poisson(hipStream_t st, const float *zR, const floa
     m.c = ma.nr >> 1;
     m.Qb = 0.0;   // read on the device from fscal
     gen_labels_poisson_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(
-        zR, zV, first, stride, count, rot0, m, ma.fscal + kQb, sub, K, inv_sin, c_phi, s_phi,
+        zR, zV, first, stride, count, rot0, m, (const double *)ma.fscal, sub, K, inv_sin, c_phi, s_phi,
         th_scaled, inv_sE, scaled, X, Y);
     return hipGetLastError();
 }
@@ -892,7 +895,7 @@ __global__ __launch_bounds__(256) void fallback_duffing_kernel(
 __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K, double2 er,
-    MeshView mv, const float2 *__restrict__ etab, const double *__restrict__ qb, int nr,
+    MeshView mv, const float2 *__restrict__ etab, const double *__restrict__ fscal, int nr,
     unsigned long long *__restrict__ hist, unsigned long long *__restrict__ total)
 {
     extern __shared__ __align__(16) unsigned char fb_smem[];
@@ -906,17 +909,23 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     float2 *Et = reinterpret_cast<float2 *>(fb_smem);
     for (int i = tid; i < nr; i += blockDim.x) Et[i] = etab[i];
     for (int i = tid; i <= nr; i += blockDim.x) mv.H[i] = 0ull;
-    mv.Qb = *qb;
+    mv.Qb = fscal[kQb];
     const bool staged = K <= kFallbackLdsK;
     const double4 *t = staged ? stage_table(fb_smem + fallback_table_offset(nr), sub, K) : nullptr;
+    // particles with |z|^2 < lim2 take the gather without range tests
+    const double lim2 = on_mesh_limit2(mv, sub, K, fscal[kEmax]);
     __syncthreads();
     const auto field = [&mv](double R) { return gather(mv, R); };
+    const auto field_on = [&mv](double R) { return gather_on(mv, R); };
     const auto run = [&](const double4 *tab) {
         for (unsigned i = blockIdx.x * blockDim.x + tid; i < count;
              i += gridDim.x * blockDim.x) {
             const unsigned p = queue[i];
             double zr = zR[p], zv = zV[p];
-            push_staged(tab, K, field, zr, zv);
+            if (fma(zr, zr, zv * zv) < lim2)
+                push_staged(tab, K, field_on, zr, zv);
+            else
+                push_staged(tab, K, field, zr, zv);
             const float fr = (float)zr, fv = (float)zv;
             zR[p] = fr;
             zV[p] = fv;
@@ -1017,7 +1026,7 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
                            : push_lds_bytes_for(ma.nr);
     return dispatch(fallback_poisson_kernel, dim3((unsigned)n_cu), dim3(kPushBlock), lds, st, zR, zV,
                     queue, qcount, sub, K, er, mesh_view(ma), (const float2 *)ma.etab,
-                    (const double *)(ma.fscal + kQb), ma.nr, ma.hist, total);
+                    (const double *)ma.fscal, ma.nr, ma.hist, total);
 }
 
 hipError_t setup_learned_lds(int nr)

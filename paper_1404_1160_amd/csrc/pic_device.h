@@ -49,6 +49,31 @@ __device__ __forceinline__ double gather(const MeshView &m, double R)
     return m.Qb / R;
 }
 
+// The gather of a position known to lie on the mesh: the arithmetic of
+// gather() without its range test, so the same bits for such R.  Without the
+// branch the compiler can keep several particles' table reads in flight.
+__device__ __forceinline__ double gather_on(const MeshView &m, double R)
+{
+    const double x = R * m.inv_hr;
+    const double fl = floor(x);
+    const float2 e = m.Et[(int)fl + m.c];
+    return fma(x - fl, (double)e.y, (double)e.x);
+}
+
+// A particle with |z|^2 below this value stays on the mesh at every substep
+// position of a K-substep push: R_mid = (cos, sin) . (z + a) with |a| at most
+// the sum of the Duhamel increments h |E| <= K h emax (by induction, since
+// every earlier position was on the mesh).  The margin 1e-9 covers the FP64
+// rounding of R_mid and R / h_r.  Negative when no |z| qualifies.
+__device__ __forceinline__ double on_mesh_limit2(const MeshView &m, const double4 *sub, int K,
+                                                 double emax)
+{
+    const double4 q = sub[0];
+    const double reach = (double)K * sqrt(q.z * q.z + q.w * q.w) * emax;
+    const double lim = m.half / m.inv_hr * (1.0 - 1e-9) - reach;
+    return lim > 0.0 ? lim * lim : -1.0;
+}
+
 // CIC deposit of one particle at R into the LDS histogram (skipped off-mesh):
 // weights 1 - th and th in units of 2^-32 of a particle weight.
 __device__ __forceinline__ void deposit(const MeshView &m, double R)
@@ -62,21 +87,50 @@ __device__ __forceinline__ void deposit(const MeshView &m, double R)
     }
 }
 
-template <int NP>
+// K substeps of NP particles in the frozen field; ON: every substep
+// position is known to lie on the mesh (on_mesh_limit2).  The ON loop does
+// the arithmetic of gather_on in three phases (cell positions of all NP
+// particles, their table reads, then the updates), so that the NP reads are
+// in flight together, and reads the next substep's coefficients ahead; same
+// results as the general loop.
+template <int NP, bool ON = false>
 __device__ __forceinline__ void push_group(const MeshView &m, const double4 *__restrict__ sub,
                                            int K, double (&zr)[NP], double (&zv)[NP])
 {
     double ar[NP], av[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) ar[p] = av[p] = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double4 q = sub[k];
+    if (ON) {
+        double4 q = sub[0];
+        for (int k = 0; k < K; ++k) {
+            const double4 qn = sub[k + 1 < K ? k + 1 : k];
+            double x[NP], fl[NP];
+            float2 e[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const double Rm = fma(q.x, zr[p] + ar[p], q.y * (zv[p] + av[p]));
-            const double E = gather(m, Rm);
-            ar[p] = fma(-q.z, E, ar[p]);
-            av[p] = fma(q.w, E, av[p]);
+            for (int p = 0; p < NP; ++p) {
+                x[p] = fma(q.x, zr[p] + ar[p], q.y * (zv[p] + av[p])) * m.inv_hr;
+                fl[p] = floor(x[p]);
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p) e[p] = m.Et[(int)fl[p] + m.c];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const double E = fma(x[p] - fl[p], (double)e[p].y, (double)e[p].x);
+                ar[p] = fma(-q.z, E, ar[p]);
+                av[p] = fma(q.w, E, av[p]);
+            }
+            q = qn;
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            const double4 q = sub[k];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const double Rm = fma(q.x, zr[p] + ar[p], q.y * (zv[p] + av[p]));
+                const double E = gather(m, Rm);
+                ar[p] = fma(-q.z, E, ar[p]);
+                av[p] = fma(q.w, E, av[p]);
+            }
         }
     }
 #pragma unroll
@@ -128,6 +182,23 @@ __device__ T block_exclusive_scan(T v, T *wtot)
     }
     __syncthreads();
     const T r = wtot[w] + excl;
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ T block_max(T v, T *wtot)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const T u = __shfl_xor(v, off, 64);
+        v = v < u ? u : v;
+    }
+    if (lane == 0) wtot[w] = v;
+    __syncthreads();
+    T r = wtot[0];
+    for (int i = 1; i < nw; ++i) r = r < wtot[i] ? wtot[i] : r;
     __syncthreads();
     return r;
 }

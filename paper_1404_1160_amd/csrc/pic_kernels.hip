@@ -171,7 +171,10 @@ hipError_t launch_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
 //           so P_k = int_{x_0}^{x_k} rho = w 2^-33 I_k
 //   Q_j   = (P_{c+j} - P_{c-j}) / 2 = w 2^-34 (I_{c+j} - I_{c-j})
 //   E_k   = Q_{|k-c|} / x_k  (k != c),  E_c = 0,  Qb = w 2^-34 I_nr
-// and the FP32 gather table (E_m, E_{m+1} - E_m).  Clears hist for the next
+// and the FP32 gather table (E_m, E_{m+1} - E_m), with the bound
+// emax = max |E_k| (1 + 2^-20) on the gathered field (a gather lies between
+// the table's node values, which are within 3 2^-24 max |E_k| of the FP64
+// ones).  Clears hist for the next
 // accumulation.  Node arrays live in the caller's LDS (2 (nr+1) u64): S and
 // I as u64, then E as FP64 in the storage of S.  Elementwise passes run
 // node-contiguous across threads; the scan runs over contiguous per-thread
@@ -216,6 +219,7 @@ __device__ void solve_field_block(unsigned char *smem, unsigned long long *__res
     charge = block_sum<unsigned long long>(charge, wu);   // syncs: I is complete
 
     const double q_scale = w * kFixScale * 0.25;
+    double emax = 0.0;
 #pragma unroll 1
     for (int k = tid; k < nn; k += nt) {
         double E = 0.0;
@@ -226,12 +230,15 @@ __device__ void solve_field_block(unsigned char *smem, unsigned long long *__res
         }
         Ed[k] = E;
         E64[k] = E;
+        emax = fmax(emax, fabs(E));
     }
+    __shared__ double wm[kSolveBlock / 64];
+    emax = block_max<double>(emax, wm);   // syncs: Ed is complete
     if (tid == 0) {
         fscal[kQb] = (double)I[nr] * q_scale;
         fscal[kMeshCharge] = (double)charge * w * kFixScale;
+        fscal[kEmax] = emax * (1.0 + 0x1p-20);
     }
-    __syncthreads();
 
 #pragma unroll 1
     for (int k = tid; k < nr; k += nt) {
@@ -356,6 +363,8 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
     m.c = nr >> 1;
     m.Qb = PUSH ? ma.fscal[kQb] : 0.0;
     const double2 er = endrot_tab ? endrot_tab[0] : endrot_val;
+    // particles with |z|^2 < lim2 take the gather without range tests
+    const double lim2 = PUSH ? on_mesh_limit2(m, sub, K, ma.fscal[kEmax]) : -1.0;
     __syncthreads();
 
     // Each thread takes U float4 groups (4 U particles) per iteration, with
@@ -383,12 +392,17 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
                 f32x4 fr = r4[u], fv = v4[u];
                 if (PUSH) {
                     double zr[4], zv[4];
+                    bool on = true;
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
                         zr[p] = fr[p];
                         zv[p] = fv[p];
+                        on = on && fma(zr[p], zr[p], zv[p] * zv[p]) < lim2;
                     }
-                    push_group<4>(m, sub, K, zr, zv);
+                    if (on)
+                        push_group<4, true>(m, sub, K, zr, zv);
+                    else
+                        push_group<4>(m, sub, K, zr, zv);
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
                         fr[p] = (float)zr[p];

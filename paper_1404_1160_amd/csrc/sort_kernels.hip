@@ -33,12 +33,17 @@ __device__ __forceinline__ SortLds sort_lds(unsigned char *smem, int nr)
     return s;
 }
 
-// New FP32 state and cell key of one particle after the step.
+// New FP32 state and cell key of one particle after the step (lim2: see
+// on_mesh_limit2).
 __device__ __forceinline__ void step_one(const MeshView &m, const double4 *__restrict__ sub, int K,
-                                         double2 er, float &fr, float &fv, int nr, int &key)
+                                         double lim2, double2 er, float &fr, float &fv, int nr,
+                                         int &key)
 {
     double zr[1] = {fr}, zv[1] = {fv};
-    push_group<1>(m, sub, K, zr, zv);
+    if (fma(zr[0], zr[0], zv[0] * zv[0]) < lim2)
+        push_group<1, true>(m, sub, K, zr, zv);
+    else
+        push_group<1>(m, sub, K, zr, zv);
     fr = (float)zr[0];
     fv = (float)zv[0];
     int k;
@@ -75,11 +80,12 @@ __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     m.c = nr >> 1;
     m.Qb = fscal[kQb];
     const double2 er = endrot[0];
+    const double lim2 = on_mesh_limit2(m, sub, K, fscal[kEmax]);
     __syncthreads();
 
     auto visit = [&](int64_t i, float fr, float fv) {
         int key;
-        step_one(m, sub, K, er, fr, fv, nr, key);
+        step_one(m, sub, K, lim2, er, fr, fv, nr, key);
         const unsigned slot = atomicAdd(&L.C[key], 1u);
         if (SCATTER) {
             oR[slot] = fr;
