@@ -187,23 +187,6 @@ __device__ T block_exclusive_scan(T v, T *wtot)
 }
 
 template <typename T>
-__device__ T block_max(T v, T *wtot)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const T u = __shfl_xor(v, off, 64);
-        v = v < u ? u : v;
-    }
-    if (lane == 0) wtot[w] = v;
-    __syncthreads();
-    T r = wtot[0];
-    for (int i = 1; i < nw; ++i) r = r < wtot[i] ? wtot[i] : r;
-    __syncthreads();
-    return r;
-}
-
-template <typename T>
 __device__ T block_sum(T v, T *wtot)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;

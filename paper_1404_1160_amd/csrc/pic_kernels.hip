@@ -189,7 +189,9 @@ __device__ void solve_field_block(unsigned char *smem, unsigned long long *__res
     double *Ed = reinterpret_cast<double *>(smem);
     unsigned long long *I = S + nn;
     __shared__ unsigned long long wu[kSolveBlock / 64];
+    __shared__ unsigned long long emax_bits;   // max |E_k| as FP64 bits (ordered for x >= 0)
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) emax_bits = 0ull;   // visible after the scan's barriers
     const int c = nr >> 1;
     const double rho_scale = w * kFixScale / hr;
 
@@ -232,13 +234,15 @@ __device__ void solve_field_block(unsigned char *smem, unsigned long long *__res
         E64[k] = E;
         emax = fmax(emax, fabs(E));
     }
-    __shared__ double wm[kSolveBlock / 64];
-    emax = block_max<double>(emax, wm);   // syncs: Ed is complete
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
+    if ((tid & 63) == 0) atomicMax(&emax_bits, (unsigned long long)__double_as_longlong(emax));
     if (tid == 0) {
         fscal[kQb] = (double)I[nr] * q_scale;
         fscal[kMeshCharge] = (double)charge * w * kFixScale;
-        fscal[kEmax] = emax * (1.0 + 0x1p-20);
     }
+    __syncthreads();
+    if (tid == 0) fscal[kEmax] = __longlong_as_double((long long)emax_bits) * (1.0 + 0x1p-20);
 
 #pragma unroll 1
     for (int k = tid; k < nr; k += nt) {

@@ -33,14 +33,17 @@ __device__ __forceinline__ SortLds sort_lds(unsigned char *smem, int nr)
     return s;
 }
 
-// New FP32 state and cell key of one particle after the step (lim2: see
-// on_mesh_limit2).
+// New FP32 state and cell key of one particle after the step.  FAST: a
+// particle with |z|^2 < lim2 (see on_mesh_limit2) takes the gather without
+// range tests; it pays only for several substeps, so the launchers choose it
+// for K > 1.
+template <bool FAST>
 __device__ __forceinline__ void step_one(const MeshView &m, const double4 *__restrict__ sub, int K,
                                          double lim2, double2 er, float &fr, float &fv, int nr,
                                          int &key)
 {
     double zr[1] = {fr}, zv[1] = {fv};
-    if (fma(zr[0], zr[0], zv[0] * zv[0]) < lim2)
+    if (FAST && fma(zr[0], zr[0], zv[0] * zv[0]) < lim2)
         push_group<1, true>(m, sub, K, zr, zv);
     else
         push_group<1>(m, sub, K, zr, zv);
@@ -57,7 +60,7 @@ __device__ __forceinline__ void step_one(const MeshView &m, const double4 *__res
 // Both passes visit the particles in the same order (float4 groups with a
 // grid stride, then the ragged tail), so that they assign each particle to
 // the same workgroup.
-template <bool SCATTER>
+template <bool SCATTER, bool FAST>
 __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     const float *__restrict__ zR, const float *__restrict__ zV, const unsigned *__restrict__ ids,
     int64_t n, const double4 *__restrict__ sub, const double2 *__restrict__ endrot, int K,
@@ -80,12 +83,12 @@ __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     m.c = nr >> 1;
     m.Qb = fscal[kQb];
     const double2 er = endrot[0];
-    const double lim2 = on_mesh_limit2(m, sub, K, fscal[kEmax]);
+    const double lim2 = FAST ? on_mesh_limit2(m, sub, K, fscal[kEmax]) : -1.0;
     __syncthreads();
 
     auto visit = [&](int64_t i, float fr, float fv) {
         int key;
-        step_one(m, sub, K, lim2, er, fr, fv, nr, key);
+        step_one<FAST>(m, sub, K, lim2, er, fr, fv, nr, key);
         const unsigned slot = atomicAdd(&L.C[key], 1u);
         if (SCATTER) {
             oR[slot] = fr;
@@ -269,18 +272,23 @@ static size_t sort_lds_bytes(int nr)
 hipError_t setup_sort_lds(int nr)
 {
     const int lds = (int)sort_lds_bytes(nr);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sort_pass_kernel<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sort_pass_kernel<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    for (const void *f : {reinterpret_cast<const void *>(&sort_pass_kernel<false, false>),
+                          reinterpret_cast<const void *>(&sort_pass_kernel<false, true>),
+                          reinterpret_cast<const void *>(&sort_pass_kernel<true, false>),
+                          reinterpret_cast<const void *>(&sort_pass_kernel<true, true>)}) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_sort_count(hipStream_t st, const SortArgs &a, int grid)
 {
-    return dispatch(sort_pass_kernel<false>, dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st,
-                    a.zR, a.zV, a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr,
-                    a.counts, (const unsigned *)nullptr, (float *)nullptr, (float *)nullptr,
+    return dispatch(a.K > 1 ? sort_pass_kernel<false, true> : sort_pass_kernel<false, false>,
+                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st, a.zR, a.zV, a.ids,
+                    a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
+                    (const unsigned *)nullptr, (float *)nullptr, (float *)nullptr,
                     (unsigned *)nullptr);
 }
 
@@ -297,9 +305,10 @@ hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid)
 
 hipError_t launch_sort_scatter(hipStream_t st, const SortArgs &a, int grid)
 {
-    return dispatch(sort_pass_kernel<true>, dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st,
-                    a.zR, a.zV, a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr,
-                    a.counts, (const unsigned *)a.starts, a.oR, a.oV, a.oid);
+    return dispatch(a.K > 1 ? sort_pass_kernel<true, true> : sort_pass_kernel<true, false>,
+                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st, a.zR, a.zV, a.ids,
+                    a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
+                    (const unsigned *)a.starts, a.oR, a.oV, a.oid);
 }
 
 hipError_t launch_sort_reduce(hipStream_t st, const SortArgs &a, const float *zR, const float *zV,
