@@ -848,6 +848,12 @@ __device__ __forceinline__ void push_staged(const double4 *__restrict__ t, int K
     zv += av;
 }
 
+// Fallback threads take the queue entries i = b + G (t + T j), j = 0, 1, ...
+// (b the workgroup, t the thread, G workgroups of T threads): entry i goes to
+// workgroup i mod G, so that a short queue still spreads over every CU (each
+// wave of a fallback runs K dependent substeps, and waves that share a SIMD
+// wait on each other).
+
 // Copies the K substep coefficients into LDS (K <= kFallbackLdsK).
 __device__ __forceinline__ double4 *stage_table(unsigned char *smem, const double4 *sub, int K)
 {
@@ -867,11 +873,11 @@ __global__ __launch_bounds__(256) void fallback_duffing_kernel(
     extern __shared__ __align__(16) unsigned char fbd_smem[];
     const unsigned count = *qcount;
     if (blockIdx.x == 0 && threadIdx.x == 0) *total += count;
-    if ((unsigned)blockIdx.x * blockDim.x >= count) return;   // uniform over the workgroup
+    if ((unsigned)blockIdx.x >= count) return;   // uniform over the workgroup
     const auto duffing = [](double R) { return -(R * R) * R; };
     const auto run = [&](const double4 *t) {
-        for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
-             i += gridDim.x * blockDim.x) {
+        for (uint64_t i = blockIdx.x + (uint64_t)threadIdx.x * gridDim.x; i < count;
+             i += (uint64_t)blockDim.x * gridDim.x) {
             const unsigned p = queue[i];
             double zr = zR[p], zv = zV[p];
             push_staged(t, K, duffing, zr, zv);
@@ -902,7 +908,7 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     const unsigned count = *qcount;
     if (blockIdx.x == 0 && threadIdx.x == 0) *total += count;
     // uniform over the workgroup: an empty workgroup has nothing to deposit
-    if ((unsigned)blockIdx.x * blockDim.x >= count) return;
+    if ((unsigned)blockIdx.x >= count) return;
     const int tid = threadIdx.x;
     mv.Et = reinterpret_cast<float2 *>(fb_smem);
     mv.H = reinterpret_cast<unsigned long long *>(fb_smem + (size_t)nr * sizeof(float2));
@@ -918,8 +924,8 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     const auto field = [&mv](double R) { return gather(mv, R); };
     const auto field_on = [&mv](double R) { return gather_on(mv, R); };
     const auto run = [&](const double4 *tab) {
-        for (unsigned i = blockIdx.x * blockDim.x + tid; i < count;
-             i += gridDim.x * blockDim.x) {
+        for (uint64_t i = blockIdx.x + (uint64_t)threadIdx.x * gridDim.x; i < count;
+             i += (uint64_t)blockDim.x * gridDim.x) {
             const unsigned p = queue[i];
             double zr = zR[p], zv = zV[p];
             if (fma(zr, zr, zv * zv) < lim2)
