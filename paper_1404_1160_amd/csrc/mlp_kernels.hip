@@ -755,11 +755,13 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const float kappa = fmaf(net.sig_k, o1 + net.b3_1, net.mu_k);
         double sc;
         if (net.scaled) {
-            // outputs are (a delta, a kappa); nothing moves at a = 0
-            const double a = sqrt(fma(zr, zr, zv * zv));
-            const double inv_a = a > 0.0 ? 1.0 / a : 0.0;
-            delta = (float)((double)delta * inv_a);
-            sc = fma((double)kappa, inv_a, 1.0);
+            // outputs are (a delta, a kappa), divided by a = |z| in FP32 (both
+            // are FP32 values; 1/a to ~1 ulp costs nothing next to them).
+            // Nothing moves below a = 2^-50, where the scaled map is void.
+            const double a2 = fma(zr, zr, zv * zv);
+            const float inv_a = a2 > 0x1p-100 ? rsqrtf((float)a2) : 0.f;
+            delta *= inv_a;
+            sc = 1.0 + (double)(kappa * inv_a);
         } else {
             sc = 1.0 + (double)kappa;
         }
