@@ -367,8 +367,13 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
     m.c = nr >> 1;
     m.Qb = PUSH ? ma.fscal[kQb] : 0.0;
     const double2 er = endrot_tab ? endrot_tab[0] : endrot_val;
-    // particles with |z|^2 < lim2 take the gather without range tests
-    const double lim2 = PUSH ? on_mesh_limit2(m, sub, K, ma.fscal[kEmax]) : -1.0;
+    // particles with |z|^2 < lim2 take the gather without range tests.  Only
+    // the two-group form, which the launcher takes for long state streams:
+    // its table reads in flight together need many resident waves to hide
+    // their latency, and with the one-group form's short grids (under two
+    // workgroups per CU) the branch-free loop measured 20-30 % slower.
+    constexpr bool kFast = PUSH && U == 2;
+    const double lim2 = kFast ? on_mesh_limit2(m, sub, K, ma.fscal[kEmax]) : -1.0;
     __syncthreads();
 
     // Each thread takes U float4 groups (4 U particles) per iteration, with
@@ -403,7 +408,7 @@ __global__ __launch_bounds__(kPushBlock) void push_poisson_kernel(
                         zv[p] = fv[p];
                         on = on && fma(zr[p], zr[p], zv[p] * zv[p]) < lim2;
                     }
-                    if (on)
+                    if (kFast && on)
                         push_group<4, true>(m, sub, K, zr, zv);
                     else
                         push_group<4>(m, sub, K, zr, zv);
