@@ -96,7 +96,9 @@ __device__ __forceinline__ f16x2 act_pair(float a, float b)
 //         MFMA each);
 //   BF16: gfx950 has no packed BF16 arithmetic, so the activations run in
 //         FP32 and are rounded to BF16; W2 and W3 as split BF16 (hi + lo, two
-//         MFMAs, ~16 bits).
+//         MFMAs, ~16 bits), and the activations into layers 2 and 3 as
+//         hi + lo too (a third MFMA, weights hi times activations lo): their
+//         8-bit rounding was the largest error term.
 // Both take the pre-activations as u = z / 64 (see act_pair).
 template <typename T>
 struct InferOp;
@@ -105,6 +107,7 @@ template <>
 struct InferOp<_Float16> {
     typedef f16x8 vec;
     static constexpr bool kSplitW = false;
+    static constexpr bool kSplitA3 = false;   // activations into layers 2, 3 as hi + lo
     static __device__ __forceinline__ vec load(uint4 q) { return __builtin_bit_cast(vec, q); }
     static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c)
     {
@@ -128,6 +131,7 @@ template <>
 struct InferOp<__bf16> {
     typedef bf16x8 vec;
     static constexpr bool kSplitW = true;
+    static constexpr bool kSplitA3 = true;
     static __device__ __forceinline__ vec load(uint4 q) { return __builtin_bit_cast(vec, q); }
     static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c)
     {
@@ -144,6 +148,19 @@ struct InferOp<__bf16> {
                                 u1 * __frsqrt_rn(fmaf(u1, u1, 0x1p-12f)));
         }
         return __builtin_bit_cast(vec, h);
+    }
+    // The same activations as hi (the bits of act) and lo = bf16(a - hi).
+    static __device__ __forceinline__ vec act_split(const f32x16 &acc, int q0, vec &lo)
+    {
+        float a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float u = acc[q0 + i];
+            a[i] = u * __frsqrt_rn(fmaf(u, u, 0x1p-12f));
+        }
+        vec hi;
+        to_bf16x8<true>(a, hi, lo);
+        return hi;
     }
 };
 
@@ -734,21 +751,34 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const vec b = Op::act(kk < 2 ? u0 : u1, 8 * (kk & 1));
+            vec b, lo;
+            if constexpr (Op::kSplitA3)
+                b = Op::act_split(kk < 2 ? u0 : u1, 8 * (kk & 1), lo);
+            else
+                b = Op::act(kk < 2 ? u0 : u1, 8 * (kk & 1));
 #pragma unroll
             for (int w = 0; w < kW; ++w) {
                 acc0 = Op::mma(Op::load(sW2[(w * 8 + kk) * 64 + lane]), b, acc0);
                 acc1 = Op::mma(Op::load(sW2[(w * 8 + 4 + kk) * 64 + lane]), b, acc1);
             }
+            if constexpr (Op::kSplitA3) {
+                acc0 = Op::mma(Op::load(sW2[kk * 64 + lane]), lo, acc0);
+                acc1 = Op::mma(Op::load(sW2[(4 + kk) * 64 + lane]), lo, acc1);
+            }
         }
-        // layer 3
+        // layer 3 (BF16: activations hi + lo as in layer 2)
         f32x16 acc3 = {};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const vec b = Op::act(kk < 2 ? acc0 : acc1, 8 * (kk & 1));
+            vec b, lo;
+            if constexpr (Op::kSplitA3)
+                b = Op::act_split(kk < 2 ? acc0 : acc1, 8 * (kk & 1), lo);
+            else
+                b = Op::act(kk < 2 ? acc0 : acc1, 8 * (kk & 1));
 #pragma unroll
             for (int w = 0; w < kW; ++w)
                 acc3 = Op::mma(Op::load(sW3[(w * 4 + kk) * 64 + lane]), b, acc3);
+            if constexpr (Op::kSplitA3) acc3 = Op::mma(Op::load(sW3[kk * 64 + lane]), lo, acc3);
         }
         const float o0 = acc3[0], o1 = acc3[1];
         float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);

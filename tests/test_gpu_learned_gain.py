@@ -71,10 +71,10 @@ def test_learned_beats_plain_at_equal_error():
     res = compare.equal_error(n_train=10_000_000, n_eval=2_000_000, log=print)
     keys = [k for k in res if k.startswith("equal_error")]
     print(json.dumps({k: res[k] for k in keys}, indent=1))
-    # FP16 inference, the closer of the two operand types to the FP64 network.
-    # (BF16's run error, ~1e-4, sits at that of the plain push at K = 100, so
-    # its equal-error point falls on either side of K = 100 from one
-    # evaluation beam to the next; it is reported, not asserted.)
+    # FP16 inference, the fast operand type.  (BF16 with split activations
+    # evaluates the network as closely, at ~0.6 of FP16's rate: its gains,
+    # ~1.1-1.2 at 1e7 particles, are too close to 1 at this size to assert;
+    # they are reported.)
     for key in ("equal_error_fp16", "equal_error_no_check_fp16"):
         assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
 

@@ -362,13 +362,21 @@ def test_invalid_step_arguments():
 
 # ------------------------------------------------------------------ at full size
 
-def full_size_parity(n, nr, eps, dt, K, n_steps, n_sample, seed):
+def full_size_parity(n, nr, eps, dt, K, n_steps, n_sample, seed, edge=False):
     """Per-particle parity at full size: the oracle runs the whole seeded beam
     itself (its own deposit, field and push of every particle, step after
     step, from its own previous state), and a sample of particles (the first
     and the last n_sample/2, so the ragged tail is included) is compared with
-    the GPU run after every step, with the run's rms radius and energy."""
+    the GPU run after every step, with the run's rms radius and energy.
+    edge: the first particles are placed at radii around the mesh edge, so
+    that their wave mixes particles that provably stay on the mesh with ones
+    that may leave it (two gather paths in one wave)."""
     R0, V0, w = synth.gaussian_truncated(n, seed=seed)
+    if edge:
+        radii = np.array([4.90, 4.95, 4.98, 4.995, 5.0, 5.01, 5.05, 5.2, 3.0, 0.5])
+        ang = np.linspace(0.1, 6.0, radii.size)
+        R0[:radii.size] = radii * np.cos(ang)
+        V0[:radii.size] = radii * np.sin(ang)
     half = n_sample // 2
     ranges = [(0, half), (n - half, half)]
     idx = np.concatenate([np.arange(a, a + c) for a, c in ranges])
@@ -398,6 +406,13 @@ def full_size_parity(n, nr, eps, dt, K, n_steps, n_sample, seed):
 def test_full_size_parity_vp_1e6():
     """N_p = 1e6, N_r = 256, eps = 0.01, dt = 0.05."""
     full_size_parity(1_000_000, 256, 0.01, 0.05, 4, 5, 20000, seed=12)
+
+
+def test_full_size_parity_vp_8e6_substeps():
+    """N_p = 8e6 (long enough for the push's two-group form and its gather
+    without range tests), N_r = 4096, eps = 1e-3, dt = 0.05, K = 16, with
+    particles around the mesh edge in the first wave."""
+    full_size_parity(8_000_000, 4096, 1e-3, 0.05, 16, 3, 20000, seed=14, edge=True)
 
 
 def test_full_size_parity_vp_1e8():
