@@ -881,10 +881,19 @@ __device__ __forceinline__ void push_staged(const double4 *__restrict__ t, int K
 }
 
 // Fallback threads take the queue entries i = b + G (t + T j), j = 0, 1, ...
-// (b the workgroup, t the thread, G workgroups of T threads): entry i goes to
+// (b the workgroup, t the thread, T threads per workgroup): entry i goes to
 // workgroup i mod G, so that a short queue still spreads over every CU (each
 // wave of a fallback runs K dependent substeps, and waves that share a SIMD
-// wait on each other).
+// wait on each other).  G is at least min_groups (one per CU) and otherwise
+// the workgroups the queue fills, up to the grid: each workgroup that takes
+// entries first stages the coefficient table, so a short queue wakes no more
+// of them than it needs.
+__device__ __forceinline__ unsigned fallback_groups(unsigned count, unsigned min_groups)
+{
+    const uint64_t need = ((uint64_t)count + blockDim.x - 1) / blockDim.x;
+    const uint64_t g = need > min_groups ? need : min_groups;
+    return g < gridDim.x ? (unsigned)g : gridDim.x;
+}
 
 // Copies the K substep coefficients into LDS (K <= kFallbackLdsK).
 __device__ __forceinline__ double4 *stage_table(unsigned char *smem, const double4 *sub, int K)
@@ -900,16 +909,17 @@ __device__ __forceinline__ double4 *stage_table(unsigned char *smem, const doubl
 __global__ __launch_bounds__(256) void fallback_duffing_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K,
-    unsigned long long *__restrict__ total)
+    unsigned long long *__restrict__ total, unsigned min_groups)
 {
     extern __shared__ __align__(16) unsigned char fbd_smem[];
     const unsigned count = *qcount;
     if (blockIdx.x == 0 && threadIdx.x == 0) *total += count;
-    if ((unsigned)blockIdx.x >= count) return;   // uniform over the workgroup
+    const unsigned G = fallback_groups(count, min_groups);
+    if ((unsigned)blockIdx.x >= G || (unsigned)blockIdx.x >= count) return;   // uniform
     const auto duffing = [](double R) { return -(R * R) * R; };
     const auto run = [&](const double4 *t) {
-        for (uint64_t i = blockIdx.x + (uint64_t)threadIdx.x * gridDim.x; i < count;
-             i += (uint64_t)blockDim.x * gridDim.x) {
+        for (uint64_t i = blockIdx.x + (uint64_t)threadIdx.x * G; i < count;
+             i += (uint64_t)blockDim.x * G) {
             const unsigned p = queue[i];
             double zr = zR[p], zv = zV[p];
             push_staged(t, K, duffing, zr, zv);
@@ -934,13 +944,15 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K, double2 er,
     MeshView mv, const float2 *__restrict__ etab, const double *__restrict__ fscal, int nr,
-    unsigned long long *__restrict__ hist, unsigned long long *__restrict__ total)
+    unsigned long long *__restrict__ hist, unsigned long long *__restrict__ total,
+    unsigned min_groups)
 {
     extern __shared__ __align__(16) unsigned char fb_smem[];
     const unsigned count = *qcount;
     if (blockIdx.x == 0 && threadIdx.x == 0) *total += count;
     // uniform over the workgroup: an empty workgroup has nothing to deposit
-    if ((unsigned)blockIdx.x >= count) return;
+    const unsigned G = fallback_groups(count, min_groups);
+    if ((unsigned)blockIdx.x >= G || (unsigned)blockIdx.x >= count) return;
     const int tid = threadIdx.x;
     mv.Et = reinterpret_cast<float2 *>(fb_smem);
     mv.H = reinterpret_cast<unsigned long long *>(fb_smem + (size_t)nr * sizeof(float2));
@@ -956,8 +968,8 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     const auto field = [&mv](double R) { return gather(mv, R); };
     const auto field_on = [&mv](double R) { return gather_on(mv, R); };
     const auto run = [&](const double4 *tab) {
-        for (uint64_t i = blockIdx.x + (uint64_t)threadIdx.x * gridDim.x; i < count;
-             i += (uint64_t)blockDim.x * gridDim.x) {
+        for (uint64_t i = blockIdx.x + (uint64_t)threadIdx.x * G; i < count;
+             i += (uint64_t)blockDim.x * G) {
             const unsigned p = queue[i];
             double zr = zR[p], zv = zV[p];
             if (fma(zr, zr, zv * zv) < lim2)
@@ -1052,7 +1064,7 @@ hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const u
 {
     const size_t lds = K <= kFallbackLdsK ? (size_t)K * sizeof(double4) : 0;
     return dispatch(fallback_duffing_kernel, dim3((unsigned)n_cu * 8), dim3(256), lds, st, zR, zV,
-                    queue, qcount, sub, K, total);
+                    queue, qcount, sub, K, total, (unsigned)n_cu);
 }
 
 hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const unsigned *queue,
@@ -1064,7 +1076,7 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
                            : push_lds_bytes_for(ma.nr);
     return dispatch(fallback_poisson_kernel, dim3((unsigned)n_cu), dim3(kPushBlock), lds, st, zR, zV,
                     queue, qcount, sub, K, er, mesh_view(ma), (const float2 *)ma.etab,
-                    (const double *)ma.fscal, ma.nr, ma.hist, total);
+                    (const double *)ma.fscal, ma.nr, ma.hist, total, (unsigned)n_cu);
 }
 
 hipError_t setup_learned_lds(int nr)
