@@ -64,11 +64,13 @@ def test_equal_error_comparison():
 
 def test_learned_beats_plain_at_equal_error():
     """At the at-scale Duffing workload (eps = 1e-3, dt = 0.05, R, V ~ N(0, 1.5),
-    200 steps, network trained on 1e7 fine-push labels; 2e6 evaluation
+    200 steps, network trained on 1e7 fine-push labels; 4e6 evaluation
     particles here) the learned push is faster than the cheapest plain push
     whose rms-radius error is as small, with FP16 inference, with the 1e-5
-    energy check and without it."""
-    res = compare.equal_error(n_train=10_000_000, n_eval=2_000_000, log=print)
+    energy check and without it.  (The fallback's latency is fixed per step,
+    so the checked gain grows with the particle count: 1.18 at 2e6, 1.75 at
+    1e7.)"""
+    res = compare.equal_error(n_train=10_000_000, n_eval=4_000_000, log=print)
     keys = [k for k in res if k.startswith("equal_error")]
     print(json.dumps({k: res[k] for k in keys}, indent=1))
     # FP16 inference, the fast operand type.  (BF16 with split activations
