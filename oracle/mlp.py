@@ -31,12 +31,6 @@ Check: the frozen-field energy H^n(y) = (R^2 + V^2)/(2 eps) + P(R), P = R^4/4
 (Duffing) or the mesh potential Psi^n (Poisson), must satisfy
 |H^n(y_{n+1}) - H^n(y_n)| <= tol |H^n(y_n)|; particles that fail take the
 plain K_fb-substep push instead.
-Energy shell: the exact frozen-field step keeps H^n, so a prediction y' that
-passes is moved radially onto the shell of y_n at its own position,
-y_{n+1} = s y' with s^2 = 2 eps (H^n(y_n) - P(R')) / |y'|^2 (where that is
-positive; otherwise y' is kept).  The network's small per-step energy
-errors share a sign and would add up over a long run; the check still
-judges the prediction y' itself.
 
 Parity unpinned: nothing (forward/backward pinned by finite differences and
 the linear limit, Adam by its closed-form first step, the output map by the
@@ -198,40 +192,17 @@ def energy(R, V, eps, potential):
     return (R * R + V * V) / (2.0 * eps) + potential(R)
 
 
-def energy_shell(R, V, R1, V1, eps, potential):
-    """y' = (R1, V1) scaled radially onto the frozen-field energy shell of
-    y_n = (R, V) at the potential of y' itself: s^2 = 2 eps (H^n(y_n) -
-    P(R1)) / |y'|^2; y' unchanged where that is not positive."""
-    a2 = 2.0 * eps * (energy(R, V, eps, potential) - potential(R1))
-    n2 = R1 * R1 + V1 * V1
-    ok = (a2 > 0.0) & (n2 > 0.0)
-    s = np.ones_like(n2)
-    s[ok] = np.sqrt(a2[ok] / n2[ok])
-    return s * R1, s * V1
-
-
-def learned_map(p, R, V, dt, eps, norm, potential, Egather=None):
-    """The network's step without the check: the polar map of its
-    prediction, moved onto the energy shell."""
-    delta, kappa = predict(p, R, V, dt, eps, norm, Egather)
-    R1, V1 = apply_polar(R, V, dt, eps, delta, kappa, scaled=norm.out_map == 1)
-    return energy_shell(R, V, R1, V1, eps, potential)
-
-
 def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=None):
     """One learned step with energy check and plain fallback.
 
     potential(R): the frozen-field potential P of H^n; plain_push(R, V): the
-    plain step used for particles that fail the check.  The check judges the
-    network's prediction; the particles that pass are moved onto the energy
-    shell.  Returns (R1, V1, fell_back[bool], ratio = |dH|/|H| of the
-    prediction)."""
+    plain step used for particles that fail the check.  Returns
+    (R1, V1, fell_back[bool], ratio = |dH|/|H|)."""
     delta, kappa = predict(p, R, V, dt, eps, norm, Egather)
     R1, V1 = apply_polar(R, V, dt, eps, delta, kappa, scaled=norm.out_map == 1)
     H0 = energy(R, V, eps, potential)
     H1 = energy(R1, V1, eps, potential)
     ratio = np.abs(H1 - H0) / np.abs(H0)
-    R1, V1 = energy_shell(R, V, R1, V1, eps, potential)
     fb = ~(ratio <= tol)
     if np.any(fb):
         Rf, Vf = plain_push(R[fb], V[fb])

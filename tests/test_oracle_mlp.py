@@ -141,8 +141,7 @@ def _duffing_fallback(dt, eps, K):
 
 def test_learned_step_fallback_limits():
     """tol = 0: every particle falls back and the step equals the plain push;
-    tol = inf: none does and the step equals the network's map (the polar
-    map of its prediction on the energy shell)."""
+    tol = inf: none does and the step equals the network's polar map."""
     R, V, _ = synth.gaussian(300, seed=6, sigma=1.5)
     dt, eps = 0.05, 1e-3
     p = synth.mlp_init(5, 64, 2, seed=7).astype(np.float64)
@@ -153,7 +152,8 @@ def test_learned_step_fallback_limits():
     assert fb.all() and np.array_equal(R0, Rp) and np.array_equal(V0, Vp)
     R1, V1, fb, _ = mlp.learned_step(p, R, V, dt, eps, norm, pot, _duffing_fallback(dt, eps, 40),
                                      math.inf)
-    Rq, Vq = mlp.learned_map(p, R, V, dt, eps, norm, pot)
+    d, k = mlp.predict(p, R, V, dt, eps, norm)
+    Rq, Vq = mlp.apply_polar(R, V, dt, eps, d, k)
     assert not fb.any() and np.array_equal(R1, Rq) and np.array_equal(V1, Vq)
     # a NaN weight makes every prediction fail the check (NaN <= tol is false)
     p_bad = p.copy()
@@ -179,40 +179,3 @@ def test_fine_labels_match_exact_step():
     assert np.median(ed) < 5e-7 and np.percentile(ed, 99) < 1e-5 and ed.max() < 5e-5, (
         np.median(ed), ed.max())
     assert np.max(np.abs(k - kx)) < 5e-6
-
-
-def test_energy_shell_projection():
-    """The shell projection, pinned by what it must do: with no potential it
-    keeps |y| exactly (the map becomes a pure rotation by the predicted
-    phase); with the Duffing potential the projected point's energy differs
-    from H^n(y_n) by exactly the change of P between the prediction and the
-    projected point (the shell is taken at the prediction's potential), which
-    is much smaller than the prediction's own energy error; it leaves the
-    direction of the prediction unchanged, and a prediction with no shell
-    (2 eps (H - P(R')) <= 0) unchanged."""
-    rng = np.random.default_rng(21)
-    R, V = rng.normal(0, 1.5, 500), rng.normal(0, 1.5, 500)
-    eps = 1e-3
-    ang = rng.uniform(0, 2 * np.pi, 500)
-    scale = 1.0 + rng.normal(0, 1e-4, 500)
-    R1 = scale * (np.cos(ang) * R + np.sin(ang) * V)
-    V1 = scale * (-np.sin(ang) * R + np.cos(ang) * V)
-    zero = lambda r: np.zeros_like(r)
-    Rp, Vp = mlp.energy_shell(R, V, R1, V1, eps, zero)
-    assert np.allclose(np.hypot(Rp, Vp), np.hypot(R, V), rtol=1e-14, atol=0)
-    assert np.allclose(np.arctan2(Vp, Rp), np.arctan2(V1, R1), rtol=0, atol=1e-12)
-    pot = lambda r: r ** 4 / 4
-    Rp, Vp = mlp.energy_shell(R, V, R1, V1, eps, pot)
-    H0 = mlp.energy(R, V, eps, pot)
-    before = np.abs(mlp.energy(R1, V1, eps, pot) - H0)
-    after = mlp.energy(Rp, Vp, eps, pot) - H0
-    assert np.allclose(after, pot(Rp) - pot(R1), rtol=0, atol=1e-11 * np.abs(H0).max())
-    big_err = before > 1e-6 * np.abs(H0)
-    assert big_err.mean() > 0.5 and np.all(np.abs(after[big_err]) < 0.1 * before[big_err])
-    steep = lambda r: 1e9 * r * r
-    none = mlp.energy(R, V, eps, steep) - steep(R1) <= 0
-    Rn, Vn = mlp.energy_shell(R, V, R1, V1, eps, steep)
-    assert 0 < none.mean() < 1
-    assert np.array_equal(Rn[none], R1[none]) and np.array_equal(Vn[none], V1[none])
-    assert not np.any(Rn[~none] == R1[~none])
-
