@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--comparison-steps", type=int, default=50)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the plain-vs-learned equal-error comparison")
+    ap.add_argument("--long-time", action="store_true",
+                    help="add the long-time learned Vlasov-Poisson run (1e7 particles, "
+                         "1e4 steps; a few minutes)")
     ap.add_argument("--no-paper-schemes", action="store_true",
                     help="skip the reference-RK4 / improved-ETD measurement")
     ap.add_argument("--learned-train", type=int, default=10_000_000)
@@ -302,6 +305,11 @@ def main():
         print("bench: learned-vs-plain comparison, Vlasov-Poisson", file=sys.stderr, flush=True)
         line["learned_vs_plain_vp"] = compare.equal_error_vp(
             n_eval=args.learned_eval, n_data=args.learned_vp_data,
+            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    if args.long_time:
+        from paper_1404_1160_amd import compare
+        print("bench: long-time learned Vlasov-Poisson run", file=sys.stderr, flush=True)
+        line["long_time_vp"] = compare.long_time_vp(
             log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if not args.no_paper_schemes:
         from paper_1404_1160_amd import compare

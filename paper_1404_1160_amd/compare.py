@@ -305,6 +305,94 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     return out
 
 
+def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=1600,
+                 plain_Ks=(100, 200), tol=1e-5, K_fb=400, n_data=1_000_000, epochs=40,
+                 precisions=(EP_MLP_FP16, EP_MLP_BF16), seed_eval=17, log=None):
+    """Long-time run of the Vlasov-Poisson beam (eps = 1e-3, dt = 0.1, to
+    t = steps dt): the learned push with the drift check against plain runs
+    and a plain reference at K_ref, all from the same particles.  Every
+    `every` steps: the rms radius (its relative error against the
+    reference), the total energy (its drift from t = 0) and, for the learned
+    runs, the fallback rate of the interval.  The network is trained on
+    samples collected over the same time span from a separate beam.  Rates
+    are timed on runs of their own, without the moment calls."""
+    def say(msg):
+        if log:
+            log(msg)
+
+    R0, V0, w = synth.gaussian_truncated(n_eval, seed=seed_eval)
+    out = {"workload": {"field": "poisson", "eps": VP_EPS, "dt": VP_DT, "n_cells": nr,
+                        "n_eval": n_eval, "steps": steps, "t_end": steps * VP_DT,
+                        "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb}}
+
+    def history(sim, learned):
+        sim.set_particles(R0, V0, w)
+        m0 = sim.moments(VP_EPS, EP_FIELD_POISSON)
+        rms, energy, fb = [m0["rms_radius"]], [m0["energy"]], []
+        f_prev = m0["n_fallback"]
+        for _ in range(steps // every):
+            sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, every)
+            m = sim.moments(VP_EPS, EP_FIELD_POISSON)
+            rms.append(m["rms_radius"])
+            energy.append(m["energy"])
+            if learned:
+                fb.append((m["n_fallback"] - f_prev) / (n_eval * every))
+                f_prev = m["n_fallback"]
+        return np.array(rms), np.array(energy), np.array(fb)
+
+    def rate(sim, n_steps):
+        sim.set_particles(R0, V0, w)
+        sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, 1)
+        sim.set_particles(R0, V0, w)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, n_steps)
+        sim.sync()
+        return n_eval * n_steps / (time.perf_counter() - t0)
+
+    with Sim(n_eval, n_cells=nr, substeps=K_ref) as ref:
+        rms_ref, e_ref, _ = history(ref, False)
+    say("long-time reference K=%d done" % K_ref)
+
+    def summary(rms, energy):
+        err = np.abs(rms - rms_ref) / rms_ref
+        drift = np.abs(energy - energy[0]) / abs(energy[0])
+        return {"rms_err_max": float(err.max()), "rms_err_final": float(err[-1]),
+                "energy_drift_max": float(drift.max()), "energy_drift_final": float(drift[-1])}
+
+    out["reference"] = {"K": K_ref, **{k: v for k, v in summary(rms_ref, e_ref).items()
+                                      if k.startswith("energy")}}
+    plain = []
+    for K in plain_Ks:
+        with Sim(n_eval, n_cells=nr, substeps=K) as sim:
+            rms, energy, _ = history(sim, False)
+            entry = {"K": K, "particle_steps_per_s": rate(sim, min(steps, 200)),
+                     **summary(rms, energy)}
+        plain.append(entry)
+        say("long-time plain K=%d: %s" % (K, entry))
+    out["plain"] = plain
+    p, norm, rep, total = train_vp(n_data, steps, nr=nr, collect_every=max(1, steps // 20),
+                                   epochs=epochs)
+    out["train"] = {"n_samples": total, "loss_first": rep["loss_first"],
+                    "loss_last": rep["loss_last"]}
+    learned = []
+    with Sim(n_eval, n_cells=nr, substeps=1) as sim:
+        capi.ep_mlp_set_weights(sim.ctx, p, norm)
+        capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, tol, K_fb)
+        for prec in precisions:
+            capi.ep_mlp_set_precision(sim.ctx, prec)
+            rms, energy, fb = history(sim, True)
+            entry = {"precision": PREC_NAMES[prec], "drift_tol": tol,
+                     "particle_steps_per_s": rate(sim, min(steps, 200)),
+                     **summary(rms, energy),
+                     "fallback_rate_first": float(fb[0]), "fallback_rate_last": float(fb[-1]),
+                     "fallback_rate_mean": float(fb.mean())}
+            learned.append(entry)
+            say("long-time learned %s: %s" % (PREC_NAMES[prec], entry))
+    out["learned"] = learned
+    return out
+
+
 # ------------------------------------------------------------ the paper's own schemes
 
 def _run_scheme(R0, V0, w, field, mode, dt, eps, steps, nr=VP_NR, substeps=1, h_fine=0.0,
