@@ -499,6 +499,64 @@ def paper_schemes(n_duffing=1_000_000, n_vp=100_000, eps=1e-3, dt=0.5, steps_duf
     return out
 
 
+def paper_schemes_long(n=100_000, eps_values=(1e-3, 1e-4), dt=0.5, t_end=90.0,
+                       checkpoints=(10.0, 30.0, 60.0, 90.0), plain_K=400, ref_refine=4,
+                       log=None):
+    """The paper's schemes over its long runs in the given (Duffing) field:
+    the paper's beam (eq. 2.7), dt = 0.5 to t = 90, eps = 1e-3 and 1e-4.  At
+    each checkpoint time every scheme's particles are compared with the
+    reference RK4 (step 2 pi eps / (100 ref_refine)): the median particle
+    error and the modulus-distribution error (mean distance between the
+    sorted moduli |y|, relative to their mean).  Rates are whole-run
+    particle-steps/s."""
+    def say(msg):
+        if log:
+            log(msg)
+
+    R0, V0, w = synth.paper_f0(n, seed=18)
+    marks = [int(round(t / dt)) for t in checkpoints if t <= t_end + 1e-9]
+    out = {"n": n, "dt": dt, "t_end": t_end, "checkpoints": [m * dt for m in marks]}
+
+    def run(mode, eps, h_fine=0.0, substeps=1):
+        snaps, elapsed, done = [], 0.0, 0
+        with Sim(n, n_cells=VP_NR, substeps=substeps) as sim:
+            sim.set_particles(R0, V0, w)
+            capi.ep_set_push_mode(sim.ctx, mode)
+            capi.ep_set_fine_solver(sim.ctx, h_fine)
+            for m in marks:
+                sim.sync()
+                t0 = time.perf_counter()
+                sim.step(dt, eps, EP_FIELD_DUFFING, m - done)
+                sim.sync()
+                elapsed += time.perf_counter() - t0
+                done = m
+                snaps.append(sim.particles())
+        return snaps, n * done / elapsed
+
+    for eps in eps_values:
+        h_ref = 2.0 * np.pi * eps / (100.0 * ref_refine)
+        ref, rate_ref = run(capi.EP_PUSH_RK4, eps, h_fine=h_ref)
+        res = {"reference": {"scheme": "RK4, step 2 pi eps/%d" % (100 * ref_refine),
+                             "particle_steps_per_s": rate_ref}}
+        schemes = (("improved_etd", capi.EP_PUSH_IMPROVED_ETD, 1),
+                   ("classic_etd", capi.EP_PUSH_CLASSIC_ETD, 1),
+                   ("modified_etd", capi.EP_PUSH_MODIFIED_ETD, 1),
+                   ("plain_K%d" % plain_K, capi.EP_PUSH_PLAIN, plain_K))
+        for name, mode, K in schemes:
+            snaps, rate = run(mode, eps, substeps=K)
+            med, modd = [], []
+            for (R, V), (Rr, Vr) in zip(snaps, ref):
+                med.append(float(np.median(np.hypot(R - Rr, V - Vr))))
+                mod, mod_ref = np.sort(np.hypot(R, V)), np.sort(np.hypot(Rr, Vr))
+                modd.append(float(np.mean(np.abs(mod - mod_ref)) / np.mean(mod_ref)))
+            res[name] = {"particle_steps_per_s": rate, "median_particle_err": med,
+                         "modulus_distribution_err": modd}
+            say("eps %g %s: %.3e particle-steps/s, median err %s" % (
+                eps, name, rate, " ".join("%.2e" % x for x in med)))
+        out["eps_%g" % eps] = res
+    return out
+
+
 def period_diagnostics(n=100_000, eps=0.01, t_end=5.0, dt=0.05, K=4, nr=1024):
     """The paper's period and modulus diagnostics (section 2) on its initial
     beam (eq. 2.7) at eps = 0.01: the Duffing periods against 2 pi eps, and in
