@@ -266,3 +266,28 @@ def test_period_diagnostics_of_the_papers_beam(golden):
     tol = 3e-7 * hi
     assert summ["unresolved"] == 0 and lo - tol < T.min() and T.max() < hi + tol
     assert summ["mean_over_2pi_eps"] < 1.0
+
+
+def test_long_run_classic_etd_blows_up_improved_stays_bounded():
+    """The paper's long-time finding on the given field (its beam, eq. 2.7,
+    eps = 1e-3, dt = 0.5, t = 30): the classic scheme of Algorithm 2.1
+    (common period 2 pi eps, extrapolated over ~80 periods per step) blows
+    up, while the improved scheme stays within 1e-2 of the reference RK4
+    (step 2 pi eps / 400) for the median particle."""
+    R0, V0, w = synth.paper_f0(4001, seed=60)
+    eps, dt, steps = 1e-3, 0.5, 60
+
+    def run(mode, **fine):
+        with Sim(R0.size, n_cells=NR, substeps=1) as sim:
+            sim.set_particles(R0, V0, w)
+            capi.ep_set_push_mode(sim.ctx, mode)
+            capi.ep_set_fine_solver(sim.ctx, **fine)
+            sim.step(dt, eps, EP_FIELD_DUFFING, steps)
+            return sim.particles()
+
+    Rr, Vr = run(EP_PUSH_RK4, h_fine=2 * math.pi * eps / 400)
+    Rc, Vc = run(capi.EP_PUSH_CLASSIC_ETD)
+    Ri, Vi = run(EP_PUSH_IMPROVED_ETD)
+    assert np.all(np.isfinite(Rr)) and np.all(np.isfinite(Ri))
+    assert not np.all(np.isfinite(Rc) & (np.abs(Rc) < 1e3))
+    assert np.median(np.hypot(Ri - Rr, Vi - Vr)) < 1e-2
