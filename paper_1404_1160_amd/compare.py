@@ -507,8 +507,8 @@ def paper_schemes_long(n=100_000, eps_values=(1e-3, 1e-4), dt=0.5, t_end=90.0,
     each checkpoint time every scheme's particles are compared with the
     reference RK4 (step 2 pi eps / (100 ref_refine)): the median particle
     error and the modulus-distribution error (mean distance between the
-    sorted moduli |y|, relative to their mean).  Rates are whole-run
-    particle-steps/s."""
+    sorted moduli |y|, relative to their mean), null once a scheme has blown
+    up.  Rates are whole-run particle-steps/s."""
     def say(msg):
         if log:
             log(msg)
@@ -545,14 +545,17 @@ def paper_schemes_long(n=100_000, eps_values=(1e-3, 1e-4), dt=0.5, t_end=90.0,
         for name, mode, K in schemes:
             snaps, rate = run(mode, eps, substeps=K)
             med, modd = [], []
+            def finite(x):   # null in the JSON line once a scheme has blown up
+                return float(x) if np.isfinite(x) else None
+
             for (R, V), (Rr, Vr) in zip(snaps, ref):
-                med.append(float(np.median(np.hypot(R - Rr, V - Vr))))
+                med.append(finite(np.median(np.hypot(R - Rr, V - Vr))))
                 mod, mod_ref = np.sort(np.hypot(R, V)), np.sort(np.hypot(Rr, Vr))
-                modd.append(float(np.mean(np.abs(mod - mod_ref)) / np.mean(mod_ref)))
+                modd.append(finite(np.mean(np.abs(mod - mod_ref)) / np.mean(mod_ref)))
             res[name] = {"particle_steps_per_s": rate, "median_particle_err": med,
                          "modulus_distribution_err": modd}
             say("eps %g %s: %.3e particle-steps/s, median err %s" % (
-                eps, name, rate, " ".join("%.2e" % x for x in med)))
+                eps, name, rate, " ".join("nan" if x is None else "%.2e" % x for x in med)))
         out["eps_%g" % eps] = res
     return out
 
