@@ -281,3 +281,59 @@ def test_learned_vp_rejects_five_input_network():
         with pytest.raises(capi.EtdpicError) as e:
             capi.ep_mlp_collect(sim.ctx, DT, EPS, 8)
         assert e.value.status == capi.EP_ENOTRAINED
+
+
+@pytest.fixture(scope="module")
+def beam_1e8():
+    """The Vlasov-Poisson beam at 1e8 particles (seed 17) and the oracle's
+    field of all of them on N_r = 4096 cells."""
+    n, nr = 100_000_000, 4096
+    R0, V0, w = synth.gaussian_truncated(n, seed=17)
+    rho, _ = oracle.deposit(R0, w, nr, -RMAX, RMAX)
+    E, Psi, Qb = oracle.poisson(rho, nr, -RMAX, RMAX)
+    return R0, V0, w, nr, E, Psi, Qb
+
+
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
+def test_learned_vp_step_at_1e8_particles(beam_1e8, precision):
+    """One learned step of the 1e8-particle beam (N_r = 4096, eps = 1e-3,
+    dt = 0.1), in the launch configuration of the long-time learned run: the
+    oracle takes the first and the last 10000 particles (ragged tail included)
+    through its own learned step in its own field of the whole beam.  tol is
+    the median drift ratio of that sample, so about half of the particles go
+    to the fallback queue (5e7 entries).  Bounds as in the check-decision
+    case; the beam's fallback fraction matches the sample's within sampling
+    noise plus the share of undecidable particles."""
+    R0, V0, w, nr, E, Psi, Qb = beam_1e8
+    n, half, K_fb = R0.size, 10000, 16
+    pois = dict(field=oracle.FIELD_POISSON, nr=nr, rmin=-RMAX, rmax=RMAX)
+    idx = np.concatenate([np.arange(half), np.arange(n - half, n)])
+    Rs, Vs = R0[idx], V0[idx]
+    p = synth.mlp_init(6, 64, 2, seed=10)
+    norm = _norm()
+    pd = p.astype(np.float64)
+    Eg = oracle.gather(Rs, E, Qb, nr, -RMAX, RMAX)
+    pot = lambda r: oracle.potential(r, E, Psi, Qb, nr, -RMAX, RMAX)
+    plain = lambda R, V: oracle.push(R, V, DT, EPS, K_fb, E=E, Qb=Qb, **pois)
+    _, _, _, ratio = mlp.learned_step(pd, Rs, Vs, DT, EPS, norm, pot, plain, math.inf, Egather=Eg)
+    tol = float(np.median(ratio))
+    Ro, Vo, fb, ratio = mlp.learned_step(pd, Rs, Vs, DT, EPS, norm, pot, plain, tol, Egather=Eg)
+    print("learned 1e8 precision=%d tol=%.3e" % (precision, tol), flush=True)
+    with Sim(n, n_cells=nr, substeps=1) as sim:
+        sim.set_particles(R0, V0, w)
+        capi.ep_mlp_set_weights(sim.ctx, p, norm.as_array())
+        capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, tol, K_fb)
+        capi.ep_mlp_set_precision(sim.ctx, precision)
+        sim.step(DT, EPS, EP_FIELD_POISSON, 1)
+        parts = [sim.particles(0, half), sim.particles(n - half, half)]
+        m = sim.moments(EPS, EP_FIELD_POISSON)
+    Rg = np.concatenate([q[0] for q in parts])
+    Vg = np.concatenate([q[1] for q in parts])
+    clear = np.abs(ratio / tol - 1.0) > 0.2
+    assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
+    err = rel_particle(Rg, Vg, Ro, Vo)
+    assert np.max(err[clear & fb]) <= 1e-6
+    assert np.max(err[clear & ~fb]) <= MAP_TOL[precision]
+    assert m["n_nan"] == 0
+    noise = 5.0 * math.sqrt(0.25 / idx.size)
+    assert abs(m["n_fallback"] / n - fb.mean()) <= noise + np.mean(~clear)
