@@ -278,7 +278,8 @@ def test_deterministic_and_order_independent():
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("nr,K,n", [(256, 2, 100003), (4096, 1, 1000001), (256, 3, 5)])
+@pytest.mark.parametrize("nr,K,n", [(256, 2, 100003), (4096, 1, 1000001), (256, 3, 5),
+                                     (4096, 1, 100_000_000)])
 def test_sorted_deposit_equals_atomic_bitwise(nr, K, n):
     """The sort-by-cell segmented reduction adds the same fixed-point weights
     as the LDS-privatised deposit, so particles (in their original order),
