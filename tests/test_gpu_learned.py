@@ -243,6 +243,44 @@ def test_check_decisions_agree_with_oracle(precision):
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
 
 
+
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
+def test_check_decisions_at_1e7_particles(precision):
+    """The same check at the inference size of the Duffing comparison: 1e7
+    particles of the evaluation beam (seed 15), K_fb = 400; the oracle takes
+    the first and the last 10000 particles (ragged tail included) through its
+    learned step, with tol at their median drift ratio, so about 5e6
+    particles go to the fallback queue.  The beam's fallback fraction matches
+    the sample's within sampling noise plus the share of undecidable
+    particles."""
+    n, half, K_fb = 10_000_000, 10000, 400
+    R0, V0, w = synth.gaussian(n, seed=15, sigma=SIG)
+    idx = np.concatenate([np.arange(half), np.arange(n - half, n)])
+    Rs, Vs = R0[idx], V0[idx]
+    p, norm = _net(seed=10)
+    pd = p.astype(np.float64)
+    pot = lambda r: r ** 4 / 4
+    plain = lambda R, V: oracle.push(R, V, DT, EPS, K_fb, field=oracle.FIELD_DUFFING)
+    _, _, _, ratio = mlp.learned_step(pd, Rs, Vs, DT, EPS, norm, pot, plain, math.inf)
+    tol = float(np.median(ratio))
+    Ro, Vo, fb, ratio = mlp.learned_step(pd, Rs, Vs, DT, EPS, norm, pot, plain, tol)
+    print("learned duffing 1e7 precision=%d tol=%.3e" % (precision, tol), flush=True)
+    sim = _learned_sim(R0, V0, w, p, norm, tol, K_fb, precision)
+    sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+    parts = [sim.particles(0, half), sim.particles(n - half, half)]
+    m = sim.moments(EPS, EP_FIELD_DUFFING)
+    sim.close()
+    Rg = np.concatenate([q[0] for q in parts])
+    Vg = np.concatenate([q[1] for q in parts])
+    clear = np.abs(ratio / tol - 1.0) > 0.2
+    assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
+    err = rel_particle(Rg, Vg, Ro, Vo)
+    assert np.max(err[clear & fb]) <= 1e-6
+    assert np.max(err[clear & ~fb]) <= MAP_TOL[precision]
+    assert m["n_nan"] == 0
+    noise = 5.0 * math.sqrt(0.25 / idx.size)
+    assert abs(m["n_fallback"] / n - fb.mean()) <= noise + np.mean(~clear)
+
 def test_training_run_matches_oracle_training():
     """A whole training run (labels, normalisation, 1024 Adam steps with the
     cosine schedule) on the GPU against the same run of the FP64 oracle: the
