@@ -60,7 +60,7 @@ def lib():
         L.orc_rk4_run.argtypes = [p, p, i64, d, d, d, i64, i32, d, i32, d, d]
         L.orc_rk4_run.restype = i32
         L.orc_improved_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i64, i32,
-                                            p, ctypes.POINTER(ctypes.c_int64)]
+                                            p, ctypes.POINTER(ctypes.c_int64), d]
         L.orc_improved_etd_step.restype = i64
         L.orc_classic_etd_step.argtypes = [p, p, i64, d, d, d, d, i32, d, i32, d, d, i32, i64,
                                            p, p]
@@ -163,10 +163,14 @@ def fine_step(eps):
 
 
 def improved_etd_step(R, V, w, dt, eps, field, nr=0, rmin=0.0, rmax=0.0, E0=0.0, h=None,
-                      max_fine=100000, T=None):
+                      max_fine=100000, T=None, alt_window=0.0):
     """One macro step of Algorithm 3.4.  Returns (R, V, T, N, n_unresolved).
     With T given (the periods of a previous step, in the given field where
-    they are constant) the period search is skipped."""
+    they are constant) the period search is skipped.  With alt_window > 0,
+    particles whose dt / T_i is within alt_window of a whole number take the
+    other valid split of dt into whole periods and a remainder (N_i one
+    smaller or larger), the outcome a computation whose T_i differs by a
+    rounding may choose there."""
     R = _f64(R).copy()
     V = _f64(V).copy()
     h = fine_step(eps) if h is None else h
@@ -175,7 +179,8 @@ def improved_etd_step(R, V, w, dt, eps, field, nr=0, rmin=0.0, rmax=0.0, E0=0.0,
     N = np.empty(R.size, dtype=np.int64)
     un = lib().orc_improved_etd_step(_ptr(R), _ptr(V), R.size, w, dt, eps, h, field, E0, nr,
                                      rmin, rmax, max_fine, 1 if given else 0, _ptr(T),
-                                     N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+                                     N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     float(alt_window))
     if un < 0:
         raise MemoryError("orc_improved_etd_step")
     return R, V, T, N, int(un)

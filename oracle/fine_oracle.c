@@ -275,10 +275,15 @@ int64_t orc_classic_etd_step(double *R, double *V, int64_t n, double w, double d
 /* One macro step of the improved ETD scheme (Algorithm 3.4).  On return R, V
  * hold y^{n+1}; T[i] the period and N[i] the whole number of periods used.
  * Returns the number of particles whose period was not resolved within
- * max_fine fine steps (they use 2 pi eps), or -1 without memory. */
+ * max_fine fine steps (they use 2 pi eps), or -1 without memory.
+ * alt_window > 0: a particle whose dt / T_i lies within alt_window of a whole
+ * number m takes the other of the two splits dt = N T_i + o_i that hold there
+ * up to rounding (N = m with o_i near 0, or N = m - 1 with o_i near T_i), with
+ * o_i = dt - N T_i; the default split is the one with 0 <= o_i < T_i. */
 int64_t orc_improved_etd_step(double *R, double *V, int64_t n, double w, double dt, double eps,
                               double h, int kind, double E0, int nr, double rmin, double rmax,
-                              int64_t max_fine, int periods_given, double *T, int64_t *N)
+                              int64_t max_fine, int periods_given, double *T, int64_t *N,
+                              double alt_window)
 {
     if (n <= 0) return 0;
     field_ctx f;
@@ -336,6 +341,13 @@ int64_t orc_improved_etd_step(double *R, double *V, int64_t n, double w, double 
         if (oi >= T[i]) {
             q += 1.0;
             oi -= T[i];
+        }
+        if (alt_window > 0.0) {
+            const double x = dt / T[i], m = floor(x + 0.5);
+            if (fabs(x - m) <= alt_window) {
+                q = q == m ? m - 1.0 : m;
+                oi = dt - q * T[i];
+            }
         }
         N[i] = (int64_t)q;
         o[i] = oi;

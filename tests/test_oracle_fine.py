@@ -130,6 +130,37 @@ def test_improved_etd_with_given_periods():
         assert np.all(np.hypot(R2 - Rx2, V2 - Vx2) <= bound2), eps
 
 
+def test_improved_etd_alternative_split_at_whole_ratios():
+    """Where dt / T_i is a whole number m, dt = N T_i + o_i holds with N = m,
+    o_i = 0 and with N = m - 1, o_i = T_i (Algorithm 3.4, Lemma 3.3: both
+    extrapolate whole periods of the same orbit).  With the exact periods given
+    and dt = m T_i for some particles, the alternative split changes N_i by one
+    for exactly those particles, and both results agree with the exact
+    solution within the scheme's interpolation bound (the captures sit at
+    other fine levels); far from whole ratios the alternative changes
+    nothing."""
+    R0, V0, w = synth.gaussian(300, seed=7)
+    eps = 1e-3
+    Tx = duffing.period(R0, V0, eps)
+    m = 80
+    dt = m * Tx[0]
+    x = dt / Tx
+    whole = np.abs(x - np.round(x)) <= 1e-9
+    assert whole[0] and whole.sum() < 5
+    Rs, Vs, _, Ns, _ = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING, T=Tx)
+    Ra, Va, _, Na, _ = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING, T=Tx,
+                                                alt_window=1e-9)
+    assert np.array_equal(np.abs(Na - Ns) == 1, whole)
+    assert set(Ns[whole]) | set(Na[whole]) == {m - 1, m}
+    far = ~whole
+    assert np.array_equal(Ra[far], Rs[far]) and np.array_equal(Va[far], Vs[far])
+    Rx, Vx = duffing.solution(R0[whole], V0[whole], eps, dt)
+    z3 = (2 * np.pi / 100) ** 3
+    bound = ((2 * m + 1) * z3 / 10) * np.hypot(Rx, Vx) * 1.5
+    for R, V in ((Rs, Vs), (Ra, Va)):
+        assert np.all(np.hypot(R[whole] - Rx, V[whole] - Vx) <= bound)
+
+
 def test_improved_etd_vp_step_tracks_the_reference():
     """Vlasov-Poisson beam, one macro step dt = 10 T of the improved scheme
     against the reference RK4 run over the same time: the rms radius agrees to

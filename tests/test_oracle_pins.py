@@ -360,6 +360,64 @@ def test_step_commutes_with_phase_space_reflection():
     assert np.array_equal(Ra, -Rb) and np.array_equal(Va, -Vb)
 
 
+def test_field_energy_of_the_gaussian_beam_by_quadrature():
+    """The moments' Vlasov-Poisson field energy int_0^{r_max} x E^2 dx against
+    an independent quadrature.  The beam is the truncated Gaussian of the
+    workloads (R ~ N(0,1), |R| < 4, total charge 1), placed at the quantiles
+    (i + 1/2)/N of its distribution so that sampling noise is O(1/N).  By
+    Gauss's law on the enclosed-charge reading of eq. 1.2,
+    E(x) = Q(x)/x with Q(x) = (1/2) erf(x/sqrt 2)/erf(2 sqrt 2) for x <= 4 and
+    1/2 beyond, so W = int_0^5 Q(x)^2/x dx, integrated by adaptive quadrature.
+    The oracle's W converges to it at second order in the cell width (CIC
+    deposit, trapezoid solve and trapezoid energy are all second order): a
+    factor 2, the two half-lines summed, a missing x or a wrong sign fail."""
+    from scipy import integrate, special, stats
+    n = 100_000
+    R = stats.truncnorm(-4.0, 4.0).ppf((np.arange(n) + 0.5) / n)
+    Z = special.erf(4.0 / math.sqrt(2.0))
+
+    def Q(x):
+        return 0.5 * special.erf(min(x, 4.0) / math.sqrt(2.0)) / Z
+
+    W, _ = integrate.quad(lambda x: Q(x) ** 2 / x if x > 0 else 0.0, 0.0, RMAX, points=[4.0],
+                          limit=200, epsabs=1e-13, epsrel=1e-12)
+    errs = []
+    for nr in (256, 1024):
+        rho, off = oracle.deposit(R, 1.0 / n, nr, -RMAX, RMAX)
+        E, _, _ = oracle.poisson(rho, nr, -RMAX, RMAX)
+        m = oracle.moments(R, np.zeros(n), 1.0 / n, 1.0, oracle.FIELD_POISSON, E=E, nr=nr,
+                           rmin=-RMAX, rmax=RMAX)
+        assert off == 0 and m["kinetic"] == pytest.approx(np.mean(R ** 2) / 2, rel=1e-12)
+        errs.append(abs(m["potential"] / W - 1.0))
+    assert errs[0] < 5e-4 and errs[1] < 5e-5, errs
+    assert 10.0 < errs[0] / errs[1] < 25.0, errs
+
+
+def test_kinetic_and_field_energy_exchange():
+    """Energy pin of the self-consistent run.  Along eq. 1.4,
+    d/dt (R^2 + V^2)/(2 eps) = E(R) dR/dt, and with E(r) = Q(|r|)/r the field
+    energy W = int_0^{r_max} Q^2/x dx changes by -E(R) dR/dt per particle, so
+    kinetic energy plus W is conserved.  A cold, compressed beam (R ~ N(0, 0.2),
+    V = 0, eps = 1) expands under its own field: W falls by half, and the
+    kinetic energy takes it up.  The oracle's run conserves the sum up to its
+    discretisation error, which falls at first order in dt (the field is
+    frozen over each macro step), with the mesh refined alongside; an energy
+    with a wrong factor or sign would leave an O(1) mismatch."""
+    rng = np.random.default_rng(5)
+    n = 100_000
+    R0, V0 = rng.normal(0.0, 0.2, n), np.zeros(n)
+    ratios = []
+    for dt, nr in ((0.05, 512), (0.025, 1024)):
+        _, _, mom = oracle.run(R0, V0, 1.0 / n, dt, 1.0, 4, int(round(2.0 / dt)),
+                               oracle.FIELD_POISSON, nr=nr, rmin=-RMAX, rmax=RMAX,
+                               with_moments=True)
+        kin, pot = mom[:, 3], mom[:, 4]
+        assert pot.min() < 0.6 * pot[0]
+        dW, dK = pot - pot[0], kin - kin[0]
+        ratios.append(np.max(np.abs(dK + dW)) / np.max(np.abs(dW)))
+    assert ratios[1] < 0.07 and 1.6 < ratios[0] / ratios[1] < 2.5, ratios
+
+
 def test_poisson_run_conserves_charge_and_is_finite():
     R0, V0, w = synth.gaussian_truncated(20000, seed=32)
     R, V, mom = oracle.run(R0, V0, w, 0.05, 0.01, 4, 20, oracle.FIELD_POISSON, nr=NR,
