@@ -71,7 +71,7 @@ typedef enum {
 } ep_push;
 
 /* Context configuration (ep_create).
- *   n_particles : capacity of the particle arrays (>= 1).
+ *   n_particles : capacity of the particle arrays (1 <= n_particles < 2^31).
  *   n_cells     : N_r, number of mesh cells; even, 2 <= N_r <= 8192.  The mesh
  *                 has N_r + 1 nodes x_k = -r_max + k h_r, h_r = 2 r_max / N_r,
  *                 with the centre node x_{N_r/2} = 0.
@@ -122,6 +122,9 @@ typedef struct {
 } ep_moments;
 
 /* Create a context on cfg->device and allocate its device buffers.
+ * n_particles must be below 2^31: the exact-integer trapezoid scan of the
+ * charge sums up to 2 N 2^32 in 64 bits, and the learned push's fallback
+ * queue holds 32-bit particle indices.
  * Errors: EP_EINVAL (bad sizes), EP_ENOMEM, EP_EHIP. */
 ep_status ep_create(const ep_config *cfg, ep_ctx **out);
 

@@ -1,7 +1,7 @@
 """ctypes binding of the etdpic C ABI (include/etdpic.h).
 
 Argument marshalling only: every function has the name of the C entry point it
-calls, converts numpy arrays / torch tensors to pointers, and raises
+calls, converts numpy arrays and device addresses to pointers, and raises
 ``EtdpicError`` on a non-zero status.  All computation happens in the HIP
 library; if ``libetdpic.so`` is missing, loading fails loudly.
 """
@@ -77,19 +77,48 @@ class ep_train_report(ctypes.Structure):
 
 _lib = None
 
+# The HIP runtime the library is linked against (ROCm's).
+ROCM_HIP_RUNTIME = "/opt/rocm/lib/libamdhip64.so.7"
+
 
 def library_path():
     return _build.LIB
 
 
+def foreign_hip_runtimes(maps="/proc/self/maps"):
+    """Paths of HIP runtimes mapped into this process from anywhere but the
+    directory of the runtime the library links (e.g. the copy a framework
+    wheel bundles).  Two runtimes in one process do not share devices,
+    streams or allocations, and a profiler attached to such a process has
+    aborted inside its own tool library."""
+    own = os.path.dirname(os.path.realpath(ROCM_HIP_RUNTIME))
+    found = set()
+    try:
+        with open(maps) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 6 and "libamdhip64" in os.path.basename(parts[-1]):
+                    found.add(parts[-1])
+    except OSError:
+        return []
+    return sorted(p for p in found if os.path.dirname(os.path.realpath(p)) != own)
+
+
 def lib():
-    """Load libetdpic.so (raises if it has not been built)."""
+    """Load libetdpic.so (raises if it has not been built, or if another HIP
+    runtime is already loaded into this process)."""
     global _lib
     if _lib is None:
         path = library_path()
         if not os.path.exists(path):
             raise ImportError("etdpic HIP library not built: %s is missing "
                               "(run __graft_entry__.build())" % path)
+        foreign = foreign_hip_runtimes()
+        if foreign:
+            raise ImportError("another HIP runtime is already loaded in this process (%s); "
+                              "libetdpic uses %s and cannot share a process with it -- "
+                              "load the library in a process that does not import it"
+                              % (", ".join(foreign), ROCM_HIP_RUNTIME))
         L = ctypes.CDLL(path)
         vp, d, u64, u32, i32 = (ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
                                 ctypes.c_uint32, ctypes.c_int32)
@@ -181,11 +210,12 @@ def ep_set_particles(ctx, R, V, w):
     _check(ctx, lib().ep_set_particles(ctx, _p(R), _p(V), R.size, float(w)))
 
 
-def ep_bind_particles(ctx, zR, zV, w):
-    """zR, zV: FP32 device tensors (torch, contiguous) in the rotating frame."""
-    n = zR.numel()
-    _check(ctx, lib().ep_bind_particles(ctx, ctypes.c_void_p(zR.data_ptr()),
-                                        ctypes.c_void_p(zV.data_ptr()), n, float(w)))
+def ep_bind_particles(ctx, zR_ptr, zV_ptr, n, w):
+    """zR_ptr, zV_ptr: addresses (ints) of caller-owned FP32 device arrays of n
+    particles in the rotating frame, allocated through the library's HIP
+    runtime (e.g. hipMalloc of ROCM_HIP_RUNTIME)."""
+    _check(ctx, lib().ep_bind_particles(ctx, ctypes.c_void_p(int(zR_ptr)),
+                                        ctypes.c_void_p(int(zV_ptr)), int(n), float(w)))
 
 
 def ep_step(ctx, dt, eps, field, n_steps=1):
@@ -349,3 +379,4 @@ def ep_load(ctx, path):
     n = ctypes.c_uint64(0)
     _check(ctx, lib().ep_load(ctx, os.fsencode(path), ctypes.byref(n)))
     return int(n.value)
+

@@ -156,6 +156,10 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
         (h.mlp_n_in && h.mlp_n_params != (uint32_t)mlp_n_params((int)h.mlp_n_in)))
         return c->fail(EP_EINVAL, "ep_load: checkpoint does not fit this context (particles, "
                                   "mesh or substeps differ)");
+    // the learned push's settings obey the bounds of ep_set_push_mode
+    if (!(h.drift_tol >= 0.0) || (h.push_mode == EP_PUSH_LEARNED && h.fallback_K == 0))
+        return c->fail(EP_EINVAL, "ep_load: checkpoint has an invalid drift bound or fallback "
+                                  "substep count");
     std::vector<float> zr(h.n), zv(h.n), params(h.mlp_n_params);
     std::vector<double> T(h.periods_saved ? h.n : 0);
     std::vector<int64_t> N(h.periods_saved ? h.n : 0);
@@ -178,8 +182,8 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
     c->zR = c->own_zR;
     c->zV = c->own_zV;
     if (h.n) {
-        HIPCHK(c, hipMemcpy(c->zR, zr.data(), h.n * 4, hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(c->zV, zv.data(), h.n * 4, hipMemcpyHostToDevice));
+        HIPCHK(c, copy_sync(c, c->zR, zr.data(), h.n * 4, hipMemcpyHostToDevice));
+        HIPCHK(c, copy_sync(c, c->zV, zv.data(), h.n * 4, hipMemcpyHostToDevice));
         if (c->ids) HIPCHK(c, launch_iota(c->stream, c->ids, 0, (int64_t)h.n));
     }
     c->n = h.n;

@@ -19,6 +19,7 @@ namespace etd {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr uint32_t kMaxCells = 8192;
+constexpr uint64_t kMaxParticles = (uint64_t(1) << 31) - 1;
 constexpr size_t kTableEntries = size_t(1) << 20;   // substep coefficients per chunk
 constexpr size_t kStageParticles = size_t(1) << 23; // FP64 staging for host transfers
 
@@ -214,6 +215,22 @@ inline hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
     return hipSuccess;
 }
 
+// Copy on the context's stream and wait for it: the copy follows every
+// kernel already queued there (the library's own stream does not synchronise
+// with the null stream, so a plain hipMemcpy could overwrite buffers that a
+// queued step still reads, or read results it has not yet written), and the
+// host buffer is free again when this returns.
+inline hipError_t copy_sync(ep_ctx *c, void *dst, const void *src, size_t bytes,
+                            hipMemcpyKind kind)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, c->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
+// Message that ep_last_error(NULL) returns: the last failed call that has no
+// context (ep_create, ep_step_noalloc).
+void set_context_free_error(const char *msg);
 hipError_t collect_timing(ep_ctx *c);
 ep_status ensure_tables(ep_ctx *c, size_t entries, size_t steps);
 ep_status refresh_field(ep_ctx *c);

@@ -241,10 +241,10 @@ ep_status restore_periods(ep_ctx *c, const double *T, const int64_t *N, uint64_t
     FineArgs &a = c->fine;
     const unsigned long long un = unresolved;
     if (c->n) {
-        HIPCHK(c, hipMemcpy(a.T, T, c->n * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(a.N, N, c->n * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIPCHK(c, copy_sync(c, a.T, T, c->n * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, copy_sync(c, a.N, N, c->n * sizeof(int64_t), hipMemcpyHostToDevice));
     }
-    HIPCHK(c, hipMemcpy(a.unresolved, &un, sizeof un, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, a.unresolved, &un, sizeof un, hipMemcpyHostToDevice));
     return EP_OK;
 }
 

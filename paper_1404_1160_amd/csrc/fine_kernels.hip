@@ -593,16 +593,15 @@ hipError_t setup_fine_lds(int nr)
 {
     hipError_t e;
 #define ETD_LDS(S, M)                                                                           \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rk4_stage_kernel<S, M>),           \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage_lds_bytes(nr)); \
+    e = raise_dynamic_lds(reinterpret_cast<const void *>(&rk4_stage_kernel<S, M>),             \
+                          (int)stage_lds_bytes(nr));                                            \
     if (e != hipSuccess) return e;
     ETD_LDS(1, 0) ETD_LDS(2, 0) ETD_LDS(3, 0) ETD_LDS(4, 0)
     ETD_LDS(1, 1) ETD_LDS(2, 1) ETD_LDS(3, 1) ETD_LDS(4, 1)
     ETD_LDS(1, 2) ETD_LDS(2, 2) ETD_LDS(3, 2) ETD_LDS(4, 2)
 #undef ETD_LDS
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&fine_deposit_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)((nr + 1) * sizeof(unsigned long long)));
+    return raise_dynamic_lds(reinterpret_cast<const void *>(&fine_deposit_kernel),
+                             (int)((nr + 1) * sizeof(unsigned long long)));
 }
 
 }  // namespace etd

@@ -43,6 +43,11 @@ inline hipError_t dispatch(F kernel, dim3 grid, dim3 block, size_t lds, hipStrea
     return dispatch_k<true, true>(kernel, grid, block, lds, st, args...);
 }
 
+// Raise a kernel's dynamic-LDS limit to at least `bytes`.  The limit is a
+// property of the kernel in the process, shared by every context: it only ever
+// grows, so a context with a smaller mesh cannot lower it under another's.
+hipError_t raise_dynamic_lds(const void *kernel, int bytes);
+
 constexpr int kPushBlock = 1024;       // threads per block of the mesh push kernels
 constexpr int kSolveBlock = 1024;      // threads of the single-block mesh solve
 constexpr int kMomentBlock = 256;

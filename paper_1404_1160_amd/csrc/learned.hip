@@ -197,10 +197,10 @@ ep_status prepare_inference(ep_ctx *c, double dt, double eps)
                     split_op(fp16, P[o.W3 + i * kH + slot_unit(kk, lane >> 5, e)], w3[at],
                              w3[kW3 + at]);
             }
-    HIPCHK(c, hipMemcpy(L.d_w1f, w1.data(), w1.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_w2f, w2.data(), w2.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_b2, b2.data(), kH * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(L.d_w3f, w3.data(), w3.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, L.d_w1f, w1.data(), w1.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, L.d_w2f, w2.data(), w2.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, L.d_b2, b2.data(), kH * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, L.d_w3f, w3.data(), w3.size() * 2, hipMemcpyHostToDevice));
     MlpInfer &I = L.infer;
     I.w1f = L.d_w1f;
     I.w2f = L.d_w2f;
@@ -255,7 +255,7 @@ ep_status upload_fp32(ep_ctx *c, const double *src, uint64_t n, float *dst)
 {
     std::vector<float> tmp(n);
     for (uint64_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
-    HIPCHK(c, hipMemcpy(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
     return EP_OK;
 }
 
@@ -398,7 +398,7 @@ ep_status ep_mlp_set_weights(ep_ctx *c, const float *params, uint32_t n_params, 
     Learned &L = c->mlp;
     L.params.assign(params, params + n_params);
     for (int i = 0; i < 8; ++i) L.norm[i] = norm[i];
-    HIPCHK(c, hipMemcpy(L.d_params, params, n_params * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, L.d_params, params, n_params * sizeof(float), hipMemcpyHostToDevice));
     L.packed = false;
     return EP_OK;
 }
@@ -429,7 +429,7 @@ ep_status ep_mlp_labels(ep_ctx *c, double dt, double eps, uint32_t K, const doub
     ep_status s = make_labels(c, dt, eps, K, 1.0, 0, R, V, n, dX.p, dY.p);
     if (s != EP_OK) return s;
     std::vector<float> Y((size_t)n * 2);
-    HIPCHK(c, hipMemcpy(Y.data(), dY.p, Y.size() * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(c, copy_sync(c, Y.data(), dY.p, Y.size() * sizeof(float), hipMemcpyDeviceToHost));
     for (uint64_t i = 0; i < n; ++i) {
         delta[i] = Y[2 * i];
         kappa[i] = Y[2 * i + 1];
@@ -454,8 +454,8 @@ ep_status ep_mlp_grad(ep_ctx *c, const float *X, const float *Y, uint32_t batch,
     HIPCHK(c, dalloc(&gpart.p, (size_t)tiles * np));
     HIPCHK(c, dalloc(&lpart.p, (size_t)tiles));
     HIPCHK(c, dalloc(&dloss.p, (size_t)1));
-    HIPCHK(c, hipMemcpy(dX.p, X, (size_t)batch * L.n_in * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(dY.p, Y, (size_t)batch * 2 * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, dX.p, X, (size_t)batch * L.n_in * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, copy_sync(c, dY.p, Y, (size_t)batch * 2 * sizeof(float), hipMemcpyHostToDevice));
     HIPCHK(c, setup_train_lds(L.n_in));
     const float nf[4] = {(float)L.norm[3], (float)(1.0 / L.norm[4]), (float)L.norm[5],
                          (float)(1.0 / L.norm[6])};
@@ -545,8 +545,8 @@ ep_status ep_mlp_get_samples(ep_ctx *c, uint64_t first, uint64_t count, float *X
                        (unsigned long long)L.t_n);
     if (count == 0) return EP_OK;
     DeviceGuard guard(c->device);
-    HIPCHK(c, hipMemcpy(X, L.d_tx + first * 6, count * 6 * sizeof(float), hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(Y, L.d_ty + first * 2, count * 2 * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(c, copy_sync(c, X, L.d_tx + first * 6, count * 6 * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(c, copy_sync(c, Y, L.d_ty + first * 2, count * 2 * sizeof(float), hipMemcpyDeviceToHost));
     return EP_OK;
 }
 
@@ -590,7 +590,7 @@ ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, cons
     // normalisation of the labels from their first samples
     const uint64_t ns = n < kNormSamples ? n : kNormSamples;
     std::vector<float> Yh((size_t)ns * 2);
-    HIPCHK(c, hipMemcpy(Yh.data(), dY, Yh.size() * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(c, copy_sync(c, Yh.data(), dY, Yh.size() * sizeof(float), hipMemcpyDeviceToHost));
     double m[2] = {0, 0}, q[2] = {0, 0};
     for (uint64_t i = 0; i < ns; ++i)
         for (int j = 0; j < 2; ++j) m[j] += Yh[2 * i + j];

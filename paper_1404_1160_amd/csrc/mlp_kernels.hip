@@ -537,10 +537,8 @@ hipError_t setup_train_lds(int n_in)
 {
     const int lds = (int)(train_lds_floats(n_in) * sizeof(float));
     if (n_in == 5)
-        return hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_train_kernel<5>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_train_kernel<6>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        return raise_dynamic_lds(reinterpret_cast<const void *>(&mlp_train_kernel<5>), lds);
+    return raise_dynamic_lds(reinterpret_cast<const void *>(&mlp_train_kernel<6>), lds);
 }
 
 static hipError_t launch_train_tiles(hipStream_t st, int n_in, const float *params,
@@ -1081,21 +1079,19 @@ hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const u
 
 hipError_t setup_learned_lds(int nr)
 {
-    hipError_t e = hipFuncSetAttribute(
+    hipError_t e = raise_dynamic_lds(
         reinterpret_cast<const void *>(&mlp_push_kernel<true, kWavesPoisson, _Float16>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_vp_lds_bytes(nr));
+        (int)mlp_vp_lds_bytes(nr));
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(
+    e = raise_dynamic_lds(
         reinterpret_cast<const void *>(&mlp_push_kernel<true, kWavesPoisson, __bf16>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_vp_lds_bytes(nr));
+        (int)mlp_vp_lds_bytes(nr));
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fallback_duffing_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kFallbackLdsK * sizeof(double4)));
+    e = raise_dynamic_lds(reinterpret_cast<const void *>(&fallback_duffing_kernel),
+                          (int)(kFallbackLdsK * sizeof(double4)));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&fallback_poisson_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(fallback_table_offset(nr) + kFallbackLdsK * sizeof(double4)));
+    return raise_dynamic_lds(reinterpret_cast<const void *>(&fallback_poisson_kernel),
+                             (int)(fallback_table_offset(nr) + kFallbackLdsK * sizeof(double4)));
 }
 
 }  // namespace etd

@@ -498,8 +498,7 @@ size_t push_lds_bytes_for(int nr) { return push_lds_bytes(nr); }
 template <bool P, int U>
 static hipError_t raise_lds(int lds)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&push_poisson_kernel<P, U>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return raise_dynamic_lds(reinterpret_cast<const void *>(&push_poisson_kernel<P, U>), lds);
 }
 
 hipError_t setup_mesh_lds(int nr)
@@ -513,8 +512,7 @@ hipError_t setup_mesh_lds(int nr)
     for (const void *k : {reinterpret_cast<const void *>(&mesh_solve_kernel<true>),
                           reinterpret_cast<const void *>(&mesh_solve_kernel<false>),
                           reinterpret_cast<const void *>(&potential_kernel)})
-        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)mesh_lds_bytes(nr))) != hipSuccess)
+        if ((e = raise_dynamic_lds(k, (int)mesh_lds_bytes(nr))) != hipSuccess)
             return e;
     return hipSuccess;
 }

@@ -1,6 +1,8 @@
 // Host runtime of the exponential-integrator PIC library: context, device
 // buffers, FP64 phase bookkeeping, step scheduling and the C ABI of etdpic.h.
 
+#include <mutex>
+
 #include "context.h"
 
 using namespace etd;
@@ -32,6 +34,21 @@ void free_all(ep_ctx *c)
 }  // namespace
 
 namespace etd {
+
+void set_context_free_error(const char *msg) { g_create_error = msg; }
+
+hipError_t raise_dynamic_lds(const void *kernel, int bytes)
+{
+    static std::mutex mu;
+    static std::map<const void *, int> limit;
+    std::lock_guard<std::mutex> lock(mu);
+    int &cur = limit[kernel];
+    if (bytes <= cur) return hipSuccess;
+    const hipError_t e =
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) cur = bytes;
+    return e;
+}
 
 LaunchEvents &next_launch_events()
 {
@@ -164,11 +181,15 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
         return EP_EINVAL;
     }
     *out = nullptr;
-    if (cfg->n_particles == 0 || cfg->substeps == 0 || cfg->n_cells < 2 || (cfg->n_cells & 1) ||
-        cfg->n_cells > kMaxCells || !(cfg->r_max > 0.0) || !isfinite(cfg->r_max) ||
+    // The trapezoid scan of the fixed-point charges sums up to 2 N 2^32 in
+    // u64, and the learned fallback queue holds 32-bit particle indices: both
+    // are exact for N < 2^31.
+    if (cfg->n_particles == 0 || cfg->n_particles > kMaxParticles || cfg->substeps == 0 ||
+        cfg->n_cells < 2 || (cfg->n_cells & 1) || cfg->n_cells > kMaxCells ||
+        !(cfg->r_max > 0.0) || !isfinite(cfg->r_max) ||
         (cfg->deposit != EP_DEPOSIT_ATOMIC && cfg->deposit != EP_DEPOSIT_SORTED)) {
-        g_create_error = "ep_create: invalid configuration (need n_particles >= 1, substeps >= 1, "
-                         "even 2 <= n_cells <= 8192, r_max > 0, valid deposit)";
+        g_create_error = "ep_create: invalid configuration (need 1 <= n_particles < 2^31, "
+                         "substeps >= 1, even 2 <= n_cells <= 8192, r_max > 0, valid deposit)";
         return EP_EINVAL;
     }
     int ndev = 0;
@@ -233,10 +254,6 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     c->zV = c->own_zV;
     const size_t nn = (size_t)cfg->n_cells + 1;
     if (cfg->deposit == EP_DEPOSIT_SORTED) {
-        if (np >= ((size_t)1 << 32)) {
-            c->fail(EP_EINVAL, "ep_create: the sorted deposit indexes particles with 32 bits");
-            return bail(EP_EINVAL);
-        }
         CREATE_CHK(dalloc(&c->sR, np_pad));
         CREATE_CHK(dalloc(&c->sV, np_pad));
         CREATE_CHK(dalloc(&c->ids, np_pad));

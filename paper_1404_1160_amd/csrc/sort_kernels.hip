@@ -276,8 +276,7 @@ hipError_t setup_sort_lds(int nr)
                           reinterpret_cast<const void *>(&sort_pass_kernel<false, true>),
                           reinterpret_cast<const void *>(&sort_pass_kernel<true, false>),
                           reinterpret_cast<const void *>(&sort_pass_kernel<true, true>)}) {
-        const hipError_t e =
-            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        const hipError_t e = raise_dynamic_lds(f, lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -55,6 +55,59 @@ def test_create_rejects_bad_configuration(lib):
         capi.ep_create(n_particles=0)
 
 
+def test_create_rejects_more_particles_than_the_charge_scan_holds(lib):
+    """The exact-integer trapezoid scan sums up to 2 N 2^32 in u64, and the
+    learned fallback queue holds 32-bit indices: N >= 2^31 is refused before
+    any device work."""
+    for n in (2 ** 31, 2 ** 40):
+        with pytest.raises(capi.EtdpicError) as ei:
+            capi.ep_create(n_particles=n)
+        assert ei.value.status == capi.EP_EINVAL
+        assert "2^31" in capi.ep_last_error(None)
+
+
+def test_foreign_hip_runtime_is_detected(tmp_path):
+    """A process map naming a HIP runtime outside ROCm's library directory is
+    reported (the library refuses to load beside it); ROCm's own is not."""
+    own = os.path.realpath(capi.ROCM_HIP_RUNTIME)
+    other = "/usr/lib/python3/site-packages/framework/lib/libamdhip64.so"
+    maps = tmp_path / "maps"
+    maps.write_text("7f00-7f10 r-xp 00000000 08:01 1 %s\n7f20-7f30 r--p 00000000 08:01 2 %s\n"
+                    "7f40-7f50 r--p 00000000 08:01 3 /usr/lib/libc.so.6\n" % (own, other))
+    assert capi.foreign_hip_runtimes(str(maps)) == [other]
+    maps.write_text("7f00-7f10 r-xp 00000000 08:01 1 %s\n" % own)
+    assert capi.foreign_hip_runtimes(str(maps)) == []
+
+
+def test_library_refuses_a_process_with_another_hip_runtime():
+    """In a process that has loaded a framework's bundled HIP runtime (here
+    PyTorch's, if importable), loading the library raises instead of sharing
+    the process with a second runtime."""
+    import subprocess
+    import sys
+    code = ("import torch\n"
+            "from paper_1404_1160_amd import capi\n"
+            "if not capi.foreign_hip_runtimes():\n"
+            "    print('NO_FOREIGN_RUNTIME'); raise SystemExit(0)\n"
+            "try:\n"
+            "    capi.lib()\n"
+            "except ImportError as e:\n"
+            "    print('REFUSED', e); raise SystemExit(0)\n"
+            "raise SystemExit('loaded beside a foreign HIP runtime')\n")
+    try:
+        import importlib.util
+        if importlib.util.find_spec("torch") is None:
+            pytest.skip("no framework with a bundled HIP runtime is installed")
+    except ImportError:
+        pytest.skip("no framework with a bundled HIP runtime is installed")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    if "NO_FOREIGN_RUNTIME" in r.stdout:
+        pytest.skip("this framework build maps no HIP runtime of its own")
+    assert "REFUSED" in r.stdout
+
+
 def test_null_context_is_rejected(lib):
     assert lib.ep_step(None, 0.1, 0.1, 1, 1) == capi.EP_EINVAL
     assert lib.ep_sync(None) == capi.EP_EINVAL

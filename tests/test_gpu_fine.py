@@ -2,12 +2,16 @@
 RK4 solver (EP_PUSH_RK4) and the improved ETD scheme (Algorithm 3.4,
 EP_PUSH_IMPROVED_ETD), for the Duffing and the self-consistent field.
 
-Tolerances: per particle 1e-6 max(|y|, 1) (FP32 storage of the state between
-macro steps, FP64 arithmetic on both sides; for the Poisson field the GPU
-gathers from its FP32 field table).  Periods: relative 1e-9 (Duffing, same
-FP64 arithmetic) and 1e-6 (Poisson).  N_i is an integer decided by
+Tolerances: per particle 1e-6 max(|y|, floor) (FP32 storage of the state
+between macro steps, FP64 arithmetic on both sides), with the floor 1e-3 in
+the Duffing field and the beam size 1 in the self-consistent field, where the
+GPU gathers from its FP32 field table and the field's jump at r = 0 stretches
+small-amplitude perturbations.  Periods: relative 1e-9 (Duffing, same FP64
+arithmetic) and 1e-6 (Poisson).  N_i is an integer decided by
 floor(dt / T_i): compared exactly where dt / T_i is not within 1e-6 of a
-whole number; the particles where it is are checked to be valid either way.
+whole number.  Where it is, both N_i = m and N_i = m - 1 split dt validly up
+to rounding; the oracle computes both outcomes and the GPU's particle must
+match the one with its N_i.
 """
 import math
 
@@ -24,8 +28,12 @@ NR, RMAX = 256, 5.0
 VP = dict(nr=NR, rmin=-RMAX, rmax=RMAX)
 
 
-def rel(Rg, Vg, Ro, Vo):
-    return np.hypot(Rg - Ro, Vg - Vo) / np.maximum(np.hypot(Ro, Vo), 1.0)
+DUFFING_FLOOR, POISSON_FLOOR = 1e-3, 1.0
+AMBIGUOUS = 1e-6     # |dt / T_i - m| below which either whole number m, m - 1 is valid
+
+
+def rel(Rg, Vg, Ro, Vo, floor=DUFFING_FLOOR):
+    return np.hypot(Rg - Ro, Vg - Vo) / np.maximum(np.hypot(Ro, Vo), floor)
 
 
 def _sim(R0, V0, w, mode, nr=NR, **fine):
@@ -61,18 +69,24 @@ def test_rk4_poisson_matches_oracle():
             sim.step(dt, eps, EP_FIELD_POISSON, 1)
             Ro, Vo = oracle.rk4_run(Ro, Vo, w, eps, dt / 12, 12, oracle.FIELD_POISSON, **VP)
             Rg, Vg = sim.particles()
-            assert rel(Rg, Vg, Ro, Vo).max() <= 1e-6, s
+            assert rel(Rg, Vg, Ro, Vo, POISSON_FLOOR).max() <= 1e-6, s
 
 
-def _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, t_tol):
+def _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, t_tol, alt, floor=DUFFING_FLOOR):
+    """Worst particle error of the GPU step against the oracle's.  alt():
+    the oracle's step with the alternative split (called only if needed),
+    returning (R, V, T, N, unresolved)."""
     assert np.max(np.abs(Tg / To - 1)) <= t_tol
     x = dt / To
-    clear = np.abs(x - np.round(x)) > 1e-6
+    clear = np.abs(x - np.round(x)) > AMBIGUOUS
     assert np.array_equal(Ng[clear], No[clear])
-    assert np.all(np.abs(Ng - No) <= 1)
-    err = rel(Rg, Vg, Ro, Vo)
-    same = Ng == No
-    return err[same].max()
+    err = rel(Rg, Vg, Ro, Vo, floor)
+    other = Ng != No
+    if np.any(other):
+        Ra, Va, _, Na, _ = alt()
+        assert np.array_equal(Ng[other], Na[other])
+        err[other] = rel(Rg[other], Vg[other], Ra[other], Va[other], floor)
+    return err.max()
 
 
 def test_improved_etd_duffing_matches_oracle():
@@ -84,7 +98,9 @@ def test_improved_etd_duffing_matches_oracle():
             Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
         Ro, Vo, To, No, uno = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING)
         assert un == uno == 0
-        worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, 1e-9)
+        alt = lambda: oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_DUFFING,
+                                               alt_window=AMBIGUOUS)
+        worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, 1e-9, alt)
         assert worst <= 1e-6, (eps, worst)
 
 
@@ -101,15 +117,17 @@ def test_improved_etd_duffing_steps_match_oracle(once):
             sim.step(dt, eps, EP_FIELD_DUFFING, 1)
             Rg, Vg = sim.particles()
             Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
-            Ro, Vo, To, No, uno = oracle.improved_etd_step(Ro, Vo, w, dt, eps,
-                                                           oracle.FIELD_DUFFING,
-                                                           T=T1 if once else None)
+            Rp, Vp, Tp = Ro, Vo, (T1 if once else None)
+            Ro, Vo, To, No, uno = oracle.improved_etd_step(Rp, Vp, w, dt, eps,
+                                                           oracle.FIELD_DUFFING, T=Tp)
             if once and s == 0:
                 T1 = To
             assert un == uno == 0, s
             # searched from FP32-stored against FP64 states after the first step
             t_tol = 1e-9 if once or s == 0 else 1e-8
-            worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, t_tol)
+            alt = lambda: oracle.improved_etd_step(Rp, Vp, w, dt, eps, oracle.FIELD_DUFFING,
+                                                   T=Tp, alt_window=AMBIGUOUS)
+            worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, t_tol, alt)
             assert worst <= 1e-6, (s, worst)
             if once and s:
                 assert np.array_equal(Tg, T1g)
@@ -166,7 +184,9 @@ def test_improved_etd_poisson_matches_oracle():
         Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
     Ro, Vo, To, No, uno = oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_POISSON, **VP)
     assert un == uno == 0
-    worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, 1e-6)
+    alt = lambda: oracle.improved_etd_step(R0, V0, w, dt, eps, oracle.FIELD_POISSON,
+                                           alt_window=AMBIGUOUS, **VP)
+    worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, 1e-6, alt, POISSON_FLOOR)
     assert worst <= 1e-5, worst
 
 
@@ -229,7 +249,7 @@ def test_modified_etd_poisson_matches_oracle():
                                                  **VP)
     assert un == uno == 0
     assert np.max(np.abs(Tg / To - 1)) <= 1e-6 and np.all(Ng == math.floor(dt / P))
-    assert rel(Rg, Vg, Ro, Vo).max() <= 1e-5
+    assert rel(Rg, Vg, Ro, Vo, POISSON_FLOOR).max() <= 1e-5
 
 
 def test_compute_periods_match_oracle_and_exact_periods():

@@ -164,10 +164,26 @@ def test_check_decisions_agree_with_oracle(precision):
     sim.close()
     clear = np.abs(ratio / tol - 1.0) > 0.2
     assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
-    err = rel_particle(Rg, Vg, Ro, Vo)
-    assert np.max(err[clear & fb]) <= 1e-6
-    assert np.max(err[clear & ~fb]) <= MAP_TOL[precision]
+    _check_decisions(Rg, Vg, R0, V0, Ro, Vo, fb, clear, pd, norm, pot, plain, Eg, precision)
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
+
+
+def _check_decisions(Rg, Vg, R0, V0, Ro, Vo, fb, clear, pd, norm, pot, plain, Eg, precision):
+    """Where the oracle's drift ratio is clear of tol the GPU took the
+    oracle's branch; where it is not, either branch is valid (the GPU applies
+    the map in FP32 before its FP64 check) and the GPU's result is one of the
+    oracle's two outcomes: its network map within the map bound, or its plain
+    push within the plain bound."""
+    err = rel_particle(Rg, Vg, Ro, Vo)
+    assert np.max(err[clear & fb], initial=0.0) <= 1e-6
+    assert np.max(err[clear & ~fb], initial=0.0) <= MAP_TOL[precision]
+    amb = ~clear
+    Rm, Vm, _, _ = mlp.learned_step(pd, R0[amb], V0[amb], DT, EPS, norm, pot, plain, math.inf,
+                                    Egather=Eg[amb])
+    Rp, Vp = plain(R0[amb], V0[amb])
+    as_map = rel_particle(Rg[amb], Vg[amb], Rm, Vm) <= MAP_TOL[precision]
+    as_plain = rel_particle(Rg[amb], Vg[amb], Rp, Vp) <= 1e-6
+    assert np.all(as_map | as_plain), np.flatnonzero(~(as_map | as_plain))[:10]
 
 
 def test_gradients_six_inputs_match_oracle():
@@ -331,9 +347,7 @@ def test_learned_vp_step_at_1e8_particles(beam_1e8, precision):
     Vg = np.concatenate([q[1] for q in parts])
     clear = np.abs(ratio / tol - 1.0) > 0.2
     assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
-    err = rel_particle(Rg, Vg, Ro, Vo)
-    assert np.max(err[clear & fb]) <= 1e-6
-    assert np.max(err[clear & ~fb]) <= MAP_TOL[precision]
+    _check_decisions(Rg, Vg, Rs, Vs, Ro, Vo, fb, clear, pd, norm, pot, plain, Eg, precision)
     assert m["n_nan"] == 0
     noise = 5.0 * math.sqrt(0.25 / idx.size)
     assert abs(m["n_fallback"] / n - fb.mean()) <= noise + np.mean(~clear)

@@ -3,14 +3,16 @@
 Tolerances (FP32 particle state, FP64 phase and in-register arithmetic,
 exact-integer charge scan):
   * per particle, after each of 10 steps:
-        |y_gpu - y_oracle|_2 / max(|y_oracle|_2, L) <= 1e-6
-    relative to the particle's own amplitude, and to the beam size L = 1 for
-    particles closer than that to the origin (the paper measures particle
-    errors against the size of the beam, section 1).  Near r = 0 the
-    self-consistent field jumps from -rho(0) to +rho(0) across the centre
-    cell, so the discrete map stretches perturbations of small-amplitude
-    particles several-fold per step; their FP32 storage rounding is amplified
-    in the oracle comparison no matter how the arithmetic is done.
+        |y_gpu - y_oracle|_2 / max(|y_oracle|_2, floor) <= 1e-6
+    relative to the particle's own amplitude.  The floor is 1e-3 for the free
+    rotation and the Duffing field, where the map is smooth and a particle's
+    FP32 storage rounding stays relative to its own amplitude.  For the
+    self-consistent field it is the beam size L = 1 (the paper measures
+    particle errors against the size of the beam, section 1): near r = 0 that
+    field jumps from -rho(0) to +rho(0) across the centre cell, so the
+    discrete map stretches perturbations of small-amplitude particles
+    several-fold per step, and their FP32 storage rounding is amplified in the
+    oracle comparison no matter how the arithmetic is done.
   * run level, at every recorded step of a full run:
         |m_gpu - m_oracle| / |m_oracle| <= 1e-4 for rms radius and energy
   * mesh field after a deposit: |E_gpu - E_oracle| <= 2e-6 max|E|, exact
@@ -32,16 +34,17 @@ pytestmark = pytest.mark.gpu
 
 TOL_PARTICLE = 1e-6
 TOL_RUN = 1e-4
-BEAM_SIZE = 1.0
+FLOOR = 1e-3       # smooth fields: relative to the particle's own amplitude
+BEAM_SIZE = 1.0    # self-consistent field: relative to the beam size (see above)
 RMAX = 5.0
 
 
-def rel_particle(Rg, Vg, Ro, Vo):
-    return np.hypot(Rg - Ro, Vg - Vo) / np.maximum(np.hypot(Ro, Vo), BEAM_SIZE)
+def rel_particle(Rg, Vg, Ro, Vo, floor=FLOOR):
+    return np.hypot(Rg - Ro, Vg - Vo) / np.maximum(np.hypot(Ro, Vo), floor)
 
 
-def assert_particles(Rg, Vg, Ro, Vo, tol=TOL_PARTICLE, what=""):
-    err = rel_particle(Rg, Vg, Ro, Vo)
+def assert_particles(Rg, Vg, Ro, Vo, tol=TOL_PARTICLE, what="", floor=FLOOR):
+    err = rel_particle(Rg, Vg, Ro, Vo, floor)
     worst = int(np.argmax(err))
     assert err[worst] <= tol, "%s: max rel err %.3e at %d (gpu %r, oracle %r)" % (
         what, err[worst], worst, (Rg[worst], Vg[worst]), (Ro[worst], Vo[worst]))
@@ -199,7 +202,8 @@ def test_poisson_ten_steps_per_particle(K, deposit):
             Ro, Vo = oracle.push(Ro, Vo, dt, eps, K, field=oracle.FIELD_POISSON, E=E, Qb=Qb,
                                  nr=nr, rmin=-RMAX, rmax=RMAX)
             R, V = sim.particles()
-            assert_particles(R, V, Ro, Vo, what="Poisson K=%d step %d" % (K, s + 1))
+            assert_particles(R, V, Ro, Vo, what="Poisson K=%d step %d" % (K, s + 1),
+                             floor=BEAM_SIZE)
 
 
 def test_poisson_full_run_moments():
@@ -253,7 +257,7 @@ def test_poisson_changing_dt_and_eps_mid_run():
             Ro, Vo = oracle.push(Ro, Vo, dt, eps, K, field=oracle.FIELD_POISSON, E=E, Qb=Qb,
                                  nr=nr, rmin=-RMAX, rmax=RMAX)
         R, V = sim.particles()
-        assert_particles(R, V, Ro, Vo, what="dt/eps changed between steps")
+        assert_particles(R, V, Ro, Vo, what="dt/eps changed between steps", floor=BEAM_SIZE)
 
 
 def test_deterministic_and_order_independent():
@@ -314,7 +318,7 @@ def test_small_and_degenerate_inputs():
             Ro, Vo = oracle.run(R0, V0, w, dt, eps, 3, 2, oracle.FIELD_POISSON, nr=nr,
                                 rmin=-RMAX, rmax=RMAX)
             R, V = sim.particles()
-            assert_particles(R, V, Ro, Vo, what="n=%d" % n)
+            assert_particles(R, V, Ro, Vo, what="n=%d" % n, floor=BEAM_SIZE)
     # a particle at rest at the origin feels no field and stays there
     with Sim(4, n_cells=nr, substeps=2) as sim:
         sim.set_particles(np.zeros(1), np.zeros(1), 1.0)
@@ -345,7 +349,7 @@ def test_off_mesh_and_nan_particles_are_counted():
         ok = np.isfinite(R0)
         Ro, Vo = oracle.run(R0[ok], V0[ok], w, 0.05, 0.01, 2, 3, oracle.FIELD_POISSON, nr=256,
                             rmin=-RMAX, rmax=RMAX)
-        assert_particles(R[ok], V[ok], Ro, Vo, what="off-mesh particles")
+        assert_particles(R[ok], V[ok], Ro, Vo, what="off-mesh particles", floor=BEAM_SIZE)
 
 
 def test_invalid_step_arguments():
@@ -393,7 +397,7 @@ def full_size_parity(n, nr, eps, dt, K, n_steps, n_sample, seed, edge=False):
             parts = [sim.particles(a, c) for a, c in ranges]
             R = np.concatenate([p[0] for p in parts])
             V = np.concatenate([p[1] for p in parts])
-            err = rel_particle(R, V, Ro[idx], Vo[idx])
+            err = rel_particle(R, V, Ro[idx], Vo[idx], BEAM_SIZE)
             worst = max(worst, float(err.max()))
             assert err.max() <= TOL_PARTICLE, (s, err.max())
             m = sim.moments(eps, EP_FIELD_POISSON)
