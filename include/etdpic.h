@@ -131,8 +131,9 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out);
 /* Release the context and all device memory it owns.  NULL is accepted. */
 ep_status ep_destroy(ep_ctx *ctx);
 
-/* Message of the last failed call on ctx (or of the last failed ep_create when
- * ctx is NULL).  Valid until the next call on the same context. */
+/* Message of the last failed call on ctx (or, when ctx is NULL, of the last
+ * failed call without a context: ep_create, ep_step_noalloc).  Valid until the
+ * next call on the same context. */
 const char *ep_last_error(const ep_ctx *ctx);
 
 /* Load n <= capacity particles (host FP64 arrays R[n], V[n], lab frame) with
@@ -372,6 +373,33 @@ ep_status ep_load(ep_ctx *ctx, const char *path, uint64_t *n_particles);
  * no context; allocates and frees two buffers of `bytes`.
  * Errors: EP_EINVAL, EP_ENOMEM, EP_EHIP. */
 ep_status ep_copy_bandwidth(int32_t device, uint64_t bytes, int32_t reps, double *gb_per_s);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the plain
+ * step of ep_step without a context.  zR[n], zV[n] are the caller's FP32
+ * device arrays (16-byte aligned) holding the rotating-frame state
+ * z = r(-phase) y at the host value *phase = t/eps mod 2 pi, with uniform
+ * weight w > 0.  n_steps macro steps of dt at eps in the field model `field`
+ * are queued on hip_stream (NULL: the null stream), and *phase receives the
+ * phase after them.  The Poisson field is first deposited from the current
+ * state and solved, as a fresh context does, on a mesh of n_cells cells on
+ * [-r_max, r_max].  The kernels, their launch order and their arguments are
+ * those of ep_step with the atomic deposit, so results equal a context's
+ * (bitwise while n_steps * substeps fits the coefficient table, else within
+ * the plain push's per-particle tolerance for the Duffing field, whose
+ * register-resident launches then store the FP32 state more often).
+ * The call allocates nothing: the mesh and the coefficient tables live in
+ * one static device array of about 1.8 MB that each device holds until the
+ * process ends.  Limits of that array: n_cells <= 8192, substeps <= 32768.
+ * Calls on the same device share it, so calls whose work overlaps on one GPU
+ * (other host threads, or other streams) race; calls queued on one stream do
+ * not.  Errors: EP_EINVAL (a limit above, n >= 2^31, bad arguments; the
+ * message says which; ep_last_error(NULL) returns it), EP_EHIP (a launch
+ * failed; asynchronous kernel errors surface at the caller's next
+ * synchronisation of hip_stream). */
+ep_status ep_step_noalloc(float *zR, float *zV, uint64_t n, double w, uint32_t n_cells,
+                          double r_max, uint32_t substeps, double dt, double eps, int32_t field,
+                          uint64_t n_steps, double *phase, int32_t device, void *hip_stream);
 
 /* Synchronise the context's stream; reports asynchronous errors. */
 ep_status ep_sync(ep_ctx *ctx);

@@ -29,7 +29,7 @@ EXPORTS = (
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
     "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect", "ep_mlp_get_samples",
     "ep_save", "ep_load", "ep_set_fine_solver", "ep_get_periods", "ep_compute_periods",
-    "ep_copy_bandwidth", "ep_mlp_set_precision",
+    "ep_copy_bandwidth", "ep_mlp_set_precision", "ep_step_noalloc",
 )
 
 
@@ -154,6 +154,7 @@ def lib():
                                 ctypes.POINTER(u64)], i32),
             "ep_save": ([vp, ctypes.c_char_p], i32),
             "ep_load": ([vp, ctypes.c_char_p, ctypes.POINTER(u64)], i32),
+            "ep_step_noalloc": ([vp, vp, u64, d, u32, d, u32, d, d, i32, u64, pd, i32, vp], i32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -380,3 +381,16 @@ def ep_load(ctx, path):
     _check(ctx, lib().ep_load(ctx, os.fsencode(path), ctypes.byref(n)))
     return int(n.value)
 
+
+def ep_step_noalloc(zR_ptr, zV_ptr, n, w, dt, eps, field, n_steps, phase, n_cells=256,
+                    r_max=5.0, substeps=1, device=0, hip_stream=None):
+    """The plain step on caller-owned FP32 device arrays (addresses as ints) at
+    the fast phase `phase`, without allocating; returns the phase after the
+    steps.  The work is queued on hip_stream (an address, or None)."""
+    ph = ctypes.c_double(float(phase))
+    _check(None, lib().ep_step_noalloc(ctypes.c_void_p(int(zR_ptr)), ctypes.c_void_p(int(zV_ptr)),
+                                       int(n), float(w), int(n_cells), float(r_max),
+                                       int(substeps), float(dt), float(eps), int(field),
+                                       int(n_steps), ctypes.byref(ph), int(device),
+                                       None if hip_stream is None else ctypes.c_void_p(hip_stream)))
+    return ph.value

@@ -66,7 +66,7 @@ struct StepTables {
 };
 
 hipError_t launch_phase_table(hipStream_t st, StepTables tab, double phi0, double dphi,
-                              double theta, double h, int K, int S);
+                              double theta, double h, int K, int S, int64_t j0 = 0);
 
 hipError_t launch_twist_in(hipStream_t st, const double *R, const double *V, float *zR,
                            float *zV, int64_t n, double c, double s);

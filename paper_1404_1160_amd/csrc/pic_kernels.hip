@@ -41,23 +41,25 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 // ------------------------------------------------------------ phase tables
 
+// Coefficients of steps j0 .. j0 + S - 1 counted from the phase phi0: step j
+// starts at fmod(phi0 + j dphi, 2 pi); entry (j - j0) K + k holds substep k.
 __global__ void phase_table_kernel(double4 *__restrict__ sub, double2 *__restrict__ endrot,
                                    double phi0, double dphi, double theta, double h, int K,
-                                   int S)
+                                   int S, int64_t j0)
 {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)S * K;
     if (idx < total) {
         const int64_t j = idx / K;
         const int64_t k = idx - j * K;
-        const double pj = fmod(phi0 + (double)j * dphi, kTwoPi);
+        const double pj = fmod(phi0 + (double)(j0 + j) * dphi, kTwoPi);
         const double ph = pj + ((double)k + 0.5) * theta;
         double s, c;
         sincos(ph, &s, &c);
         sub[idx] = make_double4(c, s, h * s, h * c);
     }
     if (idx < S) {
-        const double p1 = fmod(phi0 + (double)(idx + 1) * dphi, kTwoPi);
+        const double p1 = fmod(phi0 + (double)(j0 + idx + 1) * dphi, kTwoPi);
         double s, c;
         sincos(p1, &s, &c);
         endrot[idx] = make_double2(c, s);
@@ -65,13 +67,13 @@ __global__ void phase_table_kernel(double4 *__restrict__ sub, double2 *__restric
 }
 
 hipError_t launch_phase_table(hipStream_t st, StepTables tab, double phi0, double dphi,
-                              double theta, double h, int K, int S)
+                              double theta, double h, int K, int S, int64_t j0)
 {
     const int64_t total = (int64_t)S * K > S ? (int64_t)S * K : S;
     const int block = 256;
     const int64_t grid = (total + block - 1) / block;
     phase_table_kernel<<<dim3((unsigned)grid), dim3(block), 0, st>>>(tab.sub, tab.endrot, phi0,
-                                                                   dphi, theta, h, K, S);
+                                                                   dphi, theta, h, K, S, j0);
     return hipGetLastError();
 }
 
