@@ -425,6 +425,12 @@ def test_full_size_parity_vp_1e8():
     full_size_parity(100_000_000, 4096, 1e-3, 0.05, 1, 3, 20000, seed=13)
 
 
+def test_full_size_parity_vp_1e8_eps_1e2():
+    """The benchmark shape at the configuration's other eps: N_p = 1e8,
+    N_r = 4096, eps = 1e-2, dt = 0.05, K = 1."""
+    full_size_parity(100_000_000, 4096, 1e-2, 0.05, 1, 3, 20000, seed=13)
+
+
 def test_statistical_rms_1e8_against_oracle_subsample():
     """Full physics at scale, pinned statistically: the GPU run at N_p = 1e8
     (N_r = 4096, eps = 1e-3, dt = 0.05, K = 1) against the oracle's own
@@ -442,6 +448,36 @@ def test_statistical_rms_1e8_against_oracle_subsample():
         for _ in range(steps // every):
             sim.step(dt, eps, EP_FIELD_POISSON, every)
             gpu.append(sim.moments(eps, EP_FIELD_POISSON)["rms_radius"])
+    _, _, mom = oracle.run(Rs, Vs, 1.0 / n_sub, dt, eps, 1, steps, oracle.FIELD_POISSON, nr=nr,
+                           rmin=-RMAX, rmax=RMAX, with_moments=True)
+    orc = mom[::every, 1]
+    rel = np.abs(np.array(gpu) - orc) / orc
+    assert rel.max() <= 3.0 / math.sqrt(n_sub), rel
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("eps", [1e-3, 1e-2])
+def test_statistical_rms_1e8_full_run(eps):
+    """The at-scale configuration over its full length: 1e4 steps of the
+    1e8-particle beam (N_r = 4096, dt = 0.05, K = 1) on the GPU against the
+    oracle's own self-consistent run of the beam's first 1e6 particles
+    (weight 1e-6) over the same 1e4 steps.  The rms radii agree within
+    3/sqrt(N_sub), the sub-beam's sampling noise, every 500 steps."""
+    n, n_sub, steps, every, nr, dt = 100_000_000, 1_000_000, 10_000, 500, 4096, 0.05
+    R0, V0, w = synth.gaussian_truncated(n, seed=13)
+    Rs, Vs = R0[:n_sub].copy(), V0[:n_sub].copy()
+    gpu = []
+    with Sim(n, n_cells=nr, substeps=1) as sim:
+        sim.set_particles(R0, V0, w)
+        del R0, V0
+        gpu.append(sim.moments(eps, EP_FIELD_POISSON)["rms_radius"])
+        for _ in range(steps // every):
+            sim.step(dt, eps, EP_FIELD_POISSON, every)
+            m = sim.moments(eps, EP_FIELD_POISSON)
+            gpu.append(m["rms_radius"])
+        assert m["n_nan"] == 0 and m["n_steps"] == steps
+    print("gpu run done eps=%g, oracle sub-beam of %d for %d steps" % (eps, n_sub, steps),
+          flush=True)
     _, _, mom = oracle.run(Rs, Vs, 1.0 / n_sub, dt, eps, 1, steps, oracle.FIELD_POISSON, nr=nr,
                            rmin=-RMAX, rmax=RMAX, with_moments=True)
     orc = mom[::every, 1]
