@@ -409,7 +409,7 @@ ep_status ep_sync(ep_ctx *ctx);
  * starts collection; ep_timing_get synchronises and returns, for the kernel
  * named `kernel` ("push_poisson", "deposit", "mesh_solve", "push_duffing",
  * "mlp_push", "fallback_push",
- * "sort_count", "sort_scatter", "sort_reduce"), the summed
+ * "sort_count", "sort_offsets", "sort_scatter", "sort_combine"), the summed
  * duration in milliseconds and the number of launches.  Errors: EP_EINVAL. */
 ep_status ep_timing_enable(ep_ctx *ctx, int32_t on);
 ep_status ep_timing_get(ep_ctx *ctx, const char *kernel, double *total_ms, uint64_t *count);

@@ -118,6 +118,7 @@ struct ep_ctx {
     float *sR = nullptr, *sV = nullptr;
     unsigned *ids = nullptr, *ids2 = nullptr, *inv = nullptr;
     unsigned *counts = nullptr, *total = nullptr, *starts = nullptr;
+    unsigned long long *sums = nullptr;   // segment sums of the scatter pass [grid][nr+1]
 
     // per-chunk substep tables
     StepTables tab{};

@@ -126,14 +126,15 @@ struct SortArgs {
     float *oR, *oV;            // state after the step, cell order
     unsigned *oid;
     unsigned long long *hist;  // [nr+1] fixed-point node charges
+    unsigned long long *sums;  // [grid][nr+1] segment sums of the scatter pass
 };
 
 hipError_t setup_sort_lds(int nr);
 hipError_t launch_sort_count(hipStream_t st, const SortArgs &a, int grid);
 hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid);
 hipError_t launch_sort_scatter(hipStream_t st, const SortArgs &a, int grid);
-hipError_t launch_sort_reduce(hipStream_t st, const SortArgs &a, const float *zR, const float *zV,
-                              int n_cu);
+hipError_t launch_sort_combine(hipStream_t st, const SortArgs &a, int grid);
+size_t sort_lds_bytes_for(int nr);   // LDS of the scatter pass (the larger one)
 hipError_t launch_iota(hipStream_t st, unsigned *ids, int64_t first, int64_t n);
 hipError_t launch_inverse(hipStream_t st, const unsigned *ids, int64_t n, unsigned *inv);
 hipError_t launch_gather_f32(hipStream_t st, const float *zR, const float *zV, const unsigned *inv,

@@ -18,7 +18,7 @@ void free_all(ep_ctx *c)
                     (void *)c->fscal, (void *)c->tab.sub, (void *)c->tab.endrot,
                     (void *)c->stageR, (void *)c->stageV, (void *)c->mpartial, (void *)c->mout,
                     (void *)c->sR, (void *)c->sV, (void *)c->ids, (void *)c->ids2, (void *)c->inv,
-                    (void *)c->counts, (void *)c->total, (void *)c->starts,
+                    (void *)c->counts, (void *)c->total, (void *)c->starts, (void *)c->sums,
                     (void *)c->mcount, (void *)c->mout_count})
         if (p) (void)hipFree(p);
     for (auto &p : c->pending) c->event_pool.push_back(p.second);
@@ -154,14 +154,14 @@ ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int 
     a.oV = oV;
     a.oid = c->ids2;
     a.hist = c->hist;
+    a.sums = c->sums;
     HIPCHK(c, timed_launch(c, "sort_count", [&] { return launch_sort_count(c->stream, a, grid); }));
     HIPCHK(c, timed_launch(c, "sort_offsets", [&] { return launch_sort_offsets(c->stream, a, grid); }));
     HIPCHK(c, timed_launch(c, "sort_scatter", [&] { return launch_sort_scatter(c->stream, a, grid); }));
     c->zR = oR;
     c->zV = oV;
     std::swap(c->ids, c->ids2);
-    HIPCHK(c, timed_launch(c, "sort_reduce",
-                           [&] { return launch_sort_reduce(c->stream, a, c->zR, c->zV, c->n_cu); }));
+    HIPCHK(c, timed_launch(c, "sort_combine", [&] { return launch_sort_combine(c->stream, a, grid); }));
     return solve_mesh(c, c->mesh(), false);
 }
 
@@ -233,7 +233,10 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
         c->fail(EP_EINVAL, "ep_create: mesh of %u cells needs %zu B of LDS", cfg->n_cells, lds);
         return bail(EP_EINVAL);
     }
-    int per_cu = (int)(lds_cu / lds);
+    // the sort passes' LDS (up to 20 N_r bytes) fits twice per CU up to
+    // N_r = 4096, like the fused push's
+    const size_t lds_sort = sort_lds_bytes_for((int)cfg->n_cells);
+    int per_cu = (int)(lds_cu / (lds > lds_sort ? lds : lds_sort));
     if (per_cu > 2) per_cu = 2;
     if (per_cu < 1) per_cu = 1;
     // The sort passes keep one counter row per workgroup: the resident
@@ -260,6 +263,7 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
         CREATE_CHK(dalloc(&c->ids2, np_pad));
         CREATE_CHK(dalloc(&c->inv, np_pad));
         CREATE_CHK(dalloc(&c->counts, (size_t)c->sort_grid_cap * nn));
+        CREATE_CHK(dalloc(&c->sums, (size_t)c->sort_grid_cap * nn));
         CREATE_CHK(dalloc(&c->total, nn));
         CREATE_CHK(dalloc(&c->starts, nn));
         CREATE_CHK(setup_sort_lds((int)cfg->n_cells));

@@ -7,9 +7,13 @@
 //   sort_offsets_kernel  per key, exclusive offsets of the workgroups' counts
 //   sort_starts_kernel   exclusive scan of the key totals: segment starts
 //   sort_scatter_kernel  push again (same arithmetic, same keys) and write each
-//                        particle, with its id, to its slot in cell order
-//   sort_reduce_kernel   one workgroup per cell: segmented reduction of the
-//                        CIC weights of that cell's contiguous particles
+//                        particle, with its id, to its slot in cell order.
+//                        The particles that workgroup b sends to cell k fill
+//                        the contiguous segment (k, b) of the sorted array;
+//                        the workgroup sums that segment's CIC weights as it
+//                        writes it and stores the sums, one row per workgroup
+//   sort_combine_kernel  per node, the sum of the segment sums over the
+//                        workgroups in index order
 // The weights are the same 2^-32 fixed-point integers as the fused deposit,
 // so the node charges are bitwise identical to it; particles within one
 // (workgroup, cell) segment may land in any order, which changes no result.
@@ -20,27 +24,40 @@ namespace etd {
 
 namespace {
 
+// LDS of the sort passes, 20 N_r bytes at most (80 KB at N_r = 4096, so two
+// workgroups fit a CU): the field table, one slot counter per cell and, in
+// the scatter pass, the sum A_k of the node-(k+1) weights of the workgroup's
+// particles in cell k (u64).  Off-mesh particles (key N_r) are few: their
+// counter is a register (count pass) or the workgroup's global offset entry
+// (scatter pass).
 struct SortLds {
     float2 *Et;
     unsigned *C;
+    unsigned long long *A;
 };
+
+__host__ __device__ constexpr size_t sort_sums_offset(int nr)
+{
+    return ((size_t)nr * sizeof(float2) + (size_t)nr * sizeof(unsigned) + 7) & ~(size_t)7;
+}
 
 __device__ __forceinline__ SortLds sort_lds(unsigned char *smem, int nr)
 {
     SortLds s;
     s.Et = reinterpret_cast<float2 *>(smem);
     s.C = reinterpret_cast<unsigned *>(smem + (size_t)nr * sizeof(float2));
+    s.A = reinterpret_cast<unsigned long long *>(smem + sort_sums_offset(nr));
     return s;
 }
 
-// New FP32 state and cell key of one particle after the step.  FAST: a
-// particle with |z|^2 < lim2 (see on_mesh_limit2) takes the gather without
-// range tests; it pays only for several substeps, so the launchers choose it
-// for K > 1.
+// New FP32 state, cell key and CIC weight of one particle after the step.
+// FAST: a particle with |z|^2 < lim2 (see on_mesh_limit2) takes the gather
+// without range tests; it pays only for several substeps, so the launchers
+// choose it for K > 1.
 template <bool FAST>
 __device__ __forceinline__ void step_one(const MeshView &m, const double4 *__restrict__ sub, int K,
                                          double lim2, double2 er, float &fr, float &fv, int nr,
-                                         int &key)
+                                         int &key, double &th)
 {
     double zr[1] = {fr}, zv[1] = {fv};
     if (FAST && fma(zr[0], zr[0], zv[0] * zv[0]) < lim2)
@@ -50,7 +67,6 @@ __device__ __forceinline__ void step_one(const MeshView &m, const double4 *__res
     fr = (float)zr[0];
     fv = (float)zv[0];
     int k;
-    double th;
     key = cell_of(fma(er.x, (double)fr, er.y * (double)fv), m.inv_hr, m.half, m.c, k, th) ? k
                                                                                           : nr;
 }
@@ -66,15 +82,19 @@ __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     int64_t n, const double4 *__restrict__ sub, const double2 *__restrict__ endrot, int K,
     double inv_hr, const float2 *__restrict__ etab, const double *__restrict__ fscal, int nr,
     unsigned *__restrict__ counts, const unsigned *__restrict__ starts,
-    float *__restrict__ oR, float *__restrict__ oV, unsigned *__restrict__ oid)
+    float *__restrict__ oR, float *__restrict__ oV, unsigned *__restrict__ oid,
+    unsigned long long *__restrict__ sums)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const SortLds L = sort_lds(smem, nr);
     const int tid = threadIdx.x;
     const int nk = nr + 1;
     unsigned *cnt = counts + (size_t)blockIdx.x * nk;
-    for (int i = tid; i < nr; i += blockDim.x) L.Et[i] = etab[i];
-    for (int i = tid; i < nk; i += blockDim.x) L.C[i] = SCATTER ? starts[i] + cnt[i] : 0u;
+    for (int i = tid; i < nr; i += blockDim.x) {
+        L.Et[i] = etab[i];
+        L.C[i] = SCATTER ? starts[i] + cnt[i] : 0u;
+        if (SCATTER) L.A[i] = 0ull;
+    }
     MeshView m;
     m.Et = L.Et;
     m.H = nullptr;
@@ -84,17 +104,32 @@ __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     m.Qb = fscal[kQb];
     const double2 er = endrot[0];
     const double lim2 = FAST ? on_mesh_limit2(m, sub, K, fscal[kEmax]) : -1.0;
+    const unsigned off_base = SCATTER ? starts[nr] : 0u;
+    unsigned n_off = 0u;   // count pass: this thread's off-mesh particles
     __syncthreads();
 
     auto visit = [&](int64_t i, float fr, float fv) {
         int key;
-        step_one<FAST>(m, sub, K, lim2, er, fr, fv, nr, key);
-        const unsigned slot = atomicAdd(&L.C[key], 1u);
-        if (SCATTER) {
-            oR[slot] = fr;
-            oV[slot] = fv;
-            oid[slot] = ids[i];
+        double th = 0.0;
+        step_one<FAST>(m, sub, K, lim2, er, fr, fv, nr, key, th);
+        if (!SCATTER) {
+            if (key < nr)
+                atomicAdd(&L.C[key], 1u);
+            else
+                ++n_off;
+            return;
         }
+        unsigned slot;
+        if (key < nr) {
+            slot = atomicAdd(&L.C[key], 1u);
+            // the particle's weight to node key + 1 goes to its segment's sum
+            atomicAdd(&L.A[key], (unsigned long long)fixed_weight(th));
+        } else {
+            slot = off_base + atomicAdd(&cnt[nr], 1u);
+        }
+        oR[slot] = fr;
+        oV[slot] = fv;
+        oid[slot] = ids[i];
     };
     const int64_t n4 = n >> 2;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -112,9 +147,61 @@ __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
         const int64_t i = (n4 << 2) + gt;
         visit(i, zR[i], zV[i]);
     }
+    __syncthreads();
     if (!SCATTER) {
+        for (int i = tid; i < nr; i += blockDim.x) cnt[i] = L.C[i];
+        // the off-mesh count, summed over the workgroup in the counters'
+        // storage, which the loop above has read
+        const unsigned wsum = wave_sum(n_off);
         __syncthreads();
-        for (int i = tid; i < nk; i += blockDim.x) cnt[i] = L.C[i];
+        if ((tid & 63) == 0) L.C[tid >> 6] = wsum;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned t = 0u;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += L.C[w];
+            cnt[nr] = t;
+        }
+        return;
+    }
+    // The workgroup's particles in cell k fill segment (k, b): n_k of them,
+    // with node weights sum(2^32 - q) = n_k 2^32 - A_k to node k and A_k to
+    // node k + 1.  Row b holds the workgroup's contribution to every node.
+    unsigned long long *row = sums + (size_t)blockIdx.x * nk;
+    for (int k = tid; k < nk; k += blockDim.x) {
+        unsigned long long v = 0ull;
+        if (k < nr) {
+            const unsigned long long nk_ = (unsigned long long)(L.C[k] - starts[k] - cnt[k]);
+            v = (nk_ << 32) - L.A[k];
+        }
+        if (k > 0) v += L.A[k - 1];
+        row[k] = v;
+    }
+}
+
+// hist[k] = sum over workgroups b = 0 .. G-1 of the segment sums sums[b][k],
+// in a fixed order: a workgroup takes 16 nodes; its 16 x 16 threads sum 16
+// consecutive chunks of the rows, then one thread per node adds the chunk
+// sums in chunk order.
+constexpr int kCombKeys = 16, kCombChunks = 16;
+
+__global__ __launch_bounds__(kCombKeys * kCombChunks) void sort_combine_kernel(
+    const unsigned long long *__restrict__ sums, int G, int nk,
+    unsigned long long *__restrict__ hist)
+{
+    __shared__ unsigned long long part[kCombChunks][kCombKeys];
+    const int kl = threadIdx.x % kCombKeys, ch = threadIdx.x / kCombKeys;
+    const int k = blockIdx.x * kCombKeys + kl;
+    const int rows = (G + kCombChunks - 1) / kCombChunks;
+    const int b0 = ch * rows, b1 = min(b0 + rows, G);
+    unsigned long long a = 0ull;
+    if (k < nk)
+        for (int b = b0; b < b1; ++b) a += sums[(size_t)b * nk + k];
+    part[ch][kl] = a;
+    __syncthreads();
+    if (ch == 0 && k < nk) {
+        unsigned long long t = 0ull;
+        for (int c = 0; c < kCombChunks; ++c) t += part[c][kl];
+        hist[k] = t;
     }
 }
 
@@ -173,47 +260,6 @@ __global__ __launch_bounds__(1024) void sort_starts_kernel(const unsigned *__res
     }
 }
 
-// Segmented reduction: one workgroup per cell k.  The cell's particles are
-// contiguous in cell order; their weights (1 - th, th) go to nodes k and k+1
-// (one wave-tree sum, two global atomics per cell).  Keys are recomputed
-// with the arithmetic of the count and scatter passes, so every particle of
-// the segment lies in cell k; a particle that did not would be added on its
-// own.
-__global__ __launch_bounds__(256) void sort_reduce_kernel(
-    const float *__restrict__ zR, const float *__restrict__ zV, const unsigned *__restrict__ starts,
-    const unsigned *__restrict__ total, const double2 *__restrict__ endrot, double inv_hr, int nr,
-    unsigned long long *__restrict__ hist)
-{
-    __shared__ unsigned long long wtot[4];
-    const int k = blockIdx.x;
-    const double2 er = endrot[0];
-    const double half = 0.5 * (double)nr;
-    const int c = nr >> 1;
-    const unsigned s0 = starts[k], cnt = total[k];
-    unsigned long long A = 0ull, B = 0ull;
-    for (unsigned j = threadIdx.x; j < cnt; j += blockDim.x) {
-        const unsigned i = s0 + j;
-        int kk;
-        double th;
-        if (cell_of(fma(er.x, (double)zR[i], er.y * (double)zV[i]), inv_hr, half, c, kk, th)) {
-            const unsigned q = fixed_weight(th);
-            if (kk == k) {
-                A += 4294967296ull - q;
-                B += q;
-            } else {
-                atomicAdd(&hist[kk], 4294967296ull - q);
-                atomicAdd(&hist[kk + 1], (unsigned long long)q);
-            }
-        }
-    }
-    A = block_sum<unsigned long long>(A, wtot);
-    B = block_sum<unsigned long long>(B, wtot);
-    if (threadIdx.x == 0) {
-        if (A) atomicAdd(&hist[k], A);
-        if (B) atomicAdd(&hist[k + 1], B);
-    }
-}
-
 __global__ void iota_kernel(unsigned *__restrict__ ids, int64_t first, int64_t n)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -264,31 +310,33 @@ hipError_t launch_gather_f32(hipStream_t st, const float *zR, const float *zV, c
     return hipGetLastError();
 }
 
-static size_t sort_lds_bytes(int nr)
+static size_t sort_lds_bytes(int nr, bool scatter)
 {
-    return (size_t)nr * sizeof(float2) + (size_t)(nr + 1) * sizeof(unsigned);
+    return scatter ? sort_sums_offset(nr) + (size_t)nr * sizeof(unsigned long long)
+                   : (size_t)nr * sizeof(float2) + (size_t)nr * sizeof(unsigned);
 }
+
+size_t sort_lds_bytes_for(int nr) { return sort_lds_bytes(nr, true); }
 
 hipError_t setup_sort_lds(int nr)
 {
-    const int lds = (int)sort_lds_bytes(nr);
+    hipError_t e;
     for (const void *f : {reinterpret_cast<const void *>(&sort_pass_kernel<false, false>),
-                          reinterpret_cast<const void *>(&sort_pass_kernel<false, true>),
-                          reinterpret_cast<const void *>(&sort_pass_kernel<true, false>),
-                          reinterpret_cast<const void *>(&sort_pass_kernel<true, true>)}) {
-        const hipError_t e = raise_dynamic_lds(f, lds);
-        if (e != hipSuccess) return e;
-    }
+                          reinterpret_cast<const void *>(&sort_pass_kernel<false, true>)})
+        if ((e = raise_dynamic_lds(f, (int)sort_lds_bytes(nr, false))) != hipSuccess) return e;
+    for (const void *f : {reinterpret_cast<const void *>(&sort_pass_kernel<true, false>),
+                          reinterpret_cast<const void *>(&sort_pass_kernel<true, true>)})
+        if ((e = raise_dynamic_lds(f, (int)sort_lds_bytes(nr, true))) != hipSuccess) return e;
     return hipSuccess;
 }
 
 hipError_t launch_sort_count(hipStream_t st, const SortArgs &a, int grid)
 {
     return dispatch(a.K > 1 ? sort_pass_kernel<false, true> : sort_pass_kernel<false, false>,
-                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st, a.zR, a.zV, a.ids,
-                    a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
+                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr, false), st, a.zR, a.zV,
+                    a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
                     (const unsigned *)nullptr, (float *)nullptr, (float *)nullptr,
-                    (unsigned *)nullptr);
+                    (unsigned *)nullptr, (unsigned long long *)nullptr);
 }
 
 hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid)
@@ -305,18 +353,17 @@ hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid)
 hipError_t launch_sort_scatter(hipStream_t st, const SortArgs &a, int grid)
 {
     return dispatch(a.K > 1 ? sort_pass_kernel<true, true> : sort_pass_kernel<true, false>,
-                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr), st, a.zR, a.zV, a.ids,
-                    a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
-                    (const unsigned *)a.starts, a.oR, a.oV, a.oid);
+                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr, true), st, a.zR, a.zV,
+                    a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
+                    (const unsigned *)a.starts, a.oR, a.oV, a.oid, a.sums);
 }
 
-hipError_t launch_sort_reduce(hipStream_t st, const SortArgs &a, const float *zR, const float *zV,
-                              int n_cu)
+hipError_t launch_sort_combine(hipStream_t st, const SortArgs &a, int grid)
 {
-    (void)n_cu;
-    return dispatch(sort_reduce_kernel, dim3(a.nr), dim3(256), 0, st, zR, zV,
-                    (const unsigned *)a.starts, (const unsigned *)a.total, a.endrot, a.inv_hr,
-                    a.nr, a.hist);
+    const int nk = a.nr + 1;
+    return dispatch(sort_combine_kernel, dim3((nk + kCombKeys - 1) / kCombKeys),
+                    dim3(kCombKeys * kCombChunks), 0, st, (const unsigned long long *)a.sums, grid,
+                    nk, a.hist);
 }
 
 hipError_t launch_iota(hipStream_t st, unsigned *ids, int64_t first, int64_t n)
