@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--learned-eval", type=int, default=10_000_000)
     ap.add_argument("--learned-vp-data", type=int, default=1_000_000,
                     help="beam size of the self-generated Vlasov-Poisson training run")
+    ap.add_argument("--learned-vp-eval", type=int, default=100_000_000,
+                    help="particles of the learned Vlasov-Poisson comparison")
+    ap.add_argument("--learned-vp-steps", type=int, default=1000,
+                    help="steps of the learned Vlasov-Poisson comparison")
     return ap.parse_args()
 
 
@@ -157,9 +161,9 @@ def cpu_baseline(n_full, cells, eps, dt, K, seconds):
 
 # algorithmic HBM bytes per particle of each particle kernel (FP32 state and
 # u32 ids; the mesh is LDS/L2 resident)
-KERNEL_BYTES = {"push_poisson": 16, "sort_count": 8, "sort_scatter": 24, "sort_reduce": 8}
+KERNEL_BYTES = {"push_poisson": 16, "sort_count": 8, "sort_scatter": 24}
 STEP_KERNELS = ("push_poisson", "mesh_solve", "potential", "sort_count", "sort_offsets", "sort_scatter",
-                "sort_reduce")
+                "sort_combine")
 
 
 def run_pic(args, deposit, steps, warmup, R0, V0, w):
@@ -221,6 +225,33 @@ def run_pic(args, deposit, steps, warmup, R0, V0, w):
                 "ms_per_step_without_timing_events": ms_untimed}
     kernels["_transfer"] = transfer
     return n * steps / elapsed, elapsed / steps * 1e3, kernels, mom
+
+
+# network flops per particle-step of the learned push: 2 (5*64 + 64*64 + 64*2)
+# for the 5-input network (Duffing), 2 (6*64 + 64*64 + 64*2) with the field
+# feature; dense BF16 and FP16 MFMA peak of the MI355X
+LEARNED_FLOPS = {"duffing": 9088, "poisson": 9216}
+MFMA_PEAK_TFLOPS = 2500.0
+
+
+def learned_roofline(line):
+    """MFMA roofline of the learned push's network kernel (mlp_push), per
+    field and inference operand type: algorithmic network flops per
+    particle-step times the kernel's own particle-steps/s (HIP events around
+    its launches in the comparison runs), against the dense 16-bit MFMA peak."""
+    out = {}
+    for key, field in (("learned_vs_plain", "duffing"), ("learned_vs_plain_vp", "poisson")):
+        for e in line.get(key, {}).get("learned", []):
+            if e["drift_tol"] is not None:
+                continue
+            rate = e["network_particle_steps_per_s"]
+            tf = rate * LEARNED_FLOPS[field] / 1e12
+            out["%s_%s" % (field, e["precision"])] = {
+                "bound": "mfma", "achieved": tf, "peak": MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / MFMA_PEAK_TFLOPS, "traffic": None, "kernel": "mlp_push",
+                "flop_per_particle_step": LEARNED_FLOPS[field],
+                "network_particle_steps_per_s": rate}
+    return out
 
 
 def main():
@@ -298,14 +329,29 @@ def main():
     del R0, V0
     if not args.no_learned:
         from paper_1404_1160_amd import compare
+        say = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         print("bench: learned-vs-plain comparison", file=sys.stderr, flush=True)
         line["learned_vs_plain"] = compare.equal_error(
-            n_train=args.learned_train, n_eval=args.learned_eval,
-            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
-        print("bench: learned-vs-plain comparison, Vlasov-Poisson", file=sys.stderr, flush=True)
+            n_train=args.learned_train, n_eval=args.learned_eval, log=say)
+        print("bench: learned-vs-plain comparison, Vlasov-Poisson at scale", file=sys.stderr,
+              flush=True)
+        # the learned Vlasov-Poisson workload at its size: 1e8 particles,
+        # N_r = 4096, eps = 1e-3, dt = 0.1, 1e3 steps (the full 1e5 steps are
+        # out of the default run's time), reference plain K = 400
         line["learned_vs_plain_vp"] = compare.equal_error_vp(
-            n_eval=args.learned_eval, n_data=args.learned_vp_data,
-            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+            n_eval=args.learned_vp_eval, n_data=args.learned_vp_data,
+            steps=args.learned_vp_steps, every=max(10, args.learned_vp_steps // 20),
+            plain_Ks=(50, 100, 200), K_ref=400, extra_tols=(), single_run=True, log=say)
+        line["roofline_learned"] = learned_roofline(line)
+    if not args.no_paper_schemes:
+        from paper_1404_1160_amd import compare
+        print("bench: the paper's self-consistent long run (eps 1e-3, t = 60)", file=sys.stderr,
+              flush=True)
+        runs = ((1e-3, 60.0, (10.0, 30.0, 60.0)),)
+        if args.long_time:
+            runs += ((1e-4, 90.0, (30.0, 60.0, 90.0)),)
+        line["paper_schemes_long_vp"] = compare.paper_schemes_long_vp(
+            runs=runs, log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if args.long_time:
         from paper_1404_1160_amd import compare
         print("bench: long-time learned Vlasov-Poisson run", file=sys.stderr, flush=True)

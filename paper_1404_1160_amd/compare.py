@@ -7,9 +7,13 @@ an evaluation beam for `steps` steps.  Error = the largest relative
 rms-radius error over the run (recorded every `every` steps) against a
 reference run of the plain push with K_ref substeps; the maximum over the run
 rather than the final value, because the signed final error of a single run
-can pass through zero by chance.  Throughput = particle-steps/s of the whole run (wall clock around
-synchronised GPU work, particles resident in HBM).  The equal-error point is
-the smallest plain K whose error does not exceed the learned form's.
+can pass through zero by chance.  Throughput = particle-steps/s of the whole
+run (wall clock around synchronised GPU work, particles resident in HBM).
+The equal-error point: the plain sweep (factor-2 steps in K) is refined by
+bisection in K until a plain run's error is within 10 % of the learned
+error, and the plain throughput at the learned error is interpolated
+log-log between the nearest plain runs above and below it; the gain is the
+learned throughput over that.
 
 Vlasov-Poisson workload (`equal_error_vp`): the beam R ~ N(0, 1) truncated
 to |R| < 4, V ~ N(0, 1), N_r cells on [-5, 5], eps = 1e-3, dt = 0.1.  The
@@ -77,25 +81,82 @@ def train(sim, n_train, epochs, K_fine, seed=14, init_seed=5, batch=None, lr=3e-
     return capi.ep_mlp_train(sim.ctx, R, V, DT, EPS, K_fine, batch, epochs, lr, lr_final, SIGMA)
 
 
-def _equal_error_point(plain, entry):
-    match = [q for q in plain if q["rms_err"] <= entry["rms_err"]]
-    if not match:
+def _interp_rate(lo, hi, err):
+    """Plain throughput at the error `err` between two plain runs whose errors
+    bracket it, interpolated linearly in log(throughput) against log(error)
+    (locally err ~ K^-p and throughput ~ K^-1, both straight lines there)."""
+    if hi["rms_err"] == lo["rms_err"]:
+        return hi["particle_steps_per_s"]
+    f = (np.log(err) - np.log(lo["rms_err"])) / (np.log(hi["rms_err"]) - np.log(lo["rms_err"]))
+    return float(np.exp(np.log(lo["particle_steps_per_s"]) +
+                        f * (np.log(hi["particle_steps_per_s"]) -
+                             np.log(lo["particle_steps_per_s"]))))
+
+
+def _refine(plain, run_plain, err, rel=0.1, max_runs=4):
+    """Bisection in log K between the plain runs whose errors bracket `err`
+    (appending new runs to `plain`) until one run's error lies within
+    +-rel of it, or max_runs runs were added; returns that run or None."""
+    for _ in range(max_runs + 1):
+        near = [q for q in plain if abs(q["rms_err"] / err - 1.0) <= rel]
+        if near:
+            return min(near, key=lambda q: q["K"])
+        above = [q for q in plain if q["rms_err"] > err]
+        below = [q for q in plain if q["rms_err"] <= err]
+        if not above or not below or run_plain is None:
+            return None
+        lo = max(above, key=lambda q: q["K"])
+        hi = min((q for q in below if q["K"] > lo["K"]), key=lambda q: q["K"], default=None)
+        if hi is None:
+            return None
+        K = int(round(np.sqrt(lo["K"] * hi["K"])))
+        if K <= lo["K"] or K >= hi["K"]:
+            return None
+        plain.append(run_plain(K))
+        plain.sort(key=lambda q: q["K"])
+    return None
+
+
+def _equal_error_point(plain, entry, run_plain=None):
+    """The plain push at the learned run's error.  The plain sweep is refined
+    by bisection in K until a plain run's error is within 10 % of the learned
+    error; the gain is the learned throughput over the plain throughput
+    interpolated (log-log) at the learned error between the nearest plain
+    runs above and below it.  `matched` is the refined run itself."""
+    err = entry["rms_err"]
+    matched = _refine(plain, run_plain, err)
+    above = [q for q in plain if q["rms_err"] > err]
+    below = [q for q in plain if q["rms_err"] <= err]
+    if not below:
         return {"plain_K": None, "gain": None,
                 "note": "no plain K in the sweep reached the learned error"}
-    q = min(match, key=lambda e: e["K"])
-    return {"plain_K": q["K"], "plain_particle_steps_per_s": q["particle_steps_per_s"],
-            "learned_particle_steps_per_s": entry["particle_steps_per_s"],
-            "gain": entry["particle_steps_per_s"] / q["particle_steps_per_s"],
-            "rms_err_learned": entry["rms_err"], "rms_err_plain": q["rms_err"]}
+    hi = min(below, key=lambda q: q["K"])
+    lo = max((q for q in above if q["K"] < hi["K"]), key=lambda q: q["K"], default=None)
+    rate = hi["particle_steps_per_s"] if lo is None else _interp_rate(lo, hi, err)
+    res = {"plain_K_bracket": [None if lo is None else lo["K"], hi["K"]],
+           "plain_rms_err_bracket": [None if lo is None else lo["rms_err"], hi["rms_err"]],
+           "plain_particle_steps_per_s": rate,
+           "learned_particle_steps_per_s": entry["particle_steps_per_s"],
+           "gain": entry["particle_steps_per_s"] / rate,
+           "rms_err_learned": err,
+           "gain_vs_cheapest_not_worse": entry["particle_steps_per_s"] /
+           hi["particle_steps_per_s"]}
+    if matched is not None:
+        res["matched"] = {"K": matched["K"], "rms_err": matched["rms_err"],
+                          "particle_steps_per_s": matched["particle_steps_per_s"],
+                          "gain": entry["particle_steps_per_s"] /
+                          matched["particle_steps_per_s"]}
+    return res
 
 
 PREC_NAMES = {EP_MLP_BF16: "bf16", EP_MLP_FP16: "fp16"}
 
 
-def _equal_error_points(out, plain, learned, tol=None):
+def _equal_error_points(out, plain, learned, tol=None, run_plain=None):
     """Equal-error points of the learned runs, per precision p:
     "equal_error_<p>" at the drift bound (the first checked run unless tol is
-    given) and "equal_error_no_check_<p>"; "gains" collects their gains."""
+    given) and "equal_error_no_check_<p>"; "gains" collects their gains
+    (interpolated to the learned error, see _equal_error_point)."""
     gains = {}
     for name in dict.fromkeys(e["precision"] for e in learned):
         runs = [e for e in learned if e["precision"] == name]
@@ -103,10 +164,10 @@ def _equal_error_points(out, plain, learned, tol=None):
                    (tol is None or e["drift_tol"] == tol)]
         g = {}
         if checked:
-            out["equal_error_" + name] = _equal_error_point(plain, checked[0])
+            out["equal_error_" + name] = _equal_error_point(plain, checked[0], run_plain)
             g["with_check"] = out["equal_error_" + name]["gain"]
         out["equal_error_no_check_" + name] = _equal_error_point(
-            plain, [e for e in runs if e["drift_tol"] is None][0])
+            plain, [e for e in runs if e["drift_tol"] is None][0], run_plain)
         g["no_check"] = out["equal_error_no_check_" + name]["gain"]
         gains[name] = g
     out["gains"] = gains
@@ -139,15 +200,17 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
         return (float(np.max(np.abs(hist - hist_ref) / hist_ref)),
                 float(np.median(np.hypot(R - Rr, V - Vr))))
 
-    plain = []
-    for K in plain_Ks:
+    def run_plain(K):
         with Sim(n_eval, substeps=K) as s:
             s.set_particles(Re, Ve, we)
             el = _timed_run(s, steps)
             err, perr = run_error(s)
-        plain.append({"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
-                      "median_particle_err": perr})
-        say("plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, plain[-1]["particle_steps_per_s"], err))
+        q = {"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
+             "median_particle_err": perr}
+        say("plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, q["particle_steps_per_s"], err))
+        return q
+
+    plain = [run_plain(K) for K in plain_Ks]
     out["plain"] = plain
 
     with Sim(n_eval, substeps=1) as sim:
@@ -183,7 +246,7 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
                 learned[-1]["fallback_rate"]))
         capi.ep_set_push_mode(sim.ctx, EP_PUSH_PLAIN)
     out["learned"] = learned
-    _equal_error_points(out, plain, learned)
+    _equal_error_points(out, plain, learned, run_plain=run_plain)
     return out
 
 
@@ -195,13 +258,17 @@ VP_DT, VP_EPS, VP_NR = 0.1, 1e-3, 4096
 VP_NORM_INIT = np.array([1.0, 100.0, 0.25, 0.0, 1.0, 0.0, 1.0, 1.0])
 
 
-def _vp_history(sim, R0, V0, w, steps, every):
+def _vp_history(sim, R0, V0, w, steps, every, energy=False):
+    """rms radius (and with energy, the total energy) every `every` steps."""
     sim.set_particles(R0, V0, w)
-    out = [sim.moments(VP_EPS, EP_FIELD_POISSON)["rms_radius"]]
+    m = sim.moments(VP_EPS, EP_FIELD_POISSON)
+    out, en = [m["rms_radius"]], [m["energy"]]
     for _ in range(steps // every):
         sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, every)
-        out.append(sim.moments(VP_EPS, EP_FIELD_POISSON)["rms_radius"])
-    return np.array(out)
+        m = sim.moments(VP_EPS, EP_FIELD_POISSON)
+        out.append(m["rms_radius"])
+        en.append(m["energy"])
+    return (np.array(out), np.array(en)) if energy else np.array(out)
 
 
 def train_vp(n_data, steps, nr=VP_NR, K_data=400, K_fine=12800, collect_every=10, epochs=40,
@@ -228,22 +295,48 @@ def train_vp(n_data, steps, nr=VP_NR, K_data=400, K_fine=12800, collect_every=10
 def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs=40,
                    K_fine=12800, plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5,
                    extra_tols=(1e-4, 1e-3), K_fb=400, seed_eval=17, every=10,
-                   precisions=(EP_MLP_BF16, EP_MLP_FP16), log=None):
+                   precisions=(EP_MLP_BF16, EP_MLP_FP16), single_run=False, n_sample=1_000_000,
+                   log=None):
     """As equal_error, for the Vlasov-Poisson beam; the learned push runs, for
     each precision, at the drift bound tol (the equal-error point), at
-    extra_tols and without the check."""
+    extra_tols and without the check.  With single_run (the at-scale
+    workload, where every run is long) each scheme's rate comes from the run
+    that records its rms radius (a moments call every `every` steps, < 1 % of
+    the step time at 1e8 particles) instead of a run of its own.  Every run
+    also reports its energy drift and the median particle error of the first
+    n_sample particles at the end against the reference."""
     def say(msg):
         if log:
             log(msg)
 
     Re, Ve, we = synth.gaussian_truncated(n_eval, seed=seed_eval)
+    ns = min(n_sample, n_eval)
     out = {"workload": {"field": "poisson", "eps": VP_EPS, "dt": VP_DT, "n_cells": nr,
                         "n_eval": n_eval, "n_data": n_data, "steps": steps, "K_fine": K_fine,
-                        "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb}}
+                        "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb,
+                        "recorded_every": every}}
     with Sim(n_eval, n_cells=nr, substeps=K_ref) as ref:
-        hist_ref = _vp_history(ref, Re, Ve, we, steps, every)
+        hist_ref, e_ref = _vp_history(ref, Re, Ve, we, steps, every, energy=True)
+        Rr, Vr = ref.particles(0, ns)
     out["rms_ref"] = float(hist_ref[-1])
+    out["reference_energy_drift"] = float(abs(e_ref[-1] / e_ref[0] - 1))
     say("vp reference K=%d rms %.6f" % (K_ref, hist_ref[-1]))
+
+    def measured(sim):
+        """(seconds, rms-radius error, energy drift, median particle error);
+        timed apart from the recording run unless single_run."""
+        sim.set_particles(Re, Ve, we)
+        sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, 1)   # field and tables ready
+        el = None if single_run else timed(sim)
+        sim.sync()
+        t0 = time.perf_counter()
+        h, e = _vp_history(sim, Re, Ve, we, steps, every, energy=True)
+        sim.sync()
+        if single_run:
+            el = time.perf_counter() - t0
+        R, V = sim.particles(0, ns)
+        return (el, float(np.max(np.abs(h - hist_ref) / hist_ref)), float(abs(e[-1] / e[0] - 1)),
+                float(np.median(np.hypot(R - Rr, V - Vr))))
 
     def timed(sim):
         sim.set_particles(Re, Ve, we)
@@ -255,21 +348,20 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
         sim.sync()
         return time.perf_counter() - t0
 
-    def error(sim):
-        h = _vp_history(sim, Re, Ve, we, steps, every)
-        return float(np.max(np.abs(h - hist_ref) / hist_ref))
-
-    plain = []
-    for K in plain_Ks:
+    def run_plain(K):
         with Sim(n_eval, n_cells=nr, substeps=K) as s:
-            el = timed(s)
-            err = error(s)
-        plain.append({"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err})
-        say("vp plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, plain[-1]["particle_steps_per_s"], err))
+            el, err, drift, perr = measured(s)
+        q = {"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
+             "energy_drift": drift, "median_particle_err": perr}
+        say("vp plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, q["particle_steps_per_s"], err))
+        return q
+
+    plain = [run_plain(K) for K in plain_Ks]
     out["plain"] = plain
 
+    # the same number of collected time levels (20) whatever the run length
     p, norm, rep, n_samples = train_vp(n_data, steps, nr=nr, K_fine=K_fine, epochs=epochs,
-                                       log=log)
+                                       collect_every=max(10, steps // 20), log=log)
     rep["n_samples"] = n_samples
     out["train"] = rep
     say("vp trained on %d samples: loss %.4f -> %.4f in %d steps (%.0f ms)" % (
@@ -284,24 +376,28 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
                                   K_fb)
             sim.set_particles(Re, Ve, we)
             f0 = sim.moments(VP_EPS, EP_FIELD_POISSON)["n_fallback"]
-            el = timed(sim)
+            el, err, drift, perr = measured(sim)
             f1 = sim.moments(VP_EPS, EP_FIELD_POISSON)["n_fallback"]
             # per-kernel times from a separate short run with timing events
             capi.ep_timing_enable(sim.ctx, True)
             sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, 20)
             mlp_ms, cnt = capi.ep_timing_get(sim.ctx, "mlp_push")
+            fb_ms, _ = capi.ep_timing_get(sim.ctx, "fallback_push")
             capi.ep_timing_enable(sim.ctx, False)
-            err = error(sim)
+            runs = steps + 1 if single_run else 2 * steps + 2
             learned.append({"precision": PREC_NAMES[prec],
                             "drift_tol": None if t == float("inf") else t,
                             "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
-                            "fallback_rate": (f1 - f0) / (n_eval * (steps + 1)),
+                            "energy_drift": drift, "median_particle_err": perr,
+                            "fallback_rate": (f1 - f0) / (n_eval * runs),
+                            "network_ms_per_step": mlp_ms / cnt,
+                            "fallback_ms_per_step": fb_ms / cnt,
                             "network_particle_steps_per_s": n_eval * cnt / (mlp_ms / 1e3)})
             say("vp learned %s tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
                 PREC_NAMES[prec], t, learned[-1]["particle_steps_per_s"], err,
                 learned[-1]["fallback_rate"]))
     out["learned"] = learned
-    _equal_error_points(out, plain, learned, tol)
+    _equal_error_points(out, plain, learned, tol, run_plain=run_plain)
     return out
 
 
@@ -556,6 +652,77 @@ def paper_schemes_long(n=100_000, eps_values=(1e-3, 1e-4), dt=0.5, t_end=90.0,
                          "modulus_distribution_err": modd}
             say("eps %g %s: %.3e particle-steps/s, median err %s" % (
                 eps, name, rate, " ".join("nan" if x is None else "%.2e" % x for x in med)))
+        out["eps_%g" % eps] = res
+    return out
+
+
+def paper_schemes_long_vp(runs=((1e-3, 60.0, (10.0, 30.0, 60.0)),), n=20_000, nr=256, dt=0.5,
+                          plain_Ks=(100, 400), log=None):
+    """The paper's self-consistent long runs (section 4.2): its beam
+    (eq. 2.7) with N_p = 20000 macroparticles and the Poisson field on 256
+    cells, dt = 0.5, for each (eps, t_end, checkpoint times) of `runs` (the
+    paper's are eps = 1e-3 to t = 60 and eps = 1e-4 to t = 90).  The
+    reference is its RK4 solver at its own step 2 pi eps / 100 with the field
+    re-solved at every stage; the improved ETD scheme (Algorithm 3.4, periods
+    searched at every macro step, fine solves with the field per stage), the
+    classic ETD scheme (Algorithm 2.1) and the plain exponential integrator
+    (field frozen over each macro step) are compared with it at every
+    checkpoint: median particle error, modulus-distribution error (mean
+    distance between the sorted moduli |y|, relative to their mean: the slow
+    dynamics, independent of the fast phases) and relative rms-radius error;
+    null once a scheme has blown up.  Rates are whole-run particle-steps/s."""
+    def say(msg):
+        if log:
+            log(msg)
+
+    R0, V0, w = synth.paper_f0(n, seed=18)
+    out = {"n": n, "n_cells": nr, "dt": dt}
+
+    def finite(x):
+        return float(x) if np.isfinite(x) else None
+
+    for eps, t_end, checkpoints in runs:
+        marks = [int(round(t / dt)) for t in checkpoints if t <= t_end + 1e-9]
+
+        def run(mode, substeps=1):
+            snaps, elapsed, done = [], 0.0, 0
+            with Sim(n, n_cells=nr, substeps=substeps) as sim:
+                sim.set_particles(R0, V0, w)
+                capi.ep_set_push_mode(sim.ctx, mode)
+                capi.ep_set_fine_solver(sim.ctx, 0.0)
+                for m in marks:
+                    sim.sync()
+                    t0 = time.perf_counter()
+                    sim.step(dt, eps, EP_FIELD_POISSON, m - done)
+                    sim.sync()
+                    elapsed += time.perf_counter() - t0
+                    done = m
+                    snaps.append(sim.particles())
+                    say("vp long eps %g mode %d K %d: t = %g" % (eps, mode, substeps, m * dt))
+            return snaps, n * done / elapsed
+
+        ref, rate_ref = run(capi.EP_PUSH_RK4)
+        res = {"t_end": t_end, "checkpoints": [m * dt for m in marks],
+               "reference": {"scheme": "RK4, step 2 pi eps/100, field per stage",
+                             "particle_steps_per_s": rate_ref,
+                             "rms_radius": [float(np.sqrt(np.mean(R ** 2))) for R, _ in ref]}}
+        schemes = [("improved_etd", capi.EP_PUSH_IMPROVED_ETD, 1),
+                   ("classic_etd", capi.EP_PUSH_CLASSIC_ETD, 1)]
+        schemes += [("plain_K%d" % K, capi.EP_PUSH_PLAIN, K) for K in plain_Ks]
+        for name, mode, K in schemes:
+            snaps, rate = run(mode, substeps=K)
+            med, modd, rms = [], [], []
+            for (R, V), (Rr, Vr) in zip(snaps, ref):
+                med.append(finite(np.median(np.hypot(R - Rr, V - Vr))))
+                mod, mod_ref = np.sort(np.hypot(R, V)), np.sort(np.hypot(Rr, Vr))
+                modd.append(finite(np.mean(np.abs(mod - mod_ref)) / np.mean(mod_ref)))
+                rr = np.sqrt(np.mean(Rr ** 2))
+                rms.append(finite(abs(np.sqrt(np.mean(R ** 2)) - rr) / rr))
+            res[name] = {"particle_steps_per_s": rate, "median_particle_err": med,
+                         "modulus_distribution_err": modd, "rms_err": rms}
+            say("vp long eps %g %s: %.3e particle-steps/s, median err %s, modulus err %s" % (
+                eps, name, rate, " ".join("nan" if x is None else "%.2e" % x for x in med),
+                " ".join("nan" if x is None else "%.2e" % x for x in modd)))
         out["eps_%g" % eps] = res
     return out
 

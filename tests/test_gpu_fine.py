@@ -29,6 +29,9 @@ VP = dict(nr=NR, rmin=-RMAX, rmax=RMAX)
 
 
 DUFFING_FLOOR, POISSON_FLOOR = 1e-3, 1.0
+# improved ETD in the self-consistent field over several steps: periods and
+# states, see the long-run test
+IETD_VP_T_TOL, IETD_VP_TOL = 1e-6, 1e-5
 AMBIGUOUS = 1e-6     # |dt / T_i - m| below which either whole number m, m - 1 is valid
 
 
@@ -188,6 +191,41 @@ def test_improved_etd_poisson_matches_oracle():
                                            alt_window=AMBIGUOUS, **VP)
     worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, 1e-6, alt, POISSON_FLOOR)
     assert worst <= 1e-5, worst
+
+
+def test_improved_etd_poisson_long_run_start_matches_oracle():
+    """The start of the paper's self-consistent long run (its beam, eq. 2.7,
+    256 cells, eps = 1e-3, dt = 0.5): three macro steps of the improved ETD
+    scheme on a 2000-particle beam against the oracle's own three steps,
+    chained from its own output, at every step; then the same beam's
+    reference RK4 (step 2 pi eps / 100, field per stage) over one macro step
+    against the oracle's."""
+    R0, V0, w = synth.paper_f0(2000, seed=62)
+    eps, dt = 1e-3, 0.5
+    with _sim(R0, V0, w, EP_PUSH_IMPROVED_ETD) as sim:
+        Ro, Vo = R0, V0
+        for s in range(3):
+            sim.step(dt, eps, EP_FIELD_POISSON, 1)
+            Rg, Vg = sim.particles()
+            Tg, Ng, un = capi.ep_get_periods(sim.ctx, R0.size)
+            Rp, Vp = Ro, Vo
+            Ro, Vo, To, No, uno = oracle.improved_etd_step(Rp, Vp, w, dt, eps,
+                                                           oracle.FIELD_POISSON, **VP)
+            assert un == uno == 0, s
+            alt = lambda: oracle.improved_etd_step(Rp, Vp, w, dt, eps, oracle.FIELD_POISSON,
+                                                   alt_window=AMBIGUOUS, **VP)
+            worst = _compare_ietd(Rg, Vg, Tg, Ng, Ro, Vo, To, No, dt, IETD_VP_T_TOL, alt,
+                                  POISSON_FLOOR)
+            print("improved ETD, self-consistent, step %d: worst %.2e" % (s + 1, worst),
+                  flush=True)
+            assert worst <= IETD_VP_TOL, (s, worst)
+    h = oracle.fine_step(eps)
+    K = math.ceil(dt / h - 1e-9)
+    with _sim(R0, V0, w, EP_PUSH_RK4) as sim:
+        sim.step(dt, eps, EP_FIELD_POISSON, 1)
+        Rg, Vg = sim.particles()
+    Ro, Vo = oracle.rk4_run(R0, V0, w, eps, dt / K, K, oracle.FIELD_POISSON, **VP)
+    assert rel(Rg, Vg, Ro, Vo, POISSON_FLOOR).max() <= 1e-6
 
 
 def test_improved_etd_unresolved_particle_keeps_the_free_period():
