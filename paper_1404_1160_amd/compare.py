@@ -175,7 +175,8 @@ def _equal_error_points(out, plain, learned, tol=None, run_plain=None):
 
 def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fine=800,
                 plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5, K_fb=400,
-                seed_eval=15, every=10, precisions=(EP_MLP_BF16, EP_MLP_FP16), log=None):
+                seed_eval=15, every=10, precisions=(EP_MLP_BF16, EP_MLP_FP16), lr_final=1e-5,
+                log=None):
     """Returns a dict with the training report, the plain sweep, the learned
     runs (for each inference precision, with the check at tol and without
     it) and the equal-error points (see _equal_error_points)."""
@@ -214,7 +215,7 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
     out["plain"] = plain
 
     with Sim(n_eval, substeps=1) as sim:
-        rep = train(sim, n_train, epochs, K_fine)
+        rep = train(sim, n_train, epochs, K_fine, lr_final=lr_final)
         out["train"] = rep
         say("trained: loss %.4f -> %.4f in %d steps (%.0f ms)" % (
             rep["loss_first"], rep["loss_last"], rep["steps"], rep["train_ms"]))

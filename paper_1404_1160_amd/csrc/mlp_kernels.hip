@@ -333,9 +333,13 @@ hipError_t launch_gen_labels_poisson(hipStream_t st, const float *zR, const floa
 constexpr int kTile = 64;   // samples per training workgroup
 constexpr int kLd = kH + 1; // LDS row stride of the 64x64 matrices (no bank conflicts)
 
+// partial sums of the layer-1 gradients: [4 sample quarters][64 units][n_in + 1]
+constexpr int kPartStride = 8;
+
 static size_t train_lds_floats(int n_in)
 {
-    return (size_t)mlp_n_params(n_in) + kTile * n_in + kTile * 2 + 5 * kTile * kLd + kTile * 2;
+    return (size_t)mlp_n_params(n_in) + kTile * n_in + kTile * 2 + 5 * kTile * kLd + kTile * 2 +
+           4 * kH * kPartStride + 8;
 }
 
 // Forward and backward of the MSE loss over one tile of 64 samples: sample s
@@ -344,6 +348,10 @@ static size_t train_lds_floats(int n_in)
 // normalised on load, Yn = (Y - mu) * inv_sig.  Writes this tile's gradient
 // (flat parameter order) to gpart[tile] and its sum of squared errors to
 // lpart[tile]; the loss is the mean over the batch and both outputs.
+// The three 64 x 64 x 64 products run on MFMA; every other sum over 64 terms
+// is split over four threads (16 terms each) whose partial sums are combined
+// as (p0 + p1) + (p2 + p3), so that no thread walks a long dependent chain of
+// LDS reads, and the results do not depend on scheduling.
 template <int NIN>
 __global__ __launch_bounds__(256) void mlp_train_kernel(
     const float *__restrict__ params, const float *__restrict__ X, const float *__restrict__ Y,
@@ -353,6 +361,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     constexpr int NP = kH * NIN + kH + kH * kH + kH + kOut * kH + kOut;
     constexpr int oW1 = 0, ob1 = kH * NIN, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
                   ob3 = oW3 + kOut * kH;
+    static_assert(NIN + 1 <= kPartStride, "layer-1 partial sums fit their stride");
     extern __shared__ __align__(16) float sm[];
     float *sP = sm;                     // parameters (flat)
     float *sX = sP + NP;                // [64][NIN]
@@ -363,24 +372,64 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     float *sG = sH2 + kTile * kLd;      // dZ2
     float *sD = sG + kTile * kLd;       // dZ1
     float *sdO = sD + kTile * kLd;      // [64][2]
+    float *sQ = sdO + kTile * 2;        // [4][64][kPartStride] partial sums
+    float *sL = sQ + 4 * kH * kPartStride;   // [4] loss of each wave
 
     const int tid = threadIdx.x, nt = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, r = lane & 31, g = lane >> 5;
     const int s_base = blockIdx.x * kTile;
     float *gp = gpart + (size_t)blockIdx.x * NP;
 
-    for (int i = tid; i < NP; i += nt) sP[i] = params[i];
-    for (int i = tid; i < kH * kH; i += nt) sW2[(i >> 6) * kLd + (i & 63)] = params[oW2 + i];
-    for (int i = tid; i < kTile * NIN; i += nt) {
-        const int s = i / NIN, f = i - s * NIN;
-        sX[i] = (s_base + s < batch) ? X[(first + (int64_t)(s_base + s) * sstride) * NIN + f] : 0.f;
+    // Parameters, features and labels: every global load of the thread is
+    // issued before the first LDS store, so their latencies overlap (the
+    // parameters as float4; the host buffer is 16-byte aligned).
+    {
+        constexpr int NP4 = NP / 4, kPer = (NP4 + 255) / 256;
+        static_assert(kTile * (NIN + 2) <= 2 * 256, "features and labels: two loads per thread");
+        const float4 *p4 = reinterpret_cast<const float4 *>(params);
+        float4 buf[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * 256;
+            if (i < NP4) buf[j] = p4[i];
+        }
+        const int it = 4 * NP4 + tid;
+        const float ptail = it < NP ? params[it] : 0.f;
+        float xy[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = tid + j * 256;
+            xy[j] = 0.f;
+            if (i < kTile * NIN) {
+                const int s = i / NIN, f = i - s * NIN;
+                if (s_base + s < batch)
+                    xy[j] = X[(first + (int64_t)(s_base + s) * sstride) * NIN + f];
+            } else if (i < kTile * (NIN + 2)) {
+                const int k = i - kTile * NIN, s = k >> 1;
+                if (s_base + s < batch)
+                    xy[j] = Y[(first + (int64_t)(s_base + s) * sstride) * 2 + (k & 1)];
+            }
+        }
+        float4 *s4 = reinterpret_cast<float4 *>(sP);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * 256;
+            if (i < NP4) s4[i] = buf[j];
+        }
+        if (it < NP) sP[it] = ptail;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = tid + j * 256;
+            if (i < kTile * NIN) {
+                sX[i] = xy[j];
+            } else if (i < kTile * (NIN + 2)) {
+                const int k = i - kTile * NIN;
+                sY[k] = (k & 1) ? (xy[j] - mu_k) * is_k : (xy[j] - mu_d) * is_d;
+            }
+        }
     }
-    for (int i = tid; i < kTile * 2; i += nt) {
-        const int s = i >> 1;
-        const float y =
-            (s_base + s < batch) ? Y[(first + (int64_t)(s_base + s) * sstride) * 2 + (i & 1)] : 0.f;
-        sY[i] = (i & 1) ? (y - mu_k) * is_k : (y - mu_d) * is_d;
-    }
+    __syncthreads();
+    for (int i = tid; i < kH * kH; i += nt) sW2[(i >> 6) * kLd + (i & 63)] = sP[oW2 + i];
     __syncthreads();
 
     // layer 1 (VALU): H1[s][u] = act(b1[u] + sum_f W1[u][f] X[s][f])
@@ -406,33 +455,48 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     }
     __syncthreads();
 
-    // layer 3 (VALU), loss and dO = d loss / d O
-    if (tid < kTile * 2) {
-        const int s = tid >> 1, m = tid & 1;
-        float o = sP[ob3 + m];
-        for (int u = 0; u < kH; ++u) o = fmaf(sP[oW3 + m * kH + u], sH2[s * kLd + u], o);
+    // layer 3 (VALU), loss and dO = d loss / d O.  Sample s = tid / 4; its
+    // four threads (lanes of one wave) sum quarters of the hidden units.
+    {
+        const int s = tid >> 2, qu = tid & 3;
+        float o0 = 0.f, o1 = 0.f;
+#pragma unroll 4
+        for (int u = 16 * qu; u < 16 * qu + 16; ++u) {
+            const float h = sH2[s * kLd + u];
+            o0 = fmaf(sP[oW3 + u], h, o0);
+            o1 = fmaf(sP[oW3 + kH + u], h, o1);
+        }
+        o0 += __shfl_xor(o0, 1, 64);
+        o1 += __shfl_xor(o1, 1, 64);
+        o0 += __shfl_xor(o0, 2, 64);
+        o1 += __shfl_xor(o1, 2, 64);
         const bool valid = s_base + s < batch;
-        const float d = valid ? o - sY[tid] : 0.f;
-        sdO[tid] = 2.f * d / (float)(batch * 2);
-        sY[tid] = d * d;   // reused: squared error
+        const float d0 = valid ? (o0 + sP[ob3]) - sY[2 * s] : 0.f;
+        const float d1 = valid ? (o1 + sP[ob3 + 1]) - sY[2 * s + 1] : 0.f;
+        if (qu == 0) {
+            sdO[2 * s] = 2.f * d0 / (float)(batch * 2);
+            sdO[2 * s + 1] = 2.f * d1 / (float)(batch * 2);
+        }
+        const float l = wave_sum(qu == 0 ? fmaf(d0, d0, d1 * d1) : 0.f);
+        if (lane == 0) sL[wave] = l;
     }
     __syncthreads();
-    if (tid == 0) {
-        float l = 0.f;
-        for (int i = 0; i < kTile * 2; ++i) l += sY[i];
-        lpart[blockIdx.x] = l;
-    }
-    // dW3, db3
-    if (tid < kOut * kH) {
-        const int m = tid >> 6, u = tid & 63;
+    if (tid == 0) lpart[blockIdx.x] = (sL[0] + sL[1]) + (sL[2] + sL[3]);
+    // dW3[m][u] = sum_s dO[s][m] H2[s][u]: thread (m, u) of each sample half
+    {
+        const int o = tid & 127, m = o >> 6, u = o & 63, half = tid >> 7;
         float a = 0.f;
-        for (int s = 0; s < kTile; ++s) a = fmaf(sdO[s * 2 + m], sH2[s * kLd + u], a);
-        gp[oW3 + tid] = a;
+#pragma unroll 4
+        for (int s = 32 * half; s < 32 * half + 32; ++s) a = fmaf(sdO[s * 2 + m], sH2[s * kLd + u], a);
+        sQ[half * 128 + o] = a;
     }
-    if (tid < kOut) {
-        float a = 0.f;
-        for (int s = 0; s < kTile; ++s) a += sdO[s * 2 + tid];
-        gp[ob3 + tid] = a;
+    // db3: wave 0, one sample per lane
+    if (wave == 0) {
+        const float b0 = wave_sum(sdO[2 * lane]), b1 = wave_sum(sdO[2 * lane + 1]);
+        if (lane == 0) {
+            gp[ob3] = b0;
+            gp[ob3 + 1] = b1;
+        }
     }
     // G = dZ2 = (dO W3) * act'(Z2)
     for (int i = tid; i < kTile * kH; i += nt) {
@@ -440,6 +504,8 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
         const float d = fmaf(sdO[s * 2], sP[oW3 + u], sdO[s * 2 + 1] * sP[oW3 + kH + u]);
         sG[s * kLd + u] = d * act_grad_h(sH2[s * kLd + u]);
     }
+    __syncthreads();
+    if (tid < kOut * kH) gp[oW3 + tid] = sQ[tid] + sQ[128 + tid];
     __syncthreads();
 
     // dW2[u][k] = sum_s G[s][u] H1[s][k]   (MFMA)
@@ -449,10 +515,13 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
 #pragma unroll
         for (int q = 0; q < 16; ++q) gp[oW2 + (i0 + tile_row(q, g)) * kH + j0 + r] = acc[q];
     }
-    if (tid < kH) {
+    // db2 partials: unit u = tid % 64, samples of quarter tid / 64
+    {
+        const int u = tid & 63, qs = tid >> 6;
         float a = 0.f;
-        for (int s = 0; s < kTile; ++s) a += sG[s * kLd + tid];
-        gp[ob2 + tid] = a;
+#pragma unroll 4
+        for (int s = 16 * qs; s < 16 * qs + 16; ++s) a += sG[s * kLd + u];
+        sQ[qs * kH * kPartStride + u * kPartStride] = a;
     }
     // dH1[s][k] = sum_u G[s][u] W2[u][k]   (MFMA), D = dZ1 = dH1 * act'(Z1)
     {
@@ -465,55 +534,76 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
         }
     }
     __syncthreads();
-    // dW1, db1
-    for (int i = tid; i < kH * NIN; i += nt) {
-        const int u = i / NIN, f = i - u * NIN;
-        float a = 0.f;
-        for (int s = 0; s < kTile; ++s) a = fmaf(sD[s * kLd + u], sX[s * NIN + f], a);
-        gp[oW1 + i] = a;
-    }
     if (tid < kH) {
-        float a = 0.f;
-        for (int s = 0; s < kTile; ++s) a += sD[s * kLd + tid];
-        gp[ob1 + tid] = a;
+        const float *q0 = sQ + tid * kPartStride;
+        constexpr int qs = kH * kPartStride;
+        gp[ob2 + tid] = (q0[0] + q0[qs]) + (q0[2 * qs] + q0[3 * qs]);
+    }
+    __syncthreads();
+    // dW1[u][f] = sum_s D[s][u] X[s][f], db1[u] = sum_s D[s][u]: unit u =
+    // tid % 64, samples of quarter tid / 64, all n_in + 1 sums at once
+    {
+        const int u = tid & 63, qs = tid >> 6;
+        float a[NIN + 1];
+#pragma unroll
+        for (int f = 0; f <= NIN; ++f) a[f] = 0.f;
+#pragma unroll 4
+        for (int s = 16 * qs; s < 16 * qs + 16; ++s) {
+            const float d = sD[s * kLd + u];
+#pragma unroll
+            for (int f = 0; f < NIN; ++f) a[f] = fmaf(d, sX[s * NIN + f], a[f]);
+            a[NIN] += d;
+        }
+#pragma unroll
+        for (int f = 0; f <= NIN; ++f) sQ[(qs * kH + u) * kPartStride + f] = a[f];
+    }
+    __syncthreads();
+    for (int i = tid; i < kH * (NIN + 1); i += nt) {
+        const int u = i / (NIN + 1), f = i - u * (NIN + 1);
+        const float *q0 = sQ + u * kPartStride + f;
+        constexpr int qs = kH * kPartStride;
+        const float v = (q0[0] + q0[qs]) + (q0[2 * qs] + q0[3 * qs]);
+        if (f < NIN)
+            gp[oW1 + u * NIN + f] = v;
+        else
+            gp[ob1 + u] = v;
     }
 }
 
 // grad[p] = sum over the per-tile gradients, loss = sum of lpart / (batch * 2).
-// A workgroup of 256 threads takes 64 parameters; the four threads of a
-// parameter sum the tiles t = q, q + 4, ... (q = 0..3) and the four partial
-// sums are added as (s0 + s1) + (s2 + s3): a fixed order, so the result is
-// reproducible.  With ADAM the update of Adam (Kingma & Ba; bias corrections
+// A workgroup of 256 threads takes 16 parameters; the 16 threads of a
+// parameter sum the tiles t = c, c + 16, ... (c = 0..15), and the 16 partial
+// sums are added pairwise in a fixed tree, so the result is reproducible.
+// With ADAM the update of Adam (Kingma & Ba; bias corrections
 // bc1 = 1/(1 - b1^t), bc2 = 1/(1 - b2^t)) is applied to the parameters too.
 struct AdamArgs {
     float *p, *m, *v;
     float lr, b1, b2, bc1, bc2, eps;
 };
 
+constexpr int kRedParams = 16, kRedChunks = 16;
+
 template <bool ADAM>
-__global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(const float *__restrict__ gpart,
-                                                              const float *__restrict__ lpart,
-                                                              int tiles, int np, int batch,
-                                                              float *__restrict__ grad,
-                                                              float *__restrict__ loss, AdamArgs ad)
+__global__ __launch_bounds__(kRedParams * kRedChunks) void mlp_grad_reduce_kernel(
+    const float *__restrict__ gpart, const float *__restrict__ lpart, int tiles, int np, int batch,
+    float *__restrict__ grad, float *__restrict__ loss, AdamArgs ad)
 {
-    __shared__ float part[4][64];
+    __shared__ float part[kRedChunks][kRedParams];
     __shared__ double lw[4];
-    const int tid = threadIdx.x, pl = tid & 63, q = tid >> 6;
-    const int p = blockIdx.x * 64 + pl;
-    if (p < np) {
-        float a0 = 0.f, a1 = 0.f;
-        int t = q;
-        for (; t + 4 < tiles; t += 8) {
-            a0 += gpart[(size_t)t * np + p];
-            a1 += gpart[(size_t)(t + 4) * np + p];
-        }
-        if (t < tiles) a0 += gpart[(size_t)t * np + p];
-        part[q][pl] = a0 + a1;
-    }
+    const int tid = threadIdx.x, pl = tid % kRedParams, c = tid / kRedParams;
+    const int p = blockIdx.x * kRedParams + pl;
+    float a = 0.f;
+    if (p < np)
+        for (int t = c; t < tiles; t += kRedChunks) a += gpart[(size_t)t * np + p];
+    part[c][pl] = a;
     __syncthreads();
-    if (q == 0 && p < np) {
-        const float gi = (part[0][pl] + part[1][pl]) + (part[2][pl] + part[3][pl]);
+#pragma unroll
+    for (int w = kRedChunks / 2; w > 0; w >>= 1) {
+        if (c < w) part[c][pl] = part[c][pl] + part[c + w][pl];
+        __syncthreads();
+    }
+    if (c == 0 && p < np) {
+        const float gi = part[0][pl];
         grad[p] = gi;
         if (ADAM) {
             const float mi = fmaf(ad.b1, ad.m[p], (1.f - ad.b1) * gi);
@@ -525,7 +615,7 @@ __global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(const float *__res
     }
     if (blockIdx.x == 0) {
         double l = 0.0;
-        for (int t = tid; t < tiles; t += 256) l += lpart[t];
+        for (int t = tid; t < tiles; t += blockDim.x) l += lpart[t];
         l = wave_sum(l);
         if ((tid & 63) == 0) lw[tid >> 6] = l;
         __syncthreads();
@@ -565,7 +655,8 @@ hipError_t launch_mlp_grad(hipStream_t st, int n_in, const float *params, const 
         launch_train_tiles(st, n_in, params, X, Y, first, 1, batch, norm, gpart, lpart);
     if (e != hipSuccess) return e;
     const int np = mlp_n_params(n_in), tiles = (batch + kTile - 1) / kTile;
-    mlp_grad_reduce_kernel<false><<<dim3((np + 63) / 64), dim3(256), 0, st>>>(
+    mlp_grad_reduce_kernel<false><<<dim3((np + kRedParams - 1) / kRedParams),
+                                    dim3(kRedParams * kRedChunks), 0, st>>>(
         gpart, lpart, tiles, np, batch, grad, loss, AdamArgs{});
     return hipGetLastError();
 }
@@ -580,7 +671,8 @@ hipError_t launch_mlp_train_step(hipStream_t st, int n_in, float *params, float 
         launch_train_tiles(st, n_in, params, X, Y, first, sstride, batch, norm, gpart, lpart);
     if (e != hipSuccess) return e;
     const int np = mlp_n_params(n_in), tiles = (batch + kTile - 1) / kTile;
-    mlp_grad_reduce_kernel<true><<<dim3((np + 63) / 64), dim3(256), 0, st>>>(
+    mlp_grad_reduce_kernel<true><<<dim3((np + kRedParams - 1) / kRedParams),
+                                   dim3(kRedParams * kRedChunks), 0, st>>>(
         gpart, lpart, tiles, np, batch, grad, loss, AdamArgs{params, m, v, lr, b1, b2, bc1, bc2, eps});
     return hipGetLastError();
 }
