@@ -332,7 +332,8 @@ def main():
         say = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         print("bench: learned-vs-plain comparison", file=sys.stderr, flush=True)
         line["learned_vs_plain"] = compare.equal_error(
-            n_train=args.learned_train, n_eval=args.learned_eval, log=say)
+            n_train=args.learned_train, n_eval=args.learned_eval, epochs=240, lr_final=1e-6,
+            log=say)
         print("bench: learned-vs-plain comparison, Vlasov-Poisson at scale", file=sys.stderr,
               flush=True)
         # the learned Vlasov-Poisson workload at its size: 1e8 particles,

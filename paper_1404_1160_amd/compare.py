@@ -81,28 +81,28 @@ def train(sim, n_train, epochs, K_fine, seed=14, init_seed=5, batch=None, lr=3e-
     return capi.ep_mlp_train(sim.ctx, R, V, DT, EPS, K_fine, batch, epochs, lr, lr_final, SIGMA)
 
 
-def _interp_rate(lo, hi, err):
+def _interp_rate(lo, hi, err, key="rms_err"):
     """Plain throughput at the error `err` between two plain runs whose errors
     bracket it, interpolated linearly in log(throughput) against log(error)
     (locally err ~ K^-p and throughput ~ K^-1, both straight lines there)."""
-    if hi["rms_err"] == lo["rms_err"]:
+    if hi[key] == lo[key]:
         return hi["particle_steps_per_s"]
-    f = (np.log(err) - np.log(lo["rms_err"])) / (np.log(hi["rms_err"]) - np.log(lo["rms_err"]))
+    f = (np.log(err) - np.log(lo[key])) / (np.log(hi[key]) - np.log(lo[key]))
     return float(np.exp(np.log(lo["particle_steps_per_s"]) +
                         f * (np.log(hi["particle_steps_per_s"]) -
                              np.log(lo["particle_steps_per_s"]))))
 
 
-def _refine(plain, run_plain, err, rel=0.1, max_runs=4):
-    """Bisection in log K between the plain runs whose errors bracket `err`
-    (appending new runs to `plain`) until one run's error lies within
+def _refine(plain, run_plain, err, key="rms_err", rel=0.1, max_runs=4):
+    """Bisection in log K between the plain runs whose errors `key` bracket
+    `err` (appending new runs to `plain`) until one run's error lies within
     +-rel of it, or max_runs runs were added; returns that run or None."""
     for _ in range(max_runs + 1):
-        near = [q for q in plain if abs(q["rms_err"] / err - 1.0) <= rel]
+        near = [q for q in plain if abs(q[key] / err - 1.0) <= rel]
         if near:
             return min(near, key=lambda q: q["K"])
-        above = [q for q in plain if q["rms_err"] > err]
-        below = [q for q in plain if q["rms_err"] <= err]
+        above = [q for q in plain if q[key] > err]
+        below = [q for q in plain if q[key] <= err]
         if not above or not below or run_plain is None:
             return None
         lo = max(above, key=lambda q: q["K"])
@@ -117,32 +117,33 @@ def _refine(plain, run_plain, err, rel=0.1, max_runs=4):
     return None
 
 
-def _equal_error_point(plain, entry, run_plain=None):
-    """The plain push at the learned run's error.  The plain sweep is refined
-    by bisection in K until a plain run's error is within 10 % of the learned
-    error; the gain is the learned throughput over the plain throughput
-    interpolated (log-log) at the learned error between the nearest plain
-    runs above and below it.  `matched` is the refined run itself."""
-    err = entry["rms_err"]
-    matched = _refine(plain, run_plain, err)
-    above = [q for q in plain if q["rms_err"] > err]
-    below = [q for q in plain if q["rms_err"] <= err]
+def _equal_error_point(plain, entry, run_plain=None, key="rms_err"):
+    """The plain push at the learned run's error `key`.  The plain sweep is
+    refined by bisection in K until a plain run's error is within 10 % of the
+    learned error; the gain is the learned throughput over the plain
+    throughput interpolated (log-log) at the learned error between the
+    nearest plain runs above and below it.  `matched` is the refined run."""
+    err = entry[key]
+    matched = _refine(plain, run_plain, err, key)
+    above = [q for q in plain if q[key] > err]
+    below = [q for q in plain if q[key] <= err]
     if not below:
-        return {"plain_K": None, "gain": None,
+        return {"plain_K": None, "gain": None, "error": key,
                 "note": "no plain K in the sweep reached the learned error"}
     hi = min(below, key=lambda q: q["K"])
     lo = max((q for q in above if q["K"] < hi["K"]), key=lambda q: q["K"], default=None)
-    rate = hi["particle_steps_per_s"] if lo is None else _interp_rate(lo, hi, err)
-    res = {"plain_K_bracket": [None if lo is None else lo["K"], hi["K"]],
-           "plain_rms_err_bracket": [None if lo is None else lo["rms_err"], hi["rms_err"]],
+    rate = hi["particle_steps_per_s"] if lo is None else _interp_rate(lo, hi, err, key)
+    res = {"error": key,
+           "plain_K_bracket": [None if lo is None else lo["K"], hi["K"]],
+           "plain_err_bracket": [None if lo is None else lo[key], hi[key]],
            "plain_particle_steps_per_s": rate,
            "learned_particle_steps_per_s": entry["particle_steps_per_s"],
            "gain": entry["particle_steps_per_s"] / rate,
-           "rms_err_learned": err,
+           "err_learned": err,
            "gain_vs_cheapest_not_worse": entry["particle_steps_per_s"] /
            hi["particle_steps_per_s"]}
     if matched is not None:
-        res["matched"] = {"K": matched["K"], "rms_err": matched["rms_err"],
+        res["matched"] = {"K": matched["K"], "err": matched[key],
                           "particle_steps_per_s": matched["particle_steps_per_s"],
                           "gain": entry["particle_steps_per_s"] /
                           matched["particle_steps_per_s"]}
@@ -155,22 +156,31 @@ PREC_NAMES = {EP_MLP_BF16: "bf16", EP_MLP_FP16: "fp16"}
 def _equal_error_points(out, plain, learned, tol=None, run_plain=None):
     """Equal-error points of the learned runs, per precision p:
     "equal_error_<p>" at the drift bound (the first checked run unless tol is
-    given) and "equal_error_no_check_<p>"; "gains" collects their gains
-    (interpolated to the learned error, see _equal_error_point)."""
-    gains = {}
-    for name in dict.fromkeys(e["precision"] for e in learned):
-        runs = [e for e in learned if e["precision"] == name]
-        checked = [e for e in runs if e["drift_tol"] is not None and
-                   (tol is None or e["drift_tol"] == tol)]
-        g = {}
-        if checked:
-            out["equal_error_" + name] = _equal_error_point(plain, checked[0], run_plain)
-            g["with_check"] = out["equal_error_" + name]["gain"]
-        out["equal_error_no_check_" + name] = _equal_error_point(
-            plain, [e for e in runs if e["drift_tol"] is None][0], run_plain)
-        g["no_check"] = out["equal_error_no_check_" + name]["gain"]
-        gains[name] = g
-    out["gains"] = gains
+    given) and "equal_error_no_check_<p>"; "gains" collects their gains at
+    equal rms-radius error (interpolated to the learned error, see
+    _equal_error_point).  "gains_phase" does the same at equal median
+    particle error against the reference, an error that, unlike the rms
+    radius of a phase-mixed beam, sees the particles' fast phases."""
+    for key, gname, suffix in (("rms_err", "gains", ""),
+                               ("median_particle_err", "gains_phase", "_phase")):
+        if not all(key in q for q in plain + learned):
+            continue
+        gains = {}
+        for name in dict.fromkeys(e["precision"] for e in learned):
+            runs = [e for e in learned if e["precision"] == name]
+            checked = [e for e in runs if e["drift_tol"] is not None and
+                       (tol is None or e["drift_tol"] == tol)]
+            g = {}
+            if checked:
+                pt = _equal_error_point(plain, checked[0], run_plain, key)
+                out["equal_error%s_%s" % (suffix, name)] = pt
+                g["with_check"] = pt["gain"]
+            pt = _equal_error_point(plain, [e for e in runs if e["drift_tol"] is None][0],
+                                    run_plain, key)
+            out["equal_error%s_no_check_%s" % (suffix, name)] = pt
+            g["no_check"] = pt["gain"]
+            gains[name] = g
+        out[gname] = gains
 
 
 def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fine=800,

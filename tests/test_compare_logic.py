@@ -29,8 +29,8 @@ def test_interpolated_gain_matches_the_closed_form(err):
     K_star = err ** -0.5
     assert res["gain"] == pytest.approx(2.0e10 / (1e12 / K_star), rel=1e-9)
     m = res["matched"]
-    assert abs(m["rms_err"] / err - 1) <= 0.1 and len(calls) - n0 <= 4
-    lo, hi = res["plain_rms_err_bracket"]
+    assert abs(m["err"] / err - 1) <= 0.1 and len(calls) - n0 <= 4
+    lo, hi = res["plain_err_bracket"]
     assert lo > err >= hi
     # against the cheapest plain run that is not worse (more accurate, so
     # slower) the gain can only look larger
