@@ -5,7 +5,8 @@
  * self-consistent (Vlasov-Poisson) field, or of the Duffing field E = -R^3
  * (--field duffing; then R, V ~ N(0, 1.5) untruncated), at the given dt and
  * eps, and prints the step time; with --copy-bytes it also times a
- * device-to-device copy of that many bytes.  With --learned bf16|fp16 the
+ * device-to-device copy of that many bytes.  --deposit sorted selects the
+ * sort-by-cell deposit.  With --learned bf16|fp16 the
  * steps are the learned push with a network of seeded Glorot-uniform weights
  * (5 or 6 inputs -> 64 -> 64 -> 2; its predictions are meaningless, its cost
  * is that of any network of this shape), the drift bound --drift-tol
@@ -17,7 +18,7 @@
  *                   [--warmup W] [--dt DT] [--eps EPS] [--seed SEED]
  *                   [--field poisson|duffing] [--learned bf16|fp16]
  *                   [--drift-tol TOL] [--fallback-substeps K_FB]
- *                   [--copy-bytes B] [--copy-reps R]
+ *                   [--deposit atomic|sorted] [--copy-bytes B] [--copy-reps R]
  *
  * Exit status 0 on success, 1 on a bad argument or a library error (its
  * message goes to stderr).
@@ -96,7 +97,7 @@ int main(int argc, char **argv)
     uint32_t cells = 4096, substeps = 1, fb_substeps = 400;
     long steps = 20, warmup = 2, copy_reps = 10;
     double dt = 0.05, eps = 1e-3, drift_tol = 1e300;
-    int field = EP_FIELD_POISSON, learned = -1;
+    int field = EP_FIELD_POISSON, learned = -1, deposit = EP_DEPOSIT_ATOMIC;
     for (int i = 1; i < argc; ++i) {
         const char *a = argv[i];
         const char *v = i + 1 < argc ? argv[i + 1] : NULL;
@@ -120,6 +121,8 @@ int main(int argc, char **argv)
         else if (!strcmp(a, "--field") && !strcmp(v, "duffing")) field = EP_FIELD_DUFFING;
         else if (!strcmp(a, "--learned") && !strcmp(v, "bf16")) learned = EP_MLP_BF16;
         else if (!strcmp(a, "--learned") && !strcmp(v, "fp16")) learned = EP_MLP_FP16;
+        else if (!strcmp(a, "--deposit") && !strcmp(v, "atomic")) deposit = EP_DEPOSIT_ATOMIC;
+        else if (!strcmp(a, "--deposit") && !strcmp(v, "sorted")) deposit = EP_DEPOSIT_SORTED;
         else {
             fprintf(stderr, "etdpic_run: unknown option %s\n", a);
             return 1;
@@ -159,7 +162,7 @@ int main(int argc, char **argv)
     cfg.n_cells = cells;
     cfg.substeps = substeps;
     cfg.r_max = 5.0;
-    cfg.deposit = EP_DEPOSIT_ATOMIC;
+    cfg.deposit = deposit;
     cfg.device = 0;
     ep_ctx *ctx = NULL;
     if (check(NULL, ep_create(&cfg, &ctx), "ep_create")) return 1;
