@@ -117,9 +117,11 @@ def measured_traffic(n, cells, substeps):
 def device_copy_bandwidth(n):
     """Achieved bandwidth of a plain device copy of the particle state's size
     (8 B per particle read and written), as a practical ceiling beside the
-    8 TB/s peak: GB/s counting read plus written bytes."""
+    8 TB/s peak: GB/s counting read plus written bytes.  200 copies (about
+    0.3 s at 1e8 particles) measure the steady state rather than the first
+    milliseconds of a freshly started device."""
     from paper_1404_1160_amd import capi
-    return capi.ep_copy_bandwidth(8 * n, reps=10)
+    return capi.ep_copy_bandwidth(8 * n, reps=200)
 
 
 def cpu_baseline(n_full, cells, eps, dt, K, seconds):
