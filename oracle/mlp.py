@@ -27,6 +27,13 @@ radial displacement of the step beyond the free rotation,
 In the self-consistent field E(0+) = rho(0) > 0 = -E(0-), so the phase
 advance of small orbits grows like 1/a while s and rho stay bounded: the
 scaled targets are the ones a smooth network can fit there.
+
+Base push (base_K > 0, Duffing field).  The same polar map can act around
+the plain K_b-substep step y_b of y_n instead of the free rotation:
+    y_{n+1} = (1 + kappa) r(delta) y_b,
+so that (delta, kappa) is the plain push's defect against the fine push, a
+correction that shrinks like K_b^-2 where the plain push converges at second
+order; with base_K = 0, y_b = r(dt/eps) y_n and the two forms agree.
 Check: the frozen-field energy H^n(y) = (R^2 + V^2)/(2 eps) + P(R), P = R^4/4
 (Duffing) or the mesh potential Psi^n (Poisson), must satisfy
 |H^n(y_{n+1}) - H^n(y_n)| <= tol |H^n(y_n)|; particles that fail take the
@@ -125,18 +132,20 @@ class Norm:
     """Normalisation constants of a trained corrector (stored with its weights)."""
 
     def __init__(self, s_in=1.5, s_t=100.0, s_E=1.0, mu_d=0.0, sig_d=1.0, mu_k=0.0, sig_k=1.0,
-                 out_map=0):
+                 out_map=0, base_K=0):
         self.s_in, self.s_t, self.s_E = s_in, s_t, s_E
         self.mu_d, self.sig_d, self.mu_k, self.sig_k = mu_d, sig_d, mu_k, sig_k
         self.out_map = int(out_map)   # 0: (delta, kappa); 1: (a delta, a kappa)
+        self.base_K = int(base_K)     # 0: around the free rotation; K: around the plain K push
 
     def as_array(self):
         return np.array([self.s_in, self.s_t, self.s_E, self.mu_d, self.sig_d, self.mu_k,
-                         self.sig_k, float(self.out_map)])
+                         self.sig_k, float(self.out_map), float(self.base_K)])
 
     @classmethod
     def from_array(cls, a):
-        return cls(*[float(x) for x in a[:7]], out_map=int(a[7]))
+        return cls(*[float(x) for x in a[:7]], out_map=int(a[7]),
+                   base_K=int(a[8]) if len(a) > 8 else 0)
 
 
 def features(R, V, dt, eps, norm, Egather=None):
@@ -180,6 +189,28 @@ def polar_labels(R, V, R1, V1, dt, eps, scaled=False):
     return delta, kappa
 
 
+def apply_polar_to(Rb, Vb, delta, kappa, scaled=False):
+    """y_{n+1} = (1 + kappa) r(delta) y_b around a base point y_b (the base
+    push's result); scaled=True takes (a delta, a kappa) with a = |y_b|."""
+    if scaled:
+        a = np.hypot(Rb, Vb)
+        inv = np.divide(1.0, a, out=np.zeros_like(a), where=a > 0)
+        delta, kappa = delta * inv, kappa * inv
+    R1, V1 = rotate(delta, Rb, Vb)
+    return (1.0 + kappa) * R1, (1.0 + kappa) * V1
+
+
+def polar_labels_from(Rb, Vb, R1, V1, scaled=False):
+    """Inverse of apply_polar_to: delta = angle from y_b to y_{n+1} in the
+    direction in which r advances, kappa = |y_{n+1}|/|y_b| - 1 (scaled:
+    (a delta, |y_{n+1}| - a), a = |y_b|)."""
+    delta = np.arctan2(R1 * Vb - V1 * Rb, R1 * Rb + V1 * Vb)
+    a = np.hypot(Rb, Vb)
+    if scaled:
+        return a * delta, np.hypot(R1, V1) - a
+    return delta, np.hypot(R1, V1) / a - 1.0
+
+
 def predict(p, R, V, dt, eps, norm, Egather=None):
     """Network prediction for particles (R, V): (delta, kappa), or (a delta,
     a kappa) with the amplitude-scaled map."""
@@ -192,14 +223,24 @@ def energy(R, V, eps, potential):
     return (R * R + V * V) / (2.0 * eps) + potential(R)
 
 
-def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=None):
+def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=None,
+                 base_push=None):
     """One learned step with energy check and plain fallback.
 
     potential(R): the frozen-field potential P of H^n; plain_push(R, V): the
-    plain step used for particles that fail the check.  Returns
+    plain step used for particles that fail the check; base_push(R, V): the
+    plain step with norm.base_K substeps, which a network with a base push
+    corrects (needed then, unused otherwise).  Returns
     (R1, V1, fell_back[bool], ratio = |dH|/|H|)."""
     delta, kappa = predict(p, R, V, dt, eps, norm, Egather)
-    R1, V1 = apply_polar(R, V, dt, eps, delta, kappa, scaled=norm.out_map == 1)
+    if norm.base_K:
+        if base_push is None:
+            raise ValueError("the network corrects the plain push with %d substeps: "
+                             "pass base_push" % norm.base_K)
+        Rb, Vb = base_push(R, V)
+        R1, V1 = apply_polar_to(Rb, Vb, delta, kappa, scaled=norm.out_map == 1)
+    else:
+        R1, V1 = apply_polar(R, V, dt, eps, delta, kappa, scaled=norm.out_map == 1)
     H0 = energy(R, V, eps, potential)
     H1 = energy(R1, V1, eps, potential)
     ratio = np.abs(H1 - H0) / np.abs(H0)

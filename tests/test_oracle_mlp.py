@@ -179,3 +179,72 @@ def test_fine_labels_match_exact_step():
     assert np.median(ed) < 5e-7 and np.percentile(ed, 99) < 1e-5 and ed.max() < 5e-5, (
         np.median(ed), ed.max())
     assert np.max(np.abs(k - kx)) < 5e-6
+
+
+def test_base_polar_map_agrees_with_the_rotation_form():
+    """With the free rotation as the base point, the base form of the polar
+    map and of its labels is the rotation form: apply_polar(y, d, k) =
+    apply_polar_to(r(dt/eps) y, d, k), plain and amplitude-scaled, and the
+    labels round-trip around any base point."""
+    rng = np.random.default_rng(11)
+    R, V, _ = synth.gaussian(500, seed=11, sigma=1.5)
+    dt, eps = 0.05, 1e-3
+    d = rng.uniform(-1, 1, R.size)
+    k = rng.uniform(-0.01, 0.01, R.size)
+    Rb, Vb = mlp.rotate(dt / eps, R, V)
+    for scaled in (False, True):
+        R1, V1 = mlp.apply_polar(R, V, dt, eps, d, k, scaled=scaled)
+        R2, V2 = mlp.apply_polar_to(Rb, Vb, d, k, scaled=scaled)
+        assert np.max(np.hypot(R1 - R2, V1 - V2)) < 1e-12
+        d1, k1 = mlp.polar_labels(R, V, R1, V1, dt, eps, scaled=scaled)
+        d2, k2 = mlp.polar_labels_from(Rb, Vb, R1, V1, scaled=scaled)
+        assert np.max(np.abs(d1 - d2)) < 1e-12 and np.max(np.abs(k1 - k2)) < 1e-12
+    # round trip around an arbitrary base point
+    Rc, Vc = R + 0.1, V - 0.2
+    d3, k3 = mlp.polar_labels_from(Rc, Vc, R, V)
+    R3, V3 = mlp.apply_polar_to(Rc, Vc, d3, k3)
+    assert np.max(np.hypot(R3 - R, V3 - V)) < 1e-12
+
+
+def test_base_push_labels_are_the_plain_push_defect():
+    """Around the plain K_b-substep push the labels are that push's defect
+    against the exact Duffing step: they vanish with the defect and shrink
+    like K_b^-2 (the plain push is second order), while the labels around the
+    free rotation stay at the size of the Duffing phase advance."""
+    R, V, _ = synth.gaussian(2000, seed=12, sigma=1.5)
+    dt, eps = 0.05, 1e-3
+    Rx, Vx = duffing.solution(R, V, eps, dt)
+    size = {}
+    for Kb in (100, 200):
+        Rb, Vb = oracle.push(R, V, dt, eps, Kb, field=oracle.FIELD_DUFFING)
+        d, k = mlp.polar_labels_from(Rb, Vb, Rx, Vx)
+        size[Kb] = np.median(np.abs(d))
+        R1, V1 = mlp.apply_polar_to(Rb, Vb, d, k)
+        assert np.max(np.hypot(R1 - Rx, V1 - Vx)) < 1e-12
+    d0, _ = mlp.polar_labels(R, V, Rx, Vx, dt, eps)
+    assert 3.0 < size[100] / size[200] < 5.0, size
+    assert size[100] < 1e-3 * np.median(np.abs(d0)), (size, np.median(np.abs(d0)))
+
+
+def test_learned_step_with_a_base_push():
+    """A network with a base push: zero outputs give exactly the base push
+    (the plain K_b step), tol = 0 gives the fallback push, and a step without
+    the base push is refused."""
+    R, V, _ = synth.gaussian(300, seed=13, sigma=1.5)
+    dt, eps, Kb = 0.05, 1e-3, 50
+    p = synth.mlp_init(5, 64, 2, seed=7).astype(np.float64)
+    p[-2 - 2 * 64:] = 0.0      # W3 and b3: outputs 0
+    norm = mlp.Norm(mu_d=0.0, sig_d=1e-4, mu_k=0.0, sig_k=1e-5, base_K=Kb)
+    assert mlp.Norm.from_array(norm.as_array()).base_K == Kb
+    pot = lambda r: r ** 4 / 4
+    base = _duffing_fallback(dt, eps, Kb)
+    Rb, Vb = base(R, V)
+    R1, V1, fb, _ = mlp.learned_step(p, R, V, dt, eps, norm, pot, _duffing_fallback(dt, eps, 40),
+                                     math.inf, base_push=base)
+    assert not fb.any() and np.array_equal(R1, Rb) and np.array_equal(V1, Vb)
+    R2, V2, fb, _ = mlp.learned_step(p, R, V, dt, eps, norm, pot, _duffing_fallback(dt, eps, 40),
+                                     0.0, base_push=base)
+    Rp, Vp = oracle.push(R, V, dt, eps, 40, field=oracle.FIELD_DUFFING)
+    assert fb.all() and np.array_equal(R2, Rp) and np.array_equal(V2, Vp)
+    with pytest.raises(ValueError):
+        mlp.learned_step(p, R, V, dt, eps, norm, pot, _duffing_fallback(dt, eps, 40), 1.0)
