@@ -246,11 +246,18 @@ ep_status ep_get_periods(ep_ctx *ctx, double *T, int64_t *N, uint64_t offset, ui
  * a kappa (a = |y_n|: the arc length and the radial displacement beyond the
  * free rotation), divided by a before the map is applied; they stay bounded
  * for small orbits in the self-consistent field, whose phase advance grows
- * like 1/a.  Training labels follow the map of the loaded normalisation.
+ * like 1/a.  Base push (Duffing field, 5-input network): with K_b > 0 the
+ * same polar map acts around the plain push of y_n with K_b substeps,
+ *   y_{n+1} = (1 + kappa) r(delta) y_b,  y_b = plain K_b-substep step of y_n,
+ * so that the network predicts that push's defect against the fine push, a
+ * correction that shrinks like K_b^-2; each learned step then runs the base
+ * push (every particle, FP64, result stored in FP32) before the network.
+ * Training labels follow the map and the base of the loaded normalisation.
  * Parameters: one FP32 vector W1[64][n_in], b1[64], W2[64][64], b2[64],
  * W3[2][64], b3[2] (row-major; 4674 values for n_in = 5, 4738 for 6).
- * Normalisation: 8 doubles {s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, map},
- * map = 0 (delta, kappa) or 1 (amplitude-scaled). */
+ * Normalisation: 9 doubles {s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, map,
+ * K_b}, map = 0 (delta, kappa) or 1 (amplitude-scaled), K_b = 0 (around the
+ * free rotation) or the base push's substeps (a whole number <= 4096). */
 typedef struct {
     double dt, eps;            /* step the corrector is trained for (> 0)            */
     int32_t field;             /* EP_FIELD_DUFFING (given samples) or EP_FIELD_POISSON
@@ -288,18 +295,21 @@ typedef enum {
 ep_status ep_mlp_set_precision(ep_ctx *ctx, int32_t precision);
 
 /* Load network parameters (n_params = 4674 or 4738 FP32 values, layout above)
- * and their normalisation (8 doubles).  Errors: EP_EINVAL. */
+ * and their normalisation (9 doubles).  Errors: EP_EINVAL (also for K_b > 0
+ * with a 6-input network). */
 ep_status ep_mlp_set_weights(ep_ctx *ctx, const float *params, uint32_t n_params,
                              const double *norm);
 
-/* Copy the current parameters and normalisation out.  n_params must match.
+/* Copy the current parameters and normalisation (9 doubles) out.  n_params
+ * must match.
  * Errors: EP_EINVAL, EP_ENOTRAINED, EP_EHIP. */
 ep_status ep_mlp_get_weights(ep_ctx *ctx, float *params, uint32_t n_params, double *norm);
 
 /* Training labels: for n samples (R, V) (host FP64, rounded to FP32 like the
  * features), one plain step of dt at eps with K fine substeps in the Duffing
  * field, returned in polar form delta[n], kappa[n] (FP32): the phase advance
- * beyond the free rotation and the relative change of |y|.
+ * beyond the free rotation and the relative change of |y|, or, if the loaded
+ * network has a base push, the same from the base push's result.
  * Errors: EP_EINVAL, EP_EHIP. */
 ep_status ep_mlp_labels(ep_ctx *ctx, double dt, double eps, uint32_t fine_substeps,
                         const double *R, const double *V, uint64_t n, float *delta,
@@ -408,7 +418,7 @@ ep_status ep_sync(ep_ctx *ctx);
  * every launch of the particle kernels.  ep_timing_enable(ctx, 1) clears and
  * starts collection; ep_timing_get synchronises and returns, for the kernel
  * named `kernel` ("push_poisson", "deposit", "mesh_solve", "push_duffing",
- * "mlp_push", "fallback_push",
+ * "base_push", "mlp_push", "fallback_push",
  * "sort_count", "sort_offsets", "sort_scatter", "sort_combine"), the summed
  * duration in milliseconds and the number of launches.  Errors: EP_EINVAL. */
 ep_status ep_timing_enable(ep_ctx *ctx, int32_t on);

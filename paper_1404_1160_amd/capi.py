@@ -79,6 +79,9 @@ _lib = None
 
 # The HIP runtime the library is linked against (ROCm's).
 ROCM_HIP_RUNTIME = "/opt/rocm/lib/libamdhip64.so.7"
+# normalisation of a corrector: s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, output
+# map, base push substeps
+NORM_LEN = 9
 
 
 def library_path():
@@ -267,8 +270,10 @@ def ep_timing_get(ctx, kernel):
 def ep_mlp_set_weights(ctx, params, norm):
     params = _f32(params)
     norm = _f64(norm)
-    if norm.size != 8:
-        raise ValueError("norm must hold 8 values")
+    if norm.size == 8:     # no base push
+        norm = np.append(norm, 0.0)
+    if norm.size != NORM_LEN:
+        raise ValueError("norm must hold %d values (or 8: no base push)" % NORM_LEN)
     _check(ctx, lib().ep_mlp_set_weights(ctx, _pf(params), params.size, _p(norm)))
 
 
@@ -284,7 +289,7 @@ def mlp_n_params(n_in):
 
 def ep_mlp_get_weights(ctx, n_params):
     params = np.empty(n_params, dtype=np.float32)
-    norm = np.empty(8)
+    norm = np.empty(NORM_LEN)
     _check(ctx, lib().ep_mlp_get_weights(ctx, _pf(params), n_params, _p(norm)))
     return params, norm
 

@@ -11,13 +11,14 @@
  * (5 or 6 inputs -> 64 -> 64 -> 2; its predictions are meaningless, its cost
  * is that of any network of this shape), the drift bound --drift-tol
  * (default: none, every particle takes the network's map) and K_fb =
- * --fallback-substeps.  One process, one HIP runtime and no Python, so a
+ * --fallback-substeps; --base-substeps K_B (Duffing field) gives the network
+ * a base push of K_B plain substeps.  One process, one HIP runtime and no Python, so a
  * hardware-counter profiler can wrap it directly.
  *
  * Usage: etdpic_run [--particles N] [--cells M] [--substeps K] [--steps S]
  *                   [--warmup W] [--dt DT] [--eps EPS] [--seed SEED]
  *                   [--field poisson|duffing] [--learned bf16|fp16]
- *                   [--drift-tol TOL] [--fallback-substeps K_FB]
+ *                   [--drift-tol TOL] [--fallback-substeps K_FB] [--base-substeps K_B]
  *                   [--deposit atomic|sorted] [--copy-bytes B] [--copy-reps R]
  *
  * Exit status 0 on success, 1 on a bad argument or a library error (its
@@ -94,7 +95,7 @@ static float *network(int n_in, uint64_t seed, uint32_t *n_params)
 int main(int argc, char **argv)
 {
     uint64_t n = 100000000ull, seed = 13, copy_bytes = 0;
-    uint32_t cells = 4096, substeps = 1, fb_substeps = 400;
+    uint32_t cells = 4096, substeps = 1, fb_substeps = 400, base_substeps = 0;
     long steps = 20, warmup = 2, copy_reps = 10;
     double dt = 0.05, eps = 1e-3, drift_tol = 1e300;
     int field = EP_FIELD_POISSON, learned = -1, deposit = EP_DEPOSIT_ATOMIC;
@@ -117,6 +118,7 @@ int main(int argc, char **argv)
         else if (!strcmp(a, "--copy-reps")) copy_reps = strtol(v, NULL, 10);
         else if (!strcmp(a, "--drift-tol")) drift_tol = strtod(v, NULL);
         else if (!strcmp(a, "--fallback-substeps")) fb_substeps = (uint32_t)strtoul(v, NULL, 10);
+        else if (!strcmp(a, "--base-substeps")) base_substeps = (uint32_t)strtoul(v, NULL, 10);
         else if (!strcmp(a, "--field") && !strcmp(v, "poisson")) field = EP_FIELD_POISSON;
         else if (!strcmp(a, "--field") && !strcmp(v, "duffing")) field = EP_FIELD_DUFFING;
         else if (!strcmp(a, "--learned") && !strcmp(v, "bf16")) learned = EP_MLP_BF16;
@@ -173,9 +175,10 @@ int main(int argc, char **argv)
         const int n_in = field == EP_FIELD_POISSON ? 6 : 5;
         uint32_t np = 0;
         float *p = network(n_in, seed + 1, &np);
-        /* s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, output map */
-        const double norm[8] = {field == EP_FIELD_POISSON ? 1.0 : 1.5, 100.0, 0.25, 0.05, 0.05,
-                                0.0, 1e-3, field == EP_FIELD_POISSON ? 1.0 : 0.0};
+        /* s_in, s_t, s_E, mu_d, sig_d, mu_k, sig_k, output map, base push substeps */
+        const double norm[9] = {field == EP_FIELD_POISSON ? 1.0 : 1.5, 100.0, 0.25, 0.05, 0.05,
+                                0.0, 1e-3, field == EP_FIELD_POISSON ? 1.0 : 0.0,
+                                (double)base_substeps};
         bad = !p || check(ctx, ep_mlp_set_weights(ctx, p, np, norm), "ep_mlp_set_weights");
         free(p);
         if (!bad) bad = check(ctx, ep_mlp_set_precision(ctx, learned), "ep_mlp_set_precision");

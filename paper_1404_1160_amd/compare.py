@@ -13,7 +13,13 @@ The equal-error point: the plain sweep (factor-2 steps in K) is refined by
 bisection in K until a plain run's error is within 10 % of the learned
 error, and the plain throughput at the learned error is interpolated
 log-log between the nearest plain runs above and below it; the gain is the
-learned throughput over that.
+learned throughput over that.  The same is done at equal median particle
+error at the end of the run, an error that sees the fast phases; every run
+also reports the median error of its first step against the plain push with
+K_fine substeps.  With base_K > 0 the network corrects the plain push with
+base_K substeps instead of the free rotation (its labels are that push's
+defect, which shrinks like base_K^-2), and K_fine and K_ref must resolve
+errors far below that push's.
 
 Vlasov-Poisson workload (`equal_error_vp`): the beam R ~ N(0, 1) truncated
 to |R| < 4, V ~ N(0, 1), N_r cells on [-5, 5], eps = 1e-3, dt = 0.1.  The
@@ -67,17 +73,19 @@ def _rms_history(sim, R0, V0, w, steps, every):
 
 
 def train(sim, n_train, epochs, K_fine, seed=14, init_seed=5, batch=None, lr=3e-3,
-          lr_final=1e-5):
+          lr_final=1e-5, base_K=0):
     """Train from Glorot-initialised weights; the batch defaults to ~n/512
     (64-aligned, between 1024 and 4096) so that small sets still take enough
     Adam steps.  Small batches and long schedules pay here: at 1e7 samples,
     80 epochs of batch 4096 reach a normalised loss ~2e-4 against ~6e-3 for
     10 epochs of batch 16384, and the fallback rate at tol 1e-5 falls from
-    ~20% to ~0.5%."""
+    ~20% to ~0.5%.  base_K > 0: the network corrects the plain push with
+    base_K substeps (its labels are that push's defect)."""
     if batch is None:
         batch = max(1024, min(4096, (n_train // 512) // 64 * 64))
     R, V, _ = synth.gaussian(n_train, seed=seed, sigma=SIGMA)
-    capi.ep_mlp_set_weights(sim.ctx, synth.mlp_init(5, 64, 2, seed=init_seed), NORM_INIT)
+    norm = np.append(NORM_INIT, float(base_K))
+    capi.ep_mlp_set_weights(sim.ctx, synth.mlp_init(5, 64, 2, seed=init_seed), norm)
     return capi.ep_mlp_train(sim.ctx, R, V, DT, EPS, K_fine, batch, epochs, lr, lr_final, SIGMA)
 
 
@@ -186,10 +194,13 @@ def _equal_error_points(out, plain, learned, tol=None, run_plain=None):
 def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fine=800,
                 plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5, K_fb=400,
                 seed_eval=15, every=10, precisions=(EP_MLP_BF16, EP_MLP_FP16), lr_final=1e-5,
-                log=None):
+                base_K=0, log=None):
     """Returns a dict with the training report, the plain sweep, the learned
     runs (for each inference precision, with the check at tol and without
-    it) and the equal-error points (see _equal_error_points)."""
+    it) and the equal-error points (see _equal_error_points).  base_K > 0:
+    the network corrects the plain push with base_K substeps; K_fine and K_ref
+    must then resolve errors well below that push's (its defect shrinks like
+    K^-2)."""
     def say(msg):
         if log:
             log(msg)
@@ -197,13 +208,27 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
     Re, Ve, we = synth.gaussian(n_eval, seed=seed_eval, sigma=SIGMA)
     out = {"workload": {"field": "duffing", "eps": EPS, "dt": DT, "sigma": SIGMA,
                         "n_train": n_train, "n_eval": n_eval, "steps": steps, "K_fine": K_fine,
-                        "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb}}
+                        "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb,
+                        "base_substeps": base_K, "epochs": epochs}}
     with Sim(n_eval, substeps=K_ref) as ref:
         hist_ref = _rms_history(ref, Re, Ve, we, steps, every)
         Rr, Vr = ref.particles()
     rms_ref = float(hist_ref[-1])
     out["rms_ref"] = rms_ref
     say("reference K=%d rms %.6f" % (K_ref, rms_ref))
+    ns = min(n_eval, 1_000_000)
+    with Sim(n_eval, substeps=K_fine) as fine:
+        fine.set_particles(Re, Ve, we)
+        fine.step(DT, EPS, EP_FIELD_DUFFING, 1)
+        R1f, V1f = fine.particles(0, ns)
+
+    def one_step_err(sim):
+        """Median error of one step from the evaluation beam against the plain
+        push with K_fine substeps (the labels' accuracy)."""
+        sim.set_particles(Re, Ve, we)
+        sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+        R1, V1 = sim.particles(0, ns)
+        return float(np.median(np.hypot(R1 - R1f, V1 - V1f)))
 
     def run_error(sim):
         hist = _rms_history(sim, Re, Ve, we, steps, every)
@@ -216,8 +241,9 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
             s.set_particles(Re, Ve, we)
             el = _timed_run(s, steps)
             err, perr = run_error(s)
+            serr = one_step_err(s)
         q = {"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
-             "median_particle_err": perr}
+             "median_particle_err": perr, "one_step_err": serr}
         say("plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, q["particle_steps_per_s"], err))
         return q
 
@@ -225,7 +251,7 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
     out["plain"] = plain
 
     with Sim(n_eval, substeps=1) as sim:
-        rep = train(sim, n_train, epochs, K_fine, lr_final=lr_final)
+        rep = train(sim, n_train, epochs, K_fine, lr_final=lr_final, base_K=base_K)
         out["train"] = rep
         say("trained: loss %.4f -> %.4f in %d steps (%.0f ms)" % (
             rep["loss_first"], rep["loss_last"], rep["steps"], rep["train_ms"]))
@@ -243,15 +269,18 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
             sim.step(DT, EPS, EP_FIELD_DUFFING, 20)
             mlp_ms, cnt = capi.ep_timing_get(sim.ctx, "mlp_push")
             fb_ms, _ = capi.ep_timing_get(sim.ctx, "fallback_push")
+            base_ms, _ = capi.ep_timing_get(sim.ctx, "base_push")
             capi.ep_timing_enable(sim.ctx, False)
             err, perr = run_error(sim)
+            serr = one_step_err(sim)
             learned.append({"precision": PREC_NAMES[prec],
                             "drift_tol": None if t == float("inf") else t,
                             "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
-                            "median_particle_err": perr,
+                            "median_particle_err": perr, "one_step_err": serr,
                             "fallback_rate": (f1 - f0) / (n_eval * (steps + 1)),
                             "network_particle_steps_per_s": n_eval * cnt / (mlp_ms / 1e3),
-                            "fallback_ms_per_step": fb_ms / cnt})
+                            "fallback_ms_per_step": fb_ms / cnt,
+                            "base_push_ms_per_step": base_ms / cnt})
             say("learned %s tol=%s: %.3e particle-steps/s, rms err %.3e, fallback %.4f" % (
                 PREC_NAMES[prec], t, learned[-1]["particle_steps_per_s"], err,
                 learned[-1]["fallback_rate"]))
@@ -314,8 +343,10 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     workload, where every run is long) each scheme's rate comes from the run
     that records its rms radius (a moments call every `every` steps, < 1 % of
     the step time at 1e8 particles) instead of a run of its own.  Every run
-    also reports its energy drift and the median particle error of the first
-    n_sample particles at the end against the reference."""
+    also reports its energy drift, the median particle error of the first
+    n_sample particles at the end against the reference, and the median error
+    of its first step (same start, same frozen field) against the plain push
+    with K_fine substeps, the labels' own accuracy."""
     def say(msg):
         if log:
             log(msg)
@@ -332,12 +363,20 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     out["rms_ref"] = float(hist_ref[-1])
     out["reference_energy_drift"] = float(abs(e_ref[-1] / e_ref[0] - 1))
     say("vp reference K=%d rms %.6f" % (K_ref, hist_ref[-1]))
+    with Sim(n_eval, n_cells=nr, substeps=K_fine) as fine:
+        fine.set_particles(Re, Ve, we)
+        fine.step(VP_DT, VP_EPS, EP_FIELD_POISSON, 1)
+        R1f, V1f = fine.particles(0, ns)
+    step_errs = {}
 
     def measured(sim):
         """(seconds, rms-radius error, energy drift, median particle error);
-        timed apart from the recording run unless single_run."""
+        timed apart from the recording run unless single_run.  Records the
+        first step's error in step_errs["last"]."""
         sim.set_particles(Re, Ve, we)
         sim.step(VP_DT, VP_EPS, EP_FIELD_POISSON, 1)   # field and tables ready
+        R1, V1 = sim.particles(0, ns)
+        step_errs["last"] = float(np.median(np.hypot(R1 - R1f, V1 - V1f)))
         el = None if single_run else timed(sim)
         sim.sync()
         t0 = time.perf_counter()
@@ -363,7 +402,8 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
         with Sim(n_eval, n_cells=nr, substeps=K) as s:
             el, err, drift, perr = measured(s)
         q = {"K": K, "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
-             "energy_drift": drift, "median_particle_err": perr}
+             "energy_drift": drift, "median_particle_err": perr,
+             "one_step_err": step_errs["last"]}
         say("vp plain K=%d: %.3e particle-steps/s, rms err %.3e" % (K, q["particle_steps_per_s"], err))
         return q
 
@@ -400,6 +440,7 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
                             "drift_tol": None if t == float("inf") else t,
                             "particle_steps_per_s": n_eval * steps / el, "rms_err": err,
                             "energy_drift": drift, "median_particle_err": perr,
+                            "one_step_err": step_errs["last"],
                             "fallback_rate": (f1 - f0) / (n_eval * runs),
                             "network_ms_per_step": mlp_ms / cnt,
                             "fallback_ms_per_step": fb_ms / cnt,

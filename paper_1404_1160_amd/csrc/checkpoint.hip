@@ -7,7 +7,7 @@ using namespace etd;
 namespace {
 
 constexpr char kMagic[8] = {'E', 'T', 'D', 'P', 'I', 'C', '0', '1'};
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;   // 4: normalisation of 9 values (base push)
 
 struct Header {
     char magic[8];
@@ -129,7 +129,7 @@ ep_status ep_save(ep_ctx *c, const char *path)
     }
     if (h.mlp_n_in) {
         ok = ok && fwrite(c->mlp.params.data(), 4, h.mlp_n_params, out.f) == h.mlp_n_params;
-        ok = ok && fwrite(c->mlp.norm, 8, 8, out.f) == 8;
+        ok = ok && fwrite(c->mlp.norm, 8, kNormLen, out.f) == (size_t)kNormLen;
     }
     if (h.periods_saved) {
         ok = ok && fwrite(T.data(), 8, c->n, out.f) == c->n;
@@ -163,14 +163,14 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
     std::vector<float> zr(h.n), zv(h.n), params(h.mlp_n_params);
     std::vector<double> T(h.periods_saved ? h.n : 0);
     std::vector<int64_t> N(h.periods_saved ? h.n : 0);
-    double norm[8] = {0};
+    double norm[kNormLen] = {0};
     bool ok = true;
     if (h.n) {
         ok = fread(zr.data(), 4, h.n, in.f) == h.n && fread(zv.data(), 4, h.n, in.f) == h.n;
     }
     if (ok && h.mlp_n_in)
         ok = fread(params.data(), 4, h.mlp_n_params, in.f) == h.mlp_n_params &&
-             fread(norm, 8, 8, in.f) == 8;
+             fread(norm, 8, kNormLen, in.f) == (size_t)kNormLen;
     if (ok && h.periods_saved)
         ok = fread(T.data(), 8, h.n, in.f) == h.n && fread(N.data(), 8, h.n, in.f) == h.n;
     if (!ok) return c->fail(EP_EIO, "ep_load: %s is truncated", path);

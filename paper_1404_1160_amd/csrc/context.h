@@ -45,11 +45,16 @@ hipError_t dalloc(T **p, size_t count)
     return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
 }
 
+// Normalisation of a trained corrector: {s_in, s_t, s_E, mu_d, sig_d, mu_k,
+// sig_k, output map, base substeps}.
+constexpr int kNormLen = 9;
+constexpr uint32_t kMaxBaseK = 4096;   // substeps of a base push
+
 // Learned corrector state.
 struct Learned {
     int n_in = 0;                    // 0: no network loaded
     std::vector<float> params;       // FP32 master copy (host)
-    double norm[8] = {0};
+    double norm[kNormLen] = {0};
     float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
     // inference constants for (dt, eps) = cached_dt, cached_eps
     uint4 *d_w1f = nullptr, *d_w2f = nullptr;
@@ -67,6 +72,11 @@ struct Learned {
     // [t_n][6], raw labels [t_n][2])
     float *d_tx = nullptr, *d_ty = nullptr;
     uint64_t t_n = 0, t_cap = 0;
+    // base push (norm[8] > 0): its substep coefficients and its result
+    StepTables btab{};
+    size_t btab_cap = 0;
+    float *d_cR = nullptr, *d_cV = nullptr;
+    uint64_t base_cap = 0;
 };
 
 }  // namespace etd

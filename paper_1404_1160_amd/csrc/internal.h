@@ -172,10 +172,15 @@ struct MlpInfer {
     int scaled;          // outputs are (a delta, a kappa), a = |y|, instead of (delta, kappa)
 };
 
-// Labels (delta, kappa), or (a delta, a kappa) with scaled != 0.
+// Labels (delta, kappa), or (a delta, a kappa) with scaled != 0, around the
+// free rotation (Kb = 0) or the plain push with Kb substeps (table bsub).
 hipError_t launch_gen_labels_duffing(hipStream_t st, const float *R, const float *V, int64_t n,
-                                     const double4 *sub, int K, float inv_sin, float c_phi,
-                                     float s_phi, float th_scaled, int scaled, float *X, float *Y);
+                                     const double4 *sub, int K, const double4 *bsub, int Kb,
+                                     float inv_sin, float c_phi, float s_phi, float th_scaled,
+                                     int scaled, float *X, float *Y);
+// Plain Kb-substep Duffing push of every particle from z into c (FP32).
+hipError_t launch_base_push_duffing(hipStream_t st, const float *zR, const float *zV, float *cR,
+                                    float *cV, int64_t n, const double4 *sub, int Kb);
 hipError_t setup_train_lds(int n_in);
 // Gradient of the MSE loss over samples [first, first + batch) (X: [.][n_in],
 // Y: [.][2] raw labels, norm = {mu_d, 1/sig_d, mu_k, 1/sig_k}).
@@ -189,10 +194,12 @@ hipError_t launch_mlp_train_step(hipStream_t st, int n_in, float *params, float 
                                  float *grad, float *loss, float lr, float b1, float b2, float bc1,
                                  float bc2, float eps);
 // Learned Duffing step: network prediction, energy check |dH| <= tol |H|,
-// passing particles updated in place, failing ones appended to queue.
-hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
-                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
-                                   double tol, unsigned *qcount, unsigned *queue, int n_cu);
+// passing particles updated in place, failing ones appended to queue.  The
+// polar map acts around z (cR == nullptr) or around the base push's c.
+hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, const float *cR,
+                                   const float *cV, int64_t n, const MlpInfer &net, double2 rot0,
+                                   double2 rot1, double eps, double tol, unsigned *qcount,
+                                   unsigned *queue, int n_cu);
 // Plain K-substep Duffing push of the *qcount queued particles; adds the count
 // to *total.
 hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,

@@ -251,6 +251,37 @@ struct Events {
     }
 };
 
+// Substep table of the base push for `steps` steps of Kb substeps, and the
+// base arrays for the loaded particles.
+ep_status ensure_base(ep_ctx *c, size_t entries, size_t steps, bool arrays)
+{
+    Learned &L = c->mlp;
+    if (entries > L.btab_cap || steps > L.btab_cap) {
+        size_t cap = entries > steps ? entries : steps;
+        if (cap < 1024) cap = 1024;
+        if (L.btab.sub) (void)hipFree(L.btab.sub);
+        if (L.btab.endrot) (void)hipFree(L.btab.endrot);
+        L.btab = StepTables{};
+        L.btab_cap = 0;
+        HIPCHK(c, dalloc(&L.btab.sub, cap));
+        HIPCHK(c, dalloc(&L.btab.endrot, cap));
+        L.btab_cap = cap;
+    }
+    if (arrays && L.base_cap < c->n) {
+        if (L.d_cR) (void)hipFree(L.d_cR);
+        if (L.d_cV) (void)hipFree(L.d_cV);
+        L.d_cR = L.d_cV = nullptr;
+        L.base_cap = 0;
+        HIPCHK(c, dalloc(&L.d_cR, (size_t)c->n));
+        HIPCHK(c, dalloc(&L.d_cV, (size_t)c->n));
+        L.base_cap = c->n;
+    }
+    return EP_OK;
+}
+
+// Substeps of the loaded network's base push (0: none, or no network).
+int base_substeps(const ep_ctx *c) { return c->mlp.n_in ? (int)c->mlp.norm[8] : 0; }
+
 ep_status upload_fp32(ep_ctx *c, const double *src, uint64_t n, float *dst)
 {
     std::vector<float> tmp(n);
@@ -259,9 +290,11 @@ ep_status upload_fp32(ep_ctx *c, const double *src, uint64_t n, float *dst)
     return EP_OK;
 }
 
-// Features and raw labels of n samples into device arrays X[n][5], Y[n][2].
-ep_status make_labels(ep_ctx *c, double dt, double eps, uint32_t K, double s_in, int scaled,
-                      const double *R, const double *V, uint64_t n, float *dX, float *dY)
+// Features and raw labels of n samples into device arrays X[n][5], Y[n][2],
+// around the plain push with Kb substeps when Kb > 0.
+ep_status make_labels(ep_ctx *c, double dt, double eps, uint32_t K, int Kb, double s_in,
+                      int scaled, const double *R, const double *V, uint64_t n, float *dX,
+                      float *dY)
 {
     DevBuf<float> dR, dV;
     HIPCHK(c, dalloc(&dR.p, (size_t)n));
@@ -270,12 +303,17 @@ ep_status make_labels(ep_ctx *c, double dt, double eps, uint32_t K, double s_in,
     if (s != EP_OK) return s;
     if ((s = upload_fp32(c, V, n, dV.p)) != EP_OK) return s;
     if ((s = ensure_tables(c, K, 1)) != EP_OK) return s;
+    if (Kb > 0 && (s = ensure_base(c, (size_t)Kb, 1, false)) != EP_OK) return s;
     const double th = dt / eps;
     HIPCHK(c, launch_phase_table(c->stream, c->tab, 0.0, fmod(th, kTwoPi), th / K, dt / K, (int)K, 1));
+    if (Kb > 0)
+        HIPCHK(c, launch_phase_table(c->stream, c->mlp.btab, 0.0, fmod(th, kTwoPi), th / Kb,
+                                     dt / Kb, Kb, 1));
     const double phi = fmod(th, kTwoPi);
     HIPCHK(c, launch_gen_labels_duffing(c->stream, dR.p, dV.p, (int64_t)n, c->tab.sub, (int)K,
-                                        (float)(1.0 / s_in), (float)cos(phi), (float)sin(phi),
-                                        (float)(th / kTimeScale), scaled, dX, dY));
+                                        c->mlp.btab.sub, Kb, (float)(1.0 / s_in), (float)cos(phi),
+                                        (float)sin(phi), (float)(th / kTimeScale), scaled, dX,
+                                        dY));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return EP_OK;
 }
@@ -290,7 +328,8 @@ void free_learned(ep_ctx *c)
     for (void *p : {(void *)L.d_params, (void *)L.d_m, (void *)L.d_v, (void *)L.d_grad,
                     (void *)L.d_w2f, (void *)L.d_w1f, (void *)L.d_b2,
                     (void *)L.d_w3f, (void *)L.d_qcount, (void *)L.d_queue, (void *)L.d_total,
-                    (void *)L.d_tx, (void *)L.d_ty})
+                    (void *)L.d_tx, (void *)L.d_ty, (void *)L.btab.sub, (void *)L.btab.endrot,
+                    (void *)L.d_cR, (void *)L.d_cV})
         if (p) (void)hipFree(p);
     const int32_t precision = L.precision;   // a setting of the context, not of the network
     L = Learned();
@@ -311,10 +350,12 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
     if ((s = ensure_queue(c)) != EP_OK) return s;
     if (vp && (s = c->field_valid ? ensure_potential(c) : refresh_field(c)) != EP_OK) return s;
     const int K = (int)c->fallback_K;
+    const int Kb = vp ? 0 : base_substeps(c);   // base push (Duffing networks only)
     const double dphi = fmod(dt / eps, kTwoPi);
-    size_t chunk = kTableEntries / (size_t)K;
+    size_t chunk = kTableEntries / (size_t)(Kb > K ? Kb : K);
     if (chunk < 1) chunk = 1;
     if ((s = ensure_tables(c, chunk * (size_t)K, chunk)) != EP_OK) return s;
+    if (Kb > 0 && (s = ensure_base(c, chunk * (size_t)Kb, chunk, true)) != EP_OK) return s;
     const MeshArgs ma = c->mesh();
     uint64_t done = 0;
     while (done < n_steps) {
@@ -322,6 +363,9 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
         const int S = (int)(rem < chunk ? rem : chunk);
         HIPCHK(c, launch_phase_table(c->stream, c->tab, c->phase, dphi, dt / ((double)K * eps),
                                      dt / K, K, S));
+        if (Kb > 0)
+            HIPCHK(c, launch_phase_table(c->stream, L.btab, c->phase, dphi,
+                                         dt / ((double)Kb * eps), dt / Kb, Kb, S));
         for (int j = 0; j < S; ++j) {
             const double p0 = fmod(c->phase + (double)j * dphi, kTwoPi);
             const double p1 = fmod(c->phase + (double)(j + 1) * dphi, kTwoPi);
@@ -344,10 +388,17 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
                 // the next learned step checks energies with this field's potential
                 if (ep_status s2 = solve_mesh(c, ma, true); s2 != EP_OK) return s2;
             } else {
+                if (Kb > 0)
+                    HIPCHK(c, timed_launch(c, "base_push", [&] {
+                               return launch_base_push_duffing(c->stream, c->zR, c->zV, L.d_cR,
+                                                               L.d_cV, (int64_t)c->n,
+                                                               L.btab.sub + (size_t)j * Kb, Kb);
+                           }));
                 HIPCHK(c, timed_launch(c, "mlp_push", [&] {
-                           return launch_mlp_push_duffing(c->stream, c->zR, c->zV, (int64_t)c->n,
-                                                          L.infer, rot0, rot1, eps, c->drift_tol,
-                                                          L.d_qcount, L.d_queue, c->n_cu);
+                           return launch_mlp_push_duffing(
+                               c->stream, c->zR, c->zV, Kb > 0 ? L.d_cR : nullptr,
+                               Kb > 0 ? L.d_cV : nullptr, (int64_t)c->n, L.infer, rot0, rot1, eps,
+                               c->drift_tol, L.d_qcount, L.d_queue, c->n_cu);
                        }));
                 HIPCHK(c, timed_launch(c, "fallback_push", [&] {
                            return launch_fallback_duffing(c->stream, c->zR, c->zV, L.d_queue,
@@ -386,18 +437,24 @@ ep_status ep_mlp_set_weights(ep_ctx *c, const float *params, uint32_t n_params, 
     if (n_params == (uint32_t)mlp_n_params(6)) n_in = 6;
     if (!params || !norm || n_in == 0)
         return c->fail(EP_EINVAL, "ep_mlp_set_weights: need %d (5 inputs) or %d (6 inputs) "
-                                  "parameters and 8 normalisation values",
-                       mlp_n_params(5), mlp_n_params(6));
+                                  "parameters and %d normalisation values",
+                       mlp_n_params(5), mlp_n_params(6), kNormLen);
     if (!(norm[0] > 0.0) || !(norm[1] > 0.0) || !(norm[2] > 0.0))
         return c->fail(EP_EINVAL, "ep_mlp_set_weights: feature scales must be positive");
     if (norm[7] != 0.0 && norm[7] != 1.0)
         return c->fail(EP_EINVAL, "ep_mlp_set_weights: norm[7] (output map) must be 0 or 1");
+    if (!(norm[8] >= 0.0 && norm[8] <= (double)kMaxBaseK) || norm[8] != floor(norm[8]))
+        return c->fail(EP_EINVAL, "ep_mlp_set_weights: norm[8] (base push substeps) must be a "
+                                  "whole number in [0, %u]", kMaxBaseK);
+    if (norm[8] > 0.0 && n_in != 5)
+        return c->fail(EP_EINVAL, "ep_mlp_set_weights: a base push (norm[8] > 0) is supported "
+                                  "for the Duffing field's 5-input network only");
     DeviceGuard guard(c->device);
     ep_status s = ensure_mlp_buffers(c, n_in);
     if (s != EP_OK) return s;
     Learned &L = c->mlp;
     L.params.assign(params, params + n_params);
-    for (int i = 0; i < 8; ++i) L.norm[i] = norm[i];
+    for (int i = 0; i < kNormLen; ++i) L.norm[i] = norm[i];
     HIPCHK(c, copy_sync(c, L.d_params, params, n_params * sizeof(float), hipMemcpyHostToDevice));
     L.packed = false;
     return EP_OK;
@@ -411,7 +468,7 @@ ep_status ep_mlp_get_weights(ep_ctx *c, float *params, uint32_t n_params, double
         return c->fail(EP_EINVAL, "ep_mlp_get_weights: n_params must be %zu",
                        c->mlp.params.size());
     memcpy(params, c->mlp.params.data(), n_params * sizeof(float));
-    for (int i = 0; i < 8; ++i) norm[i] = c->mlp.norm[i];
+    for (int i = 0; i < kNormLen; ++i) norm[i] = c->mlp.norm[i];
     return EP_OK;
 }
 
@@ -426,7 +483,7 @@ ep_status ep_mlp_labels(ep_ctx *c, double dt, double eps, uint32_t K, const doub
     DevBuf<float> dX, dY;
     HIPCHK(c, dalloc(&dX.p, (size_t)n * 5));
     HIPCHK(c, dalloc(&dY.p, (size_t)n * 2));
-    ep_status s = make_labels(c, dt, eps, K, 1.0, 0, R, V, n, dX.p, dY.p);
+    ep_status s = make_labels(c, dt, eps, K, base_substeps(c), 1.0, 0, R, V, n, dX.p, dY.p);
     if (s != EP_OK) return s;
     std::vector<float> Y((size_t)n * 2);
     HIPCHK(c, copy_sync(c, Y.data(), dY.p, Y.size() * sizeof(float), hipMemcpyDeviceToHost));
@@ -579,8 +636,8 @@ ep_status ep_mlp_train(ep_ctx *c, const ep_train_cfg *cfg, const double *R, cons
     if (!vp) {
         HIPCHK(c, dalloc(&gX.p, (size_t)n * 5));
         HIPCHK(c, dalloc(&gY.p, (size_t)n * 2));
-        ep_status s = make_labels(c, cfg->dt, cfg->eps, cfg->fine_substeps, cfg->s_in,
-                                  L.norm[7] == 1.0, R, V, n, gX.p, gY.p);
+        ep_status s = make_labels(c, cfg->dt, cfg->eps, cfg->fine_substeps, base_substeps(c),
+                                  cfg->s_in, L.norm[7] == 1.0, R, V, n, gX.p, gY.p);
         if (s != EP_OK) return s;
         dX = gX.p;
         dY = gY.p;

@@ -219,21 +219,11 @@ __device__ __forceinline__ void polar_label(double zr0, double zv0, double zr, d
 
 // ------------------------------------------------------------ labels
 
-// Training pairs for the Duffing field.  Each sample y = (R, V) is pushed one
-// step with the plain scheme (K_fine substeps, FP64) from phase 0; the labels
-// are the polar form of the step: delta = angle from z_n to z_fine in the
-// direction r advances, kappa = |z_fine| / |z_n| - 1.  Features x = (R/s_in,
-// V/s_in, cos phi, sin phi, (dt/eps)/s_t).
-__global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
-    const float *__restrict__ Rs, const float *__restrict__ Vs, int64_t n,
-    const double4 *__restrict__ sub, int K, float inv_sin, float c_phi, float s_phi,
-    float th_scaled, int scaled, float *__restrict__ X, float *__restrict__ Y)
+// K substeps of the plain Duffing push (FP64, rotating frame) from z.
+__device__ __forceinline__ void duffing_substeps(const double4 *__restrict__ sub, int K,
+                                                 double &zr, double &zv)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float R = Rs[i], V = Vs[i];
-    const double zr0 = R, zv0 = V;
-    double zr = zr0, zv = zv0, ar = 0.0, av = 0.0;
+    double ar = 0.0, av = 0.0;
     for (int k = 0; k < K; ++k) {
         const double4 q = sub[k];
         const double Rm = fma(q.x, zr + ar, q.y * (zv + av));
@@ -243,6 +233,28 @@ __global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
     }
     zr += ar;
     zv += av;
+}
+
+// Training pairs for the Duffing field.  Each sample y = (R, V) is pushed one
+// step with the plain scheme (K_fine substeps, FP64) from phase 0; the labels
+// are the polar form of the step from its base point: delta = angle from z_b
+// to z_fine in the direction r advances, kappa = |z_fine| / |z_b| - 1.  The
+// base point is z_n itself (the free rotation, the identity in the rotating
+// frame) or, with Kb > 0, the plain push of z_n with Kb substeps (table bsub).
+// Features x = (R/s_in, V/s_in, cos phi, sin phi, (dt/eps)/s_t).
+__global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
+    const float *__restrict__ Rs, const float *__restrict__ Vs, int64_t n,
+    const double4 *__restrict__ sub, int K, const double4 *__restrict__ bsub, int Kb,
+    float inv_sin, float c_phi, float s_phi, float th_scaled, int scaled, float *__restrict__ X,
+    float *__restrict__ Y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float R = Rs[i], V = Vs[i];
+    double zr0 = R, zv0 = V;
+    double zr = zr0, zv = zv0;
+    duffing_substeps(sub, K, zr, zv);
+    if (Kb > 0) duffing_substeps(bsub, Kb, zr0, zv0);
     double delta, kappa;
     polar_label(zr0, zv0, zr, zv, scaled, delta, kappa);
     float *x = X + i * 5;
@@ -256,13 +268,38 @@ __global__ __launch_bounds__(256) void gen_labels_duffing_kernel(
 }
 
 hipError_t launch_gen_labels_duffing(hipStream_t st, const float *R, const float *V, int64_t n,
-                                     const double4 *sub, int K, float inv_sin, float c_phi,
-                                     float s_phi, float th_scaled, int scaled, float *X, float *Y)
+                                     const double4 *sub, int K, const double4 *bsub, int Kb,
+                                     float inv_sin, float c_phi, float s_phi, float th_scaled,
+                                     int scaled, float *X, float *Y)
 {
     if (n <= 0) return hipSuccess;
     gen_labels_duffing_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
-        R, V, n, sub, K, inv_sin, c_phi, s_phi, th_scaled, scaled, X, Y);
+        R, V, n, sub, K, bsub, Kb, inv_sin, c_phi, s_phi, th_scaled, scaled, X, Y);
     return hipGetLastError();
+}
+
+// Base push of a learned step with a base (Duffing field): the plain push of
+// every particle with Kb substeps (FP64, table sub of this step), from z into
+// the base arrays c, rounded to FP32 once.  The network then corrects c.
+__global__ __launch_bounds__(256) void base_push_duffing_kernel(
+    const float *__restrict__ zR, const float *__restrict__ zV, float *__restrict__ cR,
+    float *__restrict__ cV, int64_t n, const double4 *__restrict__ sub, int Kb)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double zr = zR[i], zv = zV[i];
+    duffing_substeps(sub, Kb, zr, zv);
+    cR[i] = (float)zr;
+    cV[i] = (float)zv;
+}
+
+hipError_t launch_base_push_duffing(hipStream_t st, const float *zR, const float *zV, float *cR,
+                                    float *cV, int64_t n, const double4 *sub, int Kb)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    return dispatch(base_push_duffing_kernel, dim3((unsigned)((n + block - 1) / block)),
+                    dim3(block), 0, st, zR, zV, cR, cV, n, sub, Kb);
 }
 
 // Training pairs from the self-consistent beam: sample j is particle
@@ -764,18 +801,21 @@ constexpr int kWavesDuffing = 4, kWavesPoisson = 8;
 // activation's range).  All weights stay in LDS and are read where used.  The
 // update and the energy check run in FP64: H = |z|^2/(2 eps) + P(R) with
 // P = R^4/4 (Duffing) or the frozen-field potential Psi^n (Poisson,
-// VP = true).  With the amplitude-scaled output map the outputs are divided
-// by a = |z| first.  Particles that fail keep their state and go to the
+// VP = true).  The polar map acts around the base point: z_n itself (the
+// free rotation) or, when c is given, the base push's result c_n (Duffing
+// field).  With the amplitude-scaled output map the outputs are divided by
+// a = |base point| first.  Particles that fail keep their state and go to the
 // fallback queue.  With VP the sixth feature is E^n(R_n), and the particles
 // that pass are deposited (CIC, fixed point) into an LDS histogram added to
 // the mesh at the end.
 template <bool VP, int WAVES, typename T>
 __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
-    float *__restrict__ zR, float *__restrict__ zV, int64_t n, MlpInfer net, double2 rot0,
-    double2 rot1, double inv2eps, double tol, unsigned *__restrict__ qcount,
-    unsigned *__restrict__ queue, MeshView mv, PotView pv, const double *__restrict__ qb,
-    unsigned long long *__restrict__ hist)
+    float *__restrict__ zR, float *__restrict__ zV, const float *__restrict__ cR,
+    const float *__restrict__ cV, int64_t n, MlpInfer net, double2 rot0, double2 rot1,
+    double inv2eps, double tol, unsigned *__restrict__ qcount, unsigned *__restrict__ queue,
+    MeshView mv, PotView pv, const double *__restrict__ qb, unsigned long long *__restrict__ hist)
 {
+    const bool base = cR != nullptr;
     typedef InferOp<T> Op;
     typedef typename Op::vec vec;
     constexpr int kW = Op::kSplitW ? 2 : 1;   // weight parts of layers 2 and 3
@@ -808,6 +848,9 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const bool valid = p < n;
         const double zr = valid ? (double)zR[p] : 0.0;
         const double zv = valid ? (double)zV[p] : 0.0;
+        // base point of the polar map
+        const double br = base && valid ? (double)cR[p] : zr;
+        const double bv = base && valid ? (double)cV[p] : zv;
         const double R = fma(rot0.x, zr, rot0.y * zv);
         const double Vl = fma(-rot0.y, zr, rot0.x * zv);
         // features, clamped, as hi + lo parts
@@ -875,10 +918,11 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const float kappa = fmaf(net.sig_k, o1 + net.b3_1, net.mu_k);
         double sc;
         if (net.scaled) {
-            // outputs are (a delta, a kappa), divided by a = |z| in FP32 (both
-            // are FP32 values; 1/a to ~1 ulp costs nothing next to them).
-            // Nothing moves below a = 2^-50, where the scaled map is void.
-            const double a2 = fma(zr, zr, zv * zv);
+            // outputs are (a delta, a kappa), divided by a = |z_b| in FP32
+            // (both are FP32 values; 1/a to ~1 ulp costs nothing next to
+            // them).  Nothing moves below a = 2^-50, where the scaled map is
+            // void.
+            const double a2 = fma(br, br, bv * bv);
             const float inv_a = a2 > 0x1p-100 ? rsqrtf((float)a2) : 0.f;
             delta *= inv_a;
             sc = 1.0 + (double)(kappa * inv_a);
@@ -887,8 +931,8 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         }
         float sd, cd;
         sincosf(delta, &sd, &cd);
-        const double nr = sc * fma((double)cd, zr, (double)sd * zv);
-        const double nv = sc * fma(-(double)sd, zr, (double)cd * zv);
+        const double nr = sc * fma((double)cd, br, (double)sd * bv);
+        const double nv = sc * fma(-(double)sd, br, (double)cd * bv);
         const double R1 = fma(rot1.x, nr, rot1.y * nv);
         double P0, P1;
         if (VP) {
@@ -1100,20 +1144,21 @@ static MeshView mesh_view(const MeshArgs &ma)
     return m;
 }
 
-hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, int64_t n,
-                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
-                                   double tol, unsigned *qcount, unsigned *queue, int n_cu)
+hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, const float *cR,
+                                   const float *cV, int64_t n, const MlpInfer &net, double2 rot0,
+                                   double2 rot1, double eps, double tol, unsigned *qcount,
+                                   unsigned *queue, int n_cu)
 {
     if (n <= 0) return hipSuccess;
     int64_t grid = (n + 32 * kWavesDuffing - 1) / (32 * kWavesDuffing);
     if (grid > (int64_t)n_cu * 8) grid = (int64_t)n_cu * 8;
     const dim3 g((unsigned)grid), b(64 * kWavesDuffing);
     if (net.fp16)
-        return dispatch(mlp_push_kernel<false, kWavesDuffing, _Float16>, g, b, 0, st, zR, zV, n,
-                        net, rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{},
-                        (const double *)nullptr, (unsigned long long *)nullptr);
-    return dispatch(mlp_push_kernel<false, kWavesDuffing, __bf16>, g, b, 0, st, zR, zV, n, net,
-                    rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{},
+        return dispatch(mlp_push_kernel<false, kWavesDuffing, _Float16>, g, b, 0, st, zR, zV, cR,
+                        cV, n, net, rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{},
+                        PotView{}, (const double *)nullptr, (unsigned long long *)nullptr);
+    return dispatch(mlp_push_kernel<false, kWavesDuffing, __bf16>, g, b, 0, st, zR, zV, cR, cV, n,
+                    net, rot0, rot1, 0.5 / eps, tol, qcount, queue, MeshView{}, PotView{},
                     (const double *)nullptr, (unsigned long long *)nullptr);
 }
 
@@ -1140,11 +1185,13 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
     const dim3 g((unsigned)grid), b(64 * kWavesPoisson);
     const size_t lds = mlp_vp_lds_bytes(ma.nr);
     if (net.fp16)
-        return dispatch(mlp_push_kernel<true, kWavesPoisson, _Float16>, g, b, lds, st, zR, zV, n,
-                        net, rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
+        return dispatch(mlp_push_kernel<true, kWavesPoisson, _Float16>, g, b, lds, st, zR, zV,
+                        (const float *)nullptr, (const float *)nullptr, n, net, rot0, rot1,
+                        0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
                         (const double *)(ma.fscal + kQb), ma.hist);
-    return dispatch(mlp_push_kernel<true, kWavesPoisson, __bf16>, g, b, lds, st, zR, zV, n, net,
-                    rot0, rot1, 0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
+    return dispatch(mlp_push_kernel<true, kWavesPoisson, __bf16>, g, b, lds, st, zR, zV,
+                    (const float *)nullptr, (const float *)nullptr, n, net, rot0, rot1,
+                    0.5 / eps, tol, qcount, queue, mesh_view(ma), pv,
                     (const double *)(ma.fscal + kQb), ma.hist);
 }
 

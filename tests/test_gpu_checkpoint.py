@@ -54,7 +54,7 @@ def test_learned_resume_restores_network(tmp_path, precision):
     R, V, w = synth.gaussian(50_001, seed=32, sigma=1.5)
     dt, eps = 0.05, 1e-3
     p = synth.mlp_init(5, 64, 2, seed=3)
-    norm = np.array([1.5, 100.0, 1.0, 0.0, 0.01, 0.0, 1e-3, 0.0])
+    norm = np.array([1.5, 100.0, 1.0, 0.0, 0.01, 0.0, 1e-3, 0.0, 0.0])
     path = str(tmp_path / "ck.bin")
     with Sim(R.size, substeps=16) as a:
         capi.ep_mlp_set_weights(a.ctx, p, norm)

@@ -7,8 +7,10 @@ size and checks:
   * that training gains over the untrained network (rms-radius error of the
     network map, no fallback, trained vs random weights);
   * that the network map beats the plain push at equal error: on the Duffing
-    field at equal rms-radius error (FP16), on the self-consistent field at
-    equal median particle error (BF16 and FP16);
+    field at equal rms-radius error (FP16), with a base push at equal
+    rms-radius error (BF16 and FP16) and at equal median particle error
+    (BF16), on the self-consistent field at equal median particle error
+    (BF16 and FP16);
 and prints the equal-error tables: plain K sweep vs learned (with the 1e-5
 energy-drift fallback and without), throughput, rms-radius and median
 particle errors, and the gains at both equal errors.
@@ -82,6 +84,31 @@ def test_learned_beats_plain_at_equal_error():
     print(json.dumps({k: res[k] for k in ("gains", "gains_phase")}))
     g = res["equal_error_no_check_fp16"]["gain"]
     assert g is not None and g > 1.0, res["equal_error_no_check_fp16"]
+
+
+def test_base_push_learned_beats_plain_at_equal_error():
+    """With a base push (the network corrects the plain push with K_b = 200
+    substeps; labels at K_fine = 6400) at the at-scale Duffing workload (4e6
+    evaluation particles here, reference K_ref = 6400): the learned step is
+    faster than the plain push of equal rms-radius error with both inference
+    operand types, and faster than the plain push of equal median particle
+    error with BF16, with and without the 1e-5 check.  Its one-step error lies
+    below that of the plain push at K = 800."""
+    res = compare.equal_error(n_train=10_000_000, n_eval=4_000_000, epochs=240, lr_final=1e-6,
+                              K_fine=6400, K_ref=6400, plain_Ks=(200, 400, 800, 1600, 3200),
+                              base_K=200, log=print)
+    keys = [k for k in res if k.startswith("equal_error")]
+    print(json.dumps({k: res[k] for k in keys}, indent=1))
+    print(json.dumps({k: res[k] for k in ("gains", "gains_phase")}))
+    for prec in ("bf16", "fp16"):
+        for key in ("equal_error_", "equal_error_no_check_"):
+            g = res[key + prec]["gain"]
+            assert g is not None and g > 1.0, (key + prec, res[key + prec])
+    for key in ("equal_error_phase_bf16", "equal_error_phase_no_check_bf16"):
+        assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
+    plain800 = [q for q in res["plain"] if q["K"] == 800][0]
+    for e in res["learned"]:
+        assert e["one_step_err"] < plain800["one_step_err"], (e, plain800)
 
 
 def test_equal_error_comparison_vp():
