@@ -455,23 +455,27 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
 
 def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=1600,
                  plain_Ks=(100, 200), tol=1e-5, K_fb=400, n_data=1_000_000, epochs=40,
-                 precisions=(EP_MLP_FP16, EP_MLP_BF16), seed_eval=17, log=None):
+                 precisions=(EP_MLP_FP16, EP_MLP_BF16), seed_eval=17, n_sample=1_000_000,
+                 log=None):
     """Long-time run of the Vlasov-Poisson beam (eps = 1e-3, dt = 0.1, to
     t = steps dt): the learned push with the drift check against plain runs
     and a plain reference at K_ref, all from the same particles.  Every
     `every` steps: the rms radius (its relative error against the
     reference), the total energy (its drift from t = 0) and, for the learned
-    runs, the fallback rate of the interval.  The network is trained on
-    samples collected over the same time span from a separate beam.  Rates
-    are timed on runs of their own, without the moment calls."""
+    runs, the fallback rate of the interval; at the end, the median particle
+    error of the first n_sample particles against the reference.  The network
+    is trained on samples collected over the same time span from a separate
+    beam.  Rates are timed on runs of their own, without the moment calls."""
     def say(msg):
         if log:
             log(msg)
 
     R0, V0, w = synth.gaussian_truncated(n_eval, seed=seed_eval)
+    ns = min(n_sample, n_eval)
     out = {"workload": {"field": "poisson", "eps": VP_EPS, "dt": VP_DT, "n_cells": nr,
                         "n_eval": n_eval, "steps": steps, "t_end": steps * VP_DT,
                         "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb}}
+    end = {}
 
     def history(sim, learned):
         sim.set_particles(R0, V0, w)
@@ -486,6 +490,7 @@ def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=160
             if learned:
                 fb.append((m["n_fallback"] - f_prev) / (n_eval * every))
                 f_prev = m["n_fallback"]
+        end["R"], end["V"] = sim.particles(0, ns)
         return np.array(rms), np.array(energy), np.array(fb)
 
     def rate(sim, n_steps):
@@ -500,13 +505,16 @@ def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=160
 
     with Sim(n_eval, n_cells=nr, substeps=K_ref) as ref:
         rms_ref, e_ref, _ = history(ref, False)
+    Rr, Vr = end["R"], end["V"]
     say("long-time reference K=%d done" % K_ref)
 
     def summary(rms, energy):
         err = np.abs(rms - rms_ref) / rms_ref
         drift = np.abs(energy - energy[0]) / abs(energy[0])
         return {"rms_err_max": float(err.max()), "rms_err_final": float(err[-1]),
-                "energy_drift_max": float(drift.max()), "energy_drift_final": float(drift[-1])}
+                "energy_drift_max": float(drift.max()), "energy_drift_final": float(drift[-1]),
+                "median_particle_err_final": float(np.median(np.hypot(end["R"] - Rr,
+                                                                      end["V"] - Vr)))}
 
     out["reference"] = {"K": K_ref, **{k: v for k, v in summary(rms_ref, e_ref).items()
                                       if k.startswith("energy")}}
