@@ -549,6 +549,88 @@ def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=160
     return out
 
 
+def long_time_duffing(n_eval=1_000_000, steps=20_000, every=1000, K_ref=6400,
+                      plain_Ks=(800, 1600), base_K=200, n_train=10_000_000, epochs=240,
+                      K_fine=6400, tol=1e-5, K_fb=400, precisions=(EP_MLP_BF16, EP_MLP_FP16),
+                      seed_eval=15, n_sample=1_000_000, log=None):
+    """Long-time run of the Duffing workload (eps = 1e-3, dt = 0.05, R, V ~
+    N(0, 1.5), to t = steps dt) with the base-push network (trained as in
+    equal_error with base_K) against plain runs and a plain reference at
+    K_ref, all from the same particles: every `every` steps the relative
+    rms-radius error against the reference and the Duffing energy's drift
+    from t = 0, at the end the median particle error of the first n_sample
+    particles against the reference.  Rates are timed on runs of their own
+    (`every` steps after one untimed step)."""
+    def say(msg):
+        if log:
+            log(msg)
+
+    R0, V0, w = synth.gaussian(n_eval, seed=seed_eval, sigma=SIGMA)
+    ns = min(n_sample, n_eval)
+    out = {"workload": {"field": "duffing", "eps": EPS, "dt": DT, "sigma": SIGMA,
+                        "n_eval": n_eval, "steps": steps, "t_end": steps * DT, "K_ref": K_ref,
+                        "base_substeps": base_K, "K_fine": K_fine, "drift_tol": tol,
+                        "fallback_substeps": K_fb}}
+    end = {}
+
+    def history(sim):
+        sim.set_particles(R0, V0, w)
+        m = sim.moments(EPS, EP_FIELD_DUFFING)
+        rms, energy = [m["rms_radius"]], [m["energy"]]
+        for _ in range(steps // every):
+            sim.step(DT, EPS, EP_FIELD_DUFFING, every)
+            m = sim.moments(EPS, EP_FIELD_DUFFING)
+            rms.append(m["rms_radius"])
+            energy.append(m["energy"])
+        end["R"], end["V"] = sim.particles(0, ns)
+        return np.array(rms), np.array(energy)
+
+    def rate(sim):
+        sim.set_particles(R0, V0, w)
+        return n_eval * every / _timed_run(sim, every)
+
+    with Sim(n_eval, substeps=K_ref) as ref:
+        rms_ref, e_ref = history(ref)
+    Rr, Vr = end["R"], end["V"]
+    say("long-time Duffing reference K=%d done" % K_ref)
+
+    def summary(rms, energy):
+        err = np.abs(rms - rms_ref) / rms_ref
+        drift = np.abs(energy - energy[0]) / abs(energy[0])
+        return {"rms_err_max": float(err.max()), "rms_err_final": float(err[-1]),
+                "energy_drift_max": float(drift.max()), "energy_drift_final": float(drift[-1]),
+                "median_particle_err_final": float(np.median(np.hypot(end["R"] - Rr,
+                                                                      end["V"] - Vr)))}
+
+    drift_ref = np.abs(e_ref - e_ref[0]) / abs(e_ref[0])
+    out["reference"] = {"K": K_ref, "energy_drift_max": float(drift_ref.max())}
+    plain = []
+    for K in plain_Ks:
+        with Sim(n_eval, substeps=K) as sim:
+            entry = {"K": K, **summary(*history(sim)), "particle_steps_per_s": rate(sim)}
+        plain.append(entry)
+        say("long-time Duffing plain K=%d: %s" % (K, entry))
+    out["plain"] = plain
+    learned = []
+    with Sim(n_eval, substeps=1) as sim:
+        rep = train(sim, n_train, epochs, K_fine, lr_final=1e-6, base_K=base_K)
+        out["train"] = {"loss_first": rep["loss_first"], "loss_last": rep["loss_last"]}
+        for prec in precisions:
+            capi.ep_mlp_set_precision(sim.ctx, prec)
+            capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, tol, K_fb)
+            sim.set_particles(R0, V0, w)
+            f0 = sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"]
+            entry = {"precision": PREC_NAMES[prec], "drift_tol": tol, **summary(*history(sim))}
+            f1 = sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"]
+            entry["fallback_rate"] = (f1 - f0) / (n_eval * steps)
+            entry["particle_steps_per_s"] = rate(sim)
+            learned.append(entry)
+            say("long-time Duffing learned %s: %s" % (PREC_NAMES[prec], entry))
+        capi.ep_set_push_mode(sim.ctx, EP_PUSH_PLAIN)
+    out["learned"] = learned
+    return out
+
+
 # ------------------------------------------------------------ the paper's own schemes
 
 def _run_scheme(R0, V0, w, field, mode, dt, eps, steps, nr=VP_NR, substeps=1, h_fine=0.0,
