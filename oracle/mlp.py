@@ -37,7 +37,11 @@ order; with base_K = 0, y_b = r(dt/eps) y_n and the two forms agree.
 Check: the frozen-field energy H^n(y) = (R^2 + V^2)/(2 eps) + P(R), P = R^4/4
 (Duffing) or the mesh potential Psi^n (Poisson), must satisfy
 |H^n(y_{n+1}) - H^n(y_n)| <= tol |H^n(y_n)|; particles that fail take the
-plain K_fb-substep push instead.
+plain K_fb-substep push instead.  Projection (optional): the exact step
+conserves H^n (the Duffing energy, or the frozen-field energy of the step),
+so a particle that passes may be moved radially back onto its energy shell
+with one Newton step (project_energy); the phase of the prediction is
+kept.
 
 Parity unpinned: nothing (forward/backward pinned by finite differences and
 the linear limit, Adam by its closed-form first step, the output map by the
@@ -223,15 +227,33 @@ def energy(R, V, eps, potential):
     return (R * R + V * V) / (2.0 * eps) + potential(R)
 
 
+def project_energy(R1, V1, H0, eps, potential, dpotential):
+    """One Newton step of the radial projection y <- s y onto the energy shell
+    H(y) = H0 (H = |y|^2/(2 eps) + P(R)) from s = 1:
+    s = 1 - (H(y) - H0) / (dH(s y)/ds at s = 1), with
+    dH/ds = |y|^2 / eps + R P'(R).  From a point within tol of the shell the
+    projected energy is off by O(tol^2).  Where the slope is not above half
+    of its kinetic part |y|^2 / eps (small orbits in a field that points
+    outward) the point is left as it is."""
+    A = (R1 * R1 + V1 * V1) / eps
+    slope = A + R1 * dpotential(R1)
+    ok = slope > 0.5 * A
+    s = 1.0 - (energy(R1, V1, eps, potential) - H0) / np.where(ok, slope, 1.0)
+    s = np.where(ok, s, 1.0)
+    return s * R1, s * V1
+
+
 def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=None,
-                 base_push=None):
+                 base_push=None, dpotential=None):
     """One learned step with energy check and plain fallback.
 
     potential(R): the frozen-field potential P of H^n; plain_push(R, V): the
     plain step used for particles that fail the check; base_push(R, V): the
     plain step with norm.base_K substeps, which a network with a base push
-    corrects (needed then, unused otherwise).  Returns
-    (R1, V1, fell_back[bool], ratio = |dH|/|H|)."""
+    corrects (needed then, unused otherwise); dpotential(R) = P'(R): given,
+    the particles that pass the check are projected onto their energy shell
+    H^n(y_{n+1}) = H^n(y_n) (project_energy) after it.  Returns
+    (R1, V1, fell_back[bool], ratio = |dH|/|H| before the projection)."""
     delta, kappa = predict(p, R, V, dt, eps, norm, Egather)
     if norm.base_K:
         if base_push is None:
@@ -245,6 +267,8 @@ def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=Non
     H1 = energy(R1, V1, eps, potential)
     ratio = np.abs(H1 - H0) / np.abs(H0)
     fb = ~(ratio <= tol)
+    if dpotential is not None:
+        R1, V1 = project_energy(R1, V1, H0, eps, potential, dpotential)
     if np.any(fb):
         Rf, Vf = plain_push(R[fb], V[fb])
         R1 = R1.copy()

@@ -27,7 +27,8 @@ EXPORTS = (
     "ep_create", "ep_destroy", "ep_last_error", "ep_set_particles", "ep_bind_particles",
     "ep_step", "ep_moments_get", "ep_get_particles", "ep_get_field", "ep_set_push_mode",
     "ep_sync", "ep_timing_enable", "ep_timing_get", "ep_mlp_set_weights", "ep_mlp_get_weights",
-    "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect", "ep_mlp_get_samples",
+    "ep_mlp_set_projection", "ep_mlp_labels", "ep_mlp_grad", "ep_mlp_train", "ep_mlp_collect",
+    "ep_mlp_get_samples",
     "ep_save", "ep_load", "ep_set_fine_solver", "ep_get_periods", "ep_compute_periods",
     "ep_copy_bandwidth", "ep_mlp_set_precision", "ep_step_noalloc",
 )
@@ -143,6 +144,7 @@ def lib():
             "ep_timing_get": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(u64)], i32),
             "ep_mlp_set_weights": ([vp, pf, u32, pd], i32),
             "ep_mlp_set_precision": ([vp, i32], i32),
+            "ep_mlp_set_projection": ([vp, i32], i32),
             "ep_mlp_get_weights": ([vp, pf, u32, pd], i32),
             "ep_mlp_labels": ([vp, d, d, u32, pd, pd, u64, pf, pf], i32),
             "ep_mlp_grad": ([vp, pf, pf, u32, pf, pd], i32),
@@ -280,6 +282,11 @@ def ep_mlp_set_weights(ctx, params, norm):
 def ep_mlp_set_precision(ctx, precision):
     """Inference operand type: EP_MLP_BF16 (default) or EP_MLP_FP16."""
     _check(ctx, lib().ep_mlp_set_precision(ctx, int(precision)))
+
+
+def ep_mlp_set_projection(ctx, on=True):
+    """Energy projection of the particles that pass the learned push's check."""
+    _check(ctx, lib().ep_mlp_set_projection(ctx, 1 if on else 0))
 
 
 def mlp_n_params(n_in):

@@ -27,7 +27,7 @@ struct Header {
     uint32_t mlp_n_in;
     uint32_t mlp_n_params;
     int32_t mlp_precision;
-    uint32_t reserved;
+    uint32_t mlp_project;       // 1: energy projection of the learned push
     double h_fine;
     uint64_t max_fine;
     int32_t periods_once;
@@ -74,6 +74,7 @@ ep_status ep_save(ep_ctx *c, const char *path)
     h.mlp_n_in = (uint32_t)c->mlp.n_in;
     h.mlp_n_params = (uint32_t)c->mlp.params.size();
     h.mlp_precision = c->mlp.precision;
+    h.mlp_project = c->mlp.project ? 1u : 0u;
     h.h_fine = c->h_fine;
     h.max_fine = c->max_fine;
     h.periods_once = c->periods_once ? 1 : 0;
@@ -199,6 +200,7 @@ ep_status ep_load(ep_ctx *c, const char *path, uint64_t *n_particles)
     c->push_mode = mode;
     if (h.mlp_precision == EP_MLP_BF16 || h.mlp_precision == EP_MLP_FP16)
         (void)ep_mlp_set_precision(c, h.mlp_precision);
+    (void)ep_mlp_set_projection(c, h.mlp_project == 1 ? 1 : 0);
     if (isfinite(h.h_fine) && h.max_fine >= 1) {
         c->h_fine = h.h_fine;
         c->max_fine = h.max_fine;

@@ -59,6 +59,7 @@ struct Learned {
     // inference constants for (dt, eps) = cached_dt, cached_eps
     uint4 *d_w1f = nullptr, *d_w2f = nullptr;
     int32_t precision = EP_MLP_BF16;   // MFMA operand type of the inference
+    bool project = false;              // energy projection of the passing particles
     float4 *d_b2 = nullptr;
     uint4 *d_w3f = nullptr;
     bool packed = false;

@@ -170,6 +170,7 @@ struct MlpInfer {
     float xmax;          // features are clamped to +-xmax
     int fp16;            // MFMA operands in FP16 (1) or BF16 (0)
     int scaled;          // outputs are (a delta, a kappa), a = |y|, instead of (delta, kappa)
+    int project;         // particles that pass are projected radially onto their energy shell
 };
 
 // Labels (delta, kappa), or (a delta, a kappa) with scaled != 0, around the

@@ -215,6 +215,7 @@ ep_status prepare_inference(ep_ctx *c, double dt, double eps)
     I.xmax = (float)xmax;
     I.fp16 = fp16;
     I.scaled = L.norm[7] == 1.0 ? 1 : 0;
+    I.project = L.project ? 1 : 0;
     L.packed = true;
     L.cached_dt = dt;
     L.cached_eps = eps;
@@ -331,9 +332,12 @@ void free_learned(ep_ctx *c)
                     (void *)L.d_tx, (void *)L.d_ty, (void *)L.btab.sub, (void *)L.btab.endrot,
                     (void *)L.d_cR, (void *)L.d_cV})
         if (p) (void)hipFree(p);
-    const int32_t precision = L.precision;   // a setting of the context, not of the network
+    // settings of the context, not of the network
+    const int32_t precision = L.precision;
+    const bool project = L.project;
     L = Learned();
     L.precision = precision;
+    L.project = project;
 }
 
 ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps)
@@ -426,6 +430,16 @@ ep_status ep_mlp_set_precision(ep_ctx *c, int32_t precision)
         return c->fail(EP_EINVAL, "ep_mlp_set_precision: unknown precision %d", (int)precision);
     if (c->mlp.precision != precision) c->mlp.packed = false;
     c->mlp.precision = precision;
+    return EP_OK;
+}
+
+ep_status ep_mlp_set_projection(ep_ctx *c, int32_t on)
+{
+    if (!c) return EP_EINVAL;
+    if (on != 0 && on != 1)
+        return c->fail(EP_EINVAL, "ep_mlp_set_projection: on must be 0 or 1, not %d", (int)on);
+    if (c->mlp.project != (on == 1)) c->mlp.packed = false;
+    c->mlp.project = on == 1;
     return EP_OK;
 }
 

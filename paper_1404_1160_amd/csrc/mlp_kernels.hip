@@ -931,8 +931,8 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         }
         float sd, cd;
         sincosf(delta, &sd, &cd);
-        const double nr = sc * fma((double)cd, br, (double)sd * bv);
-        const double nv = sc * fma(-(double)sd, br, (double)cd * bv);
+        double nr = sc * fma((double)cd, br, (double)sd * bv);
+        double nv = sc * fma(-(double)sd, br, (double)cd * bv);
         const double R1 = fma(rot1.x, nr, rot1.y * nv);
         double P0, P1;
         if (VP) {
@@ -950,6 +950,21 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const double H0 = fma(zr * zr + zv * zv, inv2eps, P0);
         const double H1 = fma(nr * nr + nv * nv, inv2eps, P1);
         const bool ok = fabs(H1 - H0) <= tol * fabs(H0);
+        if (net.project) {
+            // one Newton step of the radial projection s y onto H = H0 from
+            // s = 1: dH/ds = |y|^2 / eps + R P'(R), with R P'(R) = 4 P
+            // (Duffing) or -R E^n(R) (Poisson); skipped where that slope is
+            // below half its kinetic part (small orbits in the Poisson
+            // field).  The correction is at most tol, so FP32 is ample for it.
+            const double A = (nr * nr + nv * nv) * (2.0 * inv2eps);
+            const double slope = VP ? fma(-R1, gather(mv, R1), A) : fma(4.0, P1, A);
+            if (slope > 0.5 * A) {
+                const float corr = (float)(H1 - H0) * __builtin_amdgcn_rcpf((float)slope);
+                const double s = 1.0 - (double)corr;
+                nr *= s;
+                nv *= s;
+            }
+        }
         const bool mine = valid && g == 0;
         if (mine && ok) {
             const float fr = (float)nr, fv = (float)nv;

@@ -238,3 +238,71 @@ def test_base_push_survives_a_checkpoint(tmp_path):
         Rb, Vb = s2.particles()
     assert np.all(np.isfinite(Ra)) and np.all(np.isfinite(Va))
     assert np.array_equal(Ra, Rb) and np.array_equal(Va, Vb)
+
+
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
+@pytest.mark.parametrize("Kb", [0, 50])
+def test_energy_projection_matches_oracle(Kb, precision):
+    """With ep_mlp_set_projection the particles that pass the check end on
+    their Duffing energy shell (to the FP32 rounding of the stored state),
+    and the GPU's projected map matches the oracle's over three steps, each
+    side from its own state; without it the energy error is the map's."""
+    R0, V0, w = synth.gaussian(10001, seed=37, sigma=SIG)
+    p, norm = _net(Kb)
+    pd = p.astype(np.float64)
+    pot = lambda r: r ** 4 / 4
+    dpot = lambda r: r ** 3
+    fb = lambda R, V: push(R, V, 8)
+    base = (lambda a, b: push(a, b, Kb)) if Kb else None
+    H = lambda R, V: mlp.energy(R, V, EPS, pot)
+    sim = _learned_sim(R0, V0, w, p, norm, 1e300, 8, precision)
+    capi.ep_mlp_set_projection(sim.ctx, True)
+    R, V = R0, V0
+    for s in range(3):
+        Rg0, Vg0 = sim.particles()
+        sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+        R, V, f, _ = mlp.learned_step(pd, R, V, DT, EPS, norm, pot, fb, math.inf,
+                                      base_push=base, dpotential=dpot)
+        Rg, Vg = sim.particles()
+        err = rel_particle(Rg, Vg, R, V, MAP_FLOOR)
+        assert err.max() <= (s + 1) * MAP_TOL[precision], (s, err.max())
+        drift = np.abs(H(Rg, Vg) / H(Rg0, Vg0) - 1)
+        assert drift.max() <= 1e-6, (s, drift.max())
+    assert sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"] == 0
+    # the same network without the projection leaves its energy error
+    capi.ep_mlp_set_projection(sim.ctx, False)
+    Rg0, Vg0 = sim.particles()
+    sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+    Rg, Vg = sim.particles()
+    assert np.median(np.abs(H(Rg, Vg) / H(Rg0, Vg0) - 1)) > 1e-5
+    sim.close()
+
+
+def test_projection_keeps_the_check_decisions():
+    """The check decides on the unprojected prediction: with and without the
+    projection the same particles fall back, with the same plain results."""
+    R0, V0, w = synth.gaussian(20001, seed=38, sigma=SIG)
+    Kb, K_fb = 50, 400
+    p, norm = _net(Kb, seed=10)
+    pd = p.astype(np.float64)
+    pot = lambda r: r ** 4 / 4
+    _, _, _, ratio = mlp.learned_step(pd, R0, V0, DT, EPS, norm, pot, lambda a, b: push(a, b, K_fb),
+                                      math.inf, base_push=lambda a, b: push(a, b, Kb))
+    tol = float(np.median(ratio))
+    out = {}
+    for proj in (False, True):
+        sim = _learned_sim(R0, V0, w, p, norm, tol, K_fb)
+        capi.ep_mlp_set_projection(sim.ctx, proj)
+        sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+        out[proj] = sim.particles() + (sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"],)
+        sim.close()
+    (Ra, Va, na), (Rb, Vb, nb) = out[False], out[True]
+    assert na == nb and 0.3 * R0.size < na < 0.7 * R0.size
+    same = (Ra == Rb) & (Va == Vb)
+    # the fallback particles (and only those, up to particles the projection
+    # left unchanged) agree bitwise
+    assert same.sum() >= na
+    H = lambda R, V: mlp.energy(R, V, EPS, pot)
+    H0 = H(R0.astype(np.float32).astype(np.float64), V0.astype(np.float32).astype(np.float64))
+    moved = ~same
+    assert np.median(np.abs(H(Rb[moved], Vb[moved]) / H0[moved] - 1)) < 1e-6

@@ -351,3 +351,36 @@ def test_learned_vp_step_at_1e8_particles(beam_1e8, precision):
     assert m["n_nan"] == 0
     noise = 5.0 * math.sqrt(0.25 / idx.size)
     assert abs(m["n_fallback"] / n - fb.mean()) <= noise + np.mean(~clear)
+
+
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
+def test_energy_projection_in_the_frozen_field_matches_oracle(precision):
+    """With ep_mlp_set_projection the network map's particles are moved onto
+    their frozen-field energy shell (P = Psi^n, P' = -E^n): the GPU matches
+    the oracle's projected map after one step, and the frozen-field energy of
+    almost every particle is kept to the FP32 rounding of the state (small
+    orbits, where the slope test skips the projection, excepted)."""
+    n = 20001
+    p = synth.mlp_init(6, 64, 2, seed=9)
+    norm = _norm(mu_d=0.0, sig_d=1e-3, sig_k=2e-5)
+    sim, w = _learned_sim(n, 44, p, norm, 1e300, 8, precision=precision)
+    capi.ep_mlp_set_projection(sim.ctx, True)
+    R, V, _ = synth.gaussian_truncated(n, seed=44)
+    E, Psi, Qb = _field(R, w)
+    Eg = oracle.gather(R, E, Qb, NR, -RMAX, RMAX)
+    pot = lambda r: oracle.potential(r, E, Psi, Qb, NR, -RMAX, RMAX)
+    dpot = lambda r: -oracle.gather(r, E, Qb, NR, -RMAX, RMAX)
+    Ro, Vo, f, _ = mlp.learned_step(p.astype(np.float64), R, V, DT, EPS, norm, pot,
+                                    lambda a, b: (a, b), math.inf, Egather=Eg, dpotential=dpot)
+    assert not f.any()
+    sim.step(DT, EPS, EP_FIELD_POISSON, 1)
+    Rg, Vg = sim.particles()
+    assert rel_particle(Rg, Vg, Ro, Vo).max() <= MAP_TOL[precision]
+    H = lambda a, b: mlp.energy(a, b, EPS, pot)
+    R32, V32 = R.astype(np.float32).astype(np.float64), V.astype(np.float32).astype(np.float64)
+    drift = np.abs(H(Rg, Vg) / H(R32, V32) - 1)
+    assert np.percentile(drift, 99) <= 1e-6, np.percentile(drift, 99)
+    Rm, Vm, _, _ = mlp.learned_step(p.astype(np.float64), R, V, DT, EPS, norm, pot,
+                                    lambda a, b: (a, b), math.inf, Egather=Eg)
+    assert np.median(np.abs(H(Rm, Vm) / H(R, V) - 1)) > 10 * np.median(drift)
+    sim.close()

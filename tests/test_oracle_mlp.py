@@ -248,3 +248,56 @@ def test_learned_step_with_a_base_push():
     assert fb.all() and np.array_equal(R2, Rp) and np.array_equal(V2, Vp)
     with pytest.raises(ValueError):
         mlp.learned_step(p, R, V, dt, eps, norm, pot, _duffing_fallback(dt, eps, 40), 1.0)
+
+
+def test_energy_projection_returns_to_the_shell_and_keeps_the_phase():
+    """One Newton step of the radial projection: from points off the Duffing
+    energy shell by a relative 1e-5 the energy error falls to O(1e-10), the
+    angle of y is unchanged, points on the shell stay put, and with P = 0 the
+    step is Newton's for s^2 = H0 / H1 (error (dH/H)^2 / 8 at most)."""
+    rng = np.random.default_rng(14)
+    R, V, _ = synth.gaussian(1000, seed=14, sigma=1.5)
+    eps = 1e-3
+    pot = lambda r: r ** 4 / 4
+    dpot = lambda r: r ** 3
+    H0 = mlp.energy(R, V, eps, pot)
+    f = 1.0 + rng.uniform(-1e-5, 1e-5, R.size)
+    R1, V1 = R * f, V * f
+    Rp, Vp = mlp.project_energy(R1, V1, H0, eps, pot, dpot)
+    assert np.max(np.abs(mlp.energy(Rp, Vp, eps, pot) / H0 - 1)) < 1e-9
+    assert np.max(np.abs(np.arctan2(Vp, Rp) - np.arctan2(V1, R1))) < 1e-14
+    R2, V2 = mlp.project_energy(R, V, H0, eps, pot, dpot)
+    assert np.max(np.abs(R2 - R)) < 1e-14 and np.max(np.abs(V2 - V)) < 1e-14
+    zero = lambda r: 0.0 * r
+    H0f = mlp.energy(R, V, eps, zero)
+    Rz, Vz = mlp.project_energy(R * 1.01, V * 1.01, H0f, eps, zero, zero)
+    s_exact = 1.0 / 1.01
+    s_newton = Rz / (R * 1.01)
+    d = 1.01 ** 2 - 1.0
+    assert np.max(np.abs(s_newton - s_exact)) <= d * d / 8 + 1e-15
+
+
+def test_learned_step_with_projection():
+    """With dpotential the particles that pass the check end on their energy
+    shell; the decisions (and the fallback results) are those without it."""
+    R, V, _ = synth.gaussian(2000, seed=15, sigma=1.5)
+    dt, eps, Kb = 0.05, 1e-3, 50
+    p = synth.mlp_init(5, 64, 2, seed=7).astype(np.float64)
+    norm = mlp.Norm(mu_d=0.0, sig_d=2e-4, mu_k=0.0, sig_k=2e-5, base_K=Kb)
+    pot = lambda r: r ** 4 / 4
+    dpot = lambda r: r ** 3
+    base = _duffing_fallback(dt, eps, Kb)
+    fbp = _duffing_fallback(dt, eps, 40)
+    _, _, _, ratio = mlp.learned_step(p, R, V, dt, eps, norm, pot, fbp, math.inf, base_push=base)
+    tol = float(np.median(ratio))
+    Ra, Va, fa, ra = mlp.learned_step(p, R, V, dt, eps, norm, pot, fbp, tol, base_push=base)
+    Rb, Vb, fb, rb = mlp.learned_step(p, R, V, dt, eps, norm, pot, fbp, tol, base_push=base,
+                                      dpotential=dpot)
+    assert np.array_equal(fa, fb) and np.array_equal(ra, rb) and 0.3 < fb.mean() < 0.7
+    assert np.array_equal(Ra[fb], Rb[fb]) and np.array_equal(Va[fb], Vb[fb])
+    H0 = mlp.energy(R, V, eps, pot)
+    # Newton from within tol of the shell: O(tol^2) off it afterwards
+    after = np.abs(mlp.energy(Rb[~fb], Vb[~fb], eps, pot) / H0[~fb] - 1)
+    before = np.abs(mlp.energy(Ra[~fb], Va[~fb], eps, pot) / H0[~fb] - 1)
+    assert after.max() <= tol * tol, (after.max(), tol)
+    assert np.median(after) < 1e-3 * np.median(before)
