@@ -73,7 +73,9 @@ def parse():
                     help="skip the plain-vs-learned equal-error comparison")
     ap.add_argument("--long-time", action="store_true",
                     help="add the long-time runs: learned Vlasov-Poisson (1e7 particles, "
-                         "1e4 steps) and the paper's schemes to t = 90; a few minutes")
+                         "1e4 steps), learned Duffing with a base push (1e6 particles, 2e4 "
+                         "steps), each with and without the energy projection, and the "
+                         "paper's schemes to t = 90; several minutes")
     ap.add_argument("--no-paper-schemes", action="store_true",
                     help="skip the reference-RK4 / improved-ETD measurement")
     ap.add_argument("--learned-train", type=int, default=10_000_000)
@@ -376,6 +378,10 @@ def main():
         from paper_1404_1160_amd import compare
         print("bench: long-time learned Vlasov-Poisson run", file=sys.stderr, flush=True)
         line["long_time_vp"] = compare.long_time_vp(
+            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        print("bench: long-time Duffing run with the base-push network", file=sys.stderr,
+              flush=True)
+        line["long_time_duffing"] = compare.long_time_duffing(
             log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
         print("bench: the paper's schemes to t = 90", file=sys.stderr, flush=True)
         line["paper_schemes_long"] = compare.paper_schemes_long(

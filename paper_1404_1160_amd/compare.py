@@ -194,13 +194,14 @@ def _equal_error_points(out, plain, learned, tol=None, run_plain=None):
 def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fine=800,
                 plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5, K_fb=400,
                 seed_eval=15, every=10, precisions=(EP_MLP_BF16, EP_MLP_FP16), lr_final=1e-5,
-                base_K=0, log=None):
+                base_K=0, project=False, log=None):
     """Returns a dict with the training report, the plain sweep, the learned
     runs (for each inference precision, with the check at tol and without
     it) and the equal-error points (see _equal_error_points).  base_K > 0:
     the network corrects the plain push with base_K substeps; K_fine and K_ref
     must then resolve errors well below that push's (its defect shrinks like
-    K^-2)."""
+    K^-2).  project: the learned runs project the particles that pass the
+    check onto their energy shell (ep_mlp_set_projection)."""
     def say(msg):
         if log:
             log(msg)
@@ -209,7 +210,7 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
     out = {"workload": {"field": "duffing", "eps": EPS, "dt": DT, "sigma": SIGMA,
                         "n_train": n_train, "n_eval": n_eval, "steps": steps, "K_fine": K_fine,
                         "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb,
-                        "base_substeps": base_K, "epochs": epochs}}
+                        "base_substeps": base_K, "epochs": epochs, "projection": project}}
     with Sim(n_eval, substeps=K_ref) as ref:
         hist_ref = _rms_history(ref, Re, Ve, we, steps, every)
         Rr, Vr = ref.particles()
@@ -256,6 +257,7 @@ def equal_error(n_train=4_000_000, n_eval=1_000_000, steps=200, epochs=80, K_fin
         say("trained: loss %.4f -> %.4f in %d steps (%.0f ms)" % (
             rep["loss_first"], rep["loss_last"], rep["steps"], rep["train_ms"]))
         learned = []
+        capi.ep_mlp_set_projection(sim.ctx, project)
         for prec, t in [(p_, t_) for p_ in precisions for t_ in (tol, float("inf"))]:
             capi.ep_mlp_set_precision(sim.ctx, prec)
             sim.set_particles(Re, Ve, we)
@@ -336,7 +338,7 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
                    K_fine=12800, plain_Ks=(25, 50, 100, 200, 400, 800), K_ref=3200, tol=1e-5,
                    extra_tols=(1e-4, 1e-3), K_fb=400, seed_eval=17, every=10,
                    precisions=(EP_MLP_BF16, EP_MLP_FP16), single_run=False, n_sample=1_000_000,
-                   log=None):
+                   project=False, log=None):
     """As equal_error, for the Vlasov-Poisson beam; the learned push runs, for
     each precision, at the drift bound tol (the equal-error point), at
     extra_tols and without the check.  With single_run (the at-scale
@@ -346,7 +348,8 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     also reports its energy drift, the median particle error of the first
     n_sample particles at the end against the reference, and the median error
     of its first step (same start, same frozen field) against the plain push
-    with K_fine substeps, the labels' own accuracy."""
+    with K_fine substeps, the labels' own accuracy.  project: as in
+    equal_error."""
     def say(msg):
         if log:
             log(msg)
@@ -356,7 +359,7 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     out = {"workload": {"field": "poisson", "eps": VP_EPS, "dt": VP_DT, "n_cells": nr,
                         "n_eval": n_eval, "n_data": n_data, "steps": steps, "K_fine": K_fine,
                         "K_ref": K_ref, "drift_tol": tol, "fallback_substeps": K_fb,
-                        "recorded_every": every}}
+                        "recorded_every": every, "projection": project}}
     with Sim(n_eval, n_cells=nr, substeps=K_ref) as ref:
         hist_ref, e_ref = _vp_history(ref, Re, Ve, we, steps, every, energy=True)
         Rr, Vr = ref.particles(0, ns)
@@ -420,6 +423,7 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
     learned = []
     with Sim(n_eval, n_cells=nr, substeps=1) as sim:
         capi.ep_mlp_set_weights(sim.ctx, p, norm)
+        capi.ep_mlp_set_projection(sim.ctx, project)
         tols = (tol,) + tuple(extra_tols) + (float("inf"),)
         for prec, t in [(p_, t_) for p_ in precisions for t_ in tols]:
             capi.ep_mlp_set_precision(sim.ctx, prec)
@@ -456,7 +460,7 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
 def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=1600,
                  plain_Ks=(100, 200), tol=1e-5, K_fb=400, n_data=1_000_000, epochs=40,
                  precisions=(EP_MLP_FP16, EP_MLP_BF16), seed_eval=17, n_sample=1_000_000,
-                 log=None):
+                 projections=(False, True), log=None):
     """Long-time run of the Vlasov-Poisson beam (eps = 1e-3, dt = 0.1, to
     t = steps dt): the learned push with the drift check against plain runs
     and a plain reference at K_ref, all from the same particles.  Every
@@ -465,7 +469,8 @@ def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=160
     runs, the fallback rate of the interval; at the end, the median particle
     error of the first n_sample particles against the reference.  The network
     is trained on samples collected over the same time span from a separate
-    beam.  Rates are timed on runs of their own, without the moment calls."""
+    beam, and runs with each energy-projection setting in `projections`.
+    Rates are timed on runs of their own, without the moment calls."""
     def say(msg):
         if log:
             log(msg)
@@ -535,10 +540,11 @@ def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=160
     with Sim(n_eval, n_cells=nr, substeps=1) as sim:
         capi.ep_mlp_set_weights(sim.ctx, p, norm)
         capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, tol, K_fb)
-        for prec in precisions:
+        for prec, proj in [(p_, q_) for q_ in projections for p_ in precisions]:
             capi.ep_mlp_set_precision(sim.ctx, prec)
+            capi.ep_mlp_set_projection(sim.ctx, proj)
             rms, energy, fb = history(sim, True)
-            entry = {"precision": PREC_NAMES[prec], "drift_tol": tol,
+            entry = {"precision": PREC_NAMES[prec], "drift_tol": tol, "projection": proj,
                      "particle_steps_per_s": rate(sim, min(steps, 200)),
                      **summary(rms, energy),
                      "fallback_rate_first": float(fb[0]), "fallback_rate_last": float(fb[-1]),
@@ -552,15 +558,16 @@ def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=160
 def long_time_duffing(n_eval=1_000_000, steps=20_000, every=1000, K_ref=6400,
                       plain_Ks=(800, 1600), base_K=200, n_train=10_000_000, epochs=240,
                       K_fine=6400, tol=1e-5, K_fb=400, precisions=(EP_MLP_BF16, EP_MLP_FP16),
-                      seed_eval=15, n_sample=1_000_000, log=None):
+                      seed_eval=15, n_sample=1_000_000, projections=(False, True), log=None):
     """Long-time run of the Duffing workload (eps = 1e-3, dt = 0.05, R, V ~
     N(0, 1.5), to t = steps dt) with the base-push network (trained as in
     equal_error with base_K) against plain runs and a plain reference at
     K_ref, all from the same particles: every `every` steps the relative
     rms-radius error against the reference and the Duffing energy's drift
     from t = 0, at the end the median particle error of the first n_sample
-    particles against the reference.  Rates are timed on runs of their own
-    (`every` steps after one untimed step)."""
+    particles against the reference; the learned runs with each
+    energy-projection setting in `projections`.  Rates are timed on runs of
+    their own (`every` steps after one untimed step)."""
     def say(msg):
         if log:
             log(msg)
@@ -615,12 +622,14 @@ def long_time_duffing(n_eval=1_000_000, steps=20_000, every=1000, K_ref=6400,
     with Sim(n_eval, substeps=1) as sim:
         rep = train(sim, n_train, epochs, K_fine, lr_final=1e-6, base_K=base_K)
         out["train"] = {"loss_first": rep["loss_first"], "loss_last": rep["loss_last"]}
-        for prec in precisions:
+        for prec, proj in [(p_, q_) for q_ in projections for p_ in precisions]:
             capi.ep_mlp_set_precision(sim.ctx, prec)
+            capi.ep_mlp_set_projection(sim.ctx, proj)
             capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, tol, K_fb)
             sim.set_particles(R0, V0, w)
             f0 = sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"]
-            entry = {"precision": PREC_NAMES[prec], "drift_tol": tol, **summary(*history(sim))}
+            entry = {"precision": PREC_NAMES[prec], "drift_tol": tol, "projection": proj,
+                     **summary(*history(sim))}
             f1 = sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"]
             entry["fallback_rate"] = (f1 - f0) / (n_eval * steps)
             entry["particle_steps_per_s"] = rate(sim)

@@ -11,6 +11,8 @@ size and checks:
     rms-radius error (BF16 and FP16) and at equal median particle error
     (BF16), on the self-consistent field at equal median particle error
     (BF16 and FP16);
+  * that over a long Duffing run the energy projection keeps the base-push
+    network ahead of the plain push in the particles' positions;
 and prints the equal-error tables: plain K sweep vs learned (with the 1e-5
 energy-drift fallback and without), throughput, rms-radius and median
 particle errors, and the gains at both equal errors.
@@ -21,7 +23,7 @@ import numpy as np
 import pytest
 
 from oracle import duffing
-from paper_1404_1160_amd import EP_FIELD_DUFFING, EP_PUSH_LEARNED, Sim, capi, compare, synth
+from paper_1404_1160_amd import EP_FIELD_DUFFING, EP_MLP_BF16, EP_PUSH_LEARNED, Sim, capi, compare, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -109,6 +111,24 @@ def test_base_push_learned_beats_plain_at_equal_error():
     plain800 = [q for q in res["plain"] if q["K"] == 800][0]
     for e in res["learned"]:
         assert e["one_step_err"] < plain800["one_step_err"], (e, plain800)
+
+
+def test_projected_base_push_stays_ahead_over_a_long_run():
+    """Over 5000 steps (t = 250) of the Duffing workload (2e5 particles here)
+    the base-push network (K_b = 200) without the energy projection drifts in
+    energy; with it (BF16) it ends closer to the reference (plain K = 6400)
+    than the plain push at K = 800 in the particles' positions, at a higher
+    rate, and its energy drift is a fraction of the unprojected one."""
+    res = compare.long_time_duffing(n_eval=200_000, steps=5000, every=500,
+                                    precisions=(EP_MLP_BF16,), log=print)
+    print(json.dumps(res, indent=1))
+    plain800 = [q for q in res["plain"] if q["K"] == 800][0]
+    runs = {e["projection"]: e for e in res["learned"]}
+    proj, raw = runs[True], runs[False]
+    assert proj["median_particle_err_final"] < plain800["median_particle_err_final"], (proj,
+                                                                                      plain800)
+    assert proj["particle_steps_per_s"] > plain800["particle_steps_per_s"]
+    assert proj["energy_drift_max"] < 0.2 * raw["energy_drift_max"], (proj, raw)
 
 
 def test_equal_error_comparison_vp():
