@@ -351,7 +351,7 @@ def main():
             line["learned_vs_plain_base"] = compare.equal_error(
                 n_train=args.learned_train, n_eval=args.learned_eval, epochs=240,
                 lr_final=1e-6, K_fine=6400, K_ref=6400, plain_Ks=(200, 400, 800, 1600, 3200),
-                base_K=args.learned_base_substeps, log=say)
+                base_K=args.learned_base_substeps, K_fb=3200, log=say)
         print("bench: learned-vs-plain comparison, Vlasov-Poisson at scale", file=sys.stderr,
               flush=True)
         # the learned Vlasov-Poisson workload at its size: 1e8 particles,

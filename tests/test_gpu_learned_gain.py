@@ -98,7 +98,7 @@ def test_base_push_learned_beats_plain_at_equal_error():
     below that of the plain push at K = 800."""
     res = compare.equal_error(n_train=10_000_000, n_eval=4_000_000, epochs=240, lr_final=1e-6,
                               K_fine=6400, K_ref=6400, plain_Ks=(200, 400, 800, 1600, 3200),
-                              base_K=200, log=print)
+                              base_K=200, K_fb=3200, log=print)
     keys = [k for k in res if k.startswith("equal_error")]
     print(json.dumps({k: res[k] for k in keys}, indent=1))
     print(json.dumps({k: res[k] for k in ("gains", "gains_phase")}))
