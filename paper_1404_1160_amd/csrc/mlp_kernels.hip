@@ -991,6 +991,9 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
 // Fallback kernels keep the substep coefficients in LDS up to this many
 // substeps (64 KB); beyond it they read them from global memory.
 constexpr int kFallbackLdsK = 2048;
+// The Duffing fallback holds nothing else in LDS, so its table may take up
+// to 128 KB: the fallback of the base-push network runs K_fb = 3200 substeps.
+constexpr int kFallbackLdsKDuffing = 4096;
 
 // LDS of the Poisson fallback: field table and histogram, as in the mesh push
 // kernel, then the coefficient table at a 32-byte boundary.
@@ -1044,7 +1047,7 @@ __device__ __forceinline__ unsigned fallback_groups(unsigned count, unsigned min
     return g < gridDim.x ? (unsigned)g : gridDim.x;
 }
 
-// Copies the K substep coefficients into LDS (K <= kFallbackLdsK).
+// Copies the K substep coefficients into LDS (K within the kernel's limit).
 __device__ __forceinline__ double4 *stage_table(unsigned char *smem, const double4 *sub, int K)
 {
     double4 *t = reinterpret_cast<double4 *>(smem);
@@ -1054,7 +1057,7 @@ __device__ __forceinline__ double4 *stage_table(unsigned char *smem, const doubl
 
 // Plain push (K substeps, FP64) of the queued particles, Duffing field.
 // Workgroups past the queue's end return at once; the others stage the
-// coefficient table in LDS when it fits (K <= kFallbackLdsK).
+// coefficient table in LDS when it fits (K <= kFallbackLdsKDuffing).
 __global__ __launch_bounds__(256) void fallback_duffing_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K,
@@ -1077,7 +1080,7 @@ __global__ __launch_bounds__(256) void fallback_duffing_kernel(
         }
     };
     // two loops, so that each one's table reads use their own address space
-    if (K <= kFallbackLdsK) {
+    if (K <= kFallbackLdsKDuffing) {
         const double4 *t = stage_table(fbd_smem, sub, K);
         __syncthreads();
         run(t);
@@ -1214,7 +1217,7 @@ hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const u
                                    const unsigned *qcount, const double4 *sub, int K,
                                    unsigned long long *total, int n_cu)
 {
-    const size_t lds = K <= kFallbackLdsK ? (size_t)K * sizeof(double4) : 0;
+    const size_t lds = K <= kFallbackLdsKDuffing ? (size_t)K * sizeof(double4) : 0;
     return dispatch(fallback_duffing_kernel, dim3((unsigned)n_cu * 8), dim3(256), lds, st, zR, zV,
                     queue, qcount, sub, K, total, (unsigned)n_cu);
 }
@@ -1242,7 +1245,7 @@ hipError_t setup_learned_lds(int nr)
         (int)mlp_vp_lds_bytes(nr));
     if (e != hipSuccess) return e;
     e = raise_dynamic_lds(reinterpret_cast<const void *>(&fallback_duffing_kernel),
-                          (int)(kFallbackLdsK * sizeof(double4)));
+                          (int)(kFallbackLdsKDuffing * sizeof(double4)));
     if (e != hipSuccess) return e;
     return raise_dynamic_lds(reinterpret_cast<const void *>(&fallback_poisson_kernel),
                              (int)(fallback_table_offset(nr) + kFallbackLdsK * sizeof(double4)));
