@@ -428,13 +428,17 @@ ep_status ep_step_noalloc(float *zR, float *zV, uint64_t n, double w, uint32_t n
 /* Synchronise the context's stream; reports asynchronous errors. */
 ep_status ep_sync(ep_ctx *ctx);
 
-/* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch of the particle kernels.  ep_timing_enable(ctx, 1) clears and
- * starts collection; ep_timing_get synchronises and returns, for the kernel
+/* Per-kernel timing with HIP events attached to the launches of the particle
+ * kernels on the context's stream.  ep_timing_enable(ctx, on) clears the
+ * table and sets the collection: on = 0 stops it, on = 1 times every launch,
+ * on = n > 1 every n-th launch of each kernel (the first, the (n+1)-th, ...),
+ * which keeps the events' own cost (a few microseconds per timed launch)
+ * out of most steps.  ep_timing_get synchronises and returns, for the kernel
  * named `kernel` ("push_poisson", "deposit", "mesh_solve", "push_duffing",
  * "base_push", "mlp_push", "fallback_push",
  * "sort_count", "sort_offsets", "sort_scatter", "sort_combine"), the summed
- * duration in milliseconds and the number of launches.  Errors: EP_EINVAL. */
+ * duration in milliseconds and the number of timed launches.
+ * Errors: EP_EINVAL (also for on < 0). */
 ep_status ep_timing_enable(ep_ctx *ctx, int32_t on);
 ep_status ep_timing_get(ep_ctx *ctx, const char *kernel, double *total_ms, uint64_t *count);
 

@@ -259,7 +259,9 @@ def ep_sync(ctx):
 
 
 def ep_timing_enable(ctx, on=True):
-    _check(ctx, lib().ep_timing_enable(ctx, 1 if on else 0))
+    """on: False/0 off, True/1 every launch, n > 1 every n-th launch of each kernel."""
+    n = (1 if on else 0) if isinstance(on, bool) else int(on)
+    _check(ctx, lib().ep_timing_enable(ctx, n))
 
 
 def ep_timing_get(ctx, kernel):

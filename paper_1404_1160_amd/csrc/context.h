@@ -167,8 +167,10 @@ struct ep_ctx {
     double drift_tol = 1e-5;
     uint32_t fallback_K = 0;
 
-    // timing
+    // timing (every timing_stride-th launch of each kernel name)
     bool timing = false;
+    uint32_t timing_stride = 1;
+    std::map<std::string, uint64_t> launch_seq;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::map<std::string, std::pair<double, uint64_t>> timed;
@@ -199,11 +201,13 @@ struct ep_ctx {
 
 namespace etd {
 
-// Timed launch bracket: records events around `launch` when timing is on.
+// Timed launch bracket: records events around `launch` when timing is on,
+// for every timing_stride-th launch of each kernel name.
 template <typename F>
 inline hipError_t timed_launch(ep_ctx *c, const char *name, F &&launch)
 {
     if (!c->timing) return launch();
+    if (c->timing_stride > 1 && c->launch_seq[name]++ % c->timing_stride != 0) return launch();
     std::pair<hipEvent_t, hipEvent_t> ev;
     if (!c->event_pool.empty()) {
         ev = c->event_pool.back();

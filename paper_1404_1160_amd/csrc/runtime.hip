@@ -586,10 +586,13 @@ done:
 ep_status ep_timing_enable(ep_ctx *c, int32_t on)
 {
     if (!c) return EP_EINVAL;
+    if (on < 0) return c->fail(EP_EINVAL, "ep_timing_enable: on must be >= 0, not %d", (int)on);
     DeviceGuard guard(c->device);
     HIPCHK(c, collect_timing(c));
     c->timed.clear();
+    c->launch_seq.clear();
     c->timing = on != 0;
+    c->timing_stride = on > 1 ? (uint32_t)on : 1u;
     return EP_OK;
 }
 

@@ -191,3 +191,27 @@ def test_load_rejects_invalid_learned_settings(tmp_path):
     sim.step(0.05, 1e-3, EP_FIELD_DUFFING, 1)
     sim.close()
     assert not os.path.exists(str(tmp_path / "missing"))
+
+
+def test_sampled_timing_counts_every_nth_launch():
+    """ep_timing_enable(ctx, n): every n-th launch of each kernel carries the
+    events (the first, the (n+1)-th, ...); 1 times every launch, 0 stops the
+    collection, a negative value is refused; the timed durations are the
+    same kernel's either way, and the results do not depend on the timing."""
+    R0, V0, w = synth.gaussian_truncated(100001, seed=51)
+    out = {}
+    for stride, expect in ((1, 20), (5, 4), (3, 7), (0, 0)):
+        with Sim(R0.size, n_cells=1024) as sim:
+            sim.set_particles(R0, V0, w)
+            capi.ep_timing_enable(sim.ctx, stride)
+            sim.step(0.05, 1e-3, EP_FIELD_POISSON, 20)
+            ms, cnt = capi.ep_timing_get(sim.ctx, "push_poisson")
+            assert cnt == expect, (stride, cnt)
+            assert (ms > 0) == (expect > 0)
+            out[stride] = sim.particles()
+            with pytest.raises(capi.EtdpicError) as ei:
+                capi.ep_timing_enable(sim.ctx, -1)
+            assert ei.value.status == capi.EP_EINVAL
+    for stride in (5, 3, 0):
+        assert np.array_equal(out[stride][0], out[1][0]) and np.array_equal(out[stride][1],
+                                                                              out[1][1])
