@@ -111,4 +111,7 @@ def test_library_refuses_a_process_with_another_hip_runtime():
 def test_null_context_is_rejected(lib):
     assert lib.ep_step(None, 0.1, 0.1, 1, 1) == capi.EP_EINVAL
     assert lib.ep_sync(None) == capi.EP_EINVAL
+    assert lib.ep_mlp_set_projection(None, 1) == capi.EP_EINVAL
+    assert lib.ep_mlp_set_precision(None, 0) == capi.EP_EINVAL
+    assert lib.ep_timing_enable(None, 5) == capi.EP_EINVAL
     assert lib.ep_destroy(None) == capi.EP_OK

@@ -218,6 +218,11 @@ def test_base_push_settings_are_validated():
         # an 8-value normalisation means no base push
         capi.ep_mlp_set_weights(sim.ctx, p, norm.as_array()[:8])
         assert capi.ep_mlp_get_weights(sim.ctx, NP5)[1][8] == 0.0
+        # the projection switch takes 0 or 1 only
+        assert capi.lib().ep_mlp_set_projection(sim.ctx, 2) == capi.EP_EINVAL
+        assert capi.lib().ep_mlp_set_projection(sim.ctx, -1) == capi.EP_EINVAL
+        capi.ep_mlp_set_projection(sim.ctx, True)
+        capi.ep_mlp_set_projection(sim.ctx, False)
 
 
 def test_base_push_survives_a_checkpoint(tmp_path):
