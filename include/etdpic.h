@@ -180,9 +180,13 @@ ep_status ep_get_field(ep_ctx *ctx, double *rho, double *E, double *Psi, double 
  * relative energy-drift bound |H(y_{n+1}) - H(y_n)| <= drift_tol * H(y_n)
  * (H(y) = |y|^2/(2 eps) + P(R), the frozen-field energy of the step: P = R^4/4
  * for the Duffing field, the mesh potential Psi^n for the Poisson field), and
- * fallback_substeps the K used by the plain push for particles that fail it.
+ * fallback_substeps the K used by the plain push for particles that fail it
+ * (to help, it should be at least as accurate as the network's step; for a
+ * network with a base push that means more substeps than the base push).
  * ep_step then needs a 5-input network for the Duffing field and a 6-input
- * one for the Poisson field.  Errors: EP_EINVAL, EP_ENOTRAINED. */
+ * one for the Poisson field; the base push and the energy projection of the
+ * loaded network and context apply (see the learned section below).
+ * Errors: EP_EINVAL, EP_ENOTRAINED. */
 ep_status ep_set_push_mode(ep_ctx *ctx, int32_t push, double drift_tol,
                            uint32_t fallback_substeps);
 
