@@ -39,9 +39,9 @@ Check: the frozen-field energy H^n(y) = (R^2 + V^2)/(2 eps) + P(R), P = R^4/4
 |H^n(y_{n+1}) - H^n(y_n)| <= tol |H^n(y_n)|; particles that fail take the
 plain K_fb-substep push instead.  Projection (optional): the exact step
 conserves H^n (the Duffing energy, or the frozen-field energy of the step),
-so a particle that passes may be moved radially back onto its energy shell
-with one Newton step (project_energy); the phase of the prediction is
-kept.
+so every particle of the step (the network's and the fallback's) may be
+moved radially back onto its energy shell with one Newton step
+(project_energy); the phase of the result is kept.
 
 Parity unpinned: nothing (forward/backward pinned by finite differences and
 the linear limit, Adam by its closed-form first step, the output map by the
@@ -251,9 +251,10 @@ def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=Non
     plain step used for particles that fail the check; base_push(R, V): the
     plain step with norm.base_K substeps, which a network with a base push
     corrects (needed then, unused otherwise); dpotential(R) = P'(R): given,
-    the particles that pass the check are projected onto their energy shell
-    H^n(y_{n+1}) = H^n(y_n) (project_energy) after it.  Returns
-    (R1, V1, fell_back[bool], ratio = |dH|/|H| before the projection)."""
+    every particle, the network's and the fallback's, is projected onto its
+    energy shell H^n(y_{n+1}) = H^n(y_n) (project_energy) after the check.
+    Returns (R1, V1, fell_back[bool], ratio = |dH|/|H| of the network's
+    prediction, before the projection)."""
     delta, kappa = predict(p, R, V, dt, eps, norm, Egather)
     if norm.base_K:
         if base_push is None:
@@ -267,12 +268,12 @@ def learned_step(p, R, V, dt, eps, norm, potential, plain_push, tol, Egather=Non
     H1 = energy(R1, V1, eps, potential)
     ratio = np.abs(H1 - H0) / np.abs(H0)
     fb = ~(ratio <= tol)
-    if dpotential is not None:
-        R1, V1 = project_energy(R1, V1, H0, eps, potential, dpotential)
     if np.any(fb):
         Rf, Vf = plain_push(R[fb], V[fb])
         R1 = R1.copy()
         V1 = V1.copy()
         R1[fb] = Rf
         V1[fb] = Vf
+    if dpotential is not None:
+        R1, V1 = project_energy(R1, V1, H0, eps, potential, dpotential)
     return R1, V1, fb, ratio

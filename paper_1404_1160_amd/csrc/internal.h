@@ -201,11 +201,19 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, const f
                                    const float *cV, int64_t n, const MlpInfer &net, double2 rot0,
                                    double2 rot1, double eps, double tol, unsigned *qcount,
                                    unsigned *queue, int n_cu);
+// Energy projection of the fallback particles (as for the network's, with an
+// FP64 Newton step): on/off, the step's start and end phases, 1/(2 eps).
+struct FallbackProjection {
+    int on;
+    double2 rot0, rot1;
+    double inv2eps;
+};
 // Plain K-substep Duffing push of the *qcount queued particles; adds the count
 // to *total.
 hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,
                                    const unsigned *qcount, const double4 *sub, int K,
-                                   unsigned long long *total, int n_cu);
+                                   const FallbackProjection &proj, unsigned long long *total,
+                                   int n_cu);
 hipError_t launch_gen_labels_poisson(hipStream_t st, const float *zR, const float *zV,
                                      int64_t first, int64_t stride, int64_t count, double2 rot0,
                                      const MeshArgs &ma, const double4 *sub, int K, float inv_sin,
@@ -217,10 +225,12 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
                                    const MlpInfer &net, double2 rot0, double2 rot1, double eps,
                                    double tol, unsigned *qcount, unsigned *queue,
                                    const MeshArgs &ma, double rmax, int n_cu);
-// Plain push + deposit of the queued particles in the frozen Poisson field.
+// Plain push + deposit of the queued particles in the frozen Poisson field
+// (er: end-of-step phase; proj.rot1 is er).
 hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const unsigned *queue,
                                    const unsigned *qcount, const double4 *sub, int K, double2 er,
-                                   const MeshArgs &ma, unsigned long long *total, int n_cu);
+                                   const MeshArgs &ma, double rmax, const FallbackProjection &proj,
+                                   unsigned long long *total, int n_cu);
 hipError_t setup_learned_lds(int nr);
 
 // ------------------------------------------------------------ fine solvers

@@ -376,6 +376,7 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
             const double2 rot0 = make_double2(cos(p0), sin(p0));
             const double2 rot1 = make_double2(cos(p1), sin(p1));
             const double4 *sub = c->tab.sub + (size_t)j * K;
+            const FallbackProjection fproj{L.project ? 1 : 0, rot0, rot1, 0.5 / eps};
             HIPCHK(c, hipMemsetAsync(L.d_qcount, 0, sizeof(unsigned), c->stream));
             if (vp) {
                 HIPCHK(c, timed_launch(c, "mlp_push", [&] {
@@ -386,7 +387,8 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
                        }));
                 HIPCHK(c, timed_launch(c, "fallback_push", [&] {
                            return launch_fallback_poisson(c->stream, c->zR, c->zV, L.d_queue,
-                                                          L.d_qcount, sub, K, rot1, ma, L.d_total,
+                                                          L.d_qcount, sub, K, rot1, ma,
+                                                          c->cfg.r_max, fproj, L.d_total,
                                                           c->n_cu);
                        }));
                 // the next learned step checks energies with this field's potential
@@ -406,7 +408,8 @@ ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_
                        }));
                 HIPCHK(c, timed_launch(c, "fallback_push", [&] {
                            return launch_fallback_duffing(c->stream, c->zR, c->zV, L.d_queue,
-                                                          L.d_qcount, sub, K, L.d_total, c->n_cu);
+                                                          L.d_qcount, sub, K, fproj, L.d_total,
+                                                          c->n_cu);
                        }));
             }
         }

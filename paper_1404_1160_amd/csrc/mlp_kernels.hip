@@ -774,6 +774,22 @@ __device__ __forceinline__ double potential(const PotView &v, double R)
     return v.Psi[m] - fma(e0, d, (e1 - e0) * (d * d) * (0.5 * v.inv_hr));
 }
 
+// One Newton step of the radial projection z <- s z onto the energy H0 from
+// s = 1 (H1 the energy at z, RdP = R P'(R) at its lab position): the slope
+// dH/ds = |z|^2 / eps + R P'(R); skipped where it is not above half of its
+// kinetic part.
+__device__ __forceinline__ void project_radially(double &zr, double &zv, double H0, double H1,
+                                                 double RdP, double inv2eps)
+{
+    const double A = (zr * zr + zv * zv) * (2.0 * inv2eps);
+    const double slope = A + RdP;
+    if (slope > 0.5 * A) {
+        const double s = 1.0 - (H1 - H0) / slope;
+        zr *= s;
+        zv *= s;
+    }
+}
+
 // Waves per workgroup of the inference kernel.  With the Poisson field a
 // workgroup holds a (N_r + 1)-entry histogram in LDS, which allows two
 // workgroups per CU: eight waves each keep four waves on every SIMD.
@@ -1061,7 +1077,7 @@ __device__ __forceinline__ double4 *stage_table(unsigned char *smem, const doubl
 __global__ __launch_bounds__(256) void fallback_duffing_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K,
-    unsigned long long *__restrict__ total, unsigned min_groups)
+    FallbackProjection proj, unsigned long long *__restrict__ total, unsigned min_groups)
 {
     extern __shared__ __align__(16) unsigned char fbd_smem[];
     const unsigned count = *qcount;
@@ -1074,7 +1090,18 @@ __global__ __launch_bounds__(256) void fallback_duffing_kernel(
              i += (uint64_t)blockDim.x * G) {
             const unsigned p = queue[i];
             double zr = zR[p], zv = zV[p];
+            double H0 = 0.0;
+            if (proj.on) {
+                const double R0 = fma(proj.rot0.x, zr, proj.rot0.y * zv);
+                H0 = fma(zr * zr + zv * zv, proj.inv2eps, 0.25 * (R0 * R0) * (R0 * R0));
+            }
             push_staged(t, K, duffing, zr, zv);
+            if (proj.on) {
+                const double R1 = fma(proj.rot1.x, zr, proj.rot1.y * zv);
+                const double P1 = 0.25 * (R1 * R1) * (R1 * R1);
+                project_radially(zr, zv, H0, fma(zr * zr + zv * zv, proj.inv2eps, P1), 4.0 * P1,
+                                 proj.inv2eps);
+            }
             zR[p] = (float)zr;
             zV[p] = (float)zv;
         }
@@ -1095,9 +1122,9 @@ __global__ __launch_bounds__(256) void fallback_duffing_kernel(
 __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const unsigned *__restrict__ queue,
     const unsigned *__restrict__ qcount, const double4 *__restrict__ sub, int K, double2 er,
-    MeshView mv, const float2 *__restrict__ etab, const double *__restrict__ fscal, int nr,
-    unsigned long long *__restrict__ hist, unsigned long long *__restrict__ total,
-    unsigned min_groups)
+    MeshView mv, PotView pv, FallbackProjection proj, const float2 *__restrict__ etab,
+    const double *__restrict__ fscal, int nr, unsigned long long *__restrict__ hist,
+    unsigned long long *__restrict__ total, unsigned min_groups)
 {
     extern __shared__ __align__(16) unsigned char fb_smem[];
     const unsigned count = *qcount;
@@ -1111,7 +1138,7 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
     float2 *Et = reinterpret_cast<float2 *>(fb_smem);
     for (int i = tid; i < nr; i += blockDim.x) Et[i] = etab[i];
     for (int i = tid; i <= nr; i += blockDim.x) mv.H[i] = 0ull;
-    mv.Qb = fscal[kQb];
+    mv.Qb = pv.Qb = fscal[kQb];
     const bool staged = K <= kFallbackLdsK;
     const double4 *t = staged ? stage_table(fb_smem + fallback_table_offset(nr), sub, K) : nullptr;
     // particles with |z|^2 < lim2 take the gather without range tests
@@ -1124,10 +1151,21 @@ __global__ __launch_bounds__(kPushBlock) void fallback_poisson_kernel(
              i += (uint64_t)blockDim.x * G) {
             const unsigned p = queue[i];
             double zr = zR[p], zv = zV[p];
+            double H0 = 0.0;
+            if (proj.on) {
+                const double R0 = fma(proj.rot0.x, zr, proj.rot0.y * zv);
+                H0 = fma(zr * zr + zv * zv, proj.inv2eps, potential(pv, R0));
+            }
             if (fma(zr, zr, zv * zv) < lim2)
                 push_staged(tab, K, field_on, zr, zv);
             else
                 push_staged(tab, K, field, zr, zv);
+            if (proj.on) {
+                const double R1 = fma(er.x, zr, er.y * zv);
+                project_radially(zr, zv, H0,
+                                 fma(zr * zr + zv * zv, proj.inv2eps, potential(pv, R1)),
+                                 -R1 * gather(mv, R1), proj.inv2eps);
+            }
             const float fr = (float)zr, fv = (float)zv;
             zR[p] = fr;
             zV[p] = fv;
@@ -1182,14 +1220,9 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, const f
 
 static size_t mlp_vp_lds_bytes(int nr) { return (size_t)(nr + 1) * sizeof(unsigned long long); }
 
-hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t n,
-                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
-                                   double tol, unsigned *qcount, unsigned *queue,
-                                   const MeshArgs &ma, double rmax, int n_cu)
+// The FP64 node field and potential of the mesh (Qb is read on the device).
+static PotView pot_view(const MeshArgs &ma, double rmax)
 {
-    if (n <= 0) return hipSuccess;
-    int64_t grid = (n + 32 * kWavesPoisson - 1) / (32 * kWavesPoisson);
-    if (grid > (int64_t)n_cu * 2) grid = (int64_t)n_cu * 2;
     PotView pv;
     pv.E = ma.E64;
     pv.Psi = ma.Psi64;
@@ -1200,6 +1233,18 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
     pv.Qb = 0.0;
     pv.c = ma.nr >> 1;
     pv.nr = ma.nr;
+    return pv;
+}
+
+hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t n,
+                                   const MlpInfer &net, double2 rot0, double2 rot1, double eps,
+                                   double tol, unsigned *qcount, unsigned *queue,
+                                   const MeshArgs &ma, double rmax, int n_cu)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t grid = (n + 32 * kWavesPoisson - 1) / (32 * kWavesPoisson);
+    if (grid > (int64_t)n_cu * 2) grid = (int64_t)n_cu * 2;
+    const PotView pv = pot_view(ma, rmax);
     const dim3 g((unsigned)grid), b(64 * kWavesPoisson);
     const size_t lds = mlp_vp_lds_bytes(ma.nr);
     if (net.fp16)
@@ -1215,23 +1260,26 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
 
 hipError_t launch_fallback_duffing(hipStream_t st, float *zR, float *zV, const unsigned *queue,
                                    const unsigned *qcount, const double4 *sub, int K,
-                                   unsigned long long *total, int n_cu)
+                                   const FallbackProjection &proj, unsigned long long *total,
+                                   int n_cu)
 {
     const size_t lds = K <= kFallbackLdsKDuffing ? (size_t)K * sizeof(double4) : 0;
     return dispatch(fallback_duffing_kernel, dim3((unsigned)n_cu * 8), dim3(256), lds, st, zR, zV,
-                    queue, qcount, sub, K, total, (unsigned)n_cu);
+                    queue, qcount, sub, K, proj, total, (unsigned)n_cu);
 }
 
 hipError_t launch_fallback_poisson(hipStream_t st, float *zR, float *zV, const unsigned *queue,
                                    const unsigned *qcount, const double4 *sub, int K, double2 er,
-                                   const MeshArgs &ma, unsigned long long *total, int n_cu)
+                                   const MeshArgs &ma, double rmax, const FallbackProjection &proj,
+                                   unsigned long long *total, int n_cu)
 {
     const size_t lds = K <= kFallbackLdsK
                            ? fallback_table_offset(ma.nr) + (size_t)K * sizeof(double4)
                            : push_lds_bytes_for(ma.nr);
     return dispatch(fallback_poisson_kernel, dim3((unsigned)n_cu), dim3(kPushBlock), lds, st, zR, zV,
-                    queue, qcount, sub, K, er, mesh_view(ma), (const float2 *)ma.etab,
-                    (const double *)ma.fscal, ma.nr, ma.hist, total, (unsigned)n_cu);
+                    queue, qcount, sub, K, er, mesh_view(ma), pot_view(ma, rmax), proj,
+                    (const float2 *)ma.etab, (const double *)ma.fscal, ma.nr, ma.hist, total,
+                    (unsigned)n_cu);
 }
 
 hipError_t setup_learned_lds(int nr)

@@ -287,16 +287,24 @@ def test_energy_projection_matches_oracle(Kb, precision):
 
 
 def test_projection_keeps_the_check_decisions():
-    """The check decides on the unprojected prediction: with and without the
-    projection the same particles fall back, with the same plain results."""
+    """The check decides on the unprojected prediction, so the same particles
+    fall back with and without the projection; with it, every particle (the
+    network's and the fallback's) ends on its energy shell, and the GPU's
+    projected results match the oracle's (clear decisions: the fallback to
+    the plain-push bound, the network to its map bound)."""
     R0, V0, w = synth.gaussian(20001, seed=38, sigma=SIG)
     Kb, K_fb = 50, 400
     p, norm = _net(Kb, seed=10)
     pd = p.astype(np.float64)
     pot = lambda r: r ** 4 / 4
-    _, _, _, ratio = mlp.learned_step(pd, R0, V0, DT, EPS, norm, pot, lambda a, b: push(a, b, K_fb),
-                                      math.inf, base_push=lambda a, b: push(a, b, Kb))
+    dpot = lambda r: r ** 3
+    plain = lambda a, b: push(a, b, K_fb)
+    base = lambda a, b: push(a, b, Kb)
+    _, _, _, ratio = mlp.learned_step(pd, R0, V0, DT, EPS, norm, pot, plain, math.inf,
+                                      base_push=base)
     tol = float(np.median(ratio))
+    Ro, Vo, fbo, ratio = mlp.learned_step(pd, R0, V0, DT, EPS, norm, pot, plain, tol,
+                                          base_push=base, dpotential=dpot)
     out = {}
     for proj in (False, True):
         sim = _learned_sim(R0, V0, w, p, norm, tol, K_fb)
@@ -304,13 +312,13 @@ def test_projection_keeps_the_check_decisions():
         sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
         out[proj] = sim.particles() + (sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"],)
         sim.close()
-    (Ra, Va, na), (Rb, Vb, nb) = out[False], out[True]
-    assert na == nb and 0.3 * R0.size < na < 0.7 * R0.size
-    same = (Ra == Rb) & (Va == Vb)
-    # the fallback particles (and only those, up to particles the projection
-    # left unchanged) agree bitwise
-    assert same.sum() >= na
+    (_, _, na), (Rb, Vb, nb) = out[False], out[True]
+    assert na == nb and 0.3 * R0.size < nb < 0.7 * R0.size
+    clear = np.abs(ratio / tol - 1.0) > 0.2
+    err = rel_particle(Rb, Vb, Ro, Vo)
+    assert np.max(err[clear & fbo], initial=0.0) <= 1e-6
+    assert np.max(rel_particle(Rb, Vb, Ro, Vo, MAP_FLOOR)[clear & ~fbo],
+                  initial=0.0) <= MAP_TOL[EP_MLP_BF16]
     H = lambda R, V: mlp.energy(R, V, EPS, pot)
     H0 = H(R0.astype(np.float32).astype(np.float64), V0.astype(np.float32).astype(np.float64))
-    moved = ~same
-    assert np.median(np.abs(H(Rb[moved], Vb[moved]) / H0[moved] - 1)) < 1e-6
+    assert np.percentile(np.abs(H(Rb, Vb) / H0 - 1), 99) < 1e-6

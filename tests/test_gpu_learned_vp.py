@@ -168,6 +168,42 @@ def test_check_decisions_agree_with_oracle(precision):
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
 
 
+def test_check_decisions_with_projection_agree_with_oracle():
+    """With the energy projection the check still decides on the network's
+    prediction; where the oracle's ratio is clear of tol the GPU's result is
+    the oracle's projected one (the fallback to the plain bound, the map to
+    its bound), and the particles end on their frozen-field energy shells."""
+    n, K_fb = 20001, 64
+    p = synth.mlp_init(6, 64, 2, seed=10)
+    norm = _norm()
+    R0, V0, w = synth.gaussian_truncated(n, seed=44)
+    E, Psi, Qb = _field(R0, w)
+    Eg = oracle.gather(R0, E, Qb, NR, -RMAX, RMAX)
+    pot = lambda r: oracle.potential(r, E, Psi, Qb, NR, -RMAX, RMAX)
+    dpot = lambda r: -oracle.gather(r, E, Qb, NR, -RMAX, RMAX)
+    plain = lambda R, V: oracle.push(R, V, DT, EPS, K_fb, E=E, Qb=Qb, **POIS)
+    pd = p.astype(np.float64)
+    _, _, _, ratio = mlp.learned_step(pd, R0, V0, DT, EPS, norm, pot, plain, math.inf, Egather=Eg)
+    tol = float(np.median(ratio))
+    Ro, Vo, fb, ratio = mlp.learned_step(pd, R0, V0, DT, EPS, norm, pot, plain, tol, Egather=Eg,
+                                         dpotential=dpot)
+    sim, _ = _learned_sim(n, 44, p, norm, tol, K_fb)
+    capi.ep_mlp_set_projection(sim.ctx, True)
+    sim.step(DT, EPS, EP_FIELD_POISSON, 1)
+    Rg, Vg = sim.particles()
+    nfb = sim.moments(EPS, EP_FIELD_POISSON)["n_fallback"]
+    sim.close()
+    clear = np.abs(ratio / tol - 1.0) > 0.2
+    assert 0.3 < fb.mean() < 0.7 and clear.mean() > 0.5
+    err = rel_particle(Rg, Vg, Ro, Vo)
+    assert np.max(err[clear & fb], initial=0.0) <= 1e-6
+    assert np.max(err[clear & ~fb], initial=0.0) <= MAP_TOL[EP_MLP_BF16]
+    assert abs(nfb - fb.sum()) <= np.sum(~clear)
+    H = lambda a, b: mlp.energy(a, b, EPS, pot)
+    drift = np.abs(H(Rg, Vg) / H(R0, V0) - 1)
+    assert np.percentile(drift, 99) < 1e-6, np.percentile(drift, 99)
+
+
 def _check_decisions(Rg, Vg, R0, V0, Ro, Vo, fb, clear, pd, norm, pot, plain, Eg, precision):
     """Where the oracle's drift ratio is clear of tol the GPU took the
     oracle's branch; where it is not, either branch is valid (the GPU applies

@@ -278,8 +278,9 @@ def test_energy_projection_returns_to_the_shell_and_keeps_the_phase():
 
 
 def test_learned_step_with_projection():
-    """With dpotential the particles that pass the check end on their energy
-    shell; the decisions (and the fallback results) are those without it."""
+    """With dpotential every particle ends on its energy shell, the network's
+    and the fallback's; the decisions are those without it, and the fallback
+    particles keep the angle of their plain push."""
     R, V, _ = synth.gaussian(2000, seed=15, sigma=1.5)
     dt, eps, Kb = 0.05, 1e-3, 50
     p = synth.mlp_init(5, 64, 2, seed=7).astype(np.float64)
@@ -294,10 +295,16 @@ def test_learned_step_with_projection():
     Rb, Vb, fb, rb = mlp.learned_step(p, R, V, dt, eps, norm, pot, fbp, tol, base_push=base,
                                       dpotential=dpot)
     assert np.array_equal(fa, fb) and np.array_equal(ra, rb) and 0.3 < fb.mean() < 0.7
-    assert np.array_equal(Ra[fb], Rb[fb]) and np.array_equal(Va[fb], Vb[fb])
     H0 = mlp.energy(R, V, eps, pot)
     # Newton from within tol of the shell: O(tol^2) off it afterwards
     after = np.abs(mlp.energy(Rb[~fb], Vb[~fb], eps, pot) / H0[~fb] - 1)
     before = np.abs(mlp.energy(Ra[~fb], Va[~fb], eps, pot) / H0[~fb] - 1)
     assert after.max() <= tol * tol, (after.max(), tol)
     assert np.median(after) < 1e-3 * np.median(before)
+    # the fallback (plain K = 40) particles: on the shell to O(r^2) of their
+    # own energy error r, at the angle of the plain push
+    r = np.abs(mlp.energy(Ra[fb], Va[fb], eps, pot) / H0[fb] - 1)
+    after_fb = np.abs(mlp.energy(Rb[fb], Vb[fb], eps, pot) / H0[fb] - 1)
+    assert np.all(after_fb <= r * r + 1e-14)
+    ang = np.arctan2(Vb[fb], Rb[fb]) - np.arctan2(Va[fb], Ra[fb])
+    assert np.max(np.abs(np.angle(np.exp(1j * ang)))) < 1e-14
