@@ -199,9 +199,16 @@ def test_check_decisions_with_projection_agree_with_oracle():
     assert np.max(err[clear & fb], initial=0.0) <= 1e-6
     assert np.max(err[clear & ~fb], initial=0.0) <= MAP_TOL[EP_MLP_BF16]
     assert abs(nfb - fb.sum()) <= np.sum(~clear)
+    # on the shell to O(r^2) of each result's own energy error r before the
+    # projection (the map's, below tol; the plain push's, up to ~1e-3 at
+    # K_fb = 64), plus the FP32 rounding of the stored state
     H = lambda a, b: mlp.energy(a, b, EPS, pot)
-    drift = np.abs(H(Rg, Vg) / H(R0, V0) - 1)
-    assert np.percentile(drift, 99) < 1e-6, np.percentile(drift, 99)
+    H0 = H(R0, V0)
+    drift = np.abs(H(Rg, Vg) / H0 - 1)
+    Rp, Vp = plain(R0, V0)
+    r = np.where(fb, np.abs(H(Rp, Vp) / H0 - 1), ratio)
+    ok = drift <= 1e-6 + r * r
+    assert np.mean(ok[clear]) >= 0.99, np.percentile((drift - r * r)[clear], 99)
 
 
 def _check_decisions(Rg, Vg, R0, V0, Ro, Vo, fb, clear, pd, norm, pot, plain, Eg, precision):
