@@ -303,12 +303,13 @@ ep_status ep_mlp_set_precision(ep_ctx *ctx, int32_t precision);
  * Duffing energy, a first integral of eq. 1.4 with E = -r^3 (appendix A), or
  * the frozen-field energy of the step), which the network's map does only
  * to its fit, with errors that share a sign and add up over long runs.  With
- * the projection every particle that passes the check is moved radially back
- * onto its energy shell by one Newton step from s = 1 of
- * H^n(s y_{n+1}) = H^n(y_n): s = 1 - (H^n(y_{n+1}) - H^n(y_n)) / S,
+ * the projection every particle of the step (the network's after the check,
+ * and the fallback's) is moved radially back onto its energy shell by one
+ * Newton step from s = 1 of H^n(s y_{n+1}) = H^n(y_n):
+ * s = 1 - (H^n(y_{n+1}) - H^n(y_n)) / S,
  * S = |y_{n+1}|^2 / eps + R_{n+1} P'(R_{n+1}), skipped where S is not above
- * half of |y_{n+1}|^2 / eps; the phase of the prediction is kept and the
- * check decides on the unprojected prediction.  A setting of the context
+ * half of |y_{n+1}|^2 / eps; the phase of the result is kept and the check
+ * decides on the unprojected prediction.  A setting of the context
  * (kept across networks, saved in checkpoints).  Errors: EP_EINVAL. */
 ep_status ep_mlp_set_projection(ep_ctx *ctx, int32_t on);
 
