@@ -74,8 +74,9 @@ def parse():
     ap.add_argument("--long-time", action="store_true",
                     help="add the long-time runs: learned Vlasov-Poisson (1e7 particles, "
                          "1e4 steps), learned Duffing with a base push (1e6 particles, 2e4 "
-                         "steps), each with and without the energy projection, and the "
-                         "paper's schemes to t = 90; several minutes")
+                         "steps), each with and without the energy projection, the learned "
+                         "Vlasov-Poisson comparison at 1e8 particles with the projection, and "
+                         "the paper's schemes to t = 90; several minutes")
     ap.add_argument("--no-paper-schemes", action="store_true",
                     help="skip the reference-RK4 / improved-ETD measurement")
     ap.add_argument("--learned-train", type=int, default=10_000_000)
@@ -386,6 +387,15 @@ def main():
             runs += ((1e-4, 90.0, (30.0, 60.0, 90.0)),)
         line["paper_schemes_long_vp"] = compare.paper_schemes_long_vp(
             runs=runs, log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    if args.long_time and not args.no_learned:
+        from paper_1404_1160_amd import compare
+        print("bench: learned-vs-plain comparison, Vlasov-Poisson at scale, energy projection",
+              file=sys.stderr, flush=True)
+        line["learned_vs_plain_vp_projected"] = compare.equal_error_vp(
+            n_eval=args.learned_vp_eval, n_data=args.learned_vp_data,
+            steps=args.learned_vp_steps, every=max(10, args.learned_vp_steps // 20),
+            plain_Ks=(100, 200, 400), K_ref=1600, extra_tols=(), single_run=True, project=True,
+            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if args.long_time:
         from paper_1404_1160_amd import compare
         print("bench: long-time learned Vlasov-Poisson run", file=sys.stderr, flush=True)
