@@ -147,6 +147,35 @@ def test_equal_error_comparison_vp():
     assert res["learned"][-1]["rms_err"] < errs[0]
 
 
+def test_projection_does_not_make_an_untrained_network_look_trained():
+    """With the energy projection every amplitude is put back on its energy
+    shell, so the rms radius alone could flatter any network.  The particle
+    error does not: over 200 steps of the Vlasov-Poisson workload (1e6
+    particles, N_r = 4096, reference plain K = 3200), the trained network
+    with the projection ends far closer to the reference than the untrained
+    one with the projection."""
+    from paper_1404_1160_amd import EP_FIELD_POISSON
+    n, steps, nr = 1_000_000, 200, 4096
+    p, norm, _, _ = compare.train_vp(1_000_000, steps, nr=nr, collect_every=10)
+    R0, V0, w = synth.gaussian_truncated(n, seed=17)
+    with Sim(n, n_cells=nr, substeps=3200) as ref:
+        ref.set_particles(R0, V0, w)
+        ref.step(compare.VP_DT, compare.VP_EPS, EP_FIELD_POISSON, steps)
+        Rr, Vr = ref.particles()
+    err = {}
+    for name, params in (("trained", p), ("untrained", synth.mlp_init(6, 64, 2, seed=5))):
+        with Sim(n, n_cells=nr, substeps=1) as sim:
+            sim.set_particles(R0, V0, w)
+            capi.ep_mlp_set_weights(sim.ctx, params, norm)
+            capi.ep_mlp_set_projection(sim.ctx, True)
+            capi.ep_set_push_mode(sim.ctx, EP_PUSH_LEARNED, 1e300, 400)
+            sim.step(compare.VP_DT, compare.VP_EPS, EP_FIELD_POISSON, steps)
+            R, V = sim.particles()
+        err[name] = float(np.median(np.hypot(R - Rr, V - Vr)))
+    print(err)
+    assert err["trained"] < 0.1 * err["untrained"], err
+
+
 def test_learned_vp_beats_plain_at_equal_error():
     """At the Vlasov-Poisson workload (N_r = 4096, eps = 1e-3, dt = 0.1, 200
     steps; the network trained on samples of a separate beam labelled with
