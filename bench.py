@@ -172,14 +172,17 @@ def cpu_baseline(n_full, cells, eps, dt, K, seconds):
 
 
 # algorithmic HBM bytes per particle of each particle kernel (FP32 state and
-# u32 ids; the mesh is LDS/L2 resident)
-KERNEL_BYTES = {"push_poisson": 16, "sort_count": 8, "sort_scatter": 24}
+# u32 ids; the mesh is LDS/L2 resident).  The sort passes of every step but the
+# first of a call read the 12-byte (R, V, id) records the scatter writes; the
+# first count pass reads 8 B of SoA state, and sort_unpack turns the last
+# records back into the SoA state once per call (12 B read, 12 B written).
+KERNEL_BYTES = {"push_poisson": 16, "sort_count": 12, "sort_scatter": 24, "sort_unpack": 24}
 # HIP events on every 5th launch of each kernel: the averages come from a
 # fifth of the timed steps, and the events' own cost (a few microseconds per
 # timed launch) stays out of the other four fifths
 TIMING_STRIDE = 5
 STEP_KERNELS = ("push_poisson", "mesh_solve", "potential", "sort_count", "sort_offsets", "sort_scatter",
-                "sort_combine")
+                "sort_combine", "sort_unpack")
 
 
 def run_pic(args, deposit, steps, warmup, R0, V0, w, copy_ceiling=None):

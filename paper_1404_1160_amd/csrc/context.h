@@ -125,9 +125,10 @@ struct ep_ctx {
         return m;
     }
 
-    // sorted deposit: second particle buffer (cell order), ids, count tables
-    float *sR = nullptr, *sV = nullptr;
-    unsigned *ids = nullptr, *ids2 = nullptr, *inv = nullptr;
+    // sorted deposit: the state as records within a call (two buffers, cell
+    // order), ids, count tables
+    unsigned *rec[2] = {nullptr, nullptr};   // (R, V, id) records, 12 B per particle
+    unsigned *ids = nullptr, *inv = nullptr;
     unsigned *counts = nullptr, *total = nullptr, *starts = nullptr;
     unsigned long long *sums = nullptr;   // segment sums of the scatter pass [grid][nr+1]
 
@@ -256,7 +257,9 @@ ep_status refresh_field(ep_ctx *c);
 ep_status solve_mesh(ep_ctx *c, const MeshArgs &ma, bool potential);
 // Psi and the field energy of the current field, if a solve left them out.
 ep_status ensure_potential(ep_ctx *c);
-ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K);
+ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K, int in,
+                      int out);
+ep_status sorted_unpack(ep_ctx *c, int cur);
 void free_learned(ep_ctx *c);
 // Learned push of n_steps steps (Duffing field); defined with the learned API.
 ep_status learned_steps(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_steps);

@@ -109,9 +109,14 @@ hipError_t launch_potential(hipStream_t st, const MeshArgs &ma);
 
 // ------------------------------------------------------------ sorted deposit
 
+// Inside one multi-step call the sorted state travels as 12-byte records
+// (R, V as FP32 bits, id), so that the scatter stores one record per particle
+// instead of three scattered words; the first step of a call reads the SoA
+// state, and sort_unpack writes the last step's records back to it.
 struct SortArgs {
-    const float *zR, *zV;      // state before the step (particle order)
-    const unsigned *ids;       // particle ids in that order
+    const float *zR, *zV;      // state before the step (particle order), if rec_in is null
+    const unsigned *ids;       // particle ids in that order, if rec_in is null
+    const unsigned *rec_in;    // or the state as records [n][3]
     int64_t n;
     const double4 *sub;        // substep table of the step
     const double2 *endrot;     // rotation to the lab frame at the end of the step
@@ -123,8 +128,7 @@ struct SortArgs {
     unsigned *counts;          // [grid][nr+1]
     unsigned *total;           // [nr+1]
     unsigned *starts;          // [nr+1]
-    float *oR, *oV;            // state after the step, cell order
-    unsigned *oid;
+    unsigned *rec_out;         // state after the step, cell order, records [n][3]
     unsigned long long *hist;  // [nr+1] fixed-point node charges
     unsigned long long *sums;  // [grid][nr+1] segment sums of the scatter pass
 };
@@ -134,6 +138,8 @@ hipError_t launch_sort_count(hipStream_t st, const SortArgs &a, int grid);
 hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid);
 hipError_t launch_sort_scatter(hipStream_t st, const SortArgs &a, int grid);
 hipError_t launch_sort_combine(hipStream_t st, const SortArgs &a, int grid);
+hipError_t launch_sort_unpack(hipStream_t st, const unsigned *rec, int64_t n, float *zR, float *zV,
+                              unsigned *ids);
 size_t sort_lds_bytes_for(int nr);   // LDS of the scatter pass (the larger one)
 hipError_t launch_iota(hipStream_t st, unsigned *ids, int64_t first, int64_t n);
 hipError_t launch_inverse(hipStream_t st, const unsigned *ids, int64_t n, unsigned *inv);

@@ -17,7 +17,7 @@ void free_all(ep_ctx *c)
                     (void *)c->etab, (void *)c->rho64, (void *)c->E64, (void *)c->Psi64,
                     (void *)c->fscal, (void *)c->tab.sub, (void *)c->tab.endrot,
                     (void *)c->stageR, (void *)c->stageV, (void *)c->mpartial, (void *)c->mout,
-                    (void *)c->sR, (void *)c->sV, (void *)c->ids, (void *)c->ids2, (void *)c->inv,
+                    (void *)c->rec[0], (void *)c->rec[1], (void *)c->ids, (void *)c->inv,
                     (void *)c->counts, (void *)c->total, (void *)c->starts, (void *)c->sums,
                     (void *)c->mcount, (void *)c->mout_count})
         if (p) (void)hipFree(p);
@@ -122,8 +122,10 @@ ep_status ensure_potential(ep_ctx *c)
 }
 
 // One Poisson step with the sorted deposit: count, offsets, scatter into the
-// second buffer (which becomes the state), segmented reduction, solve.
-ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K)
+// record buffer `out` (which becomes the state), segmented reduction, solve.
+// The state before the step is record buffer `in`, or the SoA state if in < 0.
+ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int K, int in,
+                      int out)
 {
     if (c->n == 0) {
         return solve_mesh(c, c->mesh(), false);
@@ -137,6 +139,7 @@ ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int 
     a.zR = c->zR;
     a.zV = c->zV;
     a.ids = c->ids;
+    a.rec_in = in >= 0 ? c->rec[in] : nullptr;
     a.n = (int64_t)c->n;
     a.sub = sub;
     a.endrot = endrot;
@@ -148,21 +151,27 @@ ep_status sorted_step(ep_ctx *c, const double4 *sub, const double2 *endrot, int 
     a.counts = c->counts;
     a.total = c->total;
     a.starts = c->starts;
-    float *oR = c->zR == c->own_zR ? c->sR : c->own_zR;
-    float *oV = c->zV == c->own_zV ? c->sV : c->own_zV;
-    a.oR = oR;
-    a.oV = oV;
-    a.oid = c->ids2;
+    a.rec_out = c->rec[out];
     a.hist = c->hist;
     a.sums = c->sums;
     HIPCHK(c, timed_launch(c, "sort_count", [&] { return launch_sort_count(c->stream, a, grid); }));
     HIPCHK(c, timed_launch(c, "sort_offsets", [&] { return launch_sort_offsets(c->stream, a, grid); }));
     HIPCHK(c, timed_launch(c, "sort_scatter", [&] { return launch_sort_scatter(c->stream, a, grid); }));
-    c->zR = oR;
-    c->zV = oV;
-    std::swap(c->ids, c->ids2);
     HIPCHK(c, timed_launch(c, "sort_combine", [&] { return launch_sort_combine(c->stream, a, grid); }));
     return solve_mesh(c, c->mesh(), false);
+}
+
+// The records of the last sorted step back to the SoA state (cell order,
+// ids with it).
+ep_status sorted_unpack(ep_ctx *c, int cur)
+{
+    c->zR = c->own_zR;
+    c->zV = c->own_zV;
+    HIPCHK(c, timed_launch(c, "sort_unpack", [&] {
+               return launch_sort_unpack(c->stream, c->rec[cur], (int64_t)c->n, c->zR, c->zV,
+                                         c->ids);
+           }));
+    return EP_OK;
 }
 
 }  // namespace etd
@@ -257,10 +266,9 @@ ep_status ep_create(const ep_config *cfg, ep_ctx **out)
     c->zV = c->own_zV;
     const size_t nn = (size_t)cfg->n_cells + 1;
     if (cfg->deposit == EP_DEPOSIT_SORTED) {
-        CREATE_CHK(dalloc(&c->sR, np_pad));
-        CREATE_CHK(dalloc(&c->sV, np_pad));
+        CREATE_CHK(dalloc(&c->rec[0], 3 * np_pad));
+        CREATE_CHK(dalloc(&c->rec[1], 3 * np_pad));
         CREATE_CHK(dalloc(&c->ids, np_pad));
-        CREATE_CHK(dalloc(&c->ids2, np_pad));
         CREATE_CHK(dalloc(&c->inv, np_pad));
         CREATE_CHK(dalloc(&c->counts, (size_t)c->sort_grid_cap * nn));
         CREATE_CHK(dalloc(&c->sums, (size_t)c->sort_grid_cap * nn));
@@ -384,6 +392,9 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
                                     chunk);
         if (s != EP_OK) return s;
     }
+    // sorted deposit: the record buffer that holds the state, -1 while it is
+    // the SoA state
+    int rec_cur = -1;
     uint64_t done = 0;
     while (done < n_steps) {
         const uint64_t rem = n_steps - done;
@@ -398,9 +409,14 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
             const MeshArgs ma = c->mesh();
             for (int j = 0; j < S; ++j) {
                 if (c->cfg.deposit == EP_DEPOSIT_SORTED) {
+                    const int out = rec_cur == 0 ? 1 : 0;
                     ep_status st = sorted_step(c, c->tab.sub + (size_t)j * K, c->tab.endrot + j,
-                                               K);
-                    if (st != EP_OK) return st;
+                                               K, rec_cur, out);
+                    if (c->n > 0) rec_cur = out;
+                    if (st != EP_OK) {
+                        if (rec_cur >= 0) (void)sorted_unpack(c, rec_cur);
+                        return st;
+                    }
                     continue;
                 }
                 HIPCHK(c, timed_launch(c, "push_poisson", [&] {
@@ -416,6 +432,10 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
         c->t += (double)S * dt;
         c->n_steps += (uint64_t)S;
         done += (uint64_t)S;
+    }
+    if (rec_cur >= 0) {
+        ep_status s = sorted_unpack(c, rec_cur);
+        if (s != EP_OK) return s;
     }
     c->field_valid = (field == EP_FIELD_POISSON);
     return EP_OK;

@@ -7,7 +7,8 @@
 //   sort_offsets_kernel  per key, exclusive offsets of the workgroups' counts
 //   sort_starts_kernel   exclusive scan of the key totals: segment starts
 //   sort_scatter_kernel  push again (same arithmetic, same keys) and write each
-//                        particle, with its id, to its slot in cell order.
+//                        particle, with its id, as one 12-byte record to its
+//                        slot in cell order.
 //                        The particles that workgroup b sends to cell k fill
 //                        the contiguous segment (k, b) of the sorted array;
 //                        the workgroup sums that segment's CIC weights as it
@@ -17,6 +18,13 @@
 // The weights are the same 2^-32 fixed-point integers as the fused deposit,
 // so the node charges are bitwise identical to it; particles within one
 // (workgroup, cell) segment may land in any order, which changes no result.
+//
+// The records: the scatter's stores go to G x N_r slowly filling segments,
+// far more open lines than the caches hold, so each store reaches memory as
+// a partly filled request of its own; one 12-byte record per particle makes
+// one such request where three SoA words made three.  Steps after the first
+// of a call read the records (12 B per particle, coalesced), and
+// sort_unpack_kernel writes the last step's records back to the SoA state.
 
 #include "pic_device.h"
 
@@ -71,18 +79,41 @@ __device__ __forceinline__ void step_one(const MeshView &m, const double4 *__res
                                                                                           : nr;
 }
 
+// One particle of the record form: R and V (FP32) and the id, 4-byte aligned,
+// so that it is written with one 12-byte store.
+struct __attribute__((packed, aligned(4))) SortRec {
+    float r, v;
+    unsigned id;
+};
+static_assert(sizeof(SortRec) == 12, "a record is three words");
+
+// Particles 4g .. 4g+3 of a record array: three 16-byte loads, split into
+// their R, V and id quadruples.
+__device__ __forceinline__ void load_rec_group(const unsigned *__restrict__ rec, int64_t g,
+                                               float4 &r4, float4 &v4, uint4 &id4)
+{
+    const uint4 *q = reinterpret_cast<const uint4 *>(rec) + 3 * g;
+    const uint4 a = q[0], b = q[1], c = q[2];
+    r4 = make_float4(__uint_as_float(a.x), __uint_as_float(a.w), __uint_as_float(b.z),
+                     __uint_as_float(c.y));
+    v4 = make_float4(__uint_as_float(a.y), __uint_as_float(b.x), __uint_as_float(b.w),
+                     __uint_as_float(c.z));
+    id4 = make_uint4(a.z, b.y, c.x, c.w);
+}
+
 }  // namespace
 
-// Both passes visit the particles in the same order (float4 groups with a
+// Both passes visit the particles in the same order (groups of four with a
 // grid stride, then the ragged tail), so that they assign each particle to
-// the same workgroup.
-template <bool SCATTER, bool FAST>
+// the same workgroup.  REC: the state before the step is rec_in (records),
+// else zR, zV and ids.
+template <bool SCATTER, bool FAST, bool REC>
 __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     const float *__restrict__ zR, const float *__restrict__ zV, const unsigned *__restrict__ ids,
-    int64_t n, const double4 *__restrict__ sub, const double2 *__restrict__ endrot, int K,
-    double inv_hr, const float2 *__restrict__ etab, const double *__restrict__ fscal, int nr,
-    unsigned *__restrict__ counts, const unsigned *__restrict__ starts,
-    float *__restrict__ oR, float *__restrict__ oV, unsigned *__restrict__ oid,
+    const unsigned *__restrict__ rec_in, int64_t n, const double4 *__restrict__ sub,
+    const double2 *__restrict__ endrot, int K, double inv_hr, const float2 *__restrict__ etab,
+    const double *__restrict__ fscal, int nr, unsigned *__restrict__ counts,
+    const unsigned *__restrict__ starts, unsigned *__restrict__ rec_out,
     unsigned long long *__restrict__ sums)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -108,7 +139,8 @@ __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
     unsigned n_off = 0u;   // count pass: this thread's off-mesh particles
     __syncthreads();
 
-    auto visit = [&](int64_t i, float fr, float fv) {
+    SortRec *out = reinterpret_cast<SortRec *>(rec_out);
+    auto visit = [&](float fr, float fv, unsigned id) {
         int key;
         double th = 0.0;
         step_one<FAST>(m, sub, K, lim2, er, fr, fv, nr, key, th);
@@ -127,25 +159,38 @@ __global__ __launch_bounds__(kPushBlock) void sort_pass_kernel(
         } else {
             slot = off_base + atomicAdd(&cnt[nr], 1u);
         }
-        oR[slot] = fr;
-        oV[slot] = fv;
-        oid[slot] = ids[i];
+        SortRec o;
+        o.r = fr;
+        o.v = fv;
+        o.id = id;
+        out[slot] = o;
     };
     const int64_t n4 = n >> 2;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const float4 *zR4 = reinterpret_cast<const float4 *>(zR);
-    const float4 *zV4 = reinterpret_cast<const float4 *>(zV);
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + tid; g < n4; g += stride) {
-        const float4 r4 = zR4[g], v4 = zV4[g];
-        visit(4 * g, r4.x, v4.x);
-        visit(4 * g + 1, r4.y, v4.y);
-        visit(4 * g + 2, r4.z, v4.z);
-        visit(4 * g + 3, r4.w, v4.w);
+        float4 r4, v4;
+        uint4 id4 = make_uint4(0u, 0u, 0u, 0u);
+        if (REC) {
+            load_rec_group(rec_in, g, r4, v4, id4);
+        } else {
+            r4 = reinterpret_cast<const float4 *>(zR)[g];
+            v4 = reinterpret_cast<const float4 *>(zV)[g];
+            if (SCATTER) id4 = reinterpret_cast<const uint4 *>(ids)[g];
+        }
+        visit(r4.x, v4.x, id4.x);
+        visit(r4.y, v4.y, id4.y);
+        visit(r4.z, v4.z, id4.z);
+        visit(r4.w, v4.w, id4.w);
     }
     const int64_t gt = blockIdx.x * (int64_t)blockDim.x + tid;
     if (gt < n - (n4 << 2)) {
         const int64_t i = (n4 << 2) + gt;
-        visit(i, zR[i], zV[i]);
+        if (REC) {
+            const SortRec q = reinterpret_cast<const SortRec *>(rec_in)[i];
+            visit(q.r, q.v, q.id);
+        } else {
+            visit(zR[i], zV[i], SCATTER ? ids[i] : 0u);
+        }
     }
     __syncthreads();
     if (!SCATTER) {
@@ -260,6 +305,33 @@ __global__ __launch_bounds__(1024) void sort_starts_kernel(const unsigned *__res
     }
 }
 
+// The records of one call's last step back to the SoA state (particles 0 ..
+// n-1, groups of four with a grid stride, then the ragged tail).
+__global__ __launch_bounds__(256) void sort_unpack_kernel(const unsigned *__restrict__ rec,
+                                                          int64_t n, float *__restrict__ zR,
+                                                          float *__restrict__ zV,
+                                                          unsigned *__restrict__ ids)
+{
+    const int64_t n4 = n >> 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t g = gt; g < n4; g += stride) {
+        float4 r4, v4;
+        uint4 id4;
+        load_rec_group(rec, g, r4, v4, id4);
+        reinterpret_cast<float4 *>(zR)[g] = r4;
+        reinterpret_cast<float4 *>(zV)[g] = v4;
+        reinterpret_cast<uint4 *>(ids)[g] = id4;
+    }
+    if (gt < n - (n4 << 2)) {
+        const int64_t i = (n4 << 2) + gt;
+        const SortRec q = reinterpret_cast<const SortRec *>(rec)[i];
+        zR[i] = q.r;
+        zV[i] = q.v;
+        ids[i] = q.id;
+    }
+}
+
 __global__ void iota_kernel(unsigned *__restrict__ ids, int64_t first, int64_t n)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -318,25 +390,40 @@ static size_t sort_lds_bytes(int nr, bool scatter)
 
 size_t sort_lds_bytes_for(int nr) { return sort_lds_bytes(nr, true); }
 
+// The pass kernel for (scatter, K > 1, record input).
+typedef void (*SortPassFn)(const float *, const float *, const unsigned *, const unsigned *,
+                           int64_t, const double4 *, const double2 *, int, double, const float2 *,
+                           const double *, int, unsigned *, const unsigned *, unsigned *,
+                           unsigned long long *);
+
+static SortPassFn sort_pass_fn(bool scatter, bool fast, bool rec)
+{
+    static const SortPassFn tab[8] = {
+        sort_pass_kernel<false, false, false>, sort_pass_kernel<false, false, true>,
+        sort_pass_kernel<false, true, false>,  sort_pass_kernel<false, true, true>,
+        sort_pass_kernel<true, false, false>,  sort_pass_kernel<true, false, true>,
+        sort_pass_kernel<true, true, false>,   sort_pass_kernel<true, true, true>};
+    return tab[(scatter ? 4 : 0) + (fast ? 2 : 0) + (rec ? 1 : 0)];
+}
+
 hipError_t setup_sort_lds(int nr)
 {
     hipError_t e;
-    for (const void *f : {reinterpret_cast<const void *>(&sort_pass_kernel<false, false>),
-                          reinterpret_cast<const void *>(&sort_pass_kernel<false, true>)})
-        if ((e = raise_dynamic_lds(f, (int)sort_lds_bytes(nr, false))) != hipSuccess) return e;
-    for (const void *f : {reinterpret_cast<const void *>(&sort_pass_kernel<true, false>),
-                          reinterpret_cast<const void *>(&sort_pass_kernel<true, true>)})
-        if ((e = raise_dynamic_lds(f, (int)sort_lds_bytes(nr, true))) != hipSuccess) return e;
+    for (int v = 0; v < 8; ++v) {
+        const bool scatter = v >= 4;
+        const void *f = reinterpret_cast<const void *>(sort_pass_fn(scatter, v & 2, v & 1));
+        if ((e = raise_dynamic_lds(f, (int)sort_lds_bytes(nr, scatter))) != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
 hipError_t launch_sort_count(hipStream_t st, const SortArgs &a, int grid)
 {
-    return dispatch(a.K > 1 ? sort_pass_kernel<false, true> : sort_pass_kernel<false, false>,
-                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr, false), st, a.zR, a.zV,
-                    a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
-                    (const unsigned *)nullptr, (float *)nullptr, (float *)nullptr,
-                    (unsigned *)nullptr, (unsigned long long *)nullptr);
+    return dispatch(sort_pass_fn(false, a.K > 1, a.rec_in != nullptr), dim3(grid),
+                    dim3(kPushBlock), sort_lds_bytes(a.nr, false), st, a.zR, a.zV, a.ids,
+                    a.rec_in, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr,
+                    a.counts, (const unsigned *)nullptr, (unsigned *)nullptr,
+                    (unsigned long long *)nullptr);
 }
 
 hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid)
@@ -352,10 +439,20 @@ hipError_t launch_sort_offsets(hipStream_t st, const SortArgs &a, int grid)
 
 hipError_t launch_sort_scatter(hipStream_t st, const SortArgs &a, int grid)
 {
-    return dispatch(a.K > 1 ? sort_pass_kernel<true, true> : sort_pass_kernel<true, false>,
-                    dim3(grid), dim3(kPushBlock), sort_lds_bytes(a.nr, true), st, a.zR, a.zV,
-                    a.ids, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr, a.counts,
-                    (const unsigned *)a.starts, a.oR, a.oV, a.oid, a.sums);
+    return dispatch(sort_pass_fn(true, a.K > 1, a.rec_in != nullptr), dim3(grid),
+                    dim3(kPushBlock), sort_lds_bytes(a.nr, true), st, a.zR, a.zV, a.ids,
+                    a.rec_in, a.n, a.sub, a.endrot, a.K, a.inv_hr, a.etab, a.fscal, a.nr,
+                    a.counts, (const unsigned *)a.starts, a.rec_out, a.sums);
+}
+
+hipError_t launch_sort_unpack(hipStream_t st, const unsigned *rec, int64_t n, float *zR, float *zV,
+                              unsigned *ids)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t g = ((n >> 2) + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return dispatch(sort_unpack_kernel, dim3((unsigned)g), dim3(256), 0, st, rec, n, zR, zV, ids);
 }
 
 hipError_t launch_sort_combine(hipStream_t st, const SortArgs &a, int grid)
