@@ -795,10 +795,13 @@ __device__ __forceinline__ void project_radially(double &zr, double &zv, double 
 // workgroups per CU: eight waves each keep four waves on every SIMD.
 constexpr int kWavesDuffing = 4, kWavesPoisson = 8;
 
-// One learned step.  A workgroup of WAVES waves takes 32 WAVES particles per
-// iteration, 32 per wave; lanes l and l+32 share particle l%32.  All three
-// layers run on MFMA (32x32x16, operand type T: FP16 or BF16, see InferOp)
-// with FP32 accumulation:
+// One learned step.  A workgroup of WAVES waves takes 64 WAVES particles per
+// iteration, one per lane.  The network runs in two passes per wave, over the
+// particles of lanes 0-31 and then of lanes 32-63; in each pass lanes c and
+// c+32 share the particle of column c and split its k slots.  The update, the
+// check and the projection then run once per particle, in its own lane.  All
+// three layers run on MFMA (32x32x16, operand type T: FP16 or BF16, see
+// InferOp) with FP32 accumulation:
 //   layer 1  one MFMA per 32 hidden units; k slots 0-7 hold the features'
 //            hi parts, the constant 1 (bias) and the features' lo parts
 //            against the weights' hi parts, slots 8-15 the weights' lo parts
@@ -806,7 +809,8 @@ constexpr int kWavesDuffing = 4, kWavesPoisson = 8;
 //            products);
 //   layer 2  W2 times the activations, accumulators started at the bias;
 //   layer 3  W3 times the activations, lanes 0-31 receive the two outputs of
-//            their particle.
+//            the pass's particle of their column (moved to lanes 32-63 in the
+//            second pass).
 // With FP16, W2 and W3 are not split: their 2^-12 rounding costs no
 // measurable accuracy next to the activations' own, and splitting doubled
 // those layers' MFMAs.
@@ -824,8 +828,12 @@ constexpr int kWavesDuffing = 4, kWavesPoisson = 8;
 // fallback queue.  With VP the sixth feature is E^n(R_n), and the particles
 // that pass are deposited (CIC, fixed point) into an LDS histogram added to
 // the mesh at the end.
+// At most 128 VGPRs (four waves per SIMD): the split-BF16 forms would take
+// 153 (Duffing) and 161 (Vlasov-Poisson), which leaves three waves per SIMD,
+// and with eight-wave workgroups only one per CU.  The Vlasov-Poisson BF16
+// form then spills nine registers and still runs 8 % faster.
 template <bool VP, int WAVES, typename T>
-__global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
+__global__ __launch_bounds__(64 * WAVES, 4) void mlp_push_kernel(
     float *__restrict__ zR, float *__restrict__ zV, const float *__restrict__ cR,
     const float *__restrict__ cV, int64_t n, MlpInfer net, double2 rot0, double2 rot1,
     double inv2eps, double tol, unsigned *__restrict__ qcount, unsigned *__restrict__ queue,
@@ -851,16 +859,19 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         for (int i = tid; i <= pv.nr; i += blockDim.x) mv.H[i] = 0ull;
         mv.Qb = pv.Qb = *qb;
     }
-    const int lane = tid & 63, wave = tid >> 6, r = lane & 31, g = lane >> 5;
+    const int lane = tid & 63, wave = tid >> 6, g = lane >> 5;
     WaveQueue wq{s_q[wave], 0u};
     __syncthreads();
 
-    constexpr int kGroup = 32 * WAVES;   // particles per workgroup iteration
+    constexpr int kGroup = 64 * WAVES;   // particles per workgroup iteration
     const int64_t nbg = (n + kGroup - 1) / kGroup;
     for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
         // keep the LDS reads below inside the loop (no hoisting into registers)
         asm volatile("" ::: "memory");
-        const int64_t p = bg * kGroup + wave * 32 + r;
+        // lane l's own particle: the network passes below take those of lanes
+        // 0-31 and then those of lanes 32-63; the update and the check run
+        // once per particle, in its own lane
+        const int64_t p = bg * kGroup + wave * 64 + lane;
         const bool valid = p < n;
         const double zr = valid ? (double)zR[p] : 0.0;
         const double zv = valid ? (double)zV[p] : 0.0;
@@ -869,67 +880,85 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const double bv = base && valid ? (double)cV[p] : zv;
         const double R = fma(rot0.x, zr, rot0.y * zv);
         const double Vl = fma(-rot0.y, zr, rot0.x * zv);
-        // features, clamped, as hi + lo parts
-        float xf[3] = {(float)R, (float)Vl, VP ? (float)gather(mv, R) : 0.f};
-        T xh[3], xl[3];
+        // features of the lane's particle, and of the particle in lane l ^ 32
+        const float xf[3] = {(float)R, (float)Vl, VP ? (float)gather(mv, R) : 0.f};
+        float xp[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const float x = fminf(fmaxf(xf[i], -net.xmax), net.xmax);
-            xh[i] = (T)x;
-            xl[i] = g == 0 ? (T)(x - (float)xh[i]) : (T)0.f;
-        }
-        const vec xb = {xh[0], xh[1], xh[2], (T)1.f, xl[0], xl[1], xl[2], (T)0.f};
+        for (int i = 0; i < 3; ++i) xp[i] = __shfl_xor(xf[i], 32, 64);
+        float o0 = 0.f, o1 = 0.f;
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            // the weights stay in LDS across the passes too
+            asm volatile("" ::: "memory");
+            // pass h: particle 32 h + c in both lanes of column c = l mod 32;
+            // the features, clamped, as hi + lo parts
+            T xh[3], xl[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float x = fminf(fmaxf(g == h ? xf[i] : xp[i], -net.xmax), net.xmax);
+                xh[i] = (T)x;
+                xl[i] = g == 0 ? (T)(x - (float)xh[i]) : (T)0.f;
+            }
+            const vec xb = {xh[0], xh[1], xh[2], (T)1.f, xl[0], xl[1], xl[2], (T)0.f};
 
-        // layer 1: pre-activations / 64 of units 0-31 and 32-63
-        const f32x16 zero = {};
-        const f32x16 u0 = Op::mma(Op::load(sW1[lane]), xb, zero);
-        const f32x16 u1 = Op::mma(Op::load(sW1[64 + lane]), xb, zero);
-        // layer 2, accumulators started at b2 / 64
-        f32x16 acc0, acc1;
+            // layer 1: pre-activations / 64 of units 0-31 and 32-63
+            const f32x16 zero = {};
+            const f32x16 u0 = Op::mma(Op::load(sW1[lane]), xb, zero);
+            const f32x16 u1 = Op::mma(Op::load(sW1[64 + lane]), xb, zero);
+            // layer 2, accumulators started at b2 / 64
+            f32x16 acc0, acc1;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float4 c0 = sb2[2 * j + g], c1 = sb2[8 + 2 * j + g];
-            acc0[4 * j] = c0.x;
-            acc0[4 * j + 1] = c0.y;
-            acc0[4 * j + 2] = c0.z;
-            acc0[4 * j + 3] = c0.w;
-            acc1[4 * j] = c1.x;
-            acc1[4 * j + 1] = c1.y;
-            acc1[4 * j + 2] = c1.z;
-            acc1[4 * j + 3] = c1.w;
-        }
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            vec b, lo;
-            if constexpr (Op::kSplitA3)
-                b = Op::act_split(kk < 2 ? u0 : u1, 8 * (kk & 1), lo);
-            else
-                b = Op::act(kk < 2 ? u0 : u1, 8 * (kk & 1));
-#pragma unroll
-            for (int w = 0; w < kW; ++w) {
-                acc0 = Op::mma(Op::load(sW2[(w * 8 + kk) * 64 + lane]), b, acc0);
-                acc1 = Op::mma(Op::load(sW2[(w * 8 + 4 + kk) * 64 + lane]), b, acc1);
+            for (int j = 0; j < 4; ++j) {
+                const float4 c0 = sb2[2 * j + g], c1 = sb2[8 + 2 * j + g];
+                acc0[4 * j] = c0.x;
+                acc0[4 * j + 1] = c0.y;
+                acc0[4 * j + 2] = c0.z;
+                acc0[4 * j + 3] = c0.w;
+                acc1[4 * j] = c1.x;
+                acc1[4 * j + 1] = c1.y;
+                acc1[4 * j + 2] = c1.z;
+                acc1[4 * j + 3] = c1.w;
             }
-            if constexpr (Op::kSplitA3) {
-                acc0 = Op::mma(Op::load(sW2[kk * 64 + lane]), lo, acc0);
-                acc1 = Op::mma(Op::load(sW2[(4 + kk) * 64 + lane]), lo, acc1);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                vec b, lo;
+                if constexpr (Op::kSplitA3)
+                    b = Op::act_split(kk < 2 ? u0 : u1, 8 * (kk & 1), lo);
+                else
+                    b = Op::act(kk < 2 ? u0 : u1, 8 * (kk & 1));
+#pragma unroll
+                for (int w = 0; w < kW; ++w) {
+                    acc0 = Op::mma(Op::load(sW2[(w * 8 + kk) * 64 + lane]), b, acc0);
+                    acc1 = Op::mma(Op::load(sW2[(w * 8 + 4 + kk) * 64 + lane]), b, acc1);
+                }
+                if constexpr (Op::kSplitA3) {
+                    acc0 = Op::mma(Op::load(sW2[kk * 64 + lane]), lo, acc0);
+                    acc1 = Op::mma(Op::load(sW2[(4 + kk) * 64 + lane]), lo, acc1);
+                }
+            }
+            // layer 3 (BF16: activations hi + lo as in layer 2)
+            f32x16 acc3 = {};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                vec b, lo;
+                if constexpr (Op::kSplitA3)
+                    b = Op::act_split(kk < 2 ? acc0 : acc1, 8 * (kk & 1), lo);
+                else
+                    b = Op::act(kk < 2 ? acc0 : acc1, 8 * (kk & 1));
+#pragma unroll
+                for (int w = 0; w < kW; ++w)
+                    acc3 = Op::mma(Op::load(sW3[(w * 4 + kk) * 64 + lane]), b, acc3);
+                if constexpr (Op::kSplitA3) acc3 = Op::mma(Op::load(sW3[kk * 64 + lane]), lo, acc3);
+            }
+            // lanes 0-31 hold the outputs of pass h's particles; pass 1 moves
+            // them to the particles' own lanes 32-63
+            const float t0 = h ? __shfl_xor(acc3[0], 32, 64) : acc3[0];
+            const float t1 = h ? __shfl_xor(acc3[1], 32, 64) : acc3[1];
+            if (g == h) {
+                o0 = t0;
+                o1 = t1;
             }
         }
-        // layer 3 (BF16: activations hi + lo as in layer 2)
-        f32x16 acc3 = {};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            vec b, lo;
-            if constexpr (Op::kSplitA3)
-                b = Op::act_split(kk < 2 ? acc0 : acc1, 8 * (kk & 1), lo);
-            else
-                b = Op::act(kk < 2 ? acc0 : acc1, 8 * (kk & 1));
-#pragma unroll
-            for (int w = 0; w < kW; ++w)
-                acc3 = Op::mma(Op::load(sW3[(w * 4 + kk) * 64 + lane]), b, acc3);
-            if constexpr (Op::kSplitA3) acc3 = Op::mma(Op::load(sW3[kk * 64 + lane]), lo, acc3);
-        }
-        const float o0 = acc3[0], o1 = acc3[1];
         float delta = fmaf(net.sig_d, o0 + net.b3_0, net.mu_d);
         const float kappa = fmaf(net.sig_k, o1 + net.b3_1, net.mu_k);
         double sc;
@@ -952,13 +981,8 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
         const double R1 = fma(rot1.x, nr, rot1.y * nv);
         double P0, P1;
         if (VP) {
-            // the two lanes of a particle evaluate one potential each: lane
-            // l + 32 the old position, lane l (the only one whose network
-            // outputs, and so R1, are valid) the new one
-            const double Pm = potential(pv, g ? R : R1);
-            const double Po = __shfl_xor(Pm, 32, 64);
-            P0 = g ? Pm : Po;
-            P1 = g ? Po : Pm;
+            P0 = potential(pv, R);
+            P1 = potential(pv, R1);
         } else {
             P0 = 0.25 * (R * R) * (R * R);
             P1 = 0.25 * (R1 * R1) * (R1 * R1);
@@ -981,14 +1005,13 @@ __global__ __launch_bounds__(64 * WAVES) void mlp_push_kernel(
                 nv *= s;
             }
         }
-        const bool mine = valid && g == 0;
-        if (mine && ok) {
+        if (valid && ok) {
             const float fr = (float)nr, fv = (float)nv;
             zR[p] = fr;
             zV[p] = fv;
             if (VP) deposit(mv, fma(rot1.x, (double)fr, rot1.y * (double)fv));
         }
-        wave_queue_push(wq, mine && !ok, (unsigned)p, qcount, queue, lane);
+        wave_queue_push(wq, valid && !ok, (unsigned)p, qcount, queue, lane);
     }
     wave_queue_flush(wq, qcount, queue, lane);
     if (VP) {
@@ -1206,7 +1229,7 @@ hipError_t launch_mlp_push_duffing(hipStream_t st, float *zR, float *zV, const f
                                    unsigned *queue, int n_cu)
 {
     if (n <= 0) return hipSuccess;
-    int64_t grid = (n + 32 * kWavesDuffing - 1) / (32 * kWavesDuffing);
+    int64_t grid = (n + 64 * kWavesDuffing - 1) / (64 * kWavesDuffing);
     if (grid > (int64_t)n_cu * 8) grid = (int64_t)n_cu * 8;
     const dim3 g((unsigned)grid), b(64 * kWavesDuffing);
     if (net.fp16)
@@ -1242,7 +1265,7 @@ hipError_t launch_mlp_push_poisson(hipStream_t st, float *zR, float *zV, int64_t
                                    const MeshArgs &ma, double rmax, int n_cu)
 {
     if (n <= 0) return hipSuccess;
-    int64_t grid = (n + 32 * kWavesPoisson - 1) / (32 * kWavesPoisson);
+    int64_t grid = (n + 64 * kWavesPoisson - 1) / (64 * kWavesPoisson);
     if (grid > (int64_t)n_cu * 2) grid = (int64_t)n_cu * 2;
     const PotView pv = pot_view(ma, rmax);
     const dim3 g((unsigned)grid), b(64 * kWavesPoisson);
