@@ -425,33 +425,39 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
         static_assert(kTile * (NIN + 2) <= 2 * 256, "features and labels: two loads per thread");
         const float4 *p4 = reinterpret_cast<const float4 *>(params);
         float4 buf[kPer];
+        // unconditional loads (past the end: the last group again), so that
+        // buf stays in registers
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int i = tid + j * 256;
-            if (i < NP4) buf[j] = p4[i];
+            buf[j] = p4[i < NP4 ? i : NP4 - 1];
         }
         const int it = 4 * NP4 + tid;
         const float ptail = it < NP ? params[it] : 0.f;
         float xy[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
+            // one unconditional load each: an element of X or Y, or, past the
+            // tile's samples, the batch's first sample again, replaced by 0
             const int i = tid + j * 256;
-            xy[j] = 0.f;
-            if (i < kTile * NIN) {
-                const int s = i / NIN, f = i - s * NIN;
-                if (s_base + s < batch)
-                    xy[j] = X[(first + (int64_t)(s_base + s) * sstride) * NIN + f];
-            } else if (i < kTile * (NIN + 2)) {
-                const int k = i - kTile * NIN, s = k >> 1;
-                if (s_base + s < batch)
-                    xy[j] = Y[(first + (int64_t)(s_base + s) * sstride) * 2 + (k & 1)];
-            }
+            const bool isx = i < kTile * NIN;
+            const int k = i - kTile * NIN;
+            const int s = isx ? i / NIN : k >> 1;
+            const bool ok = (isx || k < kTile * 2) && s_base + s < batch;
+            const int64_t row = first + (ok ? (int64_t)(s_base + s) * sstride : 0);
+            const float *src = isx ? X + row * NIN + (ok ? i - s * NIN : 0)
+                                   : Y + row * 2 + (ok ? (k & 1) : 0);
+            const float v = *src;
+            xy[j] = ok ? v : 0.f;
         }
+        // unconditional stores too (past the end: the last group's own value
+        // again), so that loads and stores sit in one block and the loads
+        // issue together
         float4 *s4 = reinterpret_cast<float4 *>(sP);
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int i = tid + j * 256;
-            if (i < NP4) s4[i] = buf[j];
+            s4[i < NP4 ? i : NP4 - 1] = buf[j];
         }
         if (it < NP) sP[it] = ptail;
 #pragma unroll
