@@ -635,9 +635,31 @@ __global__ __launch_bounds__(kRedParams * kRedChunks) void mlp_grad_reduce_kerne
     __shared__ double lw[4];
     const int tid = threadIdx.x, pl = tid % kRedParams, c = tid / kRedParams;
     const int p = blockIdx.x * kRedParams + pl;
+    // the Adam state of the parameter, read before the sum so that its
+    // latency overlaps the partial sums' (clamped, unconditional loads)
+    float m0 = 0.f, v0 = 0.f, p0 = 0.f;
+    if (ADAM) {
+        const int pc = p < np ? p : np - 1;
+        m0 = ad.m[pc];
+        v0 = ad.v[pc];
+        p0 = ad.p[pc];
+    }
+    // rows c, c + 16, c + 32, ... summed in that order; four loads in flight
     float a = 0.f;
-    if (p < np)
-        for (int t = c; t < tiles; t += kRedChunks) a += gpart[(size_t)t * np + p];
+    if (p < np) {
+        int t = c;
+        for (; t + 3 * kRedChunks < tiles; t += 4 * kRedChunks) {
+            const float g0 = gpart[(size_t)t * np + p];
+            const float g1 = gpart[(size_t)(t + kRedChunks) * np + p];
+            const float g2 = gpart[(size_t)(t + 2 * kRedChunks) * np + p];
+            const float g3 = gpart[(size_t)(t + 3 * kRedChunks) * np + p];
+            a += g0;
+            a += g1;
+            a += g2;
+            a += g3;
+        }
+        for (; t < tiles; t += kRedChunks) a += gpart[(size_t)t * np + p];
+    }
     part[c][pl] = a;
     __syncthreads();
 #pragma unroll
@@ -649,11 +671,11 @@ __global__ __launch_bounds__(kRedParams * kRedChunks) void mlp_grad_reduce_kerne
         const float gi = part[0][pl];
         grad[p] = gi;
         if (ADAM) {
-            const float mi = fmaf(ad.b1, ad.m[p], (1.f - ad.b1) * gi);
-            const float vi = fmaf(ad.b2, ad.v[p], (1.f - ad.b2) * gi * gi);
+            const float mi = fmaf(ad.b1, m0, (1.f - ad.b1) * gi);
+            const float vi = fmaf(ad.b2, v0, (1.f - ad.b2) * gi * gi);
             ad.m[p] = mi;
             ad.v[p] = vi;
-            ad.p[p] -= ad.lr * (mi * ad.bc1) / (__fsqrt_rn(vi * ad.bc2) + ad.eps);
+            ad.p[p] = p0 - ad.lr * (mi * ad.bc1) / (__fsqrt_rn(vi * ad.bc2) + ad.eps);
         }
     }
     if (blockIdx.x == 0) {
