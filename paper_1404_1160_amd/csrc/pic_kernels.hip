@@ -197,12 +197,22 @@ __device__ void solve_field_block(unsigned char *smem, unsigned long long *__res
     const int c = nr >> 1;
     const double rho_scale = w * kFixScale / hr;
 
+    // four loads in flight per thread (clamped to the last node; a clamped
+    // duplicate is read, never stored), then their stores
 #pragma unroll 1
-    for (int k = tid; k < nn; k += nt) {
-        const unsigned long long v = hist[k];
-        S[k] = v;
-        rho64[k] = (double)v * rho_scale;
-        hist[k] = 0ull;
+    for (int kb = tid; kb < nn; kb += 4 * nt) {
+        unsigned long long v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = hist[min(kb + j * nt, nn - 1)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kb + j * nt;
+            if (k < nn) {
+                S[k] = v[j];
+                rho64[k] = (double)v[j] * rho_scale;
+                hist[k] = 0ull;
+            }
+        }
     }
     __syncthreads();
 
@@ -318,7 +328,17 @@ __global__ __launch_bounds__(kSolveBlock) void potential_kernel(const double *__
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double *Ed = reinterpret_cast<double *>(smem);
-    for (int k = threadIdx.x; k <= nr; k += blockDim.x) Ed[k] = E64[k];
+    const int nt = blockDim.x;
+    // four loads in flight per thread (clamped to the last node)
+#pragma unroll 1
+    for (int kb = threadIdx.x; kb <= nr; kb += 4 * nt) {
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = E64[min(kb + j * nt, nr)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (kb + j * nt <= nr) Ed[kb + j * nt] = v[j];
+    }
     __syncthreads();
     solve_potential_block(smem, nr, hr, Psi64, fscal);
 }

@@ -239,7 +239,9 @@ __global__ __launch_bounds__(kCombKeys * kCombChunks) void sort_combine_kernel(
     const int rows = (G + kCombChunks - 1) / kCombChunks;
     const int b0 = ch * rows, b1 = min(b0 + rows, G);
     unsigned long long a = 0ull;
+    // integer sums: unrolled, eight loads in flight, the same bits
     if (k < nk)
+#pragma unroll 8
         for (int b = b0; b < b1; ++b) a += sums[(size_t)b * nk + k];
     part[ch][kl] = a;
     __syncthreads();
@@ -265,6 +267,7 @@ __global__ __launch_bounds__(kOffKeys * kOffChunks) void sort_offsets_kernel(
     const int b0 = ch * rows, b1 = min(b0 + rows, G);
     unsigned sum = 0;
     if (k < nk)
+#pragma unroll 8
         for (int b = b0; b < b1; ++b) sum += counts[(size_t)b * nk + k];
     part[ch][kl] = sum;
     __syncthreads();
@@ -280,7 +283,19 @@ __global__ __launch_bounds__(kOffKeys * kOffChunks) void sort_offsets_kernel(
     __syncthreads();
     if (k < nk) {
         unsigned run = part[ch][kl];
-        for (int b = b0; b < b1; ++b) {
+        int b = b0;
+        // eight rows read before any of them is rewritten
+        for (; b + 8 <= b1; b += 8) {
+            unsigned v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = counts[(size_t)(b + j) * nk + k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                counts[(size_t)(b + j) * nk + k] = run;
+                run += v[j];
+            }
+        }
+        for (; b < b1; ++b) {
             const unsigned v = counts[(size_t)b * nk + k];
             counts[(size_t)b * nk + k] = run;
             run += v;
