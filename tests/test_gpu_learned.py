@@ -171,6 +171,33 @@ def test_learned_push_without_fallback_is_the_network_map(out_map, precision):
     sim.close()
 
 
+@pytest.mark.parametrize("precision", [EP_MLP_BF16, EP_MLP_FP16])
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 63, 64, 65, 127, 129, 1000])
+def test_learned_push_partial_waves(n, precision):
+    """A wave takes 64 particles, two network passes of 32 whose features and
+    outputs cross between lanes l and l ^ 32: particle counts that end
+    anywhere in a wave or in either pass give each particle its own map (no
+    check) and, with tol = 0, each particle its own fallback."""
+    R0, V0, w = synth.gaussian(n, seed=100 + n, sigma=SIG)
+    p, norm = _net()
+    pd = p.astype(np.float64)
+    sim = _learned_sim(R0, V0, w, p, norm, 1e300, 8, precision)
+    sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+    d, k = mlp.predict(pd, R0, V0, DT, EPS, norm)
+    R, V = mlp.apply_polar(R0, V0, DT, EPS, d, k)
+    Rg, Vg = sim.particles()
+    assert rel_particle(Rg, Vg, R, V, MAP_FLOOR).max() <= MAP_TOL[precision]
+    assert sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"] == 0
+    sim.close()
+    sim = _learned_sim(R0, V0, w, p, norm, 0.0, 16, precision)
+    sim.step(DT, EPS, EP_FIELD_DUFFING, 1)
+    Rg, Vg = sim.particles()
+    Ro, Vo = oracle.run(R0, V0, w, DT, EPS, 16, 1, oracle.FIELD_DUFFING)
+    assert rel_particle(Rg, Vg, Ro, Vo).max() <= 1e-6
+    assert sim.moments(EPS, EP_FIELD_DUFFING)["n_fallback"] == n
+    sim.close()
+
+
 def test_learned_push_all_fallback_is_the_plain_push():
     R0, V0, w = synth.gaussian(10001, seed=16, sigma=SIG)
     p, norm = _net()

@@ -127,6 +127,32 @@ def test_learned_push_without_fallback_is_the_network_map(out_map, precision):
     sim.close()
 
 
+@pytest.mark.parametrize("n", [1, 33, 63, 65, 129, 1000])
+def test_learned_push_partial_waves(n):
+    """Particle counts that end inside a wave (64 particles, two passes of
+    32) in the self-consistent field: each particle gets its own map, and
+    the deposit of the pushed particles is the field a fresh context
+    deposits from them."""
+    p = synth.mlp_init(6, 64, 2, seed=9)
+    norm = _norm()
+    sim, w = _learned_sim(n, 500 + n, p, norm, 1e300, 8, precision=EP_MLP_BF16)
+    R, V, _ = synth.gaussian_truncated(n, seed=500 + n)
+    E, _, Qb = _field(R, w)
+    Eg = oracle.gather(R, E, Qb, NR, -RMAX, RMAX)
+    d, k = mlp.predict(p.astype(np.float64), R, V, DT, EPS, norm, Egather=Eg)
+    R, V = mlp.apply_polar(R, V, DT, EPS, d, k, scaled=True)
+    sim.step(DT, EPS, EP_FIELD_POISSON, 1)
+    Rg, Vg = sim.particles()
+    assert rel_particle(Rg, Vg, R, V).max() <= MAP_TOL[EP_MLP_BF16]
+    _, Eg_, _, _ = sim.field()
+    with Sim(Rg.size, n_cells=NR) as fresh:
+        fresh.set_particles(Rg, Vg, w)
+        _, Ef, _, _ = fresh.field()
+    assert np.max(np.abs(Eg_ - Ef)) <= 2e-6 * np.max(np.abs(Ef))
+    assert sim.moments(EPS, EP_FIELD_POISSON)["n_fallback"] == 0
+    sim.close()
+
+
 def test_learned_push_all_fallback_is_the_plain_push():
     p = synth.mlp_init(6, 64, 2, seed=9)
     R0, V0, w = synth.gaussian_truncated(20001, seed=43)
