@@ -9,16 +9,26 @@
 //
 //   gen_labels_duffing_kernel  training pairs: the plain push with K_fine
 //                              substeps (FP64 in registers) gives the labels
+//                              (around a plain push of K_b substeps, if any)
+//   gen_labels_poisson_kernel  the same in a frozen Poisson field, from
+//                              collected snapshots of a beam
+//   base_push_duffing_kernel   the plain push of K_b substeps whose result the
+//                              network corrects (Duffing field, optional)
 //   mlp_train_kernel           forward + backward of a 64-sample tile; the
 //                              three 64x64x64 products run on BF16 MFMA with
 //                              FP32 accumulation (forward split into hi/lo
 //                              BF16 halves, three MFMAs, for ~16-bit operands)
 //   mlp_grad_reduce_kernel     per-tile gradients summed in a fixed order,
 //                              fused with Adam on the FP32 master weights
-//   mlp_push_duffing_kernel    inference, 32 particles per wave, weights in
-//                              LDS, FP64 energy check, failing particles
-//                              appended to a queue
+//   mlp_push_kernel            inference (Duffing or Poisson field, BF16 or
+//                              FP16 operands): 64 particles per wave, weights
+//                              in LDS, FP64 energy check and optional energy
+//                              projection, failing particles appended to a
+//                              queue; with the Poisson field, the deposit of
+//                              the particles that pass
 //   fallback_duffing_kernel    plain push of the queued particles
+//   fallback_poisson_kernel    plain push and deposit of the queued particles
+//                              in the frozen Poisson field
 
 #include "pic_device.h"
 
