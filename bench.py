@@ -27,7 +27,7 @@ with
                   defect against K_fine = 6400 substeps);
   learned_vs_plain_vp -- the same for the Vlasov-Poisson beam (N_r = 4096,
                   eps = 1e-3, dt = 0.1, 6-input network trained on samples
-                  self-generated from a plain run of a 1e6-particle beam,
+                  self-generated from a plain run of a 1e7-particle beam,
                   evaluated on 1e8 particles over 1e3 steps against the plain
                   push with K_ref = 1600), with the energy projection;
   paper_schemes -- the paper's improved ETD scheme (Algorithm 3.4) and the
@@ -81,8 +81,11 @@ def parse():
                     help="skip the reference-RK4 / improved-ETD measurement")
     ap.add_argument("--learned-train", type=int, default=10_000_000)
     ap.add_argument("--learned-eval", type=int, default=10_000_000)
-    ap.add_argument("--learned-vp-data", type=int, default=1_000_000,
+    ap.add_argument("--learned-vp-data", type=int, default=10_000_000,
                     help="beam size of the self-generated Vlasov-Poisson training run")
+    ap.add_argument("--learned-vp-epochs", type=int, default=4,
+                    help="training epochs of the Vlasov-Poisson network (4 epochs of the "
+                         "default 2e8 samples are 195k Adam steps)")
     ap.add_argument("--learned-vp-eval", type=int, default=100_000_000,
                     help="particles of the learned Vlasov-Poisson comparison")
     ap.add_argument("--learned-vp-steps", type=int, default=1000,
@@ -378,9 +381,14 @@ def main():
         # labels' K_fine = 12800 beside it)
         # with the energy projection (ep_mlp_set_projection), which keeps
         # the total energy to ~1e-8 where the network's own errors drift it
-        # by ~1e-5 over the run; --long-time adds the run without it
+        # by ~1e-5 over the run; --long-time adds the run without it.  The
+        # network learns from snapshots of a 1e7-particle beam: learned from
+        # a 1e6-particle beam, whose field is noisier than that of the 1e8
+        # evaluation beam, the same number of Adam steps left a 3x larger
+        # median particle error at the end of the run
         line["learned_vs_plain_vp"] = compare.equal_error_vp(
             n_eval=args.learned_vp_eval, n_data=args.learned_vp_data,
+            epochs=args.learned_vp_epochs,
             steps=args.learned_vp_steps, every=max(10, args.learned_vp_steps // 20),
             plain_Ks=(100, 200, 400), K_ref=1600, extra_tols=(), single_run=True, project=True,
             log=say)
@@ -400,6 +408,7 @@ def main():
               file=sys.stderr, flush=True)
         line["learned_vs_plain_vp_unprojected"] = compare.equal_error_vp(
             n_eval=args.learned_vp_eval, n_data=args.learned_vp_data,
+            epochs=args.learned_vp_epochs,
             steps=args.learned_vp_steps, every=max(10, args.learned_vp_steps // 20),
             plain_Ks=(100, 200, 400), K_ref=1600, extra_tols=(), single_run=True, project=False,
             log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))

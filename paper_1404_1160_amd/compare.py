@@ -458,7 +458,7 @@ def equal_error_vp(n_eval=1_000_000, n_data=500_000, steps=200, nr=VP_NR, epochs
 
 
 def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=1600,
-                 plain_Ks=(100, 200), tol=1e-5, K_fb=400, n_data=1_000_000, epochs=40,
+                 plain_Ks=(100, 200), tol=1e-5, K_fb=400, n_data=10_000_000, epochs=4,
                  precisions=(EP_MLP_FP16, EP_MLP_BF16), seed_eval=17, n_sample=1_000_000,
                  projections=(False, True), log=None):
     """Long-time run of the Vlasov-Poisson beam (eps = 1e-3, dt = 0.1, to
@@ -469,7 +469,9 @@ def long_time_vp(n_eval=10_000_000, steps=10_000, every=100, nr=VP_NR, K_ref=160
     runs, the fallback rate of the interval; at the end, the median particle
     error of the first n_sample particles against the reference.  The network
     is trained on samples collected over the same time span from a separate
-    beam, and runs with each energy-projection setting in `projections`.
+    beam of n_data particles (as many as the evaluation beam: the field of a
+    smaller beam is noisier, and a network trained on it carries a larger
+    bias), and runs with each energy-projection setting in `projections`.
     Rates are timed on runs of their own, without the moment calls."""
     def say(msg):
         if log:
