@@ -155,6 +155,11 @@ ep_status ep_bind_particles(ep_ctx *ctx, float *zR_dev, float *zV_dev, uint64_t 
  * by K-substep midpoint quadrature with E frozen at t_n (Poisson: deposit,
  * prefix-sum solve and gather, section 2.3), or the learned push when enabled.
  * dt and eps may change between calls; the phase t/eps is carried in FP64.
+ * With EP_DEPOSIT_SORTED each Poisson step leaves the particles in cell order
+ * (ep_get_particles and checkpoints still use the loaded order); between the
+ * steps of one call the state is kept as 12-byte (R, V, id) records, and the
+ * call ends with one pass that writes them back to the FP32 state, so a call
+ * of n steps costs n sorted steps and one such pass.
  * Asynchronous.  Errors: EP_EINVAL, EP_ESTATE (no particles), EP_EHIP. */
 ep_status ep_step(ep_ctx *ctx, double dt, double eps, int32_t field, uint64_t n_steps);
 
