@@ -386,7 +386,7 @@ constexpr int kPartStride = 8;
 static size_t train_lds_floats(int n_in)
 {
     return (size_t)mlp_n_params(n_in) + kTile * n_in + kTile * 2 + 5 * kTile * kLd + kTile * 2 +
-           4 * kH * kPartStride + 8;
+           3 * 4 * kH * kPartStride + 8;
 }
 
 // Forward and backward of the MSE loss over one tile of 64 samples: sample s
@@ -419,8 +419,12 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     float *sG = sH2 + kTile * kLd;      // dZ2
     float *sD = sG + kTile * kLd;       // dZ1
     float *sdO = sD + kTile * kLd;      // [64][2]
-    float *sQ = sdO + kTile * 2;        // [4][64][kPartStride] partial sums
-    float *sL = sQ + 4 * kH * kPartStride;   // [4] loss of each wave
+    // partial sums, one region per use so that no barrier waits for a
+    // region to be free: dW3 (first 256 floats), db2, dW1 ([4][64][kPartStride])
+    float *sQ = sdO + kTile * 2;
+    float *sQ2 = sQ + 4 * kH * kPartStride;
+    float *sQ1 = sQ2 + 4 * kH * kPartStride;
+    float *sL = sQ1 + 4 * kH * kPartStride;   // [4] loss of each wave
 
     const int tid = threadIdx.x, nt = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, r = lane & 31, g = lane >> 5;
@@ -559,7 +563,6 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     }
     __syncthreads();
     if (tid < kOut * kH) gp[oW3 + tid] = sQ[tid] + sQ[128 + tid];
-    __syncthreads();
 
     // dW2[u][k] = sum_s G[s][u] H1[s][k]   (MFMA)
     {
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
         float a = 0.f;
 #pragma unroll 4
         for (int s = 16 * qs; s < 16 * qs + 16; ++s) a += sG[s * kLd + u];
-        sQ[qs * kH * kPartStride + u * kPartStride] = a;
+        sQ2[qs * kH * kPartStride + u * kPartStride] = a;
     }
     // dH1[s][k] = sum_u G[s][u] W2[u][k]   (MFMA), D = dZ1 = dH1 * act'(Z1)
     {
@@ -588,11 +591,10 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     }
     __syncthreads();
     if (tid < kH) {
-        const float *q0 = sQ + tid * kPartStride;
+        const float *q0 = sQ2 + tid * kPartStride;
         constexpr int qs = kH * kPartStride;
         gp[ob2 + tid] = (q0[0] + q0[qs]) + (q0[2 * qs] + q0[3 * qs]);
     }
-    __syncthreads();
     // dW1[u][f] = sum_s D[s][u] X[s][f], db1[u] = sum_s D[s][u]: unit u =
     // tid % 64, samples of quarter tid / 64, all n_in + 1 sums at once
     {
@@ -608,12 +610,12 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
             a[NIN] += d;
         }
 #pragma unroll
-        for (int f = 0; f <= NIN; ++f) sQ[(qs * kH + u) * kPartStride + f] = a[f];
+        for (int f = 0; f <= NIN; ++f) sQ1[(qs * kH + u) * kPartStride + f] = a[f];
     }
     __syncthreads();
     for (int i = tid; i < kH * (NIN + 1); i += nt) {
         const int u = i / (NIN + 1), f = i - u * (NIN + 1);
-        const float *q0 = sQ + u * kPartStride + f;
+        const float *q0 = sQ1 + u * kPartStride + f;
         constexpr int qs = kH * kPartStride;
         const float v = (q0[0] + q0[qs]) + (q0[2 * qs] + q0[3 * qs]);
         if (f < NIN)
