@@ -195,3 +195,25 @@ def test_learned_vp_beats_plain_at_equal_error():
         assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
         checked = [e for e in res["learned"] if e["precision"] == prec and e["drift_tol"] == 1e-5]
         assert checked and checked[0]["fallback_rate"] < 0.1, checked
+
+
+def test_learned_vp_with_projection_beats_plain_in_both_errors():
+    """The default Vlasov-Poisson comparison at a reduced size (N_r = 4096,
+    eps = 1e-3, dt = 0.1, 4e6 particles, 200 steps, reference plain K = 1600):
+    with the energy projection, and the network trained on snapshots of a
+    beam as large as the evaluated one, both operand types with and without
+    the 1e-5 check beat the plain push of equal rms-radius error, and end
+    with a smaller median particle error than the plain push at K = 400 at a
+    higher rate (no plain run of the sweep is as accurate in the particles)."""
+    res = compare.equal_error_vp(n_eval=4_000_000, n_data=4_000_000, epochs=10, steps=200,
+                                 plain_Ks=(50, 100, 200, 400), K_ref=1600, extra_tols=(),
+                                 project=True, log=print)
+    print(json.dumps({k: res[k] for k in ("gains", "gains_phase")}))
+    plain400 = [p for p in res["plain"] if p["K"] == 400][0]
+    for prec in ("bf16", "fp16"):
+        for key in ("equal_error_" + prec, "equal_error_no_check_" + prec):
+            assert res[key]["gain"] is not None and res[key]["gain"] > 1.0, (key, res[key])
+        for e in [e for e in res["learned"] if e["precision"] == prec]:
+            assert e["median_particle_err"] < plain400["median_particle_err"], (e, plain400)
+            assert e["particle_steps_per_s"] > plain400["particle_steps_per_s"], (e, plain400)
+
