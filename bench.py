@@ -180,10 +180,12 @@ def cpu_baseline(n_full, cells, eps, dt, K, seconds):
 # first count pass reads 8 B of SoA state, and sort_unpack turns the last
 # records back into the SoA state once per call (12 B read, 12 B written).
 KERNEL_BYTES = {"push_poisson": 16, "sort_count": 12, "sort_scatter": 24, "sort_unpack": 24}
-# HIP events on every 5th launch of each kernel: the averages come from a
-# fifth of the timed steps, and the events' own cost (a few microseconds per
-# timed launch) stays out of the other four fifths
-TIMING_STRIDE = 5
+# HIP events on every 10th launch of each kernel: the averages come from a
+# tenth of the timed steps (50 launches of 500, 2 of 20), and the events' own
+# cost stays out of the other nine tenths: a dispatch that carries events
+# ends with a release that writes back the L2, about 28 us per timed push
+# launch, so timing every 5th launch cost 1.9 % of the step
+TIMING_STRIDE = 10
 STEP_KERNELS = ("push_poisson", "mesh_solve", "potential", "sort_count", "sort_offsets", "sort_scatter",
                 "sort_combine", "sort_unpack")
 
