@@ -412,11 +412,12 @@ ep_status ep_step(ep_ctx *c, double dt, double eps, int32_t field, uint64_t n_st
                     const int out = rec_cur == 0 ? 1 : 0;
                     ep_status st = sorted_step(c, c->tab.sub + (size_t)j * K, c->tab.endrot + j,
                                                K, rec_cur, out);
-                    if (c->n > 0) rec_cur = out;
                     if (st != EP_OK) {
+                        // leave the last completed step's state behind
                         if (rec_cur >= 0) (void)sorted_unpack(c, rec_cur);
                         return st;
                     }
+                    if (c->n > 0) rec_cur = out;
                     continue;
                 }
                 HIPCHK(c, timed_launch(c, "push_poisson", [&] {
