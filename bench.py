@@ -287,7 +287,7 @@ def learned_roofline(line):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: runs on one GPU only; --gpus %d is not supported "
               "(the multi-GPU sharding is a design note, not a run)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
