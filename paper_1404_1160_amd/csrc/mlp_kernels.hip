@@ -380,13 +380,34 @@ hipError_t launch_gen_labels_poisson(hipStream_t st, const float *zR, const floa
 constexpr int kTile = 64;   // samples per training workgroup
 constexpr int kLd = kH + 1; // LDS row stride of the 64x64 matrices (no bank conflicts)
 
-// partial sums of the layer-1 gradients: [4 sample quarters][64 units][n_in + 1]
+// A tile is one workgroup of 16 waves.  The three products run on waves 0-3
+// (one 32 x 32 block each; in the backward pass dW2 on waves 0-3 and dH1 on
+// waves 4-7 at once); every other phase is spread over all 1024 threads, so
+// that no wave walks a long dependent chain (one wave per SIMD, as with four
+// waves, left the tile bound by the latency of its instructions).
+constexpr int kTrainBlock = 1024, kTrainWaves = kTrainBlock / 64;
+// sums over the 64 samples of a tile: kSampleParts partial sums of 4 samples
+// (db2, dW1, db1) or kOutParts of 8 (dW3), added in a fixed pairwise tree
+constexpr int kSampleParts = 16, kOutParts = 8;
+// partial sums of the layer-1 gradients: [16 sample parts][64 units][n_in + 1]
 constexpr int kPartStride = 8;
 
 static size_t train_lds_floats(int n_in)
 {
     return (size_t)mlp_n_params(n_in) + kTile * n_in + kTile * 2 + 5 * kTile * kLd + kTile * 2 +
-           3 * 4 * kH * kPartStride + 8;
+           kOutParts * kOut * kH + kSampleParts * kH + kSampleParts * kH * kPartStride +
+           kTrainWaves;
+}
+
+// Sum of n = 2^m values v[0], v[stride], ... in a fixed pairwise tree.
+template <int N>
+__device__ __forceinline__ float tree_sum(const float *v, int stride)
+{
+    if constexpr (N == 1) {
+        return v[0];
+    } else {
+        return tree_sum<N / 2>(v, stride) + tree_sum<N / 2>(v + (N / 2) * stride, stride);
+    }
 }
 
 // Forward and backward of the MSE loss over one tile of 64 samples: sample s
@@ -395,12 +416,12 @@ static size_t train_lds_floats(int n_in)
 // normalised on load, Yn = (Y - mu) * inv_sig.  Writes this tile's gradient
 // (flat parameter order) to gpart[tile] and its sum of squared errors to
 // lpart[tile]; the loss is the mean over the batch and both outputs.
-// The three 64 x 64 x 64 products run on MFMA; every other sum over 64 terms
-// is split over four threads (16 terms each) whose partial sums are combined
-// as (p0 + p1) + (p2 + p3), so that no thread walks a long dependent chain of
-// LDS reads, and the results do not depend on scheduling.
+// The three 64 x 64 x 64 products run on MFMA; every other sum over the 64
+// samples or units is split into partial sums of 4 or 8 terms that are
+// combined in a fixed order, so that the results do not depend on
+// scheduling.
 template <int NIN>
-__global__ __launch_bounds__(256) void mlp_train_kernel(
+__global__ __launch_bounds__(kTrainBlock) void mlp_train_kernel(
     const float *__restrict__ params, const float *__restrict__ X, const float *__restrict__ Y,
     int64_t first, int64_t sstride, int batch, float mu_d, float is_d, float mu_k, float is_k,
     float *__restrict__ gpart, float *__restrict__ lpart)
@@ -409,6 +430,8 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     constexpr int oW1 = 0, ob1 = kH * NIN, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
                   ob3 = oW3 + kOut * kH;
     static_assert(NIN + 1 <= kPartStride, "layer-1 partial sums fit their stride");
+    static_assert(kTile * (NIN + 2) <= kTrainBlock, "features and labels: one load per thread");
+    static_assert(kTile / kSampleParts == 4 && kTile / kOutParts == 8, "partial-sum sizes");
     extern __shared__ __align__(16) float sm[];
     float *sP = sm;                     // parameters (flat)
     float *sX = sP + NP;                // [64][NIN]
@@ -419,12 +442,12 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     float *sG = sH2 + kTile * kLd;      // dZ2
     float *sD = sG + kTile * kLd;       // dZ1
     float *sdO = sD + kTile * kLd;      // [64][2]
-    // partial sums, one region per use so that no barrier waits for a
-    // region to be free: dW3 (first 256 floats), db2, dW1 ([4][64][kPartStride])
-    float *sQ = sdO + kTile * 2;
-    float *sQ2 = sQ + 4 * kH * kPartStride;
-    float *sQ1 = sQ2 + 4 * kH * kPartStride;
-    float *sL = sQ1 + 4 * kH * kPartStride;   // [4] loss of each wave
+    // partial sums, one region per use: dW3 [8][128], db2 [16][64], dW1 and
+    // db1 [16][64][kPartStride]
+    float *sQ3 = sdO + kTile * 2;
+    float *sQ2 = sQ3 + kOutParts * kOut * kH;
+    float *sQ1 = sQ2 + kSampleParts * kH;
+    float *sL = sQ1 + kSampleParts * kH * kPartStride;   // [16] loss of each wave
 
     const int tid = threadIdx.x, nt = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, r = lane & 31, g = lane >> 5;
@@ -435,25 +458,23 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     // issued before the first LDS store, so their latencies overlap (the
     // parameters as float4; the host buffer is 16-byte aligned).
     {
-        constexpr int NP4 = NP / 4, kPer = (NP4 + 255) / 256;
-        static_assert(kTile * (NIN + 2) <= 2 * 256, "features and labels: two loads per thread");
+        constexpr int NP4 = NP / 4, kPer = (NP4 + kTrainBlock - 1) / kTrainBlock;
         const float4 *p4 = reinterpret_cast<const float4 *>(params);
         float4 buf[kPer];
         // unconditional loads (past the end: the last group again), so that
         // buf stays in registers
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const int i = tid + j * 256;
+            const int i = tid + j * kTrainBlock;
             buf[j] = p4[i < NP4 ? i : NP4 - 1];
         }
         const int it = 4 * NP4 + tid;
         const float ptail = it < NP ? params[it] : 0.f;
-        float xy[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            // one unconditional load each: an element of X or Y, or, past the
-            // tile's samples, the batch's first sample again, replaced by 0
-            const int i = tid + j * 256;
+        // one unconditional load: an element of X or Y, or, past the tile's
+        // samples, the batch's first sample again, replaced by 0
+        float xy;
+        {
+            const int i = tid;
             const bool isx = i < kTile * NIN;
             const int k = i - kTile * NIN;
             const int s = isx ? i / NIN : k >> 1;
@@ -462,7 +483,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
             const float *src = isx ? X + row * NIN + (ok ? i - s * NIN : 0)
                                    : Y + row * 2 + (ok ? (k & 1) : 0);
             const float v = *src;
-            xy[j] = ok ? v : 0.f;
+            xy = ok ? v : 0.f;
         }
         // unconditional stores too (past the end: the last group's own value
         // again), so that loads and stores sit in one block and the loads
@@ -470,19 +491,15 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
         float4 *s4 = reinterpret_cast<float4 *>(sP);
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const int i = tid + j * 256;
+            const int i = tid + j * kTrainBlock;
             s4[i < NP4 ? i : NP4 - 1] = buf[j];
         }
         if (it < NP) sP[it] = ptail;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int i = tid + j * 256;
-            if (i < kTile * NIN) {
-                sX[i] = xy[j];
-            } else if (i < kTile * (NIN + 2)) {
-                const int k = i - kTile * NIN;
-                sY[k] = (k & 1) ? (xy[j] - mu_k) * is_k : (xy[j] - mu_d) * is_d;
-            }
+        if (tid < kTile * NIN) {
+            sX[tid] = xy;
+        } else if (tid < kTile * (NIN + 2)) {
+            const int k = tid - kTile * NIN;
+            sY[k] = (k & 1) ? (xy - mu_k) * is_k : (xy - mu_d) * is_d;
         }
     }
     __syncthreads();
@@ -499,9 +516,10 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     }
     __syncthreads();
 
-    // layer 2 (MFMA, split BF16): Z2[s][u] = sum_k H1[s][k] W2[u][k]
-    const int i0 = (wave >> 1) * 32, j0 = (wave & 1) * 32;
-    {
+    // layer 2 (MFMA, split BF16, waves 0-3): Z2[s][u] = sum_k H1[s][k] W2[u][k]
+    const int blk = wave & 3;
+    const int i0 = (blk >> 1) * 32, j0 = (blk & 1) * 32;
+    if (wave < 4) {
         f32x16 acc = {};
         mma64_wave<true>(sH1, kLd, 1, sW2, 1, kLd, i0, j0, acc);
 #pragma unroll
@@ -512,21 +530,22 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
     }
     __syncthreads();
 
-    // layer 3 (VALU), loss and dO = d loss / d O.  Sample s = tid / 4; its
-    // four threads (lanes of one wave) sum quarters of the hidden units.
+    // layer 3 (VALU), loss and dO = d loss / d O.  Sample s = tid / 16; its
+    // 16 threads (lanes of one wave) sum 4 hidden units each.
     {
-        const int s = tid >> 2, qu = tid & 3;
+        const int s = tid >> 4, qu = tid & 15;
         float o0 = 0.f, o1 = 0.f;
-#pragma unroll 4
-        for (int u = 16 * qu; u < 16 * qu + 16; ++u) {
+#pragma unroll
+        for (int u = 4 * qu; u < 4 * qu + 4; ++u) {
             const float h = sH2[s * kLd + u];
             o0 = fmaf(sP[oW3 + u], h, o0);
             o1 = fmaf(sP[oW3 + kH + u], h, o1);
         }
-        o0 += __shfl_xor(o0, 1, 64);
-        o1 += __shfl_xor(o1, 1, 64);
-        o0 += __shfl_xor(o0, 2, 64);
-        o1 += __shfl_xor(o1, 2, 64);
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) {
+            o0 += __shfl_xor(o0, m, 64);
+            o1 += __shfl_xor(o1, m, 64);
+        }
         const bool valid = s_base + s < batch;
         const float d0 = valid ? (o0 + sP[ob3]) - sY[2 * s] : 0.f;
         const float d1 = valid ? (o1 + sP[ob3 + 1]) - sY[2 * s + 1] : 0.f;
@@ -538,14 +557,15 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
         if (lane == 0) sL[wave] = l;
     }
     __syncthreads();
-    if (tid == 0) lpart[blockIdx.x] = (sL[0] + sL[1]) + (sL[2] + sL[3]);
-    // dW3[m][u] = sum_s dO[s][m] H2[s][u]: thread (m, u) of each sample half
+    if (tid == 0) lpart[blockIdx.x] = tree_sum<kTrainWaves>(sL, 1);
+    // dW3[m][u] = sum_s dO[s][m] H2[s][u]: thread (m, u) of each eighth of
+    // the samples
     {
-        const int o = tid & 127, m = o >> 6, u = o & 63, half = tid >> 7;
+        const int o = tid & 127, m = o >> 6, u = o & 63, part = tid >> 7;
         float a = 0.f;
-#pragma unroll 4
-        for (int s = 32 * half; s < 32 * half + 32; ++s) a = fmaf(sdO[s * 2 + m], sH2[s * kLd + u], a);
-        sQ[half * 128 + o] = a;
+#pragma unroll
+        for (int s = 8 * part; s < 8 * part + 8; ++s) a = fmaf(sdO[s * 2 + m], sH2[s * kLd + u], a);
+        sQ3[part * 128 + o] = a;
     }
     // db3: wave 0, one sample per lane
     if (wave == 0) {
@@ -562,25 +582,16 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
         sG[s * kLd + u] = d * act_grad_h(sH2[s * kLd + u]);
     }
     __syncthreads();
-    if (tid < kOut * kH) gp[oW3 + tid] = sQ[tid] + sQ[128 + tid];
+    if (tid < kOut * kH) gp[oW3 + tid] = tree_sum<kOutParts>(sQ3 + tid, 128);
 
-    // dW2[u][k] = sum_s G[s][u] H1[s][k]   (MFMA)
-    {
+    if (wave < 4) {
+        // dW2[u][k] = sum_s G[s][u] H1[s][k]   (MFMA)
         f32x16 acc = {};
         mma64_wave<false>(sG, 1, kLd, sH1, kLd, 1, i0, j0, acc);
 #pragma unroll
         for (int q = 0; q < 16; ++q) gp[oW2 + (i0 + tile_row(q, g)) * kH + j0 + r] = acc[q];
-    }
-    // db2 partials: unit u = tid % 64, samples of quarter tid / 64
-    {
-        const int u = tid & 63, qs = tid >> 6;
-        float a = 0.f;
-#pragma unroll 4
-        for (int s = 16 * qs; s < 16 * qs + 16; ++s) a += sG[s * kLd + u];
-        sQ2[qs * kH * kPartStride + u * kPartStride] = a;
-    }
-    // dH1[s][k] = sum_u G[s][u] W2[u][k]   (MFMA), D = dZ1 = dH1 * act'(Z1)
-    {
+    } else if (wave < 8) {
+        // dH1[s][k] = sum_u G[s][u] W2[u][k]   (MFMA), D = dZ1 = dH1 * act'(Z1)
         f32x16 acc = {};
         mma64_wave<false>(sG, kLd, 1, sW2, kLd, 1, i0, j0, acc);
 #pragma unroll
@@ -589,35 +600,37 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(
             sD[s * kLd + k] = acc[q] * act_grad_h(sH1[s * kLd + k]);
         }
     }
-    __syncthreads();
-    if (tid < kH) {
-        const float *q0 = sQ2 + tid * kPartStride;
-        constexpr int qs = kH * kPartStride;
-        gp[ob2 + tid] = (q0[0] + q0[qs]) + (q0[2 * qs] + q0[3 * qs]);
-    }
-    // dW1[u][f] = sum_s D[s][u] X[s][f], db1[u] = sum_s D[s][u]: unit u =
-    // tid % 64, samples of quarter tid / 64, all n_in + 1 sums at once
+    // db2 partials: unit u = tid % 64, samples of part tid / 64
     {
-        const int u = tid & 63, qs = tid >> 6;
+        const int u = tid & 63, part = tid >> 6;
+        float a = 0.f;
+#pragma unroll
+        for (int s = 4 * part; s < 4 * part + 4; ++s) a += sG[s * kLd + u];
+        sQ2[part * kH + u] = a;
+    }
+    __syncthreads();
+    if (tid < kH) gp[ob2 + tid] = tree_sum<kSampleParts>(sQ2 + tid, kH);
+    // dW1[u][f] = sum_s D[s][u] X[s][f], db1[u] = sum_s D[s][u]: unit u =
+    // tid % 64, samples of part tid / 64, all n_in + 1 sums at once
+    {
+        const int u = tid & 63, part = tid >> 6;
         float a[NIN + 1];
 #pragma unroll
         for (int f = 0; f <= NIN; ++f) a[f] = 0.f;
-#pragma unroll 4
-        for (int s = 16 * qs; s < 16 * qs + 16; ++s) {
+#pragma unroll
+        for (int s = 4 * part; s < 4 * part + 4; ++s) {
             const float d = sD[s * kLd + u];
 #pragma unroll
             for (int f = 0; f < NIN; ++f) a[f] = fmaf(d, sX[s * NIN + f], a[f]);
             a[NIN] += d;
         }
 #pragma unroll
-        for (int f = 0; f <= NIN; ++f) sQ1[(qs * kH + u) * kPartStride + f] = a[f];
+        for (int f = 0; f <= NIN; ++f) sQ1[(part * kH + u) * kPartStride + f] = a[f];
     }
     __syncthreads();
     for (int i = tid; i < kH * (NIN + 1); i += nt) {
         const int u = i / (NIN + 1), f = i - u * (NIN + 1);
-        const float *q0 = sQ1 + u * kPartStride + f;
-        constexpr int qs = kH * kPartStride;
-        const float v = (q0[0] + q0[qs]) + (q0[2 * qs] + q0[3 * qs]);
+        const float v = tree_sum<kSampleParts>(sQ1 + u * kPartStride + f, kH * kPartStride);
         if (f < NIN)
             gp[oW1 + u * NIN + f] = v;
         else
@@ -716,10 +729,10 @@ static hipError_t launch_train_tiles(hipStream_t st, int n_in, const float *para
     const int tiles = (batch + kTile - 1) / kTile;
     const size_t lds = train_lds_floats(n_in) * sizeof(float);
     if (n_in == 5)
-        mlp_train_kernel<5><<<dim3(tiles), dim3(256), lds, st>>>(
+        mlp_train_kernel<5><<<dim3(tiles), dim3(kTrainBlock), lds, st>>>(
             params, X, Y, first, sstride, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
     else
-        mlp_train_kernel<6><<<dim3(tiles), dim3(256), lds, st>>>(
+        mlp_train_kernel<6><<<dim3(tiles), dim3(kTrainBlock), lds, st>>>(
             params, X, Y, first, sstride, batch, norm[0], norm[1], norm[2], norm[3], gpart, lpart);
     return hipGetLastError();
 }
